@@ -1,0 +1,315 @@
+/*
+ * pfem.h -- C ABI of the P1 finite-element physics library for MI355X (gfx950).
+ *
+ * What the library computes (arXiv 2601.03086, "Pretrain Finite Element
+ * Method"):
+ *   - the total potential Pi(u) = sum_e vol_e Psi(grad u) - f_ext . u used as
+ *     the physics-informed loss (Sec. 'Linear elastic plate with arbitrary
+ *     holes' and Sec. 'Nonlinear hyperelasticity', loss equations);
+ *   - its gradient f_int(u) - f_ext (App. B, total-Lagrangian internal
+ *     force) and its Hessian-vector product (App. B, K_mat + K_geo), applied
+ *     matrix-free;
+ *   - warm-started iterative solves (Sec. 'Warm-start', iteration and
+ *     stopping equations; App. B): Jacobi-preconditioned CG for linear
+ *     elasticity and Newton-Krylov with load steps for Neo-Hookean
+ *     hyperelasticity, whose initial guess U0 may come from a network;
+ *   - a serving loop that admits solve requests by device-memory footprint
+ *     and advances all live requests together (continuous batching).
+ *
+ * Elements are P1 triangles (dim 2) and tetrahedra (dim 3).
+ *
+ * Conventions
+ *   - Every function returns pfem_status: 0 OK, > 0 completed with a
+ *     warning, < 0 error.  On error outputs are unspecified and
+ *     pfem_last_error() returns a message (thread-local, valid until the
+ *     next call on the same thread).  No C++ exception crosses the ABI.
+ *   - Indices are 0-based int32.  A DOF index is g = node * dim + comp in
+ *     the CALLER's node numbering unless a call takes PFEM_LAYOUT_INTERNAL,
+ *     in which case vectors are in the library's reverse-Cuthill-McKee node
+ *     order (see pfem_mesh_query_int(PFEM_Q_PERM)).
+ *   - Input arrays are caller-owned and copied during the call.  Handles are
+ *     library-owned and released with the matching *_destroy.  Output
+ *     buffers are caller-owned.
+ *   - Pointers documented as "device" must point to memory of the context's
+ *     device; "host" pointers to ordinary host memory.
+ *   - A context binds one device and one HIP stream; all device work of the
+ *     handles created from it is ordered on that stream.  Calls on one
+ *     context must be serialised by the caller (the server object is the
+ *     exception: submit/poll/result/cancel may be called from any thread).
+ */
+#ifndef PFEM_H
+#define PFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pfem_status;
+enum {
+  PFEM_OK = 0,
+  PFEM_NOT_CONVERGED = 1,     /* max iterations reached; outputs hold the last iterate */
+  PFEM_SKIPPED_FINE = 2,      /* guess already below tol_fine: no iteration run */
+  PFEM_E_INVALID_ARG = -1,
+  PFEM_E_INVALID_MESH = -2,   /* bad index, degenerate element, orphan node ... */
+  PFEM_E_OOM = -3,
+  PFEM_E_DEVICE = -4,         /* a HIP runtime call failed */
+  PFEM_E_BREAKDOWN = -5,      /* p.Ap <= 0 or NaN in a linear solve */
+  PFEM_E_INVERTED = -6,       /* an element has J <= 0 at the evaluated state */
+  PFEM_E_LINESEARCH = -7,     /* no admissible Armijo step */
+  PFEM_E_CANCELLED = -8,
+  PFEM_E_STATE = -9           /* call not valid in the handle's current state */
+};
+
+/* Constitutive models.  Linear: sigma = 2 mu eps + lambda tr(eps) I with
+ * eps = sym grad u (plane stress replaces lambda by 2 mu lambda/(lambda+2 mu)).
+ * Neo-Hookean: Psi = 1/2 lambda (ln J)^2 - mu ln J + 1/2 mu (I1 - dim). */
+enum {
+  PFEM_LIN_PLANE_STRESS = 0,
+  PFEM_LIN_PLANE_STRAIN = 1,
+  PFEM_LIN_3D = 2,
+  PFEM_NH_PLANE_STRAIN = 3,
+  PFEM_NH_3D = 4
+};
+
+/* Material parameter kinds for pfem_mesh_set_material. */
+enum { PFEM_PARAM_E_NU = 0, PFEM_PARAM_LAME = 1 };
+
+/* Arithmetic of the element kernels: FP64 throughout, or FP32 element math
+ * with FP64 reductions, FP64 outer residuals and FP64 log J. */
+enum { PFEM_FP64 = 0, PFEM_FP32 = 1 };
+
+/* Scatter strategy of the element kernels (kernel-level calls). */
+enum {
+  PFEM_SCATTER_OWNER = 0,     /* node blocks own their outputs; LDS accumulation */
+  PFEM_SCATTER_COLORED = 1,   /* colour by colour, deterministic */
+  PFEM_SCATTER_ATOMIC = 2     /* device-wide atomic adds */
+};
+
+/* Vector layout for kernel-level calls. */
+enum { PFEM_LAYOUT_USER = 0, PFEM_LAYOUT_INTERNAL = 1 };
+
+/* Masking flags for kernel-level calls (bitwise or). */
+enum {
+  PFEM_MASK_NONE = 0,
+  PFEM_MASK_OUT = 1,          /* zero the output at Dirichlet DOFs */
+  PFEM_MASK_IN = 2            /* treat the input direction as zero at Dirichlet DOFs */
+};
+
+/* Integer query hooks (bit-exact preprocessing results). */
+enum {
+  PFEM_Q_PERM = 0,            /* n_nodes: new (RCM) id of each caller node */
+  PFEM_Q_ELEM_ORDER = 1,      /* n_elems: caller element index at each sorted position */
+  PFEM_Q_COLOR = 2,           /* n_elems: colour of each sorted element */
+  PFEM_Q_FREE_INDEX = 3,      /* n_nodes*dim: rank among free DOFs (caller numbering) or -1 */
+  PFEM_Q_BLOCKS = 4           /* 3*n_blocks: per node block (first touching elem,
+                                 first owned elem, end elem) in sorted order */
+};
+
+typedef struct pfem_ctx pfem_ctx;
+typedef struct pfem_mesh pfem_mesh;
+typedef struct pfem_batch pfem_batch;
+typedef struct pfem_server pfem_server;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * run on, or NULL for a library-owned stream (default priority). */
+pfem_status pfem_ctx_create(int device, void* hip_stream, pfem_ctx** out);
+void pfem_ctx_destroy(pfem_ctx* ctx);
+/* Message of the last error on this thread ("" if none). */
+const char* pfem_last_error(void);
+/* Library version string. */
+const char* pfem_version(void);
+
+/* Kernel timing: when enabled, every element-kernel launch on the context
+ * is bracketed by HIP events on the context stream and its elapsed time is
+ * accumulated per kernel family.  `family`: 0 = linear K.v / HVP apply,
+ * 1 = internal force, 2 = energy, 3 = Jacobi diagonal, 4 = PCG vector
+ * update, 5 = direction update.  Reading synchronises the stream. */
+pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int enable);
+pfem_status pfem_ctx_kernel_time(pfem_ctx* ctx, int family, int64_t* launches,
+                                 double* total_ms);
+pfem_status pfem_ctx_reset_timing(pfem_ctx* ctx);
+/* Block until all work queued on the context stream has finished. */
+pfem_status pfem_ctx_synchronize(pfem_ctx* ctx);
+
+/* ------------------------------------------------------------------- mesh */
+
+/* Create a mesh (App. B discretisation; Sec. 'Pretraining': the mesh the
+ * point cloud comes from).  coords: host, n_nodes*dim float64, node-major.
+ * conn: host, n_elems*(dim+1) int32.  Either orientation is accepted.
+ * `ctx` may be NULL for a host-only mesh (preprocessing and queries work;
+ * device calls return PFEM_E_STATE) -- the server uploads such meshes when
+ * it admits them. */
+pfem_status pfem_mesh_create(pfem_ctx* ctx, int dim, int64_t n_nodes,
+                             const double* coords, int64_t n_elems,
+                             const int32_t* conn, pfem_mesh** out);
+/* Per-element material.  model: PFEM_LIN_* / PFEM_NH_*.  param_kind:
+ * PFEM_PARAM_E_NU (p0 = Young's modulus, p1 = Poisson ratio; Lame
+ * parameters per Sec. 'Nonlinear hyperelasticity') or PFEM_PARAM_LAME
+ * (p0 = mu, p1 = lambda).  p0, p1: host, n_elems float64 each. */
+pfem_status pfem_mesh_set_material(pfem_mesh* m, int model, int param_kind,
+                                   const double* p0, const double* p1);
+/* Dirichlet set: n triples (node, comp, final value); host arrays.  Values
+ * are the final-load values; load steps scale them.  Dirichlet overrides
+ * Neumann at shared DOFs. */
+pfem_status pfem_mesh_set_dirichlet(pfem_mesh* m, int64_t n, const int32_t* node,
+                                    const int8_t* comp, const double* value);
+/* Neumann set: n_facets boundary facets (edges in 2D: 2 nodes; triangles in
+ * 3D: 3 nodes) each with a constant traction (dim values); host arrays.
+ * f_ext puts t |facet| / n_f on each facet node (App. B, f_ext integral). */
+pfem_status pfem_mesh_set_neumann(pfem_mesh* m, int64_t n_facets,
+                                  const int32_t* facet_nodes, const double* traction);
+/* Validate and preprocess: RCM numbering, element sort, colouring, free-DOF
+ * map, node blocks; upload to the device when the mesh has a context.
+ * block_nodes: nodes per owner block (0 = automatic). */
+pfem_status pfem_mesh_finalize(pfem_mesh* m, int block_nodes);
+
+typedef struct {
+  int32_t dim, model;
+  int64_t n_nodes, n_elems, n_dof, n_free;
+  int32_t n_colors, n_blocks, block_nodes;
+  int64_t bandwidth_in, bandwidth_rcm;     /* max |i-j| over element node pairs */
+  int64_t owner_elem_visits;                /* sum over blocks of touched range lengths */
+  int64_t device_bytes;                     /* mesh arrays resident on the device */
+  int64_t solve_bytes_fp32, solve_bytes_fp64;   /* extra device bytes of one solve */
+  double f_ext_norm;
+} pfem_mesh_info;
+pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* out);
+/* Copy a preprocessing array (see PFEM_Q_*) into out (cap entries);
+ * *n receives the full length. */
+pfem_status pfem_mesh_query_int(const pfem_mesh* m, int which, int32_t* out,
+                                int64_t cap, int64_t* n);
+void pfem_mesh_destroy(pfem_mesh* m);
+
+/* Convert a vector between the caller's and the internal node order.
+ * to_internal = 1: in caller order -> out internal; 0: the reverse.
+ * prec selects float64 (PFEM_FP64) or float32 (PFEM_FP32) elements.
+ * in, out: device, n_dof entries, must not alias. */
+pfem_status pfem_permute(pfem_mesh* m, int prec, int to_internal,
+                         const void* in, void* out);
+
+/* ------------------------------------------------------ kernel-level calls
+ * All vectors are device pointers of n_dof entries in `prec` (float64 or
+ * float32), in the layout given.  Mesh must be finalized with a context. */
+
+/* y = K v (linear models) or y = K_T(u) v (Neo-Hookean; u ignored for linear
+ * models and may be NULL).  App. B: incremental internal force
+ * (K_geo + K_mat) dU.  scatter: PFEM_SCATTER_*; mask: PFEM_MASK_* bits. */
+pfem_status pfem_hvp(pfem_mesh* m, int prec, int layout, int scatter, int mask,
+                     const void* u, const void* v, void* y);
+/* y = K v: pfem_hvp at u = 0. */
+pfem_status pfem_apply_K(pfem_mesh* m, int prec, int layout, int scatter,
+                         int mask, const void* v, void* y);
+/* g = dPi/du = f_int(u) - f_ext (App. B: f_int,iI = int dN_I/dX_J P_iJ dV0). */
+pfem_status pfem_force(pfem_mesh* m, int prec, int layout, int mask,
+                       const void* u, void* g);
+/* Pi(u) = sum_e vol_e Psi_e(u) - f_ext . u, reduced in float64 in a fixed
+ * order; energy_dev: device, 1 float64.  Elements with J <= 0 give +inf. */
+pfem_status pfem_energy(pfem_mesh* m, int prec, int layout, const void* u,
+                        double* energy_dev);
+/* diag(K_T(u)) (Jacobi preconditioner of the warm-start PCG); Dirichlet DOFs
+ * get 1. */
+pfem_status pfem_diag(pfem_mesh* m, int prec, int layout, const void* u, void* d);
+
+/* ------------------------------------------------------- batched calls
+ * A batch groups finalized meshes (same context) so each element kernel
+ * runs once over all of them (one launch, one work table).  Vectors are
+ * concatenated in batch order in INTERNAL layout: mesh i occupies
+ * [offset_i, offset_i + n_dof_i) with offsets from pfem_batch_offsets. */
+pfem_status pfem_batch_create(pfem_ctx* ctx, int32_t n, pfem_mesh* const* meshes,
+                              pfem_batch** out);
+void pfem_batch_destroy(pfem_batch* b);
+/* offsets: host, n+1 int64 entries. */
+pfem_status pfem_batch_offsets(const pfem_batch* b, int64_t* offsets);
+/* energies_dev: device, n float64 (one energy per mesh). */
+pfem_status pfem_batch_energy(pfem_batch* b, int prec, const void* u,
+                              double* energies_dev);
+pfem_status pfem_batch_force(pfem_batch* b, int prec, int mask, const void* u,
+                             void* g);
+pfem_status pfem_batch_hvp(pfem_batch* b, int prec, int mask, const void* u,
+                           const void* v, void* y);
+
+/* --------------------------------------------------------------- solves */
+typedef struct {
+  double tol;           /* relative residual target |r_f| / |r_f(lifted)| (App. B) */
+  double tol_fine;      /* skip iterating if the guess is already below (Sec. 'Warm-start'); 0 = off */
+  int32_t max_iter;     /* cap on K.v products in all Krylov loops; 0 = 10 * n_free */
+  int32_t n_load_steps; /* Neo-Hookean: load steps N_f (warm start jumps to N_f) */
+  int32_t max_newton;   /* per load step; 0 = 50 */
+  int32_t prec;         /* PFEM_FP64 or PFEM_FP32 (FP32 Krylov, FP64 outer residual) */
+  int32_t record_history;
+  double inner_rtol;    /* FP32 mode: residual reduction per refinement sweep; 0 = 1e-4 */
+} pfem_solve_opts;
+
+typedef struct {
+  pfem_status status;
+  int32_t kv_count;          /* K.v / HVP products in Krylov loops */
+  int32_t pcg_iters;
+  int32_t newton_iters;      /* summed over load steps */
+  int32_t load_steps_done;
+  int32_t residual_evals;    /* FP64 residual (internal force) evaluations */
+  int32_t outer_sweeps;      /* refinement sweeps / PCG restarts */
+  int32_t line_search_evals;
+  double rel_residual_initial;
+  double rel_residual_final;
+  int64_t history_len;
+  double t_device_ms;        /* wall time of the solve on the context stream */
+} pfem_solve_report;
+
+/* Fill opts with defaults (tol 1e-8, FP32 mode, history on). */
+void pfem_solve_opts_default(pfem_solve_opts* o);
+
+/* Solve for the displacement field (Sec. 'Warm-start': U^(0) = u0, stop at
+ * the relative-residual tolerance).  u0: NULL (zero start; Neo-Hookean runs
+ * all load steps) or n_dof float64 (warm start; Neo-Hookean starts at the
+ * final load step).  u0/u_out are device pointers if ptr_is_device else
+ * host; caller numbering.  Dirichlet DOFs of u_out hold the prescribed
+ * values.  history: host, history_cap float64 relative residuals (may be
+ * NULL).  rep: host (may be NULL). */
+pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
+                       double* u_out, int ptr_is_device, double* history,
+                       int64_t history_cap, pfem_solve_report* rep);
+
+/* --------------------------------------------------------------- serving */
+/* Create a server on ctx's device: at most max_slots live solves whose
+ * device footprint (mesh arrays + solver state) sums to at most
+ * hbm_budget_bytes.  A worker thread admits queued requests in arrival
+ * order as slots and memory free up, keeps each live solve's state on the
+ * device and advances all live solves together, one batched launch per
+ * kernel family per step. */
+pfem_status pfem_server_create(pfem_ctx* ctx, int64_t hbm_budget_bytes,
+                               int32_t max_slots, pfem_server** out);
+/* Queue a solve.  `m` must be finalized (a host-only mesh is fine); the
+ * server keeps a reference, so the caller must not destroy it before the
+ * result is collected.  u0: host n_dof float64 or NULL.  req_id must be
+ * unique among requests not yet collected.  Returns PFEM_E_OOM if the
+ * request alone can never fit the budget. */
+pfem_status pfem_server_submit(pfem_server* s, pfem_mesh* m, const double* u0,
+                               const pfem_solve_opts* o, int64_t req_id);
+/* Completed request ids not yet reported (non-blocking). */
+pfem_status pfem_server_poll(pfem_server* s, int64_t* done_ids, int64_t cap,
+                             int64_t* n_done);
+/* Collect a completed request: u_out host n_dof float64 (may be NULL); times
+ * in seconds since the server started (submit, admission, completion).
+ * Releases the request. */
+pfem_status pfem_server_result(pfem_server* s, int64_t req_id, double* u_out,
+                               pfem_solve_report* rep, double* t_submit,
+                               double* t_admit, double* t_done);
+/* Cancel a queued or live request (its result reports PFEM_E_CANCELLED). */
+pfem_status pfem_server_cancel(pfem_server* s, int64_t req_id);
+typedef struct {
+  int64_t submitted, completed, live, queued, peak_live;
+  int64_t bytes_in_use, peak_bytes, budget;
+  int64_t steps, launches;
+} pfem_server_stats;
+pfem_status pfem_server_get_stats(pfem_server* s, pfem_server_stats* out);
+/* Stop the worker (live requests are cancelled) and free everything. */
+void pfem_server_destroy(pfem_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFEM_H */

@@ -11,8 +11,10 @@
   values are scaled to n / N_f, then Newton iterations
   u <- u + s Delta with K_T(u) Delta = -r_f(u) until the relative residual
   is below tol.  A warm start skips the first N_f - 1 load steps.
-  Readings (paper silent): the relative residual divides by the residual of
-  the lifted state (free DOFs zero, load-step Dirichlet values); the step
+  Readings (paper silent): load step n applies the fraction n / N_f of the
+  whole load, prescribed displacements and tractions alike; the relative
+  residual divides by the residual of the lifted state (free DOFs zero,
+  load-step Dirichlet values, load-step tractions); the step
   length s follows Armijo backtracking on the total potential (factor 1/2,
   sufficient-decrease constant 1e-4, at most 20 halvings), rejecting any
   trial state with J <= 0; no load-step predictor.
@@ -120,6 +122,7 @@ def newton(prob, u0=None, tol=1e-8, n_load_steps=None, max_newton=50,
     converged displacement (copy), Newton count and residual history.
     """
     m = Model(prob)
+    f_full = m.f_ext.copy()
     nls = prob.n_load_steps if n_load_steps is None else n_load_steps
     fr = m.free_dofs
     if u0 is None:
@@ -132,6 +135,7 @@ def newton(prob, u0=None, tol=1e-8, n_load_steps=None, max_newton=50,
     status = 0
     for n in steps:
         scale = n / nls
+        m.f_ext = scale * f_full
         u[m.dir_dofs] = scale * m.dir_vals
         den = np.linalg.norm(_residual_free(m, m.lifted(scale)))
         hist = []
@@ -172,4 +176,5 @@ def newton(prob, u0=None, tol=1e-8, n_load_steps=None, max_newton=50,
                     "history": hist})
         if status < 0:
             break
+    m.f_ext = f_full
     return u, {"steps": out, "status": status}

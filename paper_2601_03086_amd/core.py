@@ -1,0 +1,315 @@
+"""Python view of the C ABI with torch tensors for device memory and streams.
+
+Argument marshalling only: every computation happens in libpfem.so.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check
+
+MODEL_IDS = {"lin_plane_stress": L.PFEM_LIN_PLANE_STRESS,
+             "lin_plane_strain": L.PFEM_LIN_PLANE_STRAIN,
+             "lin_3d": L.PFEM_LIN_3D,
+             "nh_plane_strain": L.PFEM_NH_PLANE_STRAIN,
+             "nh_3d": L.PFEM_NH_3D}
+PARAM_IDS = {"E_nu": L.PFEM_PARAM_E_NU, "lame": L.PFEM_PARAM_LAME}
+PREC = {"fp64": L.PFEM_FP64, "fp32": L.PFEM_FP32, L.PFEM_FP64: L.PFEM_FP64,
+        L.PFEM_FP32: L.PFEM_FP32}
+SCATTER = {"owner": L.PFEM_SCATTER_OWNER, "colored": L.PFEM_SCATTER_COLORED,
+           "atomic": L.PFEM_SCATTER_ATOMIC}
+LAYOUT = {"user": L.PFEM_LAYOUT_USER, "internal": L.PFEM_LAYOUT_INTERNAL}
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return C.c_void_p(a.data_ptr())
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(C.c_void_p)
+    raise TypeError(type(a))
+
+
+def _dtype(prec):
+    return torch.float64 if PREC[prec] == L.PFEM_FP64 else torch.float32
+
+
+class Context:
+    """One device + one HIP stream (torch's current stream by default)."""
+
+    def __init__(self, device=0, stream=None):
+        L.load()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        check(L.pfem_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            L.pfem_ctx_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def set_timing(self, on=True):
+        check(L.pfem_ctx_set_timing(self.h, 1 if on else 0))
+
+    def reset_timing(self):
+        check(L.pfem_ctx_reset_timing(self.h))
+
+    def kernel_time(self, family):
+        n = C.c_int64()
+        ms = C.c_double()
+        check(L.pfem_ctx_kernel_time(self.h, family, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    def synchronize(self):
+        check(L.pfem_ctx_synchronize(self.h))
+
+
+class Mesh:
+    """A finalized mesh with material and boundary sets (see pfem_mesh_*)."""
+
+    def __init__(self, ctx, dim, coords, conn, model, param_kind, p0, p1,
+                 dir_nodes=(), dir_comps=(), dir_values=(), facets=None,
+                 traction=None, block_nodes=0):
+        L.load()
+        self.ctx = ctx
+        self.dim = int(dim)
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        self.n_nodes = coords.shape[0]
+        self.n_elems = conn.shape[0]
+        self.n_dof = self.n_nodes * self.dim
+        self.model = model
+        self.nonlinear = model.startswith("nh")
+        h = C.c_void_p()
+        check(L.pfem_mesh_create(ctx.h if ctx is not None else None, self.dim,
+                                 self.n_nodes, _ptr(coords), self.n_elems, _ptr(conn),
+                                 C.byref(h)))
+        self.h = h
+        p0 = np.ascontiguousarray(np.broadcast_to(p0, (self.n_elems,)), dtype=np.float64)
+        p1 = np.ascontiguousarray(np.broadcast_to(p1, (self.n_elems,)), dtype=np.float64)
+        check(L.pfem_mesh_set_material(h, MODEL_IDS[model], PARAM_IDS[param_kind],
+                                       _ptr(p0), _ptr(p1)))
+        dn = np.ascontiguousarray(dir_nodes, dtype=np.int32)
+        dc = np.ascontiguousarray(dir_comps, dtype=np.int8)
+        dv = np.ascontiguousarray(dir_values, dtype=np.float64)
+        check(L.pfem_mesh_set_dirichlet(h, dn.size, _ptr(dn), _ptr(dc), _ptr(dv)))
+        if facets is not None and len(facets):
+            fa = np.ascontiguousarray(facets, dtype=np.int32)
+            tr = np.ascontiguousarray(traction, dtype=np.float64)
+            check(L.pfem_mesh_set_neumann(h, fa.shape[0], _ptr(fa), _ptr(tr)))
+        check(L.pfem_mesh_finalize(h, int(block_nodes)))
+        self.info = self.get_info()
+
+    @classmethod
+    def from_problem(cls, ctx, prob, block_nodes=0):
+        """Build from any object with the fields of a problem description."""
+        return cls(ctx, prob.coords.shape[1], prob.coords, prob.conn, prob.model,
+                   prob.param_kind, prob.p0, prob.p1, prob.dir_nodes, prob.dir_comps,
+                   prob.dir_values, prob.neu_facets, prob.neu_traction, block_nodes)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            L.pfem_mesh_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def get_info(self):
+        inf = L.pfem_mesh_info()
+        check(L.pfem_mesh_get_info(self.h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in inf._fields_}
+
+    def query(self, which):
+        n = C.c_int64()
+        check(L.pfem_mesh_query_int(self.h, which, None, 0, C.byref(n)))
+        out = np.empty(n.value, dtype=np.int32)
+        check(L.pfem_mesh_query_int(self.h, which, _ptr(out), n.value, C.byref(n)))
+        return out
+
+    # ---------------------------------------------------- device vectors
+    def new_vec(self, prec="fp64"):
+        return torch.empty(self.n_dof, dtype=_dtype(prec), device=self.ctx.device)
+
+    def _vec(self, x, prec):
+        t = torch.as_tensor(x, device=self.ctx.device, dtype=_dtype(prec))
+        if t.numel() != self.n_dof:
+            raise ValueError(f"vector has {t.numel()} entries, mesh has {self.n_dof} DOFs")
+        return t.contiguous()
+
+    def permute(self, x, to_internal=True, prec="fp64"):
+        x = self._vec(x, prec)
+        y = torch.empty_like(x)
+        check(L.pfem_permute(self.h, PREC[prec], 1 if to_internal else 0, _ptr(x), _ptr(y)))
+        return y
+
+    def hvp(self, u, v, prec="fp32", layout="user", scatter="owner", mask=0, out=None):
+        v = self._vec(v, prec)
+        u = self._vec(u, prec) if u is not None else None
+        y = torch.empty_like(v) if out is None else out
+        check(L.pfem_hvp(self.h, PREC[prec], LAYOUT[layout], SCATTER[scatter], mask,
+                         _ptr(u), _ptr(v), _ptr(y)))
+        return y
+
+    def apply_K(self, v, prec="fp32", layout="user", scatter="owner", mask=0, out=None):
+        v = self._vec(v, prec)
+        y = torch.empty_like(v) if out is None else out
+        check(L.pfem_apply_K(self.h, PREC[prec], LAYOUT[layout], SCATTER[scatter], mask,
+                             _ptr(v), _ptr(y)))
+        return y
+
+    def force(self, u, prec="fp64", layout="user", mask=0, out=None):
+        u = self._vec(u, prec)
+        y = torch.empty_like(u) if out is None else out
+        check(L.pfem_force(self.h, PREC[prec], LAYOUT[layout], mask, _ptr(u), _ptr(y)))
+        return y
+
+    def energy(self, u, prec="fp64", layout="user"):
+        u = self._vec(u, prec)
+        e = torch.empty((), dtype=torch.float64, device=self.ctx.device)
+        check(L.pfem_energy(self.h, PREC[prec], LAYOUT[layout], _ptr(u), _ptr(e)))
+        return e
+
+    def diag(self, u=None, prec="fp64", layout="user"):
+        uu = self._vec(u, prec) if u is not None else None
+        y = self.new_vec(prec)
+        check(L.pfem_diag(self.h, PREC[prec], LAYOUT[layout], _ptr(uu), _ptr(y)))
+        return y
+
+    # ------------------------------------------------------------ solve
+    @staticmethod
+    def opts(tol=1e-8, prec="fp32", tol_fine=0.0, max_iter=0, n_load_steps=10,
+             max_newton=50, record_history=1, inner_rtol=1e-4):
+        o = L.pfem_solve_opts()
+        L.pfem_solve_opts_default(C.byref(o))
+        o.tol = tol
+        o.tol_fine = tol_fine
+        o.max_iter = max_iter
+        o.n_load_steps = n_load_steps
+        o.max_newton = max_newton
+        o.prec = PREC[prec]
+        o.record_history = record_history
+        o.inner_rtol = inner_rtol
+        return o
+
+    def solve(self, u0=None, history_cap=100000, device_io=False, out=None, **kw):
+        """Warm-started solve; returns (u, report dict, history ndarray)."""
+        o = self.opts(**kw)
+        rep = L.pfem_solve_report()
+        hist = np.zeros(max(history_cap, 1), dtype=np.float64)
+        if device_io:
+            u0t = self._vec(u0, "fp64") if u0 is not None else None
+            u = self.new_vec("fp64") if out is None else out
+            st = L.pfem_solve(self.h, _ptr(u0t), C.byref(o), _ptr(u), 1, _ptr(hist),
+                              history_cap, C.byref(rep))
+        else:
+            u0a = (np.ascontiguousarray(u0, dtype=np.float64)
+                   if u0 is not None else None)
+            u = np.zeros(self.n_dof, dtype=np.float64)
+            st = L.pfem_solve(self.h, _ptr(u0a), C.byref(o), _ptr(u), 0, _ptr(hist),
+                              history_cap, C.byref(rep))
+        r = rep.as_dict()
+        r["status_name"] = L.STATUS_NAMES.get(rep.status, rep.status)
+        if st < 0:
+            check(st)
+        return u, r, hist[:rep.history_len].copy()
+
+
+class Batch:
+    """Several meshes evaluated by one launch per kernel (internal layout)."""
+
+    def __init__(self, ctx, meshes):
+        self.ctx = ctx
+        self.meshes = list(meshes)
+        arr = (C.c_void_p * len(self.meshes))(*[m.h.value for m in self.meshes])
+        h = C.c_void_p()
+        check(L.pfem_batch_create(ctx.h, len(self.meshes), arr, C.byref(h)))
+        self.h = h
+        off = np.zeros(len(self.meshes) + 1, dtype=np.int64)
+        check(L.pfem_batch_offsets(h, _ptr(off)))
+        self.offsets = off
+        self.n_dof = int(off[-1])
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            L.pfem_batch_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def energy(self, u, prec="fp32"):
+        u = u.contiguous()
+        e = torch.empty(len(self.meshes), dtype=torch.float64, device=self.ctx.device)
+        check(L.pfem_batch_energy(self.h, PREC[prec], _ptr(u), _ptr(e)))
+        return e
+
+    def force(self, u, prec="fp32", mask=0):
+        u = u.contiguous()
+        g = torch.empty_like(u)
+        check(L.pfem_batch_force(self.h, PREC[prec], mask, _ptr(u), _ptr(g)))
+        return g
+
+    def hvp(self, u, v, prec="fp32", mask=0):
+        v = v.contiguous()
+        y = torch.empty_like(v)
+        check(L.pfem_batch_hvp(self.h, PREC[prec], mask, _ptr(u.contiguous()), _ptr(v),
+                               _ptr(y)))
+        return y
+
+
+class Server:
+    """Continuous-batching solve server (pfem_server_*)."""
+
+    def __init__(self, ctx, hbm_budget_bytes, max_slots=32):
+        self.ctx = ctx
+        h = C.c_void_p()
+        check(L.pfem_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), C.byref(h)))
+        self.h = h
+        self._meshes = {}
+
+    def submit(self, req_id, mesh, u0=None, **kw):
+        o = Mesh.opts(**kw)
+        u0a = np.ascontiguousarray(u0, dtype=np.float64) if u0 is not None else None
+        check(L.pfem_server_submit(self.h, mesh.h, _ptr(u0a), C.byref(o), int(req_id)))
+        self._meshes[req_id] = mesh
+
+    def poll(self, cap=1024):
+        ids = np.zeros(cap, dtype=np.int64)
+        n = C.c_int64()
+        check(L.pfem_server_poll(self.h, _ptr(ids), cap, C.byref(n)))
+        return ids[:n.value].tolist()
+
+    def result(self, req_id):
+        mesh = self._meshes.pop(req_id)
+        u = np.zeros(mesh.n_dof, dtype=np.float64)
+        rep = L.pfem_solve_report()
+        ts, ta, td = C.c_double(), C.c_double(), C.c_double()
+        st = L.pfem_server_result(self.h, int(req_id), _ptr(u), C.byref(rep), C.byref(ts),
+                                  C.byref(ta), C.byref(td))
+        r = rep.as_dict()
+        r["status_name"] = L.STATUS_NAMES.get(rep.status, rep.status)
+        r.update(t_submit=ts.value, t_admit=ta.value, t_done=td.value, call_status=st)
+        return u, r
+
+    def cancel(self, req_id):
+        check(L.pfem_server_cancel(self.h, int(req_id)))
+
+    def stats(self):
+        s = L.pfem_server_stats()
+        check(L.pfem_server_get_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            L.pfem_server_destroy(self.h)
+            self.h = None
+
+    __del__ = close

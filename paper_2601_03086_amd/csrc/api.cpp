@@ -1,0 +1,671 @@
+// C ABI: argument checking, error translation and call orchestration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "mesh.h"
+#include "solver.h"
+
+using namespace pfem;
+
+struct pfem_batch {
+  pfem_ctx* ctx = nullptr;
+  std::vector<pfem_mesh*> meshes;
+  std::vector<int64_t> offsets;       // DOF offsets (n + 1)
+  int dim = 0;
+  int bn_max = 0;
+  int n_work = 0;
+  int2* work = nullptr;               // persistent device work table
+  double* part = nullptr;             // per mesh: n_blocks * kRedSlots
+  unsigned* counters = nullptr;       // per mesh: 16 words
+  double* outs = nullptr;             // per mesh: kRedSlots
+  std::vector<int64_t> part_off;
+};
+
+namespace pfem {
+void launch_energy_out(Ctx* ctx, const double* red, double* out, int n, int stride);
+}
+
+#define PFEM_TRY_BEGIN try {
+#define PFEM_TRY_END                                   \
+  }                                                    \
+  catch (const pfem::Error& e) {                       \
+    pfem::set_error(e.msg);                            \
+    return e.code;                                     \
+  }                                                    \
+  catch (const std::bad_alloc&) {                      \
+    pfem::set_error("host out of memory");             \
+    return PFEM_E_OOM;                                 \
+  }                                                    \
+  catch (const std::exception& e) {                    \
+    pfem::set_error(e.what());                         \
+    return PFEM_E_INVALID_ARG;                         \
+  }                                                    \
+  catch (...) {                                        \
+    pfem::set_error("unknown error");                  \
+    return PFEM_E_INVALID_ARG;                         \
+  }                                                    \
+  pfem::set_error("");                                 \
+  return PFEM_OK;
+
+extern "C" {
+
+const char* pfem_last_error(void) { return pfem::last_error_cstr(); }
+const char* pfem_version(void) { return "pfem-mi355x 0.1 (gfx950)"; }
+
+pfem_status pfem_ctx_create(int device, void* hip_stream, pfem_ctx** out) {
+  PFEM_TRY_BEGIN
+  require(out != nullptr, PFEM_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  PFEM_HIP(hipGetDeviceCount(&n));
+  require(device >= 0 && device < n, PFEM_E_INVALID_ARG, "device index out of range");
+  PFEM_HIP(hipSetDevice(device));
+  pfem_ctx* c = new pfem_ctx();
+  c->c.device = device;
+  try {
+    if (hip_stream != nullptr) {
+      c->c.stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      PFEM_HIP(hipStreamCreateWithFlags(&c->c.stream, hipStreamNonBlocking));
+      c->c.own_stream = true;
+    }
+    c->c.ring.init(16u << 20, c->c.stream);
+  } catch (...) {
+    delete c;
+    throw;
+  }
+  *out = c;
+  PFEM_TRY_END
+}
+
+void pfem_ctx_destroy(pfem_ctx* ctx) {
+  if (ctx == nullptr) return;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipStreamSynchronize(ctx->c.stream);
+  ctx->c.ring.release();
+  for (auto& p : ctx->c.pending) {
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
+  }
+  for (hipEvent_t e : ctx->c.event_pool) (void)hipEventDestroy(e);
+  if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
+  delete ctx;
+}
+
+pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int enable) {
+  PFEM_TRY_BEGIN
+  require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
+  ctx->c.drain_timing();
+  ctx->c.timing = enable != 0;
+  PFEM_TRY_END
+}
+
+pfem_status pfem_ctx_kernel_time(pfem_ctx* ctx, int family, int64_t* launches,
+                                 double* total_ms) {
+  PFEM_TRY_BEGIN
+  require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
+  require(family >= 0 && family < FAM_COUNT, PFEM_E_INVALID_ARG, "bad kernel family");
+  ctx->c.drain_timing();
+  if (launches) *launches = ctx->c.fam_launches[family];
+  if (total_ms) *total_ms = ctx->c.fam_ms[family];
+  PFEM_TRY_END
+}
+
+pfem_status pfem_ctx_reset_timing(pfem_ctx* ctx) {
+  PFEM_TRY_BEGIN
+  require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
+  ctx->c.drain_timing();
+  for (int i = 0; i < FAM_COUNT; ++i) {
+    ctx->c.fam_launches[i] = 0;
+    ctx->c.fam_ms[i] = 0.0;
+  }
+  PFEM_TRY_END
+}
+
+pfem_status pfem_ctx_synchronize(pfem_ctx* ctx) {
+  PFEM_TRY_BEGIN
+  require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
+  PFEM_HIP(hipStreamSynchronize(ctx->c.stream));
+  PFEM_TRY_END
+}
+
+// ------------------------------------------------------------------- mesh
+pfem_status pfem_mesh_create(pfem_ctx* ctx, int dim, int64_t n_nodes, const double* coords,
+                             int64_t n_elems, const int32_t* conn, pfem_mesh** out) {
+  PFEM_TRY_BEGIN
+  require(out != nullptr, PFEM_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  require(dim == 2 || dim == 3, PFEM_E_INVALID_ARG, "dim must be 2 or 3");
+  require(n_nodes > 0 && n_elems > 0, PFEM_E_INVALID_MESH, "empty mesh");
+  require(n_nodes < INT32_MAX / 3 && n_elems < INT32_MAX / 4, PFEM_E_INVALID_ARG,
+          "mesh too large for int32 indexing");
+  require(coords != nullptr && conn != nullptr, PFEM_E_INVALID_ARG, "NULL array");
+  pfem_mesh* m = new pfem_mesh();
+  m->ctx = ctx != nullptr ? &ctx->c : nullptr;
+  m->dim = dim;
+  m->n_nodes = n_nodes;
+  m->n_elems = n_elems;
+  m->coords.assign(coords, coords + n_nodes * dim);
+  m->conn.assign(conn, conn + n_elems * (dim + 1));
+  *out = m;
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_set_material(pfem_mesh* m, int model, int param_kind, const double* p0,
+                                   const double* p1) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr && p0 != nullptr && p1 != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+  require(!m->finalized, PFEM_E_STATE, "mesh already finalized");
+  require(model >= PFEM_LIN_PLANE_STRESS && model <= PFEM_NH_3D, PFEM_E_INVALID_ARG, "bad model");
+  require(param_kind == PFEM_PARAM_E_NU || param_kind == PFEM_PARAM_LAME, PFEM_E_INVALID_ARG,
+          "bad param_kind");
+  const bool three = model == PFEM_LIN_3D || model == PFEM_NH_3D;
+  require(three == (m->dim == 3), PFEM_E_INVALID_ARG, "model does not match mesh dimension");
+  m->model = model;
+  m->nonlinear = model == PFEM_NH_PLANE_STRAIN || model == PFEM_NH_3D;
+  m->mu.resize(m->n_elems);
+  m->lam.resize(m->n_elems);
+  for (int64_t e = 0; e < m->n_elems; ++e)
+    lame_from_params(model, param_kind, p0[e], p1[e], &m->mu[e], &m->lam[e]);
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_set_dirichlet(pfem_mesh* m, int64_t n, const int32_t* node,
+                                    const int8_t* comp, const double* value) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
+  require(!m->finalized, PFEM_E_STATE, "mesh already finalized");
+  require(n >= 0 && (n == 0 || (node && comp && value)), PFEM_E_INVALID_ARG, "bad Dirichlet arrays");
+  std::vector<double> seen(m->n_nodes * m->dim, std::nan(""));
+  m->dnode.clear();
+  m->dcomp.clear();
+  m->dval.clear();
+  for (int64_t i = 0; i < n; ++i) {
+    require(node[i] >= 0 && node[i] < m->n_nodes && comp[i] >= 0 && comp[i] < m->dim,
+            PFEM_E_INVALID_ARG, "Dirichlet entry out of range");
+    require(std::isfinite(value[i]), PFEM_E_INVALID_ARG, "non-finite Dirichlet value");
+    const int64_t g = (int64_t)node[i] * m->dim + comp[i];
+    if (!std::isnan(seen[g])) {
+      require(seen[g] == value[i], PFEM_E_INVALID_ARG, "conflicting Dirichlet values");
+      continue;
+    }
+    seen[g] = value[i];
+    m->dnode.push_back(node[i]);
+    m->dcomp.push_back(comp[i]);
+    m->dval.push_back(value[i]);
+  }
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_set_neumann(pfem_mesh* m, int64_t n_facets, const int32_t* facet_nodes,
+                                  const double* traction) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
+  require(!m->finalized, PFEM_E_STATE, "mesh already finalized");
+  require(n_facets >= 0 && (n_facets == 0 || (facet_nodes && traction)), PFEM_E_INVALID_ARG,
+          "bad Neumann arrays");
+  for (int64_t i = 0; i < n_facets * m->dim; ++i)
+    require(facet_nodes[i] >= 0 && facet_nodes[i] < m->n_nodes, PFEM_E_INVALID_ARG,
+            "Neumann facet node out of range");
+  for (int64_t i = 0; i < n_facets * m->dim; ++i)
+    require(std::isfinite(traction[i]), PFEM_E_INVALID_ARG, "non-finite traction");
+  m->n_facets = n_facets;
+  m->facets.assign(facet_nodes, facet_nodes + n_facets * m->dim);
+  m->traction.assign(traction, traction + n_facets * m->dim);
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_finalize(pfem_mesh* m, int block_nodes) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
+  require(!m->finalized, PFEM_E_STATE, "mesh already finalized");
+  require(block_nodes >= 0, PFEM_E_INVALID_ARG, "block_nodes < 0");
+  mesh_finalize_host(m, block_nodes);
+  if (m->ctx != nullptr) mesh_upload(m, m->ctx);
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* o) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr && o != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+  *o = pfem_mesh_info{};
+  o->dim = m->dim;
+  o->model = m->model;
+  o->n_nodes = m->n_nodes;
+  o->n_elems = m->n_elems;
+  o->n_dof = m->n_dof();
+  o->n_free = m->n_free;
+  o->n_colors = m->n_colors;
+  o->n_blocks = m->n_blocks;
+  o->block_nodes = m->bn;
+  o->bandwidth_in = m->bw_in;
+  o->bandwidth_rcm = m->bw_rcm;
+  o->owner_elem_visits = m->owner_visits;
+  o->device_bytes = m->finalized ? mesh_device_bytes(m) : 0;
+  o->solve_bytes_fp32 = m->finalized ? solve_bytes(m, PFEM_FP32) : 0;
+  o->solve_bytes_fp64 = m->finalized ? solve_bytes(m, PFEM_FP64) : 0;
+  o->f_ext_norm = m->fext_norm;
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_query_int(const pfem_mesh* m, int which, int32_t* out, int64_t cap,
+                                int64_t* n) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
+  require(m->finalized, PFEM_E_STATE, "mesh not finalized");
+  std::vector<int32_t> tmp;
+  const std::vector<int32_t>* src = nullptr;
+  switch (which) {
+    case PFEM_Q_PERM: src = &m->perm; break;
+    case PFEM_Q_ELEM_ORDER: src = &m->elem_order; break;
+    case PFEM_Q_COLOR: src = &m->color; break;
+    case PFEM_Q_FREE_INDEX: src = &m->free_index; break;
+    case PFEM_Q_BLOCKS:
+      for (const int4& b : m->blocks) {
+        tmp.push_back(b.x);
+        tmp.push_back(b.y);
+        tmp.push_back(b.z);
+      }
+      src = &tmp;
+      break;
+    default: throw Error{PFEM_E_INVALID_ARG, "bad query"};
+  }
+  if (n) *n = (int64_t)src->size();
+  if (out != nullptr) {
+    require(cap >= 0, PFEM_E_INVALID_ARG, "cap < 0");
+    std::copy(src->begin(), src->begin() + std::min<int64_t>(cap, src->size()), out);
+  }
+  PFEM_TRY_END
+}
+
+void pfem_mesh_destroy(pfem_mesh* m) {
+  if (m == nullptr) return;
+  try {
+    if (m->uploaded) {
+      (void)hipSetDevice(m->ctx->device);
+      mesh_release_device(m);
+    }
+  } catch (...) {
+  }
+  delete m;
+}
+
+// ----------------------------------------------------- kernel-level calls
+static void need_device(pfem_mesh* m) {
+  require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
+  require(m->finalized, PFEM_E_STATE, "mesh not finalized");
+  require(m->uploaded && m->ctx != nullptr, PFEM_E_STATE, "mesh has no device context");
+  PFEM_HIP(hipSetDevice(m->ctx->device));
+}
+
+static void check_prec(int prec) {
+  require(prec == PFEM_FP64 || prec == PFEM_FP32, PFEM_E_INVALID_ARG, "bad precision");
+}
+
+pfem_status pfem_permute(pfem_mesh* m, int prec, int to_internal, const void* in, void* out) {
+  PFEM_TRY_BEGIN
+  need_device(m);
+  check_prec(prec);
+  require(in != nullptr && out != nullptr && in != out, PFEM_E_INVALID_ARG, "bad vectors");
+  launch_permute(m->ctx, prec, m->dim, m->dev.perm, m->n_nodes, to_internal != 0, in, out);
+  PFEM_TRY_END
+}
+
+static void elem_call(pfem_mesh* m, int prec, int layout, int scatter, int mask, int op,
+                      const void* u, const void* v, void* y, double inv_diag) {
+  need_device(m);
+  check_prec(prec);
+  require(layout == PFEM_LAYOUT_USER || layout == PFEM_LAYOUT_INTERNAL, PFEM_E_INVALID_ARG,
+          "bad layout");
+  require(scatter >= PFEM_SCATTER_OWNER && scatter <= PFEM_SCATTER_ATOMIC, PFEM_E_INVALID_ARG,
+          "bad scatter mode");
+  require(y != nullptr, PFEM_E_INVALID_ARG, "output is NULL");
+  Ctx* ctx = m->ctx;
+  m->scratch.ensure(m->n_dof(), m->n_blocks);
+  const bool need_u = (op != OP_APPLY && !(op == OP_DIAG && !m->nonlinear)) ||
+                      (op == OP_APPLY && m->nonlinear);
+  if (need_u) require(u != nullptr, PFEM_E_INVALID_ARG, "state u is NULL");
+  if (op == OP_APPLY) require(v != nullptr, PFEM_E_INVALID_ARG, "direction is NULL");
+  const void* ui = u;
+  const void* vi = v;
+  void* yi = y;
+  if (layout == PFEM_LAYOUT_USER) {
+    if (need_u) {
+      launch_permute(ctx, prec, m->dim, m->dev.perm, m->n_nodes, true, u, m->scratch.in64);
+      ui = m->scratch.in64;
+    }
+    if (v != nullptr) {
+      launch_permute(ctx, prec, m->dim, m->dev.perm, m->n_nodes, true, v, m->scratch.v64);
+      vi = m->scratch.v64;
+    }
+    yi = m->scratch.out64;
+  }
+  Task t{};
+  t.m = m->md;
+  t.u = ui;
+  t.v = vi;
+  t.y = yi;
+  t.mask = mask;
+  t.active = 1;
+  t.finisher = FIN_STORE;
+  t.s = inv_diag;
+  t.fscale = 1.0;
+  if (scatter == PFEM_SCATTER_OWNER) {
+    const Task* td = static_cast<const Task*>(ctx->ring.put(&t, sizeof(Task)));
+    launch_elem(ctx, m->dim, prec, op, PFEM_SCATTER_OWNER, td, m->dev.work, m->n_blocks, m->bn,
+                nullptr, nullptr);
+  } else {
+    launch_elem(ctx, m->dim, prec, op, scatter, nullptr, nullptr, 0, m->bn, &t, &m->color_ptr);
+  }
+  if (layout == PFEM_LAYOUT_USER)
+    launch_permute(ctx, prec, m->dim, m->dev.perm, m->n_nodes, false, yi, y);
+}
+
+pfem_status pfem_hvp(pfem_mesh* m, int prec, int layout, int scatter, int mask, const void* u,
+                     const void* v, void* y) {
+  PFEM_TRY_BEGIN
+  elem_call(m, prec, layout, scatter, mask, OP_APPLY, u, v, y, 0.0);
+  PFEM_TRY_END
+}
+
+pfem_status pfem_apply_K(pfem_mesh* m, int prec, int layout, int scatter, int mask,
+                         const void* v, void* y) {
+  PFEM_TRY_BEGIN
+  need_device(m);
+  const void* u = nullptr;
+  if (m->nonlinear) {   // K = K_T(0)
+    m->scratch.ensure(m->n_dof(), m->n_blocks);
+    u = m->scratch.zero64;
+  }
+  elem_call(m, prec, layout, scatter, mask, OP_APPLY, u, v, y, 0.0);
+  PFEM_TRY_END
+}
+
+pfem_status pfem_force(pfem_mesh* m, int prec, int layout, int mask, const void* u, void* g) {
+  PFEM_TRY_BEGIN
+  elem_call(m, prec, layout, PFEM_SCATTER_OWNER, mask, OP_FORCE, u, nullptr, g, 0.0);
+  PFEM_TRY_END
+}
+
+pfem_status pfem_diag(pfem_mesh* m, int prec, int layout, const void* u, void* d) {
+  PFEM_TRY_BEGIN
+  elem_call(m, prec, layout, PFEM_SCATTER_OWNER, PFEM_MASK_NONE, OP_DIAG, u, nullptr, d, 0.0);
+  PFEM_TRY_END
+}
+
+pfem_status pfem_energy(pfem_mesh* m, int prec, int layout, const void* u, double* energy_dev) {
+  PFEM_TRY_BEGIN
+  need_device(m);
+  check_prec(prec);
+  require(u != nullptr && energy_dev != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+  Ctx* ctx = m->ctx;
+  m->scratch.ensure(m->n_dof(), m->n_blocks);
+  const void* ui = u;
+  if (layout == PFEM_LAYOUT_USER) {
+    launch_permute(ctx, prec, m->dim, m->dev.perm, m->n_nodes, true, u, m->scratch.in64);
+    ui = m->scratch.in64;
+  }
+  Task t{};
+  t.m = m->md;
+  t.u = ui;
+  t.active = 1;
+  t.fscale = 1.0;
+  t.finisher = FIN_STORE;
+  t.red.part = m->scratch.part;
+  t.red.counter = m->scratch.counter;
+  t.red.out = m->scratch.out;
+  const Task* td = static_cast<const Task*>(ctx->ring.put(&t, sizeof(Task)));
+  launch_energy(ctx, m->dim, prec, false, td, m->dev.work, m->n_blocks);
+  launch_energy_out(ctx, m->scratch.out, energy_dev, 1, kRedSlots);
+  PFEM_TRY_END
+}
+
+// -------------------------------------------------------------- batches
+pfem_status pfem_batch_create(pfem_ctx* ctx, int32_t n, pfem_mesh* const* meshes,
+                              pfem_batch** out) {
+  PFEM_TRY_BEGIN
+  require(ctx != nullptr && out != nullptr && meshes != nullptr && n > 0, PFEM_E_INVALID_ARG,
+          "bad batch arguments");
+  *out = nullptr;
+  pfem_batch* b = new pfem_batch();
+  b->ctx = ctx;
+  try {
+    PFEM_HIP(hipSetDevice(ctx->c.device));
+    b->offsets.push_back(0);
+    int total = 0;
+    int64_t poff = 0;
+    for (int i = 0; i < n; ++i) {
+      pfem_mesh* m = meshes[i];
+      need_device(m);
+      require(m->ctx == &ctx->c, PFEM_E_INVALID_ARG, "mesh belongs to another context");
+      if (i == 0) b->dim = m->dim;
+      require(m->dim == b->dim, PFEM_E_INVALID_ARG, "all meshes of a batch share one dimension");
+      b->meshes.push_back(m);
+      b->offsets.push_back(b->offsets.back() + m->n_dof());
+      b->bn_max = std::max(b->bn_max, m->bn);
+      b->part_off.push_back(poff);
+      poff += (int64_t)m->n_blocks * kRedSlots;
+      total += m->n_blocks;
+    }
+    std::vector<int2> nat;
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < meshes[i]->n_blocks; ++k) nat.push_back(make_int2(i, k));
+    std::vector<int2> w(total);
+    int cnt[8], pre[8];
+    for (int k = 0; k < 8; ++k) cnt[k] = std::max((total - k + 7) / 8, 0);
+    pre[0] = 0;
+    for (int k = 1; k < 8; ++k) pre[k] = pre[k - 1] + cnt[k - 1];
+    for (int i = 0; i < total; ++i) w[i] = nat[pre[i % 8] + i / 8];
+    b->n_work = total;
+    PFEM_HIP(hipMalloc((void**)&b->work, w.size() * sizeof(int2)));
+    PFEM_HIP(hipMemcpy(b->work, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice));
+    PFEM_HIP(hipMalloc((void**)&b->part, std::max<int64_t>(poff, 1) * 8));
+    PFEM_HIP(hipMalloc((void**)&b->counters, (size_t)n * 64));
+    PFEM_HIP(hipMemset(b->counters, 0, (size_t)n * 64));
+    PFEM_HIP(hipMalloc((void**)&b->outs, (size_t)n * kRedSlots * 8));
+  } catch (...) {
+    if (b->work) (void)hipFree(b->work);
+    if (b->part) (void)hipFree(b->part);
+    if (b->counters) (void)hipFree(b->counters);
+    if (b->outs) (void)hipFree(b->outs);
+    delete b;
+    throw;
+  }
+  *out = b;
+  PFEM_TRY_END
+}
+
+void pfem_batch_destroy(pfem_batch* b) {
+  if (b == nullptr) return;
+  (void)hipSetDevice(b->ctx->c.device);
+  (void)hipStreamSynchronize(b->ctx->c.stream);
+  if (b->work) (void)hipFree(b->work);
+  if (b->part) (void)hipFree(b->part);
+  if (b->counters) (void)hipFree(b->counters);
+  if (b->outs) (void)hipFree(b->outs);
+  delete b;
+}
+
+pfem_status pfem_batch_offsets(const pfem_batch* b, int64_t* offsets) {
+  PFEM_TRY_BEGIN
+  require(b != nullptr && offsets != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+  std::copy(b->offsets.begin(), b->offsets.end(), offsets);
+  PFEM_TRY_END
+}
+
+static std::vector<Task> batch_tasks(pfem_batch* b, int prec, const void* u, const void* v,
+                                     void* y, int mask) {
+  const size_t s = prec == PFEM_FP64 ? 8 : 4;
+  std::vector<Task> ts;
+  for (size_t i = 0; i < b->meshes.size(); ++i) {
+    Task t{};
+    t.m = b->meshes[i]->md;
+    const size_t off = (size_t)b->offsets[i] * s;
+    t.u = u ? static_cast<const char*>(u) + off : nullptr;
+    t.v = v ? static_cast<const char*>(v) + off : nullptr;
+    t.y = y ? static_cast<char*>(y) + off : nullptr;
+    t.mask = mask;
+    t.active = 1;
+    t.fscale = 1.0;
+    t.finisher = FIN_STORE;
+    t.red.part = b->part + b->part_off[i];
+    t.red.counter = b->counters + 16 * i;
+    t.red.out = b->outs + kRedSlots * i;
+    ts.push_back(t);
+  }
+  return ts;
+}
+
+pfem_status pfem_batch_energy(pfem_batch* b, int prec, const void* u, double* energies_dev) {
+  PFEM_TRY_BEGIN
+  require(b != nullptr && u != nullptr && energies_dev != nullptr, PFEM_E_INVALID_ARG,
+          "NULL argument");
+  check_prec(prec);
+  Ctx* ctx = &b->ctx->c;
+  PFEM_HIP(hipSetDevice(ctx->device));
+  std::vector<Task> ts = batch_tasks(b, prec, u, nullptr, nullptr, 0);
+  const Task* td = static_cast<const Task*>(ctx->ring.put(ts.data(), ts.size() * sizeof(Task)));
+  launch_energy(ctx, b->dim, prec, false, td, b->work, b->n_work);
+  launch_energy_out(ctx, b->outs, energies_dev, (int)b->meshes.size(), kRedSlots);
+  PFEM_TRY_END
+}
+
+static pfem_status batch_elem(pfem_batch* b, int prec, int mask, int op, const void* u,
+                              const void* v, void* y) {
+  require(b != nullptr && y != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+  check_prec(prec);
+  Ctx* ctx = &b->ctx->c;
+  PFEM_HIP(hipSetDevice(ctx->device));
+  std::vector<Task> ts = batch_tasks(b, prec, u, v, y, mask);
+  for (Task& t : ts) t.red.part = nullptr;
+  const Task* td = static_cast<const Task*>(ctx->ring.put(ts.data(), ts.size() * sizeof(Task)));
+  launch_elem(ctx, b->dim, prec, op, PFEM_SCATTER_OWNER, td, b->work, b->n_work, b->bn_max,
+              nullptr, nullptr);
+  return PFEM_OK;
+}
+
+pfem_status pfem_batch_force(pfem_batch* b, int prec, int mask, const void* u, void* g) {
+  PFEM_TRY_BEGIN
+  require(u != nullptr, PFEM_E_INVALID_ARG, "u is NULL");
+  batch_elem(b, prec, mask, OP_FORCE, u, nullptr, g);
+  PFEM_TRY_END
+}
+
+pfem_status pfem_batch_hvp(pfem_batch* b, int prec, int mask, const void* u, const void* v,
+                           void* y) {
+  PFEM_TRY_BEGIN
+  require(v != nullptr, PFEM_E_INVALID_ARG, "v is NULL");
+  for (pfem_mesh* m : b->meshes)
+    if (m->nonlinear) require(u != nullptr, PFEM_E_INVALID_ARG, "u is NULL");
+  batch_elem(b, prec, mask, OP_APPLY, u, v, y);
+  PFEM_TRY_END
+}
+
+// ----------------------------------------------------------------- solve
+void pfem_solve_opts_default(pfem_solve_opts* o) {
+  if (o == nullptr) return;
+  *o = pfem_solve_opts{};
+  o->tol = 1e-8;
+  o->tol_fine = 0.0;
+  o->max_iter = 0;
+  o->n_load_steps = 10;
+  o->max_newton = 50;
+  o->prec = PFEM_FP32;
+  o->record_history = 1;
+  o->inner_rtol = 1e-4;
+}
+
+pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o, double* u_out,
+                       int ptr_is_device, double* history, int64_t history_cap,
+                       pfem_solve_report* rep) {
+  PFEM_TRY_BEGIN
+  need_device(m);
+  require(o != nullptr && u_out != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+  require(o->tol > 0 && std::isfinite(o->tol), PFEM_E_INVALID_ARG, "tol must be > 0");
+  require(o->prec == PFEM_FP64 || o->prec == PFEM_FP32, PFEM_E_INVALID_ARG, "bad precision");
+  require(history_cap >= 0, PFEM_E_INVALID_ARG, "history_cap < 0");
+  Ctx* ctx = m->ctx;
+  const int64_t nd = m->n_dof();
+  const int64_t hcap = (o->record_history && history) ? history_cap : 0;
+  m->scratch.ensure(nd, m->n_blocks);
+  // (re)use the mesh's cached solver state
+  std::unique_ptr<SolveState>& cached = m->solve_state;
+  const int prec = o->prec;
+  if (!cached || cached->prec != prec || cached->hist_cap < hcap) {
+    cached.reset();
+    cached.reset(new SolveState());
+    cached->alloc(prec, nd, m->n_blocks, std::max<int64_t>(hcap, 1024), m->nonlinear);
+  }
+  SlotRun s;
+  s.m = m;
+  s.o = *o;
+  s.prec = prec;
+  s.nl = m->nonlinear;
+  s.st = cached.get();
+  PFEM_HIP(hipHostMalloc((void**)&s.sc_host, sizeof(Scalars), hipHostMallocDefault));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  pfem_status status = PFEM_OK;
+  try {
+    PFEM_HIP(hipEventCreate(&e0));
+    PFEM_HIP(hipEventCreate(&e1));
+    const double* u0_int = nullptr;
+    if (u0 != nullptr) {
+      const void* src = u0;
+      if (!ptr_is_device) {
+        PFEM_HIP(hipMemcpyAsync(m->scratch.v64, u0, nd * 8, hipMemcpyHostToDevice, ctx->stream));
+        src = m->scratch.v64;
+      }
+      launch_permute(ctx, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, true, src, m->scratch.in64);
+      u0_int = static_cast<const double*>(m->scratch.in64);
+    }
+    PFEM_HIP(hipEventRecord(e0, ctx->stream));
+    slot_begin(ctx, &s, u0_int);
+    std::vector<SlotRun*> live{&s};
+    int64_t launches = 0;
+    while (engine_tick(ctx, live, &launches) > 0) {
+    }
+    PFEM_HIP(hipEventRecord(e1, ctx->stream));
+    // outputs
+    if (ptr_is_device) {
+      launch_permute(ctx, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, false, s.st->x64, u_out);
+    } else {
+      launch_permute(ctx, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, false, s.st->x64,
+                     m->scratch.out64);
+      PFEM_HIP(hipMemcpyAsync(u_out, m->scratch.out64, nd * 8, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    PFEM_HIP(hipMemcpyAsync(s.sc_host, s.st->sc, sizeof(Scalars), hipMemcpyDeviceToHost,
+                            ctx->stream));
+    PFEM_HIP(hipStreamSynchronize(ctx->stream));
+    const int64_t hl = std::min<int64_t>(s.sc_host->hist_len, hcap);
+    if (hl > 0)
+      PFEM_HIP(hipMemcpy(history, s.st->hist, hl * 8, hipMemcpyDeviceToHost));
+    float ms = 0.f;
+    PFEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    s.rep.history_len = hl;
+    s.rep.t_device_ms = ms;
+    s.rep.status = s.status;
+    if (rep) *rep = s.rep;
+    status = s.status;
+  } catch (...) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipHostFree(s.sc_host);
+    s.st = nullptr;
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipHostFree(s.sc_host);
+  s.sc_host = nullptr;
+  s.st = nullptr;
+  if (status < 0) {
+    set_error(std::string("solve failed with status ") + std::to_string(status));
+    return status;
+  }
+  set_error("");
+  return status;
+  PFEM_TRY_END
+}
+
+}  // extern "C"

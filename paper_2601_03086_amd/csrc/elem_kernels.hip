@@ -1,0 +1,509 @@
+// Element kernels: K.v / Hessian-vector product, internal force, Jacobi
+// diagonal and energy on P1 triangles (D = 2) and tetrahedra (D = 3).
+//
+// Owner-computes scatter (default).  Nodes are numbered by reverse
+// Cuthill-McKee and cut into contiguous blocks of `bn` nodes; elements are
+// sorted by their smallest node id.  One workgroup owns one node block: it
+// walks the (contiguous) range of sorted elements that touch the block,
+// evaluates each element once, accumulates the contributions that land on
+// its own nodes in LDS, and finally writes every owned DOF exactly once with
+// coalesced stores.  No device-wide atomics, no zero-fill of the output, and
+// dot products with the output are fused into the write loop.  Elements that
+// straddle two blocks are evaluated by both; their gathers hit L2 because
+// consecutive blocks are scheduled on the same XCD (work-table remap).
+//
+// Alternatives for comparison: a device-wide atomic scatter over all
+// elements, and a colour-by-colour deterministic scatter.
+#include "elem_math.h"
+#include "pfem_internal.h"
+#include "reduce.h"
+
+namespace pfem {
+
+template <int D, typename T>
+__device__ __forceinline__ void load_nodal(const T* __restrict__ p, int n, T (&o)[D]) {
+  if constexpr (D == 2 && sizeof(T) == 4) {
+    const float2 q = *reinterpret_cast<const float2*>(p + (size_t)n * 2);
+    o[0] = q.x;
+    o[1] = q.y;
+  } else if constexpr (D == 2 && sizeof(T) == 8) {
+    const double2 q = *reinterpret_cast<const double2*>(p + (size_t)n * 2);
+    o[0] = q.x;
+    o[1] = q.y;
+  } else {
+#pragma unroll
+    for (int i = 0; i < D; ++i) o[i] = p[(size_t)n * D + i];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void load_conn(const int32_t* __restrict__ conn, int e,
+                                          int (&nd)[D + 1]) {
+  if constexpr (D == 3) {
+    const int4 q = *reinterpret_cast<const int4*>(conn + (size_t)e * 4);
+    nd[0] = q.x;
+    nd[1] = q.y;
+    nd[2] = q.z;
+    nd[3] = q.w;
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nd[a] = conn[(size_t)e * 3 + a];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T mat_mu(const MeshDev& m, int e) {
+  if constexpr (sizeof(T) == 4) return m.mu32[e]; else return m.mu64[e];
+}
+template <typename T>
+__device__ __forceinline__ T mat_lam(const MeshDev& m, int e) {
+  if constexpr (sizeof(T) == 4) return m.lam32[e]; else return m.lam64[e];
+}
+
+// Element output for one op; y[a][i] is the contribution to node a, comp i.
+template <int D, typename T, int OP>
+__device__ __forceinline__ void element_output(const MeshDev& m, const T* __restrict__ U,
+                                               const T* __restrict__ V, int mask, int e,
+                                               const int (&nd)[D + 1], T (&y)[D + 1][D]) {
+  Geo<D, T> g;
+  load_geometry<D, T>(m.X, nd, g);
+  const T mu = mat_mu<T>(m, e);
+  const T lam = mat_lam<T>(m, e);
+  const T adet = g.det < T(0) ? -g.det : g.det;
+  const T s_sym = T(1) / (T(Fact<D>::v) * adet);       // vol / det^2
+  if (OP == OP_DIAG) {
+    T cc[D + 1][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) cc[0][i] = T(0);
+#pragma unroll
+    for (int a = 1; a <= D; ++a)
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        cc[a][i] = g.c[a - 1][i];
+        cc[0][i] -= g.c[a - 1][i];
+      }
+    if (!m.nonlinear) {
+#pragma unroll
+      for (int a = 0; a <= D; ++a) {
+        T n2 = T(0);
+#pragma unroll
+        for (int i = 0; i < D; ++i) n2 += cc[a][i] * cc[a][i];
+#pragma unroll
+        for (int i = 0; i < D; ++i) y[a][i] = s_sym * (mu * n2 + (lam + mu) * cc[a][i] * cc[a][i]);
+      }
+    } else {
+      T uu[D + 1][D];
+#pragma unroll
+      for (int a = 0; a <= D; ++a) load_nodal<D, T>(U, nd[a], uu[a]);
+      T Ht[D][D];
+      grad_tilde<D, T>(uu, g, Ht);
+      NHState<D, T> st;
+      nh_state<D, T>(Ht, T(1) / g.det, st);
+      const T coef = (T)((double)lam + (double)mu - (double)lam * st.lnJ);
+#pragma unroll
+      for (int a = 0; a <= D; ++a) {
+        T n2 = T(0);
+#pragma unroll
+        for (int i = 0; i < D; ++i) n2 += cc[a][i] * cc[a][i];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          T w = T(0);
+#pragma unroll
+          for (int k = 0; k < D; ++k) w += st.FinvT[i][k] * cc[a][k];
+          y[a][i] = s_sym * (mu * n2 + coef * w * w);
+        }
+      }
+    }
+    return;
+  }
+  if (!m.nonlinear) {
+    // K v (OP_APPLY) or K u (OP_FORCE, f_ext subtracted by the caller)
+    T vv[D + 1][D];
+    const T* src = (OP == OP_APPLY) ? V : U;
+#pragma unroll
+    for (int a = 0; a <= D; ++a) load_nodal<D, T>(src, nd[a], vv[a]);
+    if (OP == OP_APPLY && (mask & PFEM_MASK_IN)) {
+#pragma unroll
+      for (int a = 0; a <= D; ++a) {
+        const int bits = m.dmask[nd[a]];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+          if (bits & (1 << i)) vv[a][i] = T(0);
+      }
+    }
+    T M[D][D], S[D][D];
+    grad_tilde<D, T>(vv, g, M);
+    linear_stress_tilde<D, T>(M, mu, lam, S);
+    scatter_rows<D, T>(S, g, s_sym, y);
+    return;
+  }
+  // Neo-Hookean
+  T uu[D + 1][D];
+#pragma unroll
+  for (int a = 0; a <= D; ++a) load_nodal<D, T>(U, nd[a], uu[a]);
+  T Ht[D][D];
+  grad_tilde<D, T>(uu, g, Ht);
+  NHState<D, T> st;
+  nh_state<D, T>(Ht, T(1) / g.det, st);
+  if (OP == OP_FORCE) {
+    T P[D][D];
+    nh_piola<D, T>(st, mu, lam, P);
+    const T s_sgn = (g.det < T(0) ? T(-1) : T(1)) / T(Fact<D>::v);   // vol / det
+    scatter_rows<D, T>(P, g, s_sgn, y);
+  } else {
+    T vv[D + 1][D];
+#pragma unroll
+    for (int a = 0; a <= D; ++a) load_nodal<D, T>(V, nd[a], vv[a]);
+    if (mask & PFEM_MASK_IN) {
+#pragma unroll
+      for (int a = 0; a <= D; ++a) {
+        const int bits = m.dmask[nd[a]];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+          if (bits & (1 << i)) vv[a][i] = T(0);
+      }
+    }
+    T dF[D][D], dP[D][D];
+    grad_tilde<D, T>(vv, g, dF);
+    nh_dpiola<D, T>(st, mu, lam, dF, dP);
+    scatter_rows<D, T>(dP, g, s_sym, y);
+  }
+}
+
+// ------------------------------------------------------------ owner kernel
+template <int D, typename T, int OP>
+__global__ void __launch_bounds__(kThreads)
+k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  if (tp->finisher == FIN_PQ && tp->sc->state != 0) return;
+  const MeshDev m = tp->m;
+  const int blk = wk.y;
+  const int n0 = blk * m.bn;
+  const int nloc = min(m.bn, m.n_nodes - n0);
+  const int4 br = m.blocks[blk];
+  T* acc = reinterpret_cast<T*>(smem_raw);
+  const int nown = nloc * D;
+  for (int i = threadIdx.x; i < nown; i += kThreads) acc[i] = T(0);
+  __syncthreads();
+  const T* U = static_cast<const T*>(tp->u);
+  const T* V = static_cast<const T*>(tp->v);
+  const int mask = tp->mask;
+  for (int e = br.x + (int)threadIdx.x; e < br.z; e += kThreads) {
+    int nd[D + 1];
+    load_conn<D>(m.conn, e, nd);
+    bool touch = false;
+#pragma unroll
+    for (int a = 0; a <= D; ++a) touch |= (unsigned)(nd[a] - n0) < (unsigned)nloc;
+    if (!touch) continue;
+    T y[D + 1][D];
+    element_output<D, T, OP>(m, U, V, mask, e, nd, y);
+#pragma unroll
+    for (int a = 0; a <= D; ++a) {
+      const int ln = nd[a] - n0;
+      if ((unsigned)ln < (unsigned)nloc) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) atomicAdd(&acc[ln * D + i], y[a][i]);
+      }
+    }
+  }
+  __syncthreads();
+  T* Y = static_cast<T*>(tp->y);
+  const T* W = static_cast<const T*>(tp->w);
+  double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
+  const size_t g0 = (size_t)n0 * D;
+  for (int i = threadIdx.x; i < nown; i += kThreads) {
+    const size_t gi = g0 + i;
+    T val = acc[i];
+    const bool con = (m.dmask[n0 + i / D] >> (i % D)) & 1;
+    if (OP == OP_FORCE) val -= (T)(tp->fscale * m.fext[gi]);
+    if (OP == OP_DIAG) {
+      if (con) val = T(1);
+      else if (tp->s != 0.0) val = T(1) / val;   // inverse diagonal for PCG
+    } else if ((mask & PFEM_MASK_OUT) && con) {
+      val = T(0);
+    }
+    Y[gi] = val;
+    if (W != nullptr) part[0] += (double)val * (double)W[gi];
+    part[1] += (double)val * (double)val;
+  }
+  reduce_finish(tp, blk, m.n_blocks, part);
+}
+
+// -------------------------------------------------- alternative scatters
+template <int D, typename T, int OP>
+__global__ void __launch_bounds__(kThreads) k_atomic(Task t) {
+  const MeshDev& m = t.m;
+  const T* U = static_cast<const T*>(t.u);
+  const T* V = static_cast<const T*>(t.v);
+  T* Y = static_cast<T*>(t.y);
+  for (int e = blockIdx.x * kThreads + threadIdx.x; e < m.n_elems;
+       e += gridDim.x * kThreads) {
+    int nd[D + 1];
+    load_conn<D>(m.conn, e, nd);
+    T y[D + 1][D];
+    element_output<D, T, OP>(m, U, V, t.mask, e, nd, y);
+#pragma unroll
+    for (int a = 0; a <= D; ++a)
+#pragma unroll
+      for (int i = 0; i < D; ++i) atomicAdd(&Y[(size_t)nd[a] * D + i], y[a][i]);
+  }
+}
+
+template <int D, typename T, int OP>
+__global__ void __launch_bounds__(kThreads) k_colored(Task t, int c0, int c1) {
+  const MeshDev& m = t.m;
+  const T* U = static_cast<const T*>(t.u);
+  const T* V = static_cast<const T*>(t.v);
+  T* Y = static_cast<T*>(t.y);
+  for (int k = c0 + blockIdx.x * kThreads + threadIdx.x; k < c1;
+       k += gridDim.x * kThreads) {
+    const int e = m.colored[k];
+    int nd[D + 1];
+    load_conn<D>(m.conn, e, nd);
+    T y[D + 1][D];
+    element_output<D, T, OP>(m, U, V, t.mask, e, nd, y);
+#pragma unroll
+    for (int a = 0; a <= D; ++a)
+#pragma unroll
+      for (int i = 0; i < D; ++i) Y[(size_t)nd[a] * D + i] += y[a][i];
+  }
+}
+
+// Output fix-up for the alternative scatters: subtract f_ext (force),
+// Dirichlet handling, all in one pass over the DOFs.
+template <int D, typename T, int OP>
+__global__ void __launch_bounds__(kThreads) k_alt_fixup(Task t) {
+  const MeshDev& m = t.m;
+  T* Y = static_cast<T*>(t.y);
+  const size_t n = (size_t)m.n_nodes * D;
+  for (size_t g = (size_t)blockIdx.x * kThreads + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * kThreads) {
+    const bool con = (m.dmask[g / D] >> (g % D)) & 1;
+    T val = Y[g];
+    if (OP == OP_FORCE) val -= (T)(t.fscale * m.fext[g]);
+    if (OP == OP_DIAG) {
+      if (con) val = T(1);
+      else if (t.s != 0.0) val = T(1) / val;
+    } else if ((t.mask & PFEM_MASK_OUT) && con) {
+      val = T(0);
+    }
+    Y[g] = val;
+  }
+}
+
+// ----------------------------------------------------------------- energy
+// Pi = sum_e vol_e Psi_e - f_ext . u over the elements a block owns (each
+// element once) and the DOFs it owns.  With DIFF the kernel returns
+// Pi(u + s v) - Pi(u) accumulated element by element in float64 (no
+// cancellation between two large totals), and counts elements with J <= 0
+// at the trial state.  red.out = (energy or difference, #inverted, 0, 0).
+template <int D, typename TU, typename TV, bool DIFF>
+__global__ void __launch_bounds__(kThreads)
+k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  const MeshDev m = tp->m;
+  const int blk = wk.y;
+  const int n0 = blk * m.bn;
+  const int nloc = min(m.bn, m.n_nodes - n0);
+  const int4 br = m.blocks[blk];
+  const TU* U = static_cast<const TU*>(tp->u);
+  const TV* V = static_cast<const TV*>(tp->v);
+  const double s = tp->s;
+  double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
+  using T = TU;   // element arithmetic type
+  for (int e = br.y + (int)threadIdx.x; e < br.z; e += kThreads) {
+    int nd[D + 1];
+    load_conn<D>(m.conn, e, nd);
+    Geo<D, T> g;
+    load_geometry<D, T>(m.X, nd, g);
+    const T mu = mat_mu<T>(m, e);
+    const T lam = mat_lam<T>(m, e);
+    const T adet = g.det < T(0) ? -g.det : g.det;
+    const double vol = (double)adet / Fact<D>::v;
+    T uu[D + 1][D];
+#pragma unroll
+    for (int a = 0; a <= D; ++a) load_nodal<D, TU>(U, nd[a], uu[a]);
+    T Ht[D][D];
+    grad_tilde<D, T>(uu, g, Ht);
+    double psi0, psi1 = 0.0;
+    T H[D][D];
+    const T inv_det = T(1) / g.det;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < D; ++k) H[i][k] = Ht[i][k] * inv_det;
+    if (!m.nonlinear) {
+      T S[D][D];
+      linear_stress_tilde<D, T>(H, mu, lam, S);
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc += (double)S[i][k] * 0.5 * ((double)H[i][k] + (double)H[k][i]);
+      psi0 = 0.5 * acc;
+    } else {
+      psi0 = nh_energy_density<D, T>(H, (double)mu, (double)lam);
+    }
+    if (DIFF) {
+      T vv[D + 1][D];
+#pragma unroll
+      for (int a = 0; a <= D; ++a) {
+        TV t[D];
+        load_nodal<D, TV>(V, nd[a], t);
+#pragma unroll
+        for (int i = 0; i < D; ++i) vv[a][i] = uu[a][i] + (T)(s * (double)t[i]);
+      }
+      T Mt[D][D];
+      grad_tilde<D, T>(vv, g, Mt);
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int k = 0; k < D; ++k) H[i][k] = Mt[i][k] * inv_det;
+      if (!m.nonlinear) {
+        T S[D][D];
+        linear_stress_tilde<D, T>(H, mu, lam, S);
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int k = 0; k < D; ++k) acc += (double)S[i][k] * 0.5 * ((double)H[i][k] + (double)H[k][i]);
+        psi1 = 0.5 * acc;
+      } else {
+        psi1 = nh_energy_density<D, T>(H, (double)mu, (double)lam);
+      }
+      if (psi1 == __builtin_inf()) {
+        part[1] += 1.0;
+      } else {
+        part[0] += vol * (psi1 - psi0);
+      }
+    } else {
+      if (psi0 == __builtin_inf()) part[1] += 1.0;
+      else part[0] += vol * psi0;
+    }
+  }
+  // - f_ext . u   (or - s f_ext . v for the difference)
+  const size_t g0 = (size_t)n0 * D;
+  for (int i = threadIdx.x; i < nloc * D; i += kThreads) {
+    const double f = tp->fscale * m.fext[g0 + i];
+    if (DIFF) part[0] -= s * f * (double)V[g0 + i];
+    else part[0] -= f * (double)U[g0 + i];
+  }
+  reduce_finish(tp, blk, m.n_blocks, part);
+}
+
+// ---------------------------------------------------------------- launchers
+static int smem_bytes(int dim, int prec, int bn) {
+  return bn * dim * (prec == PFEM_FP64 ? 8 : 4);
+}
+
+template <int D, typename T>
+static void launch_owner_typed(Ctx* ctx, int op, const Task* tasks, const int2* work,
+                               int n_work, int bn_max) {
+  const size_t sm = (size_t)bn_max * D * sizeof(T);
+  dim3 grid(n_work), block(kThreads);
+  switch (op) {
+    case OP_APPLY:
+      hipLaunchKernelGGL((k_owner<D, T, OP_APPLY>), grid, block, sm, ctx->stream, tasks, work);
+      break;
+    case OP_FORCE:
+      hipLaunchKernelGGL((k_owner<D, T, OP_FORCE>), grid, block, sm, ctx->stream, tasks, work);
+      break;
+    default:
+      hipLaunchKernelGGL((k_owner<D, T, OP_DIAG>), grid, block, sm, ctx->stream, tasks, work);
+      break;
+  }
+}
+
+template <int D, typename T>
+static void launch_alt_typed(Ctx* ctx, int op, int mode, const Task& t,
+                             const std::vector<int>* color_ptr) {
+  const int ne = t.m.n_elems;
+  const int grid = std::max(1, std::min((ne + kThreads - 1) / kThreads, 4096));
+  launch_fill(ctx, sizeof(T) == 8 ? PFEM_FP64 : PFEM_FP32, t.y, (int64_t)t.m.n_nodes * D, 0.0);
+  if (mode == PFEM_SCATTER_ATOMIC) {
+#define PFEM_ATOMIC(OPV) hipLaunchKernelGGL((k_atomic<D, T, OPV>), dim3(grid), dim3(kThreads), 0, ctx->stream, t)
+    if (op == OP_APPLY) PFEM_ATOMIC(OP_APPLY);
+    else if (op == OP_FORCE) PFEM_ATOMIC(OP_FORCE);
+    else PFEM_ATOMIC(OP_DIAG);
+#undef PFEM_ATOMIC
+  } else {
+    const std::vector<int>& cp = *color_ptr;
+    for (size_t c = 0; c + 1 < cp.size(); ++c) {
+      const int cnt = cp[c + 1] - cp[c];
+      if (cnt <= 0) continue;
+      const int g = std::max(1, std::min((cnt + kThreads - 1) / kThreads, 4096));
+#define PFEM_COLOR(OPV) hipLaunchKernelGGL((k_colored<D, T, OPV>), dim3(g), dim3(kThreads), 0, ctx->stream, t, cp[c], cp[c + 1])
+      if (op == OP_APPLY) PFEM_COLOR(OP_APPLY);
+      else if (op == OP_FORCE) PFEM_COLOR(OP_FORCE);
+      else PFEM_COLOR(OP_DIAG);
+#undef PFEM_COLOR
+    }
+  }
+  const size_t n = (size_t)t.m.n_nodes * D;
+  const int gf = (int)std::max<size_t>(1, std::min<size_t>((n + kThreads - 1) / kThreads, 4096));
+#define PFEM_FIX(OPV) hipLaunchKernelGGL((k_alt_fixup<D, T, OPV>), dim3(gf), dim3(kThreads), 0, ctx->stream, t)
+  if (op == OP_APPLY) PFEM_FIX(OP_APPLY);
+  else if (op == OP_FORCE) PFEM_FIX(OP_FORCE);
+  else PFEM_FIX(OP_DIAG);
+#undef PFEM_FIX
+}
+
+static int family_of(int op) {
+  return op == OP_APPLY ? FAM_APPLY : (op == OP_FORCE ? FAM_FORCE : FAM_DIAG);
+}
+
+void launch_elem(Ctx* ctx, int dim, int prec, int op, int scatter_mode,
+                 const Task* tasks_dev, const int2* work_dev, int n_work, int bn_max,
+                 const Task* host_task_for_alt, const std::vector<int>* color_ptr) {
+  hipEvent_t ev = nullptr;
+  ctx->timing_begin(family_of(op), &ev);
+  if (scatter_mode == PFEM_SCATTER_OWNER) {
+    if (n_work > 0) {
+      if (dim == 2 && prec == PFEM_FP32) launch_owner_typed<2, float>(ctx, op, tasks_dev, work_dev, n_work, bn_max);
+      else if (dim == 2) launch_owner_typed<2, double>(ctx, op, tasks_dev, work_dev, n_work, bn_max);
+      else if (prec == PFEM_FP32) launch_owner_typed<3, float>(ctx, op, tasks_dev, work_dev, n_work, bn_max);
+      else launch_owner_typed<3, double>(ctx, op, tasks_dev, work_dev, n_work, bn_max);
+    }
+  } else {
+    const Task& t = *host_task_for_alt;
+    const std::vector<int>* cp = color_ptr;
+    if (dim == 2 && prec == PFEM_FP32) launch_alt_typed<2, float>(ctx, op, scatter_mode, t, cp);
+    else if (dim == 2) launch_alt_typed<2, double>(ctx, op, scatter_mode, t, cp);
+    else if (prec == PFEM_FP32) launch_alt_typed<3, float>(ctx, op, scatter_mode, t, cp);
+    else launch_alt_typed<3, double>(ctx, op, scatter_mode, t, cp);
+  }
+  PFEM_HIP(hipGetLastError());
+  ctx->timing_end(family_of(op), ev);
+}
+
+void launch_energy(Ctx* ctx, int dim, int prec, bool diff, const Task* tasks_dev,
+                   const int2* work_dev, int n_work) {
+  if (n_work <= 0) return;
+  hipEvent_t ev = nullptr;
+  ctx->timing_begin(FAM_ENERGY, &ev);
+  dim3 grid(n_work), block(kThreads);
+  hipStream_t s = ctx->stream;
+  // diff: u is float64 state, v is the increment in `prec`
+  if (!diff) {
+    if (dim == 2 && prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<2, float, float, false>), grid, block, 0, s, tasks_dev, work_dev);
+    else if (dim == 2) hipLaunchKernelGGL((k_energy<2, double, double, false>), grid, block, 0, s, tasks_dev, work_dev);
+    else if (prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<3, float, float, false>), grid, block, 0, s, tasks_dev, work_dev);
+    else hipLaunchKernelGGL((k_energy<3, double, double, false>), grid, block, 0, s, tasks_dev, work_dev);
+  } else {
+    if (dim == 2 && prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<2, double, float, true>), grid, block, 0, s, tasks_dev, work_dev);
+    else if (dim == 2) hipLaunchKernelGGL((k_energy<2, double, double, true>), grid, block, 0, s, tasks_dev, work_dev);
+    else if (prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<3, double, float, true>), grid, block, 0, s, tasks_dev, work_dev);
+    else hipLaunchKernelGGL((k_energy<3, double, double, true>), grid, block, 0, s, tasks_dev, work_dev);
+  }
+  PFEM_HIP(hipGetLastError());
+  ctx->timing_end(FAM_ENERGY, ev);
+}
+
+int block_nodes_max() { return 4096; }
+
+}  // namespace pfem

@@ -1,0 +1,282 @@
+// Per-element P1 physics shared by every element kernel (device code).
+//
+// Geometry (App. B, P1 total-Lagrangian discretisation): with edge vectors
+// e_a = X_a - X_0 (a = 1..D) the rows of J^{-1} (J = [e_1 .. e_D]) are the
+// shape-function gradients grad N_a = c_a / det J, where c_a are the
+// cofactor rows (2D: c_1 = (e2y, -e2x), c_2 = (-e1y, e1x); 3D:
+// c_1 = e2 x e3, c_2 = e3 x e1, c_3 = e1 x e2) and grad N_0 = -sum_a grad N_a.
+// The element measure is |det J| / D!.  Coordinates are float64 and the
+// differences are taken in float64 before rounding to the kernel type, so
+// the geometry keeps its relative accuracy on small elements.
+//
+// Every nodal output y_a is formed from the unnormalised c_a; vol/det^2 =
+// 1/(D! |det|) and vol/det = sign(det)/D! carry the normalisation, so each
+// element needs a single division.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pfem {
+
+template <int D>
+struct Fact;
+template <>
+struct Fact<2> { static constexpr double v = 2.0; };
+template <>
+struct Fact<3> { static constexpr double v = 6.0; };
+
+template <int D, typename T>
+struct Geo {
+  T c[D][D];   // c[a-1][j]: unnormalised gradient of node a (a = 1..D)
+  T det;       // signed det J
+};
+
+template <int D, typename T>
+__device__ __forceinline__ void load_geometry(const double* __restrict__ X,
+                                              const int (&nd)[D + 1],
+                                              Geo<D, T>& g) {
+  double x0[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) x0[i] = X[(size_t)nd[0] * D + i];
+  T e[D][D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+      e[a][i] = (T)(X[(size_t)nd[a + 1] * D + i] - x0[i]);
+  if constexpr (D == 2) {
+    g.c[0][0] = e[1][1];
+    g.c[0][1] = -e[1][0];
+    g.c[1][0] = -e[0][1];
+    g.c[1][1] = e[0][0];
+    g.det = e[0][0] * e[1][1] - e[0][1] * e[1][0];
+  } else {
+    // c_1 = e2 x e3, c_2 = e3 x e1, c_3 = e1 x e2
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T* p = e[(a + 1) % 3];
+      const T* q = e[(a + 2) % 3];
+      g.c[a][0] = p[1] * q[2] - p[2] * q[1];
+      g.c[a][1] = p[2] * q[0] - p[0] * q[2];
+      g.c[a][2] = p[0] * q[1] - p[1] * q[0];
+    }
+    g.det = e[0][0] * g.c[0][0] + e[0][1] * g.c[0][1] + e[0][2] * g.c[0][2];
+  }
+}
+
+// Gradient-like tensor M_ij = sum_{a>=1} (v_a - v_0)_i c_a,j.
+template <int D, typename T>
+__device__ __forceinline__ void grad_tilde(const T (&v)[D + 1][D],
+                                           const Geo<D, T>& g, T (&M)[D][D]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) M[i][j] = T(0);
+#pragma unroll
+  for (int a = 1; a <= D; ++a) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const T dv = v[a][i] - v[0][i];
+#pragma unroll
+      for (int j = 0; j < D; ++j) M[i][j] += dv * g.c[a - 1][j];
+    }
+  }
+}
+
+// y_a = s * S c_a (a >= 1), y_0 = -sum_a y_a.
+template <int D, typename T>
+__device__ __forceinline__ void scatter_rows(const T (&S)[D][D], const Geo<D, T>& g,
+                                             T s, T (&y)[D + 1][D]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) y[0][i] = T(0);
+#pragma unroll
+  for (int a = 1; a <= D; ++a) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc += S[i][j] * g.c[a - 1][j];
+      y[a][i] = s * acc;
+      y[0][i] -= y[a][i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- linear
+// sigma = mu (M + M^T) + lambda tr(M) I applied to M = sum dv (x) c
+// (Sec. 'Linear elastic plate...': sigma = 2 mu eps + lambda tr eps I).
+template <int D, typename T>
+__device__ __forceinline__ void linear_stress_tilde(const T (&M)[D][D], T mu, T lam,
+                                                    T (&S)[D][D]) {
+  T tr = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) tr += M[i][i];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      S[i][j] = mu * (M[i][j] + M[j][i]) + (i == j ? lam * tr : T(0));
+}
+
+// ------------------------------------------------------------ Neo-Hookean
+// Kinematic state of one element: H = grad u, F^{-T}, ln J (float64).
+template <int D, typename T>
+struct NHState {
+  T H[D][D];
+  T FinvT[D][D];
+  double j;      // J - 1
+  double lnJ;
+  bool ok;       // J > 0
+};
+
+// J - 1 from the invariants of H (exact identities):
+//   2D: tr H + det H;  3D: tr H + ((tr H)^2 - tr H^2)/2 + det H.
+template <int D, typename T>
+__device__ __forceinline__ double jm1(const T (&H)[D][D]) {
+  if constexpr (D == 2) {
+    const double h00 = H[0][0], h01 = H[0][1], h10 = H[1][0], h11 = H[1][1];
+    return (h00 + h11) + (h00 * h11 - h01 * h10);
+  } else {
+    double h[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) h[i][k] = H[i][k];
+    const double tr = h[0][0] + h[1][1] + h[2][2];
+    double trH2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) trH2 += h[i][k] * h[k][i];
+    const double det = h[0][0] * (h[1][1] * h[2][2] - h[1][2] * h[2][1]) -
+                       h[0][1] * (h[1][0] * h[2][2] - h[1][2] * h[2][0]) +
+                       h[0][2] * (h[1][0] * h[2][1] - h[1][1] * h[2][0]);
+    return tr + 0.5 * (tr * tr - trH2) + det;
+  }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void nh_state(const T (&Ht)[D][D], T inv_det,
+                                         NHState<D, T>& st) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) st.H[i][k] = Ht[i][k] * inv_det;
+  st.j = jm1<D, T>(st.H);
+  st.ok = st.j > -1.0;
+  const double J = 1.0 + st.j;
+  st.lnJ = st.ok ? log1p(st.j) : 0.0;
+  const T invJ = (T)(st.ok ? 1.0 / J : 0.0);
+  T F[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) F[i][k] = st.H[i][k] + (i == k ? T(1) : T(0));
+  // F^{-T} = cof(F) / J
+  if constexpr (D == 2) {
+    st.FinvT[0][0] = F[1][1] * invJ;
+    st.FinvT[0][1] = -F[1][0] * invJ;
+    st.FinvT[1][0] = -F[0][1] * invJ;
+    st.FinvT[1][1] = F[0][0] * invJ;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const T* p = F[(r + 1) % 3];
+      const T* q = F[(r + 2) % 3];
+      st.FinvT[r][0] = (p[1] * q[2] - p[2] * q[1]) * invJ;
+      st.FinvT[r][1] = (p[2] * q[0] - p[0] * q[2]) * invJ;
+      st.FinvT[r][2] = (p[0] * q[1] - p[1] * q[0]) * invJ;
+    }
+  }
+}
+
+// First Piola stress P = mu (H + F^{-T} H^T) + lambda ln J F^{-T}
+// (= mu (F - F^{-T}) + lambda ln J F^{-T}; App. B internal force).
+template <int D, typename T>
+__device__ __forceinline__ void nh_piola(const NHState<D, T>& st, T mu, T lam,
+                                         T (&P)[D][D]) {
+  const T ll = (T)((double)lam * st.lnJ);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T a = T(0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) a += st.FinvT[i][l] * st.H[k][l];
+      P[i][k] = mu * (st.H[i][k] + a) + ll * st.FinvT[i][k];
+    }
+}
+
+// dP = mu dF + lambda (F^{-T}:dF) F^{-T} + (mu - lambda ln J) F^{-T} dF^T F^{-T}
+// (App. B tangent K_mat + K_geo in first-Piola form), dF given unnormalised.
+template <int D, typename T>
+__device__ __forceinline__ void nh_dpiola(const NHState<D, T>& st, T mu, T lam,
+                                          const T (&dF)[D][D], T (&dP)[D][D]) {
+  T tr = T(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) tr += st.FinvT[i][k] * dF[i][k];
+  const T c2 = (T)((double)mu - (double)lam * st.lnJ);
+  T A[D][D];  // A = dF^T F^{-T}
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T a = T(0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) a += dF[l][i] * st.FinvT[l][k];
+      A[i][k] = a;
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T b = T(0);
+#pragma unroll
+      for (int l = 0; l < D; ++l) b += st.FinvT[i][l] * A[l][k];
+      dP[i][k] = mu * dF[i][k] + lam * tr * st.FinvT[i][k] + c2 * b;
+    }
+}
+
+// Psi(H) in float64 from the kernel-type H:
+//   mu[(tr H - j) + |H|^2/2 + (j - log1p j)] + lambda (log1p j)^2 / 2
+// (Sec. 'Nonlinear hyperelasticity' density with I1 - D = 2 tr H + |H|^2,
+// ln J = log1p j; tr H - j = -det H in 2D, -(((tr H)^2 - tr H^2)/2 + det H)
+// in 3D).  Returns +inf when J <= 0.
+template <int D, typename T>
+__device__ __forceinline__ double nh_energy_density(const T (&Hk)[D][D], double mu,
+                                                    double lam) {
+  double H[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) H[i][k] = Hk[i][k];
+  double tr = 0.0, h2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) tr += H[i][i];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int k = 0; k < D; ++k) h2 += H[i][k] * H[i][k];
+  double second;  // j - tr H
+  if constexpr (D == 2) {
+    second = H[0][0] * H[1][1] - H[0][1] * H[1][0];
+  } else {
+    double trH2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) trH2 += H[i][k] * H[k][i];
+    const double det = H[0][0] * (H[1][1] * H[2][2] - H[1][2] * H[2][1]) -
+                       H[0][1] * (H[1][0] * H[2][2] - H[1][2] * H[2][0]) +
+                       H[0][2] * (H[1][0] * H[2][1] - H[1][1] * H[2][0]);
+    second = 0.5 * (tr * tr - trH2) + det;
+  }
+  const double j = tr + second;
+  if (!(j > -1.0)) return __builtin_inf();
+  const double l = log1p(j);
+  return mu * (-second + 0.5 * h2 + (j - l)) + 0.5 * lam * l * l;
+}
+
+}  // namespace pfem

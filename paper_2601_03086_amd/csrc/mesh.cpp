@@ -1,0 +1,491 @@
+// Mesh validation, bit-exact preprocessing and device upload.
+//
+// Preprocessing rules (the paper fixes no ordering; these tie-broken rules
+// make every result reproducible bit for bit):
+//  * reverse Cuthill-McKee on the node graph (nodes adjacent when they share
+//    an element): each connected component starts at the unvisited node of
+//    smallest degree (ties: smallest caller id); a dequeued node appends its
+//    unvisited neighbours ordered by (degree, caller id); the visiting order
+//    is reversed at the end;
+//  * elements sorted by the ascending tuple of their new node ids, ties by
+//    caller element index (so the smallest node id is non-decreasing);
+//  * colours by first fit in decreasing priority (fmix32(k ^ 0x9E3779B9), k)
+//    with k the sorted position and fmix32 the MurmurHash3 finaliser;
+//  * free DOFs ranked by increasing caller DOF index.
+#include "mesh.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace pfem {
+
+uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Lame parameters (Sec. 'Nonlinear hyperelasticity': lambda = nu E /
+// ((1+nu)(1-2nu)), mu = E / (2(1+nu))); plane stress uses the textbook
+// lambda* = E nu / (1 - nu^2) = 2 mu lambda / (lambda + 2 mu).
+void lame_from_params(int model, int param_kind, double p0, double p1, double* mu,
+                      double* lam) {
+  if (param_kind == PFEM_PARAM_E_NU) {
+    const double E = p0, nu = p1;
+    *mu = E / (2.0 * (1.0 + nu));
+    if (model == PFEM_LIN_PLANE_STRESS)
+      *lam = E * nu / (1.0 - nu * nu);
+    else
+      *lam = nu * E / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  } else {
+    *mu = p0;
+    *lam = p1;
+    if (model == PFEM_LIN_PLANE_STRESS) *lam = 2.0 * p0 * p1 / (p1 + 2.0 * p0);
+  }
+}
+
+static void validate(const pfem_mesh* m) {
+  const int D = m->dim;
+  const int nv = D + 1;
+  require(m->model >= 0, PFEM_E_STATE, "material not set");
+  std::vector<char> used(m->n_nodes, 0);
+  for (int64_t e = 0; e < m->n_elems; ++e) {
+    const int32_t* c = &m->conn[e * nv];
+    for (int a = 0; a < nv; ++a) {
+      require(c[a] >= 0 && c[a] < m->n_nodes, PFEM_E_INVALID_MESH,
+              "element " + std::to_string(e) + " references node out of range");
+      used[c[a]] = 1;
+      for (int b = 0; b < a; ++b)
+        require(c[a] != c[b], PFEM_E_INVALID_MESH,
+                "element " + std::to_string(e) + " repeats a node");
+    }
+    // degeneracy: |det J| against the longest edge^D
+    double ev[3][3] = {};
+    double lmax = 0.0;
+    for (int a = 0; a < D; ++a) {
+      double l2 = 0.0;
+      for (int i = 0; i < D; ++i) {
+        ev[a][i] = m->coords[(size_t)c[a + 1] * D + i] - m->coords[(size_t)c[0] * D + i];
+        l2 += ev[a][i] * ev[a][i];
+      }
+      lmax = std::max(lmax, std::sqrt(l2));
+    }
+    double det;
+    if (D == 2)
+      det = ev[0][0] * ev[1][1] - ev[0][1] * ev[1][0];
+    else
+      det = ev[0][0] * (ev[1][1] * ev[2][2] - ev[1][2] * ev[2][1]) -
+            ev[0][1] * (ev[1][0] * ev[2][2] - ev[1][2] * ev[2][0]) +
+            ev[0][2] * (ev[1][0] * ev[2][1] - ev[1][1] * ev[2][0]);
+    require(std::isfinite(det) && std::fabs(det) > 1e-12 * std::pow(lmax, D),
+            PFEM_E_INVALID_MESH, "element " + std::to_string(e) + " is degenerate");
+  }
+  for (int64_t n = 0; n < m->n_nodes; ++n)
+    require(used[n], PFEM_E_INVALID_MESH,
+            "node " + std::to_string(n) + " belongs to no element");
+  for (double v : m->coords)
+    require(std::isfinite(v), PFEM_E_INVALID_MESH, "non-finite coordinate");
+  for (size_t i = 0; i < m->mu.size(); ++i)
+    require(std::isfinite(m->mu[i]) && std::isfinite(m->lam[i]), PFEM_E_INVALID_ARG,
+            "non-finite material parameter");
+}
+
+// ----------------------------------------------------------------- RCM
+static void node_graph(const pfem_mesh* m, std::vector<int64_t>& ptr,
+                       std::vector<int32_t>& nbr) {
+  const int nv = m->dim + 1;
+  const int64_t N = m->n_nodes;
+  std::vector<int64_t> cnt(N + 1, 0);
+  for (int64_t e = 0; e < m->n_elems; ++e)
+    for (int a = 0; a < nv; ++a) cnt[m->conn[e * nv + a] + 1] += nv - 1;
+  for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int32_t> raw(cnt[N]);
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t e = 0; e < m->n_elems; ++e)
+    for (int a = 0; a < nv; ++a)
+      for (int b = 0; b < nv; ++b)
+        if (a != b) raw[fill[m->conn[e * nv + a]]++] = m->conn[e * nv + b];
+  ptr.assign(N + 1, 0);
+  nbr.clear();
+  nbr.reserve(raw.size() / 2);
+  for (int64_t i = 0; i < N; ++i) {
+    auto b = raw.begin() + cnt[i], en = raw.begin() + cnt[i + 1];
+    std::sort(b, en);
+    auto last = std::unique(b, en);
+    nbr.insert(nbr.end(), b, last);
+    ptr[i + 1] = (int64_t)nbr.size();
+  }
+}
+
+static void rcm(const pfem_mesh* m, std::vector<int32_t>& new_id) {
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> nbr;
+  node_graph(m, ptr, nbr);
+  const int64_t N = m->n_nodes;
+  std::vector<int32_t> deg(N);
+  for (int64_t i = 0; i < N; ++i) deg[i] = (int32_t)(ptr[i + 1] - ptr[i]);
+  std::vector<int32_t> starts(N);
+  std::iota(starts.begin(), starts.end(), 0);
+  std::stable_sort(starts.begin(), starts.end(),
+                   [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+  std::vector<char> vis(N, 0);
+  std::vector<int32_t> q;
+  q.reserve(N);
+  std::vector<int32_t> tmp;
+  int64_t si = 0;
+  size_t head = 0;
+  while ((int64_t)q.size() < N) {
+    while (vis[starts[si]]) ++si;
+    const int32_t s = starts[si];
+    vis[s] = 1;
+    q.push_back(s);
+    while (head < q.size()) {
+      const int32_t v = q[head++];
+      tmp.clear();
+      for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k)
+        if (!vis[nbr[k]]) tmp.push_back(nbr[k]);
+      std::sort(tmp.begin(), tmp.end(), [&](int32_t a, int32_t b) {
+        return deg[a] != deg[b] ? deg[a] < deg[b] : a < b;
+      });
+      for (int32_t w : tmp) {
+        vis[w] = 1;
+        q.push_back(w);
+      }
+    }
+  }
+  new_id.assign(N, 0);
+  for (int64_t i = 0; i < N; ++i) new_id[q[N - 1 - i]] = (int32_t)i;
+}
+
+static int64_t bandwidth(const pfem_mesh* m, const int32_t* numbering) {
+  const int nv = m->dim + 1;
+  int64_t bw = 0;
+  for (int64_t e = 0; e < m->n_elems; ++e) {
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
+    for (int a = 0; a < nv; ++a) {
+      const int32_t v = numbering ? numbering[m->conn[e * nv + a]] : m->conn[e * nv + a];
+      lo = std::min(lo, v);
+      hi = std::max(hi, v);
+    }
+    bw = std::max<int64_t>(bw, hi - lo);
+  }
+  return bw;
+}
+
+void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
+  validate(m);
+  const int D = m->dim;
+  const int nv = D + 1;
+  const int64_t N = m->n_nodes, NE = m->n_elems;
+  // 1. RCM
+  rcm(m, m->perm);
+  m->bw_in = bandwidth(m, nullptr);
+  m->bw_rcm = bandwidth(m, m->perm.data());
+  // 2. element order
+  std::vector<int32_t> keys((size_t)NE * nv);
+  for (int64_t e = 0; e < NE; ++e) {
+    int32_t* k = &keys[e * nv];
+    for (int a = 0; a < nv; ++a) k[a] = m->perm[m->conn[e * nv + a]];
+    std::sort(k, k + nv);
+  }
+  m->elem_order.resize(NE);
+  std::iota(m->elem_order.begin(), m->elem_order.end(), 0);
+  std::sort(m->elem_order.begin(), m->elem_order.end(), [&](int32_t a, int32_t b) {
+    const int32_t* ka = &keys[(size_t)a * nv];
+    const int32_t* kb = &keys[(size_t)b * nv];
+    for (int i = 0; i < nv; ++i)
+      if (ka[i] != kb[i]) return ka[i] < kb[i];
+    return a < b;
+  });
+  // internal connectivity (node order inside the element kept)
+  m->conn_int.resize((size_t)NE * nv);
+  for (int64_t s = 0; s < NE; ++s)
+    for (int a = 0; a < nv; ++a)
+      m->conn_int[s * nv + a] = m->perm[m->conn[(size_t)m->elem_order[s] * nv + a]];
+  // 3. colouring
+  std::vector<int64_t> n2e_ptr(N + 1, 0);
+  for (int64_t s = 0; s < NE; ++s)
+    for (int a = 0; a < nv; ++a) n2e_ptr[m->conn_int[s * nv + a] + 1]++;
+  for (int64_t i = 0; i < N; ++i) n2e_ptr[i + 1] += n2e_ptr[i];
+  std::vector<int32_t> n2e(n2e_ptr[N]);
+  {
+    std::vector<int64_t> fill(n2e_ptr.begin(), n2e_ptr.end() - 1);
+    for (int64_t s = 0; s < NE; ++s)
+      for (int a = 0; a < nv; ++a) n2e[fill[m->conn_int[s * nv + a]]++] = (int32_t)s;
+  }
+  std::vector<uint32_t> h(NE);
+  for (int64_t k = 0; k < NE; ++k) h[k] = fmix32((uint32_t)k ^ 0x9E3779B9u);
+  std::vector<int32_t> order(NE);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return h[a] != h[b] ? h[a] > h[b] : a > b;
+  });
+  m->color.assign(NE, -1);
+  std::vector<int64_t> stamp(64, -1);
+  int ncol = 0;
+  for (int32_t e : order) {
+    for (int a = 0; a < nv; ++a) {
+      const int32_t n = m->conn_int[(size_t)e * nv + a];
+      for (int64_t k = n2e_ptr[n]; k < n2e_ptr[n + 1]; ++k) {
+        const int32_t c = m->color[n2e[k]];
+        if (c >= 0) {
+          if ((size_t)c >= stamp.size()) stamp.resize(2 * c + 2, -1);
+          stamp[c] = e;
+        }
+      }
+    }
+    int c = 0;
+    while ((size_t)c < stamp.size() && stamp[c] == e) ++c;
+    m->color[e] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  m->n_colors = ncol;
+  m->color_ptr.assign(ncol + 1, 0);
+  for (int64_t s = 0; s < NE; ++s) m->color_ptr[m->color[s] + 1]++;
+  for (int c = 0; c < ncol; ++c) m->color_ptr[c + 1] += m->color_ptr[c];
+  m->colored.resize(NE);
+  {
+    std::vector<int> fill(m->color_ptr.begin(), m->color_ptr.end() - 1);
+    for (int64_t s = 0; s < NE; ++s) m->colored[fill[m->color[s]]++] = (int32_t)s;
+  }
+  // 4. free-DOF map and Dirichlet data
+  const int64_t ndof = N * D;
+  std::vector<char> con(ndof, 0);
+  std::vector<double> dv(ndof, 0.0);
+  for (size_t i = 0; i < m->dnode.size(); ++i) {
+    const int64_t g = (int64_t)m->dnode[i] * D + m->dcomp[i];
+    con[g] = 1;
+    dv[g] = m->dval[i];
+  }
+  m->free_index.assign(ndof, -1);
+  int64_t rank = 0;
+  for (int64_t g = 0; g < ndof; ++g)
+    if (!con[g]) m->free_index[g] = (int32_t)rank++;
+  m->n_free = rank;
+  m->dmask.assign(N, 0);
+  m->ubar_int.assign(ndof, 0.0);
+  for (int64_t n = 0; n < N; ++n)
+    for (int c = 0; c < D; ++c)
+      if (con[n * D + c]) {
+        m->dmask[m->perm[n]] |= (uint8_t)(1u << c);
+        m->ubar_int[(int64_t)m->perm[n] * D + c] = dv[n * D + c];
+      }
+  // 5. external force (App. B: t |facet| / n_f on each facet node)
+  std::vector<double> fext(ndof, 0.0);
+  for (int64_t f = 0; f < m->n_facets; ++f) {
+    const int32_t* fn = &m->facets[f * D];
+    const double* t = &m->traction[f * D];
+    double meas;
+    if (D == 2) {
+      const double dx = m->coords[fn[1] * 2] - m->coords[fn[0] * 2];
+      const double dy = m->coords[fn[1] * 2 + 1] - m->coords[fn[0] * 2 + 1];
+      meas = std::sqrt(dx * dx + dy * dy);
+    } else {
+      double a[3], b[3];
+      for (int i = 0; i < 3; ++i) {
+        a[i] = m->coords[fn[1] * 3 + i] - m->coords[fn[0] * 3 + i];
+        b[i] = m->coords[fn[2] * 3 + i] - m->coords[fn[0] * 3 + i];
+      }
+      const double cx = a[1] * b[2] - a[2] * b[1];
+      const double cy = a[2] * b[0] - a[0] * b[2];
+      const double cz = a[0] * b[1] - a[1] * b[0];
+      meas = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+    }
+    for (int a = 0; a < D; ++a)
+      for (int i = 0; i < D; ++i) fext[(int64_t)fn[a] * D + i] += t[i] * meas / D;
+  }
+  m->fext_int.assign(ndof, 0.0);
+  double fn2 = 0.0;
+  for (int64_t n = 0; n < N; ++n)
+    for (int c = 0; c < D; ++c) {
+      m->fext_int[(int64_t)m->perm[n] * D + c] = fext[n * D + c];
+      fn2 += fext[n * D + c] * fext[n * D + c];
+    }
+  m->fext_norm = std::sqrt(fn2);
+  // 6. internal coordinates and materials
+  m->X_int.resize(ndof);
+  for (int64_t n = 0; n < N; ++n)
+    for (int c = 0; c < D; ++c) m->X_int[(int64_t)m->perm[n] * D + c] = m->coords[n * D + c];
+  m->mu_int.resize(NE);
+  m->lam_int.resize(NE);
+  for (int64_t s = 0; s < NE; ++s) {
+    m->mu_int[s] = m->mu[m->elem_order[s]];
+    m->lam_int[s] = m->lam[m->elem_order[s]];
+  }
+  // 7. owner node blocks
+  int bn = block_nodes;
+  if (bn <= 0) {
+    const int64_t target = 1200;
+    bn = (int)std::min<int64_t>(2048, std::max<int64_t>(64, ((N / target) + 31) / 32 * 32));
+  }
+  require(bn <= block_nodes_max(), PFEM_E_INVALID_ARG, "block_nodes too large");
+  m->bn = bn;
+  m->n_blocks = (int)((N + bn - 1) / bn);
+  m->blocks.assign(m->n_blocks, make_int4(-1, 0, 0, 0));
+  for (int64_t s = 0; s < NE; ++s)
+    for (int a = 0; a < nv; ++a) {
+      const int b = m->conn_int[s * nv + a] / bn;
+      if (m->blocks[b].x < 0) m->blocks[b].x = (int)s;
+    }
+  {
+    int64_t s = 0;
+    for (int b = 0; b < m->n_blocks; ++b) {
+      const int32_t n0 = b * bn;
+      // elements are sorted by their smallest node id
+      while (s < NE && m->conn_int[s * nv] >= 0) {
+        int32_t mn = m->conn_int[s * nv];
+        for (int a = 1; a < nv; ++a) mn = std::min(mn, m->conn_int[s * nv + a]);
+        if (mn >= n0) break;
+        ++s;
+      }
+      m->blocks[b].y = (int)s;
+    }
+    for (int b = 0; b < m->n_blocks; ++b)
+      m->blocks[b].z = (b + 1 < m->n_blocks) ? m->blocks[b + 1].y : (int)NE;
+    m->owner_visits = 0;
+    for (int b = 0; b < m->n_blocks; ++b) {
+      require(m->blocks[b].x >= 0 && m->blocks[b].x <= m->blocks[b].y, PFEM_E_INVALID_MESH,
+              "internal: block without elements");
+      m->owner_visits += m->blocks[b].z - m->blocks[b].x;
+    }
+  }
+  // work table: consecutive blocks on the same XCD (workgroup i runs on
+  // XCD i % 8 when dispatched round-robin)
+  const int nb = m->n_blocks;
+  m->work.resize(nb);
+  {
+    int cnt[8], pre[8];
+    for (int k = 0; k < 8; ++k) cnt[k] = (nb - k + 7) / 8;
+    pre[0] = 0;
+    for (int k = 1; k < 8; ++k) pre[k] = pre[k - 1] + std::max(cnt[k - 1], 0);
+    for (int i = 0; i < nb; ++i) m->work[i] = make_int2(0, pre[i % 8] + i / 8);
+  }
+  m->finalized = true;
+}
+
+// --------------------------------------------------------------- device
+template <typename T>
+static T* upload(const std::vector<T>& v, int64_t& bytes) {
+  T* p = nullptr;
+  const size_t n = std::max<size_t>(v.size(), 1) * sizeof(T);
+  PFEM_HIP(hipMalloc((void**)&p, n));
+  if (!v.empty()) PFEM_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  bytes += (int64_t)n;
+  return p;
+}
+
+void mesh_upload(pfem_mesh* m, Ctx* ctx) {
+  require(m->finalized, PFEM_E_STATE, "mesh not finalized");
+  if (m->uploaded) return;
+  PFEM_HIP(hipSetDevice(ctx->device));
+  MeshDevBuffers& d = m->dev;
+  d.bytes = 0;
+  std::vector<float> mu32(m->mu_int.begin(), m->mu_int.end());
+  std::vector<float> lam32(m->lam_int.begin(), m->lam_int.end());
+  try {
+    d.X = upload(m->X_int, d.bytes);
+    d.conn = upload(m->conn_int, d.bytes);
+    d.mu32 = upload(mu32, d.bytes);
+    d.lam32 = upload(lam32, d.bytes);
+    d.mu64 = upload(m->mu_int, d.bytes);
+    d.lam64 = upload(m->lam_int, d.bytes);
+    d.dmask = upload(m->dmask, d.bytes);
+    d.blocks = upload(m->blocks, d.bytes);
+    d.fext = upload(m->fext_int, d.bytes);
+    d.ubar = upload(m->ubar_int, d.bytes);
+    d.colored = upload(m->colored, d.bytes);
+    d.perm = upload(m->perm, d.bytes);
+    d.work = upload(m->work, d.bytes);
+  } catch (...) {
+    mesh_release_device(m);
+    throw;
+  }
+  MeshDev& md = m->md;
+  md.X = d.X;
+  md.conn = d.conn;
+  md.mu32 = d.mu32;
+  md.lam32 = d.lam32;
+  md.mu64 = d.mu64;
+  md.lam64 = d.lam64;
+  md.dmask = d.dmask;
+  md.blocks = d.blocks;
+  md.fext = d.fext;
+  md.ubar = d.ubar;
+  md.colored = d.colored;
+  md.n_nodes = (int32_t)m->n_nodes;
+  md.n_elems = (int32_t)m->n_elems;
+  md.n_blocks = m->n_blocks;
+  md.bn = m->bn;
+  md.dim = m->dim;
+  md.model = m->model;
+  md.nonlinear = m->nonlinear ? 1 : 0;
+  m->ctx = ctx;
+  m->uploaded = true;
+}
+
+void CallScratch::ensure(int64_t nd, int nb) {
+  if (nd <= n_dof && nb <= n_blocks && in64 != nullptr) return;
+  release();
+  PFEM_HIP(hipMalloc(&in64, nd * 8));
+  PFEM_HIP(hipMalloc(&v64, nd * 8));
+  PFEM_HIP(hipMalloc(&out64, nd * 8));
+  PFEM_HIP(hipMalloc(&zero64, nd * 8));
+  PFEM_HIP(hipMemset(zero64, 0, nd * 8));
+  PFEM_HIP(hipMalloc((void**)&part, (size_t)std::max(nb, 1) * kRedSlots * 8));
+  PFEM_HIP(hipMalloc((void**)&counter, 64));
+  PFEM_HIP(hipMemset(counter, 0, 64));
+  PFEM_HIP(hipMalloc((void**)&out, kRedSlots * 8));
+  n_dof = nd;
+  n_blocks = nb;
+}
+
+void CallScratch::release() {
+  if (in64) (void)hipFree(in64);
+  if (v64) (void)hipFree(v64);
+  if (out64) (void)hipFree(out64);
+  if (zero64) (void)hipFree(zero64);
+  if (part) (void)hipFree(part);
+  if (counter) (void)hipFree(counter);
+  if (out) (void)hipFree(out);
+  in64 = v64 = out64 = zero64 = nullptr;
+  part = nullptr;
+  counter = nullptr;
+  out = nullptr;
+  n_dof = 0;
+  n_blocks = 0;
+}
+
+void mesh_release_device(pfem_mesh* m) {
+  if (m->ctx != nullptr && m->ctx->stream != nullptr) (void)hipStreamSynchronize(m->ctx->stream);
+  m->solve_state.reset();
+  m->scratch.release();
+  MeshDevBuffers& d = m->dev;
+  void* ptrs[] = {d.X, d.conn, d.mu32, d.lam32, d.mu64, d.lam64, d.dmask, d.blocks,
+                  d.fext, d.ubar, d.colored, d.perm, d.work};
+  for (void* p : ptrs)
+    if (p != nullptr) (void)hipFree(p);
+  d = MeshDevBuffers{};
+  m->md = MeshDev{};
+  m->uploaded = false;
+}
+
+int64_t mesh_device_bytes(const pfem_mesh* m) {
+  const int64_t N = m->n_nodes, NE = m->n_elems, D = m->dim;
+  auto r = [](int64_t b) { return std::max<int64_t>(b, 1); };
+  return r(N * D * 8) + r(NE * (D + 1) * 4) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
+         r((int64_t)m->n_blocks * 16) + 2 * r(N * D * 8) + r(NE * 4) + r(N * 4) +
+         r((int64_t)m->n_blocks * 8);
+}
+
+int64_t solve_bytes(const pfem_mesh* m, int prec) {
+  const int64_t nd = m->n_dof();
+  const int64_t s = prec == PFEM_FP64 ? 8 : 4;
+  return 3 * nd * 8 + 6 * nd * s + (int64_t)m->n_blocks * kRedSlots * 8 + 4096 +
+         (int64_t)8 * 65536;
+}
+
+}  // namespace pfem

@@ -1,0 +1,185 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pfem.h"
+
+namespace pfem {
+
+constexpr int kThreads = 256;       // threads per workgroup (4 wave64s)
+constexpr int kRedSlots = 4;        // partial sums per block per reduction
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  pfem_status code;
+  std::string msg;
+};
+void set_error(const std::string& msg);
+const char* last_error_cstr();
+
+#define PFEM_HIP(call)                                                       \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      throw ::pfem::Error{PFEM_E_DEVICE,                                     \
+                          std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+inline void require(bool ok, pfem_status code, const std::string& msg) {
+  if (!ok) throw Error{code, msg};
+}
+
+// ------------------------------------------------------- device descriptors
+// Everything a kernel needs to know about one finalized mesh (POD).
+struct MeshDev {
+  const double* X;        // n_nodes * dim, internal node order
+  const int32_t* conn;    // n_elems * (dim+1), sorted element order, internal ids
+  const float* mu32;      // n_elems
+  const float* lam32;     // n_elems
+  const double* mu64;     // n_elems
+  const double* lam64;    // n_elems
+  const uint8_t* dmask;   // n_nodes, bit c set when component c is Dirichlet
+  const int4* blocks;     // n_blocks: (first touching elem, first owned elem, end, 0)
+  const double* fext;     // n_dof, internal order
+  const double* ubar;     // n_dof, final Dirichlet values, 0 on free DOFs
+  const int32_t* colored; // n_elems: sorted element ids grouped by colour
+  int32_t n_nodes, n_elems, n_blocks, bn;
+  int32_t dim, model, nonlinear, pad;
+};
+
+// Reduction bookkeeping of one task in one launch.
+struct RedDev {
+  double* part;           // n_blocks * kRedSlots partial sums
+  unsigned* counter;      // finished-block counter (reset by the last block)
+  double* out;            // reduced sums land here (kRedSlots doubles)
+};
+
+// Per-slot scalars of the Krylov state machine (device-resident).
+struct Scalars {
+  double rz, pq, rr, alpha, beta;
+  double rho;             // latest |r| / den
+  double den;             // |r_f(lifted)| (denominator of the relative residual)
+  double target2;         // stop when |r|^2 <= target2
+  double bnorm;           // |r| at inner start
+  double red[kRedSlots];  // last reduction outputs
+  int32_t k;              // Krylov iterations done in the current inner solve
+  int32_t kmax;           // cap for the current inner solve
+  int32_t state;          // 0 running, 1 converged, 2 max-iter, 3 breakdown, 4 negative curvature
+  int32_t hist_len, hist_cap, total_k, pad0, pad1;
+};
+
+// One unit of work for a launch: a mesh plus operand pointers.
+struct Task {
+  MeshDev m;
+  const void* u;          // state (Neo-Hookean) / input of force, energy, diag
+  const void* v;          // direction (HVP), increment (line search)
+  void* y;                // output vector (owned nodes written)
+  const void* w;          // dot partner of y (or nullptr)
+  RedDev red;
+  Scalars* sc;            // Krylov scalars (PCG launches)
+  double* hist;           // residual history (PCG launches)
+  const void* minv;       // inverse Jacobi diagonal (PCG launches)
+  void* r;                // Krylov residual (PCG launches)
+  void* p;                // search direction (PCG launches)
+  void* d;                // correction accumulated by PCG (PCG launches)
+  double s;               // step length (line search); inverse flag (diagonal)
+  double fscale;          // load factor applied to f_ext (load steps)
+  int32_t mask;           // PFEM_MASK_* bits
+  int32_t active;         // 0: every workgroup of this task returns at once
+  int32_t finisher;       // what the last block does with the reduction
+  int32_t pad;
+};
+
+enum Finisher {
+  FIN_STORE = 0,          // copy sums[0..1] to red.out[0..1]
+  FIN_PQ = 1,             // sums[0] = p.q -> alpha (PCG)
+  FIN_RZ = 2,             // sums = (r.z, r.r) -> beta, rho, state (PCG)
+  FIN_INIT = 3            // sums = (r.z, r.r) at inner start -> rz, bnorm (PCG)
+};
+
+// Element-kernel operations.
+enum ElemOp { OP_APPLY = 0, OP_FORCE = 1, OP_DIAG = 2 };
+
+// Kernel timing families (pfem_ctx_kernel_time).
+enum Family { FAM_APPLY = 0, FAM_FORCE = 1, FAM_ENERGY = 2, FAM_DIAG = 3,
+              FAM_UPDATE = 4, FAM_DIRECTION = 5, FAM_COUNT = 6 };
+
+// ----------------------------------------------------- launch descriptors
+struct Ctx;
+// Staging ring: small launch descriptors go host(pinned) -> device here.
+class ArgRing {
+ public:
+  void init(size_t bytes, hipStream_t s);
+  void release();
+  // Copies `n` bytes to device memory valid for launches enqueued next.
+  void* put(const void* src, size_t n);
+ private:
+  static constexpr int kSeg = 8;
+  char* host_ = nullptr;
+  char* dev_ = nullptr;
+  size_t cap_ = 0, off_ = 0;
+  int seg_ = 0;
+  hipEvent_t ev_[kSeg] = {};
+  bool used_[kSeg] = {};
+  hipStream_t stream_ = nullptr;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  ArgRing ring;
+  bool timing = false;
+  int64_t fam_launches[FAM_COUNT] = {};
+  double fam_ms[FAM_COUNT] = {};
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> event_pool;
+  void timing_begin(int fam, hipEvent_t* a);
+  void timing_end(int fam, hipEvent_t a);
+  void drain_timing();
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on ctx->stream.  `tasks_dev` points to n_tasks Task
+// structs in device memory; `work_dev` to n_work (task, block) pairs.
+void launch_elem(Ctx* ctx, int dim, int prec, int op, int scatter_mode,
+                 const Task* tasks_dev, const int2* work_dev, int n_work,
+                 int bn_max, const Task* host_task_for_alt,
+                 const std::vector<int>* color_ptr);
+void launch_energy(Ctx* ctx, int dim, int prec, bool diff,
+                   const Task* tasks_dev, const int2* work_dev, int n_work);
+// PCG vector passes over owned node blocks.
+void launch_pcg_init(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
+                     const int2* work_dev, int n_work);
+void launch_pcg_update(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
+                       const int2* work_dev, int n_work);
+void launch_pcg_direction(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
+                          const int2* work_dev, int n_work);
+void launch_dot(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
+                const int2* work_dev, int n_work);
+void launch_set_scalars(Ctx* ctx, Scalars* sc, double den, double target2, int kmax,
+                        bool reset_hist, bool reset_total);
+// Misc vector kernels (grid-stride, single vector).
+void launch_permute(Ctx* ctx, int prec, int dim, const int32_t* perm,
+                    int64_t n_nodes, bool to_internal, const void* in, void* out);
+void launch_fill(Ctx* ctx, int prec, void* p, int64_t n, double value);
+void launch_cast(Ctx* ctx, bool to32, const void* in, void* out, int64_t n);
+// x64 = base64 + s * inc (inc precision `prec`), then Dirichlet DOFs of the
+// result set to scale * ubar (when set_dirichlet).
+void launch_axpy_state(Ctx* ctx, int prec, const MeshDev& m, double* out,
+                       const double* base, const void* inc, double s,
+                       bool set_dirichlet, double scale);
+// out = scale * ubar on Dirichlet DOFs, keep others of `base` (or 0 if base null)
+void launch_lift(Ctx* ctx, const MeshDev& m, double* out, const double* base,
+                 double scale);
+
+// Host-side helpers.
+int block_nodes_max();  // largest block size the kernels accept
+
+}  // namespace pfem

@@ -1,0 +1,102 @@
+// Host runtime pieces: error reporting, launch-descriptor ring, kernel timing.
+#include <algorithm>
+
+#include "pfem_internal.h"
+
+namespace pfem {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------ ArgRing
+void ArgRing::init(size_t bytes, hipStream_t s) {
+  stream_ = s;
+  cap_ = bytes;
+  PFEM_HIP(hipHostMalloc((void**)&host_, cap_, hipHostMallocDefault));
+  PFEM_HIP(hipMalloc((void**)&dev_, cap_));
+  for (int i = 0; i < kSeg; ++i) {
+    PFEM_HIP(hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming));
+    used_[i] = false;
+  }
+  off_ = 0;
+  seg_ = 0;
+}
+
+void ArgRing::release() {
+  if (stream_ != nullptr) (void)hipStreamSynchronize(stream_);
+  for (int i = 0; i < kSeg; ++i)
+    if (ev_[i] != nullptr) (void)hipEventDestroy(ev_[i]);
+  if (host_ != nullptr) (void)hipHostFree(host_);
+  if (dev_ != nullptr) (void)hipFree(dev_);
+  host_ = dev_ = nullptr;
+}
+
+void* ArgRing::put(const void* src, size_t n) {
+  const size_t seg_bytes = cap_ / kSeg;
+  const size_t need = (n + 255) & ~size_t(255);
+  require(need <= seg_bytes, PFEM_E_INVALID_ARG,
+          "launch descriptor larger than the staging segment");
+  size_t off = off_;
+  int seg = (int)(off / seg_bytes);
+  if ((off % seg_bytes) + need > seg_bytes) {   // does not fit: next segment
+    seg = (seg + 1) % kSeg;
+    off = (size_t)seg * seg_bytes;
+  }
+  if (seg != seg_) {
+    // leaving seg_: everything that used it has been enqueued
+    PFEM_HIP(hipEventRecord(ev_[seg_], stream_));
+    used_[seg_] = true;
+    if (used_[seg]) PFEM_HIP(hipEventSynchronize(ev_[seg]));
+    seg_ = seg;
+  }
+  std::memcpy(host_ + off, src, n);
+  PFEM_HIP(hipMemcpyAsync(dev_ + off, host_ + off, n, hipMemcpyHostToDevice, stream_));
+  off_ = off + need;
+  return dev_ + off;
+}
+
+// ---------------------------------------------------------------- timing
+void Ctx::timing_begin(int fam, hipEvent_t* a) {
+  (void)fam;
+  *a = nullptr;
+  if (!timing) return;
+  if (event_pool.empty()) {
+    hipEvent_t e;
+    PFEM_HIP(hipEventCreate(&e));
+    event_pool.push_back(e);
+  }
+  *a = event_pool.back();
+  event_pool.pop_back();
+  PFEM_HIP(hipEventRecord(*a, stream));
+}
+
+void Ctx::timing_end(int fam, hipEvent_t a) {
+  if (!timing || a == nullptr) return;
+  if (event_pool.empty()) {
+    hipEvent_t e;
+    PFEM_HIP(hipEventCreate(&e));
+    event_pool.push_back(e);
+  }
+  hipEvent_t b = event_pool.back();
+  event_pool.pop_back();
+  PFEM_HIP(hipEventRecord(b, stream));
+  pending.push_back({fam, {a, b}});
+  if (pending.size() > 4096) drain_timing();
+}
+
+void Ctx::drain_timing() {
+  for (auto& p : pending) {
+    PFEM_HIP(hipEventSynchronize(p.second.second));
+    float ms = 0.f;
+    PFEM_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+    fam_ms[p.first] += ms;
+    fam_launches[p.first] += 1;
+    event_pool.push_back(p.second.first);
+    event_pool.push_back(p.second.second);
+  }
+  pending.clear();
+}
+
+}  // namespace pfem

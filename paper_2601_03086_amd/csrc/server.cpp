@@ -1,0 +1,414 @@
+// Solve server with continuous batching.
+//
+// Requests are queued in arrival order.  A worker thread admits the head of
+// the queue whenever a slot is free and its device footprint (mesh arrays +
+// solver state) fits the memory budget, uploads it, and from then on every
+// tick advances all live requests together: one launch per kernel family
+// and (dimension, precision) group covers every request that needs that
+// step, so requests that arrive while others are on the device overlap with
+// them.  A finished request leaves at the end of its tick and its memory is
+// returned before the next admission check.
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+#include "mesh.h"
+#include "solver.h"
+
+using namespace pfem;
+
+namespace {
+struct Req {
+  int64_t id = -1;
+  pfem_mesh* m = nullptr;
+  std::vector<double> u0;
+  bool has_u0 = false;
+  pfem_solve_opts o{};
+  double t_submit = 0, t_admit = -1, t_done = -1;
+  int64_t bytes = 0;
+  SlotRun slot;
+  bool admitted = false, done = false, cancel = false, server_uploaded = false;
+  std::vector<double> u_out;
+  pfem_solve_report rep{};
+};
+}  // namespace
+
+struct pfem_server {
+  Ctx c;
+  int64_t budget = 0;
+  int max_slots = 0;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool stop = false;
+  std::deque<Req*> queue;
+  std::vector<Req*> live;
+  std::map<int64_t, Req*> all;
+  std::deque<int64_t> done_ids;
+  std::chrono::steady_clock::time_point t0;
+  int64_t bytes_in_use = 0, peak_bytes = 0, peak_live = 0;
+  int64_t submitted = 0, completed = 0, steps = 0, launches = 0;
+  std::string worker_error;
+  std::map<pfem_mesh*, int> mesh_refs;   // meshes this server uploaded
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  void run();
+  void admit(Req* r);
+  void complete(Req* r);
+};
+
+static int64_t req_bytes(const pfem_mesh* m, int prec) {
+  return (m->uploaded ? 0 : mesh_device_bytes(m)) + solve_bytes(m, prec);
+}
+
+void pfem_server::admit(Req* r) {
+  pfem_mesh* m = r->m;
+  auto it = mesh_refs.find(m);
+  if (it != mesh_refs.end()) {
+    ++it->second;
+    r->server_uploaded = true;
+  } else if (!m->uploaded) {
+    mesh_upload(m, &c);
+    mesh_refs[m] = 1;
+    r->server_uploaded = true;
+  }
+  slot_alloc(&r->slot, m, r->o, 65536);
+  r->slot.id = r->id;
+  const double* u0_int = nullptr;
+  if (r->has_u0) {
+    PFEM_HIP(hipMemcpyAsync(r->slot.st->g64, r->u0.data(), m->n_dof() * 8,
+                            hipMemcpyHostToDevice, c.stream));
+    launch_permute(&c, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, true, r->slot.st->g64,
+                   r->slot.st->aux64);
+    PFEM_HIP(hipStreamSynchronize(c.stream));   // u0 host buffer may be released below
+    u0_int = r->slot.st->aux64;
+  }
+  slot_begin(&c, &r->slot, u0_int);
+  r->admitted = true;
+  r->t_admit = now();
+}
+
+void pfem_server::complete(Req* r) {
+  pfem_mesh* m = r->m;
+  if (r->slot.st != nullptr) {
+    r->u_out.resize(m->n_dof());
+    launch_permute(&c, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, false, r->slot.st->x64,
+                   r->slot.st->g64);
+    PFEM_HIP(hipMemcpyAsync(r->u_out.data(), r->slot.st->g64, m->n_dof() * 8,
+                            hipMemcpyDeviceToHost, c.stream));
+    PFEM_HIP(hipStreamSynchronize(c.stream));
+  }
+  r->rep = r->slot.rep;
+  r->rep.status = r->cancel ? PFEM_E_CANCELLED : r->slot.status;
+  slot_free(&r->slot);
+  if (r->server_uploaded && --mesh_refs[r->m] == 0) {
+    mesh_refs.erase(r->m);
+    mesh_release_device(r->m);
+  }
+  r->u0.clear();
+  r->u0.shrink_to_fit();
+  r->t_done = now();
+  r->done = true;
+}
+
+void pfem_server::run() {
+  (void)hipSetDevice(c.device);
+  for (;;) {
+    std::vector<Req*> to_admit;
+    std::vector<Req*> cancelled_live;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return stop || !queue.empty() || !live.empty(); });
+      if (stop) break;
+      // cancellations in the queue finish at once
+      for (auto it = queue.begin(); it != queue.end();) {
+        Req* r = *it;
+        if (r->cancel) {
+          r->rep = pfem_solve_report{};
+          r->rep.status = PFEM_E_CANCELLED;
+          r->t_done = now();
+          r->done = true;
+          done_ids.push_back(r->id);
+          ++completed;
+          it = queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      for (Req* r : live)
+        if (r->cancel) cancelled_live.push_back(r);
+      // admission in arrival order: head of line waits for memory
+      int64_t in_use = bytes_in_use;
+      int64_t n_live = (int64_t)live.size() - (int64_t)cancelled_live.size();
+      for (Req* r : cancelled_live) in_use -= r->bytes;
+      while (!queue.empty() && n_live < max_slots) {
+        Req* r = queue.front();
+        if (in_use + r->bytes > budget) break;
+        queue.pop_front();
+        in_use += r->bytes;
+        ++n_live;
+        to_admit.push_back(r);
+      }
+    }
+    try {
+      for (Req* r : cancelled_live) {
+        complete(r);
+        std::lock_guard<std::mutex> lk(mu);
+        live.erase(std::find(live.begin(), live.end(), r));
+        bytes_in_use -= r->bytes;
+        done_ids.push_back(r->id);
+        ++completed;
+      }
+      for (Req* r : to_admit) {
+        admit(r);
+        std::lock_guard<std::mutex> lk(mu);
+        live.push_back(r);
+        bytes_in_use += r->bytes;
+        peak_bytes = std::max(peak_bytes, bytes_in_use);
+        peak_live = std::max<int64_t>(peak_live, (int64_t)live.size());
+      }
+      std::vector<SlotRun*> slots;
+      std::vector<Req*> snapshot;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        snapshot = live;
+      }
+      for (Req* r : snapshot) slots.push_back(&r->slot);
+      if (!slots.empty()) {
+        int64_t nl = 0;
+        engine_tick(&c, slots, &nl);
+        std::lock_guard<std::mutex> lk(mu);
+        ++steps;
+        launches += nl;
+      }
+      for (Req* r : snapshot) {
+        if (!r->slot.finished) continue;
+        complete(r);
+        std::lock_guard<std::mutex> lk(mu);
+        live.erase(std::find(live.begin(), live.end(), r));
+        bytes_in_use -= r->bytes;
+        done_ids.push_back(r->id);
+        ++completed;
+      }
+    } catch (const pfem::Error& e) {
+      // a device failure ends every live request with the error
+      std::lock_guard<std::mutex> lk(mu);
+      worker_error = e.msg;
+      for (Req* r : live) {
+        r->rep = r->slot.rep;
+        r->rep.status = e.code;
+        r->t_done = now();
+        r->done = true;
+        done_ids.push_back(r->id);
+        ++completed;
+        try {
+          slot_free(&r->slot);
+        } catch (...) {
+        }
+      }
+      live.clear();
+      bytes_in_use = 0;
+    }
+  }
+}
+
+extern "C" {
+
+pfem_status pfem_server_create(pfem_ctx* ctx, int64_t hbm_budget_bytes, int32_t max_slots,
+                               pfem_server** out) {
+  try {
+    require(ctx != nullptr && out != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+    require(hbm_budget_bytes > 0 && max_slots > 0, PFEM_E_INVALID_ARG, "bad budget or slots");
+    *out = nullptr;
+    const int device = ctx->c.device;
+    PFEM_HIP(hipSetDevice(device));
+    pfem_server* s = new pfem_server();
+    s->c.device = device;
+    s->budget = hbm_budget_bytes;
+    s->max_slots = max_slots;
+    try {
+      PFEM_HIP(hipStreamCreateWithFlags(&s->c.stream, hipStreamNonBlocking));
+      s->c.own_stream = true;
+      s->c.ring.init(16u << 20, s->c.stream);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    s->t0 = std::chrono::steady_clock::now();
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    set_error("");
+    return PFEM_OK;
+  } catch (const pfem::Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (...) {
+    set_error("server creation failed");
+    return PFEM_E_DEVICE;
+  }
+}
+
+pfem_status pfem_server_submit(pfem_server* s, pfem_mesh* m, const double* u0,
+                               const pfem_solve_opts* o, int64_t req_id) {
+  try {
+    require(s != nullptr && m != nullptr && o != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+    require(m->finalized, PFEM_E_STATE, "mesh not finalized");
+    require(o->tol > 0, PFEM_E_INVALID_ARG, "tol must be > 0");
+    require(o->prec == PFEM_FP64 || o->prec == PFEM_FP32, PFEM_E_INVALID_ARG, "bad precision");
+    Req* r = new Req();
+    r->id = req_id;
+    r->m = m;
+    r->o = *o;
+    r->has_u0 = u0 != nullptr;
+    if (u0) r->u0.assign(u0, u0 + m->n_dof());
+    r->bytes = req_bytes(m, o->prec);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->all.count(req_id)) {
+        delete r;
+        throw Error{PFEM_E_INVALID_ARG, "duplicate request id"};
+      }
+      if (r->bytes > s->budget) {
+        delete r;
+        throw Error{PFEM_E_OOM, "request footprint exceeds the server budget"};
+      }
+      r->t_submit = s->now();
+      s->all[req_id] = r;
+      s->queue.push_back(r);
+      ++s->submitted;
+    }
+    s->cv.notify_one();
+    set_error("");
+    return PFEM_OK;
+  } catch (const pfem::Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (...) {
+    set_error("submit failed");
+    return PFEM_E_INVALID_ARG;
+  }
+}
+
+pfem_status pfem_server_poll(pfem_server* s, int64_t* done_ids, int64_t cap, int64_t* n_done) {
+  if (s == nullptr || n_done == nullptr || (cap > 0 && done_ids == nullptr)) {
+    set_error("NULL argument");
+    return PFEM_E_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  int64_t n = 0;
+  while (!s->done_ids.empty() && n < cap) {
+    done_ids[n++] = s->done_ids.front();
+    s->done_ids.pop_front();
+  }
+  *n_done = n;
+  set_error("");
+  return PFEM_OK;
+}
+
+pfem_status pfem_server_result(pfem_server* s, int64_t req_id, double* u_out,
+                               pfem_solve_report* rep, double* t_submit, double* t_admit,
+                               double* t_done) {
+  if (s == nullptr) {
+    set_error("NULL server");
+    return PFEM_E_INVALID_ARG;
+  }
+  Req* r = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(req_id);
+    if (it == s->all.end()) {
+      set_error("unknown request id");
+      return PFEM_E_INVALID_ARG;
+    }
+    if (!it->second->done) {
+      set_error("request not finished");
+      return PFEM_E_STATE;
+    }
+    r = it->second;
+    s->all.erase(it);
+  }
+  if (u_out && !r->u_out.empty()) std::copy(r->u_out.begin(), r->u_out.end(), u_out);
+  if (rep) *rep = r->rep;
+  if (t_submit) *t_submit = r->t_submit;
+  if (t_admit) *t_admit = r->t_admit;
+  if (t_done) *t_done = r->t_done;
+  const pfem_status st = r->rep.status;
+  delete r;
+  set_error("");
+  return st < 0 ? st : PFEM_OK;
+}
+
+pfem_status pfem_server_cancel(pfem_server* s, int64_t req_id) {
+  if (s == nullptr) {
+    set_error("NULL server");
+    return PFEM_E_INVALID_ARG;
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(req_id);
+    if (it == s->all.end()) {
+      set_error("unknown request id");
+      return PFEM_E_INVALID_ARG;
+    }
+    it->second->cancel = true;
+  }
+  s->cv.notify_one();
+  set_error("");
+  return PFEM_OK;
+}
+
+pfem_status pfem_server_get_stats(pfem_server* s, pfem_server_stats* o) {
+  if (s == nullptr || o == nullptr) {
+    set_error("NULL argument");
+    return PFEM_E_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  o->submitted = s->submitted;
+  o->completed = s->completed;
+  o->live = (int64_t)s->live.size();
+  o->queued = (int64_t)s->queue.size();
+  o->peak_live = s->peak_live;
+  o->bytes_in_use = s->bytes_in_use;
+  o->peak_bytes = s->peak_bytes;
+  o->budget = s->budget;
+  o->steps = s->steps;
+  o->launches = s->launches;
+  set_error("");
+  return PFEM_OK;
+}
+
+void pfem_server_destroy(pfem_server* s) {
+  if (s == nullptr) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipSetDevice(s->c.device);
+  (void)hipStreamSynchronize(s->c.stream);
+  for (Req* r : s->live) {
+    try {
+      slot_free(&r->slot);
+    } catch (...) {
+    }
+  }
+  for (auto& kv : s->mesh_refs) {
+    try {
+      mesh_release_device(kv.first);
+    } catch (...) {
+    }
+  }
+  for (auto& kv : s->all) delete kv.second;
+  s->c.ring.release();
+  if (s->c.own_stream) (void)hipStreamDestroy(s->c.stream);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,472 @@
+// Batched solve engine (see solver.h).
+#include "solver.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+
+namespace pfem {
+
+// ------------------------------------------------------------ state memory
+void SolveState::alloc(int pr, int64_t nd, int nb, int64_t hcap, bool nonlinear) {
+  prec = pr;
+  n_dof = nd;
+  n_blocks = nb;
+  const size_t s = pr == PFEM_FP64 ? 8 : 4;
+  bytes = 0;
+  auto A = [&](void** p, size_t n) {
+    PFEM_HIP(hipMalloc(p, std::max<size_t>(n, 8)));
+    bytes += (int64_t)std::max<size_t>(n, 8);
+  };
+  A((void**)&x64, nd * 8);
+  A((void**)&g64, nd * 8);
+  A((void**)&aux64, nd * 8);
+  A(&d, nd * s);
+  A(&r, nd * s);
+  A(&p, nd * s);
+  A(&q, nd * s);
+  A(&minv, nd * s);
+  if (nonlinear && pr == PFEM_FP32) A(&u32, nd * 4);
+  A((void**)&part, (size_t)std::max(nb, 1) * kRedSlots * 8);
+  A((void**)&counter, 64);
+  PFEM_HIP(hipMemset(counter, 0, 64));
+  A((void**)&sc, sizeof(Scalars));
+  PFEM_HIP(hipMemset(sc, 0, sizeof(Scalars)));
+  hist_cap = std::max<int64_t>(hcap, 0);
+  A((void**)&hist, (size_t)std::max<int64_t>(hist_cap, 1) * 8);
+  Scalars init{};
+  init.hist_cap = (int32_t)std::min<int64_t>(hist_cap, INT32_MAX);
+  PFEM_HIP(hipMemcpy(sc, &init, sizeof(Scalars), hipMemcpyHostToDevice));
+}
+
+void SolveState::release() {
+  void* ptrs[] = {x64, g64, aux64, d, r, p, q, minv, u32, part, counter, sc, hist};
+  for (void* ptr : ptrs)
+    if (ptr != nullptr) (void)hipFree(ptr);
+  x64 = g64 = aux64 = nullptr;
+  d = r = p = q = minv = u32 = nullptr;
+  part = nullptr;
+  counter = nullptr;
+  sc = nullptr;
+  hist = nullptr;
+  bytes = 0;
+}
+
+void slot_alloc(SlotRun* s, pfem_mesh* m, const pfem_solve_opts& o, int64_t hist_cap) {
+  s->m = m;
+  s->o = o;
+  s->prec = o.prec == PFEM_FP64 ? PFEM_FP64 : PFEM_FP32;
+  s->nl = m->nonlinear;
+  s->st = new SolveState();
+  try {
+    s->st->alloc(s->prec, m->n_dof(), m->n_blocks, hist_cap, m->nonlinear);
+    PFEM_HIP(hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault));
+  } catch (...) {
+    delete s->st;
+    s->st = nullptr;
+    throw;
+  }
+}
+
+void slot_free(SlotRun* s) {
+  delete s->st;
+  s->st = nullptr;
+  if (s->sc_host != nullptr) (void)hipHostFree(s->sc_host);
+  s->sc_host = nullptr;
+}
+
+// ---------------------------------------------------------------- helpers
+static Task base_task(SlotRun* s) {
+  Task t{};
+  t.m = s->m->md;
+  t.active = 1;
+  t.sc = s->st->sc;
+  t.hist = s->st->hist;
+  t.minv = s->st->minv;
+  t.r = s->st->r;
+  t.p = s->st->p;
+  t.d = s->st->d;
+  t.red.part = s->st->part;
+  t.red.counter = s->st->counter;
+  t.red.out = &s->st->sc->red[0];
+  t.mask = PFEM_MASK_OUT;
+  t.finisher = FIN_STORE;
+  t.fscale = (double)s->step / s->n_steps;   // load step n applies n / N_f of the load
+  return t;
+}
+
+struct Group {
+  int dim, prec;
+  std::vector<SlotRun*> slots;
+};
+
+// Groups slots by (dim, precision) so one templated launch covers a group.
+static std::vector<Group> group_by(const std::vector<SlotRun*>& v, bool force_fp64) {
+  std::map<std::pair<int, int>, Group> g;
+  for (SlotRun* s : v) {
+    const int pr = force_fp64 ? PFEM_FP64 : s->prec;
+    auto key = std::make_pair(s->m->dim, pr);
+    auto it = g.find(key);
+    if (it == g.end()) it = g.emplace(key, Group{s->m->dim, pr, {}}).first;
+    it->second.slots.push_back(s);
+  }
+  std::vector<Group> out;
+  for (auto& kv : g) out.push_back(kv.second);
+  return out;
+}
+
+struct Uploaded {
+  const Task* tasks = nullptr;
+  const int2* work = nullptr;
+  int n_work = 0;
+  int bn_max = 0;
+};
+
+// Work table for a group: all (task, block) pairs, remapped so that
+// consecutive blocks of a mesh land on the same XCD.
+static Uploaded upload_group(Ctx* ctx, const Group& g, const std::vector<Task>& tasks) {
+  Uploaded u;
+  u.tasks = static_cast<const Task*>(ctx->ring.put(tasks.data(), tasks.size() * sizeof(Task)));
+  int total = 0;
+  for (SlotRun* s : g.slots) {
+    total += s->m->n_blocks;
+    u.bn_max = std::max(u.bn_max, s->m->bn);
+  }
+  u.n_work = total;
+  if (g.slots.size() == 1) {
+    u.work = g.slots[0]->m->dev.work;   // persistent single-mesh table (task 0)
+    return u;
+  }
+  std::vector<int2> nat;
+  nat.reserve(total);
+  for (size_t i = 0; i < g.slots.size(); ++i)
+    for (int b = 0; b < g.slots[i]->m->n_blocks; ++b) nat.push_back(make_int2((int)i, b));
+  std::vector<int2> w(total);
+  int cnt[8], pre[8];
+  for (int k = 0; k < 8; ++k) cnt[k] = std::max((total - k + 7) / 8, 0);
+  pre[0] = 0;
+  for (int k = 1; k < 8; ++k) pre[k] = pre[k - 1] + cnt[k - 1];
+  for (int i = 0; i < total; ++i) w[i] = nat[pre[i % 8] + i / 8];
+  u.work = static_cast<const int2*>(ctx->ring.put(w.data(), w.size() * sizeof(int2)));
+  return u;
+}
+
+static double inner_target(const SlotRun* s) {
+  const double floor_abs = 0.5 * s->o.tol * s->den;
+  if (!s->nl) {
+    if (s->prec == PFEM_FP64) return s->o.tol * s->den;
+    const double rt = s->o.inner_rtol > 0 ? s->o.inner_rtol : 1e-4;
+    return std::max(rt * s->gnorm, floor_abs);
+  }
+  double eta = std::min(0.1, s->rho);
+  if (s->prec == PFEM_FP32) eta = std::max(eta, 1e-5);
+  return std::max(eta * s->gnorm, floor_abs);
+}
+
+static void finish(SlotRun* s, pfem_status st) {
+  s->status = st;
+  s->finished = true;
+  s->action = A_DONE;
+  s->rep.status = st;
+  s->rep.rel_residual_final = s->rho;
+}
+
+// ----------------------------------------------------------------- begin
+void slot_begin(Ctx* ctx, SlotRun* s, const double* u0_dev) {
+  pfem_mesh* m = s->m;
+  s->warm = u0_dev != nullptr;
+  s->n_steps = s->nl ? std::max(1, s->o.n_load_steps) : 1;
+  s->step = (s->warm || !s->nl) ? s->n_steps : 1;
+  s->max_iter = s->o.max_iter > 0 ? s->o.max_iter : (int)std::min<int64_t>(10 * std::max<int64_t>(m->n_free, 1), INT32_MAX / 2);
+  s->rep = pfem_solve_report{};
+  s->first_resid = true;
+  s->minv_valid = false;
+  s->newton_in_step = 0;
+  s->finished = false;
+  s->status = PFEM_OK;
+  const double scale = (double)s->step / s->n_steps;
+  // x64: caller guess (Dirichlet DOFs forced to the load-step values) or lift
+  if (s->warm)
+    launch_axpy_state(ctx, PFEM_FP64, m->md, s->st->x64, u0_dev, nullptr, 0.0, true, scale);
+  else
+    launch_lift(ctx, m->md, s->st->x64, nullptr, scale);
+  launch_lift(ctx, m->md, s->st->aux64, nullptr, scale);
+  launch_set_scalars(ctx, s->st->sc, 1.0, 0.0, 0, true, true);
+  s->action = A_DEN;
+}
+
+// ------------------------------------------------------------- launches
+static void do_force(Ctx* ctx, const std::vector<SlotRun*>& v, bool at_lift, int64_t* nl) {
+  for (const Group& g : group_by(v, true)) {
+    std::vector<Task> ts;
+    for (SlotRun* s : g.slots) {
+      Task t = base_task(s);
+      t.u = at_lift ? s->st->aux64 : s->st->x64;
+      t.y = s->st->g64;
+      t.w = nullptr;
+      ts.push_back(t);
+    }
+    Uploaded u = upload_group(ctx, g, ts);
+    launch_elem(ctx, g.dim, PFEM_FP64, OP_FORCE, PFEM_SCATTER_OWNER, u.tasks, u.work,
+                u.n_work, u.bn_max, nullptr, nullptr);
+    ++*nl;
+  }
+}
+
+static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
+                      const std::vector<SlotRun*>& all, int64_t* nl) {
+  // diagonal + init for the slots that start an inner solve
+  if (!start.empty()) {
+    std::vector<SlotRun*> need_diag;
+    for (SlotRun* s : start) {
+      if (s->nl && s->prec == PFEM_FP32)
+        launch_cast(ctx, true, s->st->x64, s->st->u32, s->m->n_dof());
+      if (s->nl || !s->minv_valid) need_diag.push_back(s);
+      launch_set_scalars(ctx, s->st->sc, s->den, inner_target(s) * inner_target(s),
+                         std::max(0, s->max_iter - s->rep.kv_count), false, false);
+    }
+    for (const Group& g : group_by(need_diag, false)) {
+      std::vector<Task> ts;
+      for (SlotRun* s : g.slots) {
+        Task t = base_task(s);
+        t.u = s->nl ? (s->prec == PFEM_FP32 ? s->st->u32 : (void*)s->st->x64) : nullptr;
+        t.y = s->st->minv;
+        t.s = 1.0;  // write the inverse diagonal
+        t.red.part = nullptr;
+        ts.push_back(t);
+        s->minv_valid = true;
+      }
+      Uploaded u = upload_group(ctx, g, ts);
+      launch_elem(ctx, g.dim, g.prec, OP_DIAG, PFEM_SCATTER_OWNER, u.tasks, u.work, u.n_work,
+                  u.bn_max, nullptr, nullptr);
+      ++*nl;
+    }
+    for (const Group& g : group_by(start, false)) {
+      std::vector<Task> ts;
+      for (SlotRun* s : g.slots) {
+        Task t = base_task(s);
+        t.u = s->st->g64;
+        t.finisher = FIN_INIT;
+        ts.push_back(t);
+      }
+      Uploaded u = upload_group(ctx, g, ts);
+      launch_pcg_init(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work);
+      ++*nl;
+    }
+  }
+  // chunk of iterations for every Krylov slot
+  int k = 0;
+  for (SlotRun* s : all) k = std::max(k, s->chunk);
+  for (const Group& g : group_by(all, false)) {
+    std::vector<Task> apply, upd;
+    for (SlotRun* s : g.slots) {
+      Task t = base_task(s);
+      t.u = s->nl ? (s->prec == PFEM_FP32 ? s->st->u32 : (void*)s->st->x64) : nullptr;
+      t.v = s->st->p;
+      t.y = s->st->q;
+      t.w = s->st->p;
+      t.finisher = FIN_PQ;
+      apply.push_back(t);
+      Task t2 = base_task(s);
+      t2.y = s->st->q;
+      t2.finisher = FIN_RZ;
+      upd.push_back(t2);
+    }
+    Uploaded ua = upload_group(ctx, g, apply);
+    Uploaded uu = upload_group(ctx, g, upd);
+    for (int it = 0; it < k; ++it) {
+      launch_elem(ctx, g.dim, g.prec, OP_APPLY, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
+                  ua.n_work, ua.bn_max, nullptr, nullptr);
+      launch_pcg_update(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work);
+      launch_pcg_direction(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work);
+      *nl += 3;
+    }
+  }
+}
+
+static void do_linesearch(Ctx* ctx, const std::vector<SlotRun*>& v, int64_t* nl) {
+  std::vector<SlotRun*> first;
+  for (SlotRun* s : v)
+    if (s->ls_tries == 0) first.push_back(s);
+  for (const Group& g : group_by(first, false)) {   // slope g . d -> red[2]
+    std::vector<Task> ts;
+    for (SlotRun* s : g.slots) {
+      Task t = base_task(s);
+      t.u = s->st->g64;
+      t.v = s->st->d;
+      t.red.out = &s->st->sc->red[2];
+      ts.push_back(t);
+    }
+    Uploaded u = upload_group(ctx, g, ts);
+    launch_dot(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work);
+    ++*nl;
+  }
+  for (const Group& g : group_by(v, false)) {   // Pi(x + s d) - Pi(x) -> red[0], #inverted -> red[1]
+    std::vector<Task> ts;
+    for (SlotRun* s : g.slots) {
+      Task t = base_task(s);
+      t.u = s->st->x64;
+      t.v = s->st->d;
+      t.s = s->ls_s;
+      ts.push_back(t);
+    }
+    Uploaded u = upload_group(ctx, g, ts);
+    launch_energy(ctx, g.dim, g.prec, true, u.tasks, u.work, u.n_work);
+    ++*nl;
+  }
+}
+
+// -------------------------------------------------------- transitions
+static void after_resid(Ctx* ctx, SlotRun* s) {
+  const Scalars& h = *s->sc_host;
+  s->gnorm = std::sqrt(h.red[1]);
+  s->rho = s->gnorm / s->den;
+  s->rep.residual_evals += 1;
+  if (!std::isfinite(s->rho)) {
+    finish(s, PFEM_E_BREAKDOWN);
+    return;
+  }
+  if (s->first_resid) {
+    s->first_resid = false;
+    s->rep.rel_residual_initial = s->rho;
+    if (s->o.tol_fine > 0 && s->rho < s->o.tol_fine) {
+      finish(s, PFEM_SKIPPED_FINE);
+      return;
+    }
+  }
+  if (s->rho <= s->o.tol) {
+    if (s->nl) s->rep.load_steps_done += 1;
+    if (s->nl && s->step < s->n_steps) {
+      s->step += 1;
+      const double scale = (double)s->step / s->n_steps;
+      launch_lift(ctx, s->m->md, s->st->x64, s->st->x64, scale);
+      launch_lift(ctx, s->m->md, s->st->aux64, nullptr, scale);
+      s->newton_in_step = 0;
+      s->first_resid = false;
+      s->action = A_DEN;
+      return;
+    }
+    finish(s, PFEM_OK);
+    return;
+  }
+  if (s->rep.kv_count >= s->max_iter) {
+    finish(s, PFEM_NOT_CONVERGED);
+    return;
+  }
+  if (s->nl && s->newton_in_step >= (s->o.max_newton > 0 ? s->o.max_newton : 50)) {
+    finish(s, PFEM_NOT_CONVERGED);
+    return;
+  }
+  s->chunk = 16;
+  s->k_chunk = 0;
+  s->rho_chunk = s->rho;
+  s->action = A_KRYLOV_START;
+}
+
+static void after_krylov(Ctx* ctx, SlotRun* s) {
+  const Scalars& h = *s->sc_host;
+  if (h.state == 0) {
+    // still running: size the next chunk from the observed convergence rate
+    const int dk = h.k - s->k_chunk;
+    int next = std::min(2 * s->chunk, 256);
+    if (dk > 0 && h.rho > 0 && s->rho_chunk > 0 && h.rho < s->rho_chunk) {
+      const double rate = std::log(s->rho_chunk / h.rho) / dk;
+      const double target = std::sqrt(std::max(h.target2, 1e-300)) / s->den;
+      const double rem = std::log(h.rho / std::max(target, 1e-300)) / rate;
+      next = (int)std::min(256.0, std::max(8.0, rem + 2.0));
+    }
+    s->chunk = next;
+    s->k_chunk = h.k;
+    s->rho_chunk = h.rho;
+    s->action = A_KRYLOV;
+    return;
+  }
+  s->rep.kv_count += h.k;
+  s->rep.pcg_iters += h.k;
+  s->rep.outer_sweeps += 1;
+  if (h.state == 3 && (!s->nl || h.k == 0)) {
+    if (!s->nl) {
+      finish(s, PFEM_E_BREAKDOWN);
+      return;
+    }
+    // negative curvature on the first step: preconditioned steepest descent
+    PFEM_HIP(hipMemcpyAsync(s->st->d, s->st->p, s->m->n_dof() * (s->prec == PFEM_FP64 ? 8 : 4),
+                            hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  if (!s->nl) {
+    launch_axpy_state(ctx, s->prec, s->m->md, s->st->x64, s->st->x64, s->st->d, 1.0, false, 0.0);
+    s->action = A_RESID;
+    return;
+  }
+  s->ls_s = 1.0;
+  s->ls_tries = 0;
+  s->action = A_LS;
+}
+
+static void after_ls(Ctx* ctx, SlotRun* s) {
+  const Scalars& h = *s->sc_host;
+  if (s->ls_tries == 0) s->ls_slope = h.red[2];
+  s->rep.line_search_evals += 1;
+  const double de = h.red[0];
+  const bool inverted = h.red[1] > 0.5;
+  if (!inverted && std::isfinite(de) && de <= 1e-4 * s->ls_s * s->ls_slope) {
+    launch_axpy_state(ctx, s->prec, s->m->md, s->st->x64, s->st->x64, s->st->d, s->ls_s,
+                      false, 0.0);
+    s->newton_in_step += 1;
+    s->rep.newton_iters += 1;
+    s->action = A_RESID;
+    return;
+  }
+  s->ls_tries += 1;
+  if (s->ls_tries > 20) {
+    finish(s, inverted ? PFEM_E_INVERTED : PFEM_E_LINESEARCH);
+    return;
+  }
+  s->ls_s *= 0.5;
+  s->action = A_LS;
+}
+
+int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches) {
+  std::vector<SlotRun*> den, resid, kstart, kall, ls;
+  for (SlotRun* s : live) {
+    if (s->finished) continue;
+    switch (s->action) {
+      case A_DEN: den.push_back(s); break;
+      case A_RESID: resid.push_back(s); break;
+      case A_KRYLOV_START: kstart.push_back(s); kall.push_back(s); break;
+      case A_KRYLOV: kall.push_back(s); break;
+      case A_LS: ls.push_back(s); break;
+      default: break;
+    }
+  }
+  int64_t nl = 0;
+  if (!den.empty()) do_force(ctx, den, true, &nl);
+  if (!resid.empty()) do_force(ctx, resid, false, &nl);
+  if (!kall.empty()) do_krylov(ctx, kstart, kall, &nl);
+  if (!ls.empty()) do_linesearch(ctx, ls, &nl);
+  // read back the scalars of every slot that did something
+  std::vector<SlotRun*> touched;
+  touched.insert(touched.end(), den.begin(), den.end());
+  touched.insert(touched.end(), resid.begin(), resid.end());
+  touched.insert(touched.end(), kall.begin(), kall.end());
+  touched.insert(touched.end(), ls.begin(), ls.end());
+  for (SlotRun* s : touched)
+    PFEM_HIP(hipMemcpyAsync(s->sc_host, s->st->sc, sizeof(Scalars), hipMemcpyDeviceToHost,
+                            ctx->stream));
+  PFEM_HIP(hipStreamSynchronize(ctx->stream));
+  if (launches) *launches += nl;
+  for (SlotRun* s : den) {
+    const double dn = std::sqrt(s->sc_host->red[1]);
+    s->den = dn > 0 ? dn : 1.0;
+    s->action = A_RESID;
+  }
+  for (SlotRun* s : resid) after_resid(ctx, s);
+  for (SlotRun* s : kall) after_krylov(ctx, s);
+  for (SlotRun* s : ls) after_ls(ctx, s);
+  int running = 0;
+  for (SlotRun* s : live)
+    if (!s->finished) ++running;
+  return running;
+}
+
+}  // namespace pfem

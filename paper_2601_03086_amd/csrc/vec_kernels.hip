@@ -1,0 +1,298 @@
+// Jacobi-PCG vector passes and small vector kernels.
+//
+// PCG (Saad, Alg. 9.1, with the Jacobi preconditioner M = diag A; App. B
+// iteration U^(k+1) = phi(U^(k))) solves A d = r0 for the correction d.  One
+// iteration is three launches over the owned node blocks of every live
+// task:
+//   apply      q = A p            fused with p.q, alpha = rz / pq   (element kernel)
+//   update     d += alpha p, r -= alpha q, fused with r.M^-1 r and r.r;
+//              beta, the relative residual, the history entry and the
+//              convergence flag are set by the last workgroup
+//   direction  p = M^-1 r + beta p
+// z = M^-1 r is never stored.  Every kernel returns at once for a task whose
+// state is no longer "running", so the host can queue several iterations
+// before it looks at the flags.
+#include "pfem_internal.h"
+#include "reduce.h"
+
+namespace pfem {
+
+template <int D>
+__device__ __forceinline__ void block_range(const Task* tp, int blk, size_t& g0, int& n) {
+  const int n0 = blk * tp->m.bn;
+  const int nloc = min(tp->m.bn, tp->m.n_nodes - n0);
+  g0 = (size_t)n0 * D;
+  n = nloc * D;
+}
+
+// r = -g (g: float64 gradient at the outer iterate, Dirichlet-masked);
+// d = 0; p = M^-1 r.  Reduction: (r.M^-1 r, r.r) -> FIN_INIT.
+template <int D, typename T>
+__global__ void __launch_bounds__(kThreads)
+k_pcg_init(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  size_t g0;
+  int n;
+  block_range<D>(tp, wk.y, g0, n);
+  const double* G = static_cast<const double*>(tp->u);
+  const T* Mi = static_cast<const T*>(tp->minv);
+  T* R = static_cast<T*>(tp->r);
+  T* P = static_cast<T*>(tp->p);
+  T* Dd = static_cast<T*>(tp->d);
+  double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const size_t g = g0 + i;
+    const T r = (T)(-G[g]);
+    const T z = Mi[g] * r;
+    R[g] = r;
+    P[g] = z;
+    Dd[g] = T(0);
+    part[0] += (double)r * (double)z;
+    part[1] += (double)r * (double)r;
+  }
+  reduce_finish(tp, wk.y, tp->m.n_blocks, part);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(kThreads)
+k_pcg_update(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  const Scalars* sc = tp->sc;
+  if (sc->state != 0) return;
+  const T alpha = (T)sc->alpha;
+  const double alpha64 = sc->alpha;
+  size_t g0;
+  int n;
+  block_range<D>(tp, wk.y, g0, n);
+  const T* Q = static_cast<const T*>(tp->y);
+  const T* P = static_cast<const T*>(tp->p);
+  const T* Mi = static_cast<const T*>(tp->minv);
+  T* R = static_cast<T*>(tp->r);
+  T* Dd = static_cast<T*>(tp->d);
+  double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const size_t g = g0 + i;
+    const T p = P[g];
+    const T r = R[g] - alpha * Q[g];
+    R[g] = r;
+    if constexpr (sizeof(T) == 8) Dd[g] += alpha64 * p;
+    else Dd[g] += alpha * p;
+    part[0] += (double)r * (double)Mi[g] * (double)r;
+    part[1] += (double)r * (double)r;
+  }
+  reduce_finish(tp, wk.y, tp->m.n_blocks, part);
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(kThreads)
+k_pcg_direction(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  const Scalars* sc = tp->sc;
+  if (sc->state != 0) return;
+  const T beta = (T)sc->beta;
+  size_t g0;
+  int n;
+  block_range<D>(tp, wk.y, g0, n);
+  const T* Mi = static_cast<const T*>(tp->minv);
+  const T* R = static_cast<const T*>(tp->r);
+  T* P = static_cast<T*>(tp->p);
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const size_t g = g0 + i;
+    P[g] = Mi[g] * R[g] + beta * P[g];
+  }
+}
+
+// red.out = (u . v, 0, 0, 0) over owned DOFs; u float64, v kernel type.
+template <int D, typename T>
+__global__ void __launch_bounds__(kThreads)
+k_dot(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  size_t g0;
+  int n;
+  block_range<D>(tp, wk.y, g0, n);
+  const double* A = static_cast<const double*>(tp->u);
+  const T* B = static_cast<const T*>(tp->v);
+  double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += kThreads) part[0] += A[g0 + i] * (double)B[g0 + i];
+  reduce_finish(tp, wk.y, tp->m.n_blocks, part);
+}
+
+#define PFEM_VEC_LAUNCH(KERNEL, FAM)                                                  \
+  do {                                                                                \
+    if (n_work <= 0) return;                                                          \
+    hipEvent_t ev = nullptr;                                                          \
+    ctx->timing_begin(FAM, &ev);                                                      \
+    dim3 grid(n_work), block(kThreads);                                               \
+    if (dim == 2 && prec == PFEM_FP32)                                                \
+      hipLaunchKernelGGL((KERNEL<2, float>), grid, block, 0, ctx->stream, tasks, work); \
+    else if (dim == 2)                                                                \
+      hipLaunchKernelGGL((KERNEL<2, double>), grid, block, 0, ctx->stream, tasks, work); \
+    else if (prec == PFEM_FP32)                                                       \
+      hipLaunchKernelGGL((KERNEL<3, float>), grid, block, 0, ctx->stream, tasks, work); \
+    else                                                                              \
+      hipLaunchKernelGGL((KERNEL<3, double>), grid, block, 0, ctx->stream, tasks, work); \
+    PFEM_HIP(hipGetLastError());                                                      \
+    ctx->timing_end(FAM, ev);                                                         \
+  } while (0)
+
+void launch_pcg_init(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
+                     int n_work) {
+  PFEM_VEC_LAUNCH(k_pcg_init, FAM_UPDATE);
+}
+void launch_pcg_update(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
+                       int n_work) {
+  PFEM_VEC_LAUNCH(k_pcg_update, FAM_UPDATE);
+}
+void launch_pcg_direction(Ctx* ctx, int dim, int prec, const Task* tasks,
+                          const int2* work, int n_work) {
+  PFEM_VEC_LAUNCH(k_pcg_direction, FAM_DIRECTION);
+}
+void launch_dot(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
+                int n_work) {
+  PFEM_VEC_LAUNCH(k_dot, FAM_UPDATE);
+}
+
+__global__ void k_set_scalars(Scalars* sc, double den, double target2, int kmax,
+                              int reset_hist, int reset_total) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->den = den;
+    sc->target2 = target2;
+    sc->kmax = kmax;
+    sc->k = 0;
+    sc->state = 0;
+    if (reset_hist) sc->hist_len = 0;
+    if (reset_total) sc->total_k = 0;
+  }
+}
+
+void launch_set_scalars(Ctx* ctx, Scalars* sc, double den, double target2, int kmax,
+                        bool reset_hist, bool reset_total) {
+  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, ctx->stream, sc, den, target2,
+                     kmax, reset_hist ? 1 : 0, reset_total ? 1 : 0);
+  PFEM_HIP(hipGetLastError());
+}
+
+// energies from FIN_STORE pairs (value, #inverted): +inf where any J <= 0.
+__global__ void k_energy_out(const double* red, double* out, int n, int stride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = red[(size_t)i * stride + 1] > 0.5 ? __builtin_inf() : red[(size_t)i * stride];
+}
+
+void launch_energy_out(Ctx* ctx, const double* red, double* out, int n, int stride) {
+  hipLaunchKernelGGL(k_energy_out, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, red, out,
+                     n, stride);
+  PFEM_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ small kernels
+static int grid_for(int64_t n) {
+  const int64_t g = (n + kThreads - 1) / kThreads;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+template <typename T>
+__global__ void k_permute(const int32_t* __restrict__ perm, int64_t n_nodes, int dim,
+                          bool to_internal, const T* __restrict__ in, T* __restrict__ out) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_nodes * dim;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t node = k / dim;
+    const int c = (int)(k % dim);
+    const int64_t nn = perm[node];   // caller node -> internal node
+    if (to_internal) out[nn * dim + c] = in[k];
+    else out[k] = in[nn * dim + c];
+  }
+}
+
+void launch_permute(Ctx* ctx, int prec, int dim, const int32_t* perm, int64_t n_nodes,
+                    bool to_internal, const void* in, void* out) {
+  const int g = grid_for(n_nodes * dim);
+  if (prec == PFEM_FP64)
+    hipLaunchKernelGGL(k_permute<double>, dim3(g), dim3(kThreads), 0, ctx->stream, perm,
+                       n_nodes, dim, to_internal, (const double*)in, (double*)out);
+  else
+    hipLaunchKernelGGL(k_permute<float>, dim3(g), dim3(kThreads), 0, ctx->stream, perm,
+                       n_nodes, dim, to_internal, (const float*)in, (float*)out);
+  PFEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
+
+void launch_fill(Ctx* ctx, int prec, void* p, int64_t n, double value) {
+  if (n <= 0) return;
+  const int g = grid_for(n);
+  if (prec == PFEM_FP64)
+    hipLaunchKernelGGL(k_fill<double>, dim3(g), dim3(kThreads), 0, ctx->stream,
+                       (double*)p, n, value);
+  else
+    hipLaunchKernelGGL(k_fill<float>, dim3(g), dim3(kThreads), 0, ctx->stream,
+                       (float*)p, n, (float)value);
+  PFEM_HIP(hipGetLastError());
+}
+
+__global__ void k_cast64to32(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = (float)in[k];
+}
+__global__ void k_cast32to64(const float* __restrict__ in, double* __restrict__ out, int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = (double)in[k];
+}
+
+void launch_cast(Ctx* ctx, bool to32, const void* in, void* out, int64_t n) {
+  if (n <= 0) return;
+  const int g = grid_for(n);
+  if (to32)
+    hipLaunchKernelGGL(k_cast64to32, dim3(g), dim3(kThreads), 0, ctx->stream,
+                       (const double*)in, (float*)out, n);
+  else
+    hipLaunchKernelGGL(k_cast32to64, dim3(g), dim3(kThreads), 0, ctx->stream,
+                       (const float*)in, (double*)out, n);
+  PFEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void k_axpy_state(const uint8_t* __restrict__ dmask, const double* __restrict__ ubar,
+                             int dim, int64_t n, double* out, const double* base,
+                             const T* __restrict__ inc, double s, bool set_dir, double scale) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double v = base != nullptr ? base[k] : 0.0;
+    if (inc != nullptr) v += s * (double)inc[k];
+    if (set_dir && ((dmask[k / dim] >> (k % dim)) & 1)) v = scale * ubar[k];
+    out[k] = v;
+  }
+}
+
+void launch_axpy_state(Ctx* ctx, int prec, const MeshDev& m, double* out, const double* base,
+                       const void* inc, double s, bool set_dirichlet, double scale) {
+  const int64_t n = (int64_t)m.n_nodes * m.dim;
+  const int g = grid_for(n);
+  if (prec == PFEM_FP64)
+    hipLaunchKernelGGL(k_axpy_state<double>, dim3(g), dim3(kThreads), 0, ctx->stream, m.dmask,
+                       m.ubar, m.dim, n, out, base, (const double*)inc, s, set_dirichlet, scale);
+  else
+    hipLaunchKernelGGL(k_axpy_state<float>, dim3(g), dim3(kThreads), 0, ctx->stream, m.dmask,
+                       m.ubar, m.dim, n, out, base, (const float*)inc, s, set_dirichlet, scale);
+  PFEM_HIP(hipGetLastError());
+}
+
+void launch_lift(Ctx* ctx, const MeshDev& m, double* out, const double* base, double scale) {
+  launch_axpy_state(ctx, PFEM_FP64, m, out, base, nullptr, 0.0, true, scale);
+}
+
+}  // namespace pfem

@@ -1,0 +1,143 @@
+"""C-ABI checks that need no GPU: the library loads and exports every symbol
+the header declares, and the host-side preprocessing (RCM numbering,
+element order, colouring, free-DOF map, owner blocks) equals the oracle's
+bit for bit."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import prep
+from tests import meshkit as mk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfem.h")
+
+
+def _lib():
+    from paper_2601_03086_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libpfem.so not built (run __graft_entry__.build())")
+    return L
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pfem_[A-Za-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported():
+    L = _lib()
+    lib = C.CDLL(L.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in pfem.h but not exported"
+    assert sorted(L.PROTOTYPES) == names, "binding prototypes differ from the header"
+
+
+def test_version_and_error_string():
+    L = _lib()
+    L.load()
+    assert b"gfx950" in L.pfem_version()
+    # a call with a NULL handle reports an error without a device
+    st = L.pfem_mesh_finalize(None, 0)
+    assert st == L.PFEM_E_INVALID_ARG
+    assert b"NULL" in L.pfem_last_error()
+
+
+def _host_mesh(prob, block_nodes=0):
+    from paper_2601_03086_amd import core
+    return core.Mesh.from_problem(None, prob, block_nodes)
+
+
+PROBLEMS = {
+    "c1": lambda: synth.unit_square_c1(),
+    "plate": lambda: synth.plate_problem(31, 32, 33, n_holes=4, target_tris=4000),
+    "box": lambda: synth.box_problem(41, 42, n_per_unit=5, n_voids=3, n_load_steps=2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_preprocessing_bit_exact(name):
+    L = _lib()
+    p = PROBLEMS[name]()
+    m = _host_mesh(p)
+    ref = prep.preprocess(p)
+    assert np.array_equal(m.query(L.PFEM_Q_PERM), ref["perm"])
+    assert np.array_equal(m.query(L.PFEM_Q_ELEM_ORDER), ref["elem_order"])
+    assert np.array_equal(m.query(L.PFEM_Q_COLOR), ref["color"])
+    assert np.array_equal(m.query(L.PFEM_Q_FREE_INDEX), ref["free_index"])
+    info = m.info
+    assert info["n_colors"] == int(ref["color"].max()) + 1
+    assert info["bandwidth_rcm"] == prep.bandwidth(p.conn, ref["perm"])
+    assert info["n_free"] == int((ref["free_index"] >= 0).sum())
+
+
+@pytest.mark.parametrize("bn", [32, 64, 96])
+def test_owner_blocks_cover_every_touch(bn):
+    """Each node block's element range contains every element touching it,
+    and the owned ranges partition the sorted elements."""
+    L = _lib()
+    p = synth.plate_problem(51, 52, 53, n_holes=2, target_tris=2500)
+    m = _host_mesh(p, block_nodes=bn)
+    ref = prep.preprocess(p)
+    sconn = ref["perm"][p.conn[ref["elem_order"]]]
+    blk = m.query(L.PFEM_Q_BLOCKS).reshape(-1, 3)
+    nb = (p.n_nodes + bn - 1) // bn
+    assert blk.shape[0] == nb == m.info["n_blocks"]
+    assert blk[0, 1] == 0 and blk[-1, 2] == p.n_elems
+    assert np.all(blk[1:, 1] == blk[:-1, 2])
+    owner = sconn.min(axis=1) // bn
+    for b in range(nb):
+        touching = np.nonzero(np.any(sconn // bn == b, axis=1))[0]
+        assert touching.min() == blk[b, 0]
+        assert touching.max() < blk[b, 2]
+        own = np.nonzero(owner == b)[0]
+        assert own.size == 0 or (own.min() == blk[b, 1] and own.max() == blk[b, 2] - 1)
+    assert m.info["owner_elem_visits"] == int((blk[:, 2] - blk[:, 0]).sum())
+
+
+def test_invalid_meshes_rejected():
+    L = _lib()
+    from paper_2601_03086_amd import core
+    coords = np.array([[0, 0], [1, 0], [0, 1], [1, 1]], dtype=np.float64)
+    good = np.array([[0, 1, 2], [1, 3, 2]], dtype=np.int32)
+    cases = {
+        "out of range": np.array([[0, 1, 4], [1, 3, 2]], dtype=np.int32),
+        "repeated node": np.array([[0, 1, 1], [1, 3, 2]], dtype=np.int32),
+        "orphan node": np.array([[0, 1, 2], [0, 1, 2]], dtype=np.int32),
+    }
+    for what, conn in cases.items():
+        with pytest.raises(L.PfemError) as ei:
+            core.Mesh(None, 2, coords, conn, "lin_plane_strain", "E_nu", 1.0, 0.3)
+        assert ei.value.status == L.PFEM_E_INVALID_MESH, what
+    flat = np.array([[0, 0], [1, 0], [2, 0], [1, 1]], dtype=np.float64)
+    with pytest.raises(L.PfemError) as ei:
+        core.Mesh(None, 2, flat, np.array([[0, 1, 2], [0, 1, 3]], np.int32),
+                  "lin_plane_strain", "E_nu", 1.0, 0.3)
+    assert ei.value.status == L.PFEM_E_INVALID_MESH
+    with pytest.raises(L.PfemError) as ei:
+        core.Mesh(None, 2, coords, good, "lin_plane_strain", "E_nu", 1.0, 0.3,
+                  dir_nodes=[0, 0], dir_comps=[0, 0], dir_values=[0.0, 1.0])
+    assert ei.value.status == L.PFEM_E_INVALID_ARG
+    with pytest.raises(L.PfemError) as ei:
+        core.Mesh(None, 2, coords, good, "lin_3d", "E_nu", 1.0, 0.3)
+    assert ei.value.status == L.PFEM_E_INVALID_ARG
+    m = core.Mesh(None, 2, coords, good, "lin_plane_strain", "E_nu", 1.0, 0.3)
+    st = L.pfem_energy(m.h, 0, 0, None, None)
+    assert st in (L.PFEM_E_STATE, L.PFEM_E_INVALID_ARG)
+
+
+def test_host_only_mesh_refuses_device_calls():
+    L = _lib()
+    p = synth.unit_square_c1(n=5)
+    m = _host_mesh(p)
+    dummy = C.c_void_p(1)
+    st = L.pfem_apply_K(m.h, 0, 0, 0, 0, dummy, dummy)
+    assert st == L.PFEM_E_STATE
+    assert b"device" in L.pfem_last_error()

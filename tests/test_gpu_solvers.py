@@ -1,0 +1,170 @@
+"""Solver parity: device Jacobi-PCG and Newton-Krylov against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import fe, solve as osolve
+from tests import meshkit as mk
+from tests.gpu_util import rel, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch_cuda()
+    from paper_2601_03086_amd import core
+    c = core.Context(0)
+    yield c
+    c.close()
+
+
+def _mesh(ctx, p, bn=0):
+    from paper_2601_03086_amd import core
+    return core.Mesh.from_problem(ctx, p, bn)
+
+
+def _oracle_rel_residual(p, u):
+    m = fe.Model(p)
+    Kff, Ff, _ = osolve.reduced_system(m)
+    return osolve.relative_residual(Kff, Ff, u[m.free_dofs])
+
+
+def test_c1_fp64_against_oracle(ctx):
+    """Same algorithm, same start as the oracle PCG: iteration counts within
+    2, histories and displacements agree (C1: 2,048 triangles, tol 1e-10)."""
+    p = synth.unit_square_c1()
+    m = _mesh(ctx, p)
+    u, rep, hist = m.solve(tol=1e-10, prec="fp64")
+    uo, ro = osolve.solve_linear(p, tol=1e-10)
+    print("c1 kv", rep["kv_count"], ro["kv_count"], rep["status_name"], flush=True)
+    assert rep["status"] == 0
+    assert abs(rep["kv_count"] - ro["kv_count"]) <= 2
+    n = min(len(hist), len(ro["history"]), 50)
+    assert np.allclose(hist[:n], ro["history"][:n], rtol=1e-6, atol=0)
+    assert rel(u, uo) <= 1e-9
+    assert rep["rel_residual_final"] <= 1e-10
+    assert _oracle_rel_residual(p, u) <= 1.01e-10
+    # against the direct solve at a tight tolerance
+    u12, rep12, _ = m.solve(tol=1e-12, prec="fp64")
+    ud, _ = osolve.solve_linear(p, method="direct")
+    assert rel(u12, ud) <= 1e-10
+    # Dirichlet DOFs hold their values exactly
+    left = np.nonzero(p.coords[:, 0] == 0)[0]
+    assert np.all(u.reshape(-1, 2)[left] == 0.0)
+
+
+def test_c1_warm_start_and_tol_fine(ctx):
+    p = synth.unit_square_c1()
+    m = _mesh(ctx, p)
+    ud, _ = osolve.solve_linear(p, method="direct")
+    u0 = synth.warm_start_guess(ud, p.coords, p.dir_nodes, seed=11)
+    _, rz, _ = m.solve(tol=1e-10, prec="fp64")
+    uw, rw, hw = m.solve(u0=u0, tol=1e-10, prec="fp64")
+    _, ro = osolve.solve_linear(p, u0=u0, tol=1e-10)
+    assert rw["status"] == 0
+    assert rw["kv_count"] < rz["kv_count"]
+    assert abs(rw["kv_count"] - ro["kv_count"]) <= 2
+    assert rel(uw, ud) <= 1e-8
+    assert abs(rw["rel_residual_initial"] - ro["history"][0]) <= 1e-9 * ro["history"][0]
+    # tol_fine: a guess already good enough is returned untouched
+    us, rs, _ = m.solve(u0=ud, tol=1e-10, tol_fine=1e-6, prec="fp64")
+    assert rs["status_name"] == "SKIPPED_FINE" and rs["kv_count"] == 0
+    assert rel(us, ud) <= 1e-15
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_plate_mixed_precision_reaches_1e8(ctx, prec):
+    """FP32 Krylov + FP64 residual refinement reaches a 1e-8 relative
+    residual as judged by the oracle, and matches the direct solve."""
+    p = synth.plate_problem(71, 72, 73, n_holes=6, target_tris=20000)
+    m = _mesh(ctx, p)
+    ud, _ = osolve.solve_linear(p, method="direct")
+    u0 = synth.warm_start_guess(ud, p.coords, p.dir_nodes, seed=12)
+    for guess in (None, u0):
+        u, rep, hist = m.solve(u0=guess, tol=1e-8, prec=prec)
+        print(prec, "warm" if guess is not None else "zero", rep["kv_count"],
+              rep["outer_sweeps"], rep["rel_residual_final"], flush=True)
+        assert rep["status"] == 0
+        assert _oracle_rel_residual(p, u) <= 1.05e-8
+        assert rel(u, ud) <= 1e-6
+        assert len(hist) >= 2 and hist[0] > hist[-1]
+
+
+def test_device_io_matches_host_io(ctx):
+    torch = torch_cuda()
+    p = synth.plate_problem(74, 75, 76, n_holes=3, target_tris=5000)
+    m = _mesh(ctx, p)
+    ud, _ = osolve.solve_linear(p, method="direct")
+    u0 = synth.warm_start_guess(ud, p.coords, p.dir_nodes, seed=13)
+    uh, rh, _ = m.solve(u0=u0, tol=1e-9, prec="fp32")
+    ut, rt, _ = m.solve(u0=torch.tensor(u0, device="cuda"), tol=1e-9, prec="fp32",
+                        device_io=True)
+    assert rh["kv_count"] == rt["kv_count"]
+    assert rel(ut.cpu().numpy(), uh) <= 1e-12
+
+
+def _small_box(seed=81, n=5, steps=4, uz=0.3):
+    return synth.box_problem(seed, seed + 1, n_per_unit=n, n_voids=3, uz=uz,
+                             n_load_steps=steps)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_newton_load_steps_match_oracle(ctx, prec):
+    p = _small_box()
+    m = _mesh(ctx, p)
+    uo, ro = osolve.newton(p, tol=1e-9)
+    assert ro["status"] == 0
+    u, rep, hist = m.solve(tol=1e-9, prec=prec, n_load_steps=p.n_load_steps)
+    print(prec, rep, flush=True)
+    assert rep["status"] == 0
+    assert rep["load_steps_done"] == p.n_load_steps
+    assert rel(u, uo) <= 1e-6
+    om = fe.Model(p)
+    g = om.gradient(u)[om.free_dofs]
+    den = np.linalg.norm(om.gradient(om.lifted(1.0))[om.free_dofs])
+    assert np.linalg.norm(g) / den <= 1.05e-9
+    # warm start at the final load step from the oracle solution + 1% noise
+    u0 = synth.warm_start_guess(uo, p.coords, p.dir_nodes, seed=14)
+    uw, rw, _ = m.solve(u0=u0, tol=1e-9, prec=prec, n_load_steps=p.n_load_steps)
+    assert rw["status"] == 0 and rw["load_steps_done"] == 1
+    assert rw["newton_iters"] < rep["newton_iters"]
+    assert rel(uw, uo) <= 1e-6
+
+
+def test_nh_plane_strain_with_traction(ctx):
+    p = synth.plate_problem(91, 92, 93, n_holes=3, target_tris=3000,
+                            model="nh_plane_strain")
+    p.neu_traction = p.neu_traction * 20.0     # drive it into the nonlinear range
+    p.n_load_steps = 3
+    m = _mesh(ctx, p)
+    uo, ro = osolve.newton(p, tol=1e-10)
+    assert ro["status"] == 0
+    u, rep, _ = m.solve(tol=1e-10, prec="fp64", n_load_steps=3)
+    assert rep["status"] == 0
+    assert rel(u, uo) <= 1e-7
+
+
+def test_failures_reported(ctx):
+    from paper_2601_03086_amd import _lib as L
+    p = synth.unit_square_c1(n=9)
+    # negative modulus: K is not positive definite -> breakdown
+    q = mk.make_problem("lin_plane_stress", p.coords, p.conn, E=-1.0,
+                        dir_nodes=p.dir_nodes, dir_comps=p.dir_comps,
+                        dir_values=p.dir_values, facets=p.neu_facets,
+                        traction=p.neu_traction)
+    mq = _mesh(ctx, q)
+    with pytest.raises(L.PfemError) as ei:
+        mq.solve(tol=1e-10, prec="fp64")
+    assert ei.value.status == L.PFEM_E_BREAKDOWN
+    # an iteration cap below what the tolerance needs -> NOT_CONVERGED with history
+    m = _mesh(ctx, p)
+    u, rep, hist = m.solve(tol=1e-14, prec="fp64", max_iter=5)
+    assert rep["status_name"] == "NOT_CONVERGED"
+    assert rep["kv_count"] == 5 and len(hist) == 6
+    # a NaN in the guess is caught by the first residual
+    u0 = np.zeros(p.n_dof)
+    u0[7] = np.nan
+    with pytest.raises(L.PfemError) as ei:
+        m.solve(u0=u0, tol=1e-10, prec="fp64")
+    assert ei.value.status == L.PFEM_E_BREAKDOWN
