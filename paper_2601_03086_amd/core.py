@@ -2,13 +2,48 @@
 
 Argument marshalling only: every computation happens in libpfem.so.
 """
+import atexit
 import ctypes as C
+import functools
+import weakref
 
 import numpy as np
 import torch
 
 from . import _lib as L
 from ._lib import check
+
+# Handles still open at interpreter exit are closed here, servers first and
+# contexts last, before the HIP runtime itself shuts down.
+_LIVE = {k: weakref.WeakSet() for k in ("server", "batch", "mesh", "ctx")}
+
+
+@atexit.register
+def _close_all():
+    for kind in ("server", "batch", "mesh", "ctx"):
+        for obj in list(_LIVE[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+def _on_stream(fn):
+    """Order a library call after the caller's current torch stream and make
+    the caller's stream wait for the library's work before reusing memory."""
+    @functools.wraps(fn)
+    def wrap(self, *a, **kw):
+        ctx = self.ctx
+        cur = torch.cuda.current_stream(ctx.device)
+        ctx.stream.wait_stream(cur)
+        try:
+            # staging copies made by the wrapper run on the library stream too
+            with torch.cuda.stream(ctx.stream):
+                return fn(self, *a, **kw)
+        finally:
+            cur.wait_stream(ctx.stream)
+    return wrap
+
 
 MODEL_IDS = {"lin_plane_stress": L.PFEM_LIN_PLANE_STRESS,
              "lin_plane_strain": L.PFEM_LIN_PLANE_STRAIN,
@@ -38,17 +73,19 @@ def _dtype(prec):
 
 
 class Context:
-    """One device + one HIP stream (torch's current stream by default)."""
+    """One device + one HIP stream (a dedicated torch stream by default;
+    calls are ordered against the caller's current stream with events)."""
 
     def __init__(self, device=0, stream=None):
         L.load()
         self.device = torch.device("cuda", device)
-        if stream is None:
-            stream = torch.cuda.current_stream(self.device)
+        if stream is None:   # a stream of our own (default priority)
+            stream = torch.cuda.Stream(device=self.device)
         self.stream = stream
         h = C.c_void_p()
         check(L.pfem_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
+        _LIVE["ctx"].add(self)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -108,6 +145,7 @@ class Mesh:
             check(L.pfem_mesh_set_neumann(h, fa.shape[0], _ptr(fa), _ptr(tr)))
         check(L.pfem_mesh_finalize(h, int(block_nodes)))
         self.info = self.get_info()
+        _LIVE["mesh"].add(self)
 
     @classmethod
     def from_problem(cls, ctx, prob, block_nodes=0):
@@ -145,12 +183,14 @@ class Mesh:
             raise ValueError(f"vector has {t.numel()} entries, mesh has {self.n_dof} DOFs")
         return t.contiguous()
 
+    @_on_stream
     def permute(self, x, to_internal=True, prec="fp64"):
         x = self._vec(x, prec)
         y = torch.empty_like(x)
         check(L.pfem_permute(self.h, PREC[prec], 1 if to_internal else 0, _ptr(x), _ptr(y)))
         return y
 
+    @_on_stream
     def hvp(self, u, v, prec="fp32", layout="user", scatter="owner", mask=0, out=None):
         v = self._vec(v, prec)
         u = self._vec(u, prec) if u is not None else None
@@ -159,6 +199,7 @@ class Mesh:
                          _ptr(u), _ptr(v), _ptr(y)))
         return y
 
+    @_on_stream
     def apply_K(self, v, prec="fp32", layout="user", scatter="owner", mask=0, out=None):
         v = self._vec(v, prec)
         y = torch.empty_like(v) if out is None else out
@@ -166,18 +207,21 @@ class Mesh:
                              _ptr(v), _ptr(y)))
         return y
 
+    @_on_stream
     def force(self, u, prec="fp64", layout="user", mask=0, out=None):
         u = self._vec(u, prec)
         y = torch.empty_like(u) if out is None else out
         check(L.pfem_force(self.h, PREC[prec], LAYOUT[layout], mask, _ptr(u), _ptr(y)))
         return y
 
+    @_on_stream
     def energy(self, u, prec="fp64", layout="user"):
         u = self._vec(u, prec)
         e = torch.empty((), dtype=torch.float64, device=self.ctx.device)
         check(L.pfem_energy(self.h, PREC[prec], LAYOUT[layout], _ptr(u), _ptr(e)))
         return e
 
+    @_on_stream
     def diag(self, u=None, prec="fp64", layout="user"):
         uu = self._vec(u, prec) if u is not None else None
         y = self.new_vec(prec)
@@ -200,6 +244,7 @@ class Mesh:
         o.inner_rtol = inner_rtol
         return o
 
+    @_on_stream
     def solve(self, u0=None, history_cap=100000, device_io=False, out=None, **kw):
         """Warm-started solve; returns (u, report dict, history ndarray)."""
         o = self.opts(**kw)
@@ -237,6 +282,7 @@ class Batch:
         check(L.pfem_batch_offsets(h, _ptr(off)))
         self.offsets = off
         self.n_dof = int(off[-1])
+        _LIVE["batch"].add(self)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -245,18 +291,21 @@ class Batch:
 
     __del__ = close
 
+    @_on_stream
     def energy(self, u, prec="fp32"):
         u = u.contiguous()
         e = torch.empty(len(self.meshes), dtype=torch.float64, device=self.ctx.device)
         check(L.pfem_batch_energy(self.h, PREC[prec], _ptr(u), _ptr(e)))
         return e
 
+    @_on_stream
     def force(self, u, prec="fp32", mask=0):
         u = u.contiguous()
         g = torch.empty_like(u)
         check(L.pfem_batch_force(self.h, PREC[prec], mask, _ptr(u), _ptr(g)))
         return g
 
+    @_on_stream
     def hvp(self, u, v, prec="fp32", mask=0):
         v = v.contiguous()
         y = torch.empty_like(v)
@@ -274,6 +323,7 @@ class Server:
         check(L.pfem_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), C.byref(h)))
         self.h = h
         self._meshes = {}
+        _LIVE["server"].add(self)
 
     def submit(self, req_id, mesh, u0=None, **kw):
         o = Mesh.opts(**kw)

@@ -9,7 +9,7 @@
 using namespace pfem;
 
 struct pfem_batch {
-  pfem_ctx* ctx = nullptr;
+  Ctx* ctx = nullptr;
   std::vector<pfem_mesh*> meshes;
   std::vector<int64_t> offsets;       // DOF offsets (n + 1)
   int dim = 0;
@@ -61,43 +61,37 @@ pfem_status pfem_ctx_create(int device, void* hip_stream, pfem_ctx** out) {
   PFEM_HIP(hipGetDeviceCount(&n));
   require(device >= 0 && device < n, PFEM_E_INVALID_ARG, "device index out of range");
   PFEM_HIP(hipSetDevice(device));
-  pfem_ctx* c = new pfem_ctx();
-  c->c.device = device;
+  Ctx* c = new Ctx();
+  c->device = device;
   try {
     if (hip_stream != nullptr) {
-      c->c.stream = static_cast<hipStream_t>(hip_stream);
+      c->stream = static_cast<hipStream_t>(hip_stream);
     } else {
-      PFEM_HIP(hipStreamCreateWithFlags(&c->c.stream, hipStreamNonBlocking));
-      c->c.own_stream = true;
+      PFEM_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
     }
-    c->c.ring.init(16u << 20, c->c.stream);
+    c->ring.init(16u << 20, c->stream);
   } catch (...) {
-    delete c;
+    ctx_unref(c);
     throw;
   }
-  *out = c;
+  pfem_ctx* h = new pfem_ctx();
+  h->c = c;
+  *out = h;
   PFEM_TRY_END
 }
 
 void pfem_ctx_destroy(pfem_ctx* ctx) {
   if (ctx == nullptr) return;
-  (void)hipSetDevice(ctx->c.device);
-  (void)hipStreamSynchronize(ctx->c.stream);
-  ctx->c.ring.release();
-  for (auto& p : ctx->c.pending) {
-    (void)hipEventDestroy(p.second.first);
-    (void)hipEventDestroy(p.second.second);
-  }
-  for (hipEvent_t e : ctx->c.event_pool) (void)hipEventDestroy(e);
-  if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
+  ctx_unref(ctx->c);   // freed once the last mesh / batch on it is gone
   delete ctx;
 }
 
 pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int enable) {
   PFEM_TRY_BEGIN
   require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
-  ctx->c.drain_timing();
-  ctx->c.timing = enable != 0;
+  ctx->c->drain_timing();
+  ctx->c->timing = enable != 0;
   PFEM_TRY_END
 }
 
@@ -106,19 +100,19 @@ pfem_status pfem_ctx_kernel_time(pfem_ctx* ctx, int family, int64_t* launches,
   PFEM_TRY_BEGIN
   require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
   require(family >= 0 && family < FAM_COUNT, PFEM_E_INVALID_ARG, "bad kernel family");
-  ctx->c.drain_timing();
-  if (launches) *launches = ctx->c.fam_launches[family];
-  if (total_ms) *total_ms = ctx->c.fam_ms[family];
+  ctx->c->drain_timing();
+  if (launches) *launches = ctx->c->fam_launches[family];
+  if (total_ms) *total_ms = ctx->c->fam_ms[family];
   PFEM_TRY_END
 }
 
 pfem_status pfem_ctx_reset_timing(pfem_ctx* ctx) {
   PFEM_TRY_BEGIN
   require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
-  ctx->c.drain_timing();
+  ctx->c->drain_timing();
   for (int i = 0; i < FAM_COUNT; ++i) {
-    ctx->c.fam_launches[i] = 0;
-    ctx->c.fam_ms[i] = 0.0;
+    ctx->c->fam_launches[i] = 0;
+    ctx->c->fam_ms[i] = 0.0;
   }
   PFEM_TRY_END
 }
@@ -126,7 +120,7 @@ pfem_status pfem_ctx_reset_timing(pfem_ctx* ctx) {
 pfem_status pfem_ctx_synchronize(pfem_ctx* ctx) {
   PFEM_TRY_BEGIN
   require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
-  PFEM_HIP(hipStreamSynchronize(ctx->c.stream));
+  PFEM_HIP(hipStreamSynchronize(ctx->c->stream));
   PFEM_TRY_END
 }
 
@@ -142,7 +136,7 @@ pfem_status pfem_mesh_create(pfem_ctx* ctx, int dim, int64_t n_nodes, const doub
           "mesh too large for int32 indexing");
   require(coords != nullptr && conn != nullptr, PFEM_E_INVALID_ARG, "NULL array");
   pfem_mesh* m = new pfem_mesh();
-  m->ctx = ctx != nullptr ? &ctx->c : nullptr;
+  m->ctx = ctx != nullptr ? ctx->c : nullptr;
   m->dim = dim;
   m->n_nodes = n_nodes;
   m->n_elems = n_elems;
@@ -429,16 +423,16 @@ pfem_status pfem_batch_create(pfem_ctx* ctx, int32_t n, pfem_mesh* const* meshes
           "bad batch arguments");
   *out = nullptr;
   pfem_batch* b = new pfem_batch();
-  b->ctx = ctx;
+  b->ctx = ctx->c;
   try {
-    PFEM_HIP(hipSetDevice(ctx->c.device));
+    PFEM_HIP(hipSetDevice(ctx->c->device));
     b->offsets.push_back(0);
     int total = 0;
     int64_t poff = 0;
     for (int i = 0; i < n; ++i) {
       pfem_mesh* m = meshes[i];
       need_device(m);
-      require(m->ctx == &ctx->c, PFEM_E_INVALID_ARG, "mesh belongs to another context");
+      require(m->ctx == ctx->c, PFEM_E_INVALID_ARG, "mesh belongs to another context");
       if (i == 0) b->dim = m->dim;
       require(m->dim == b->dim, PFEM_E_INVALID_ARG, "all meshes of a batch share one dimension");
       b->meshes.push_back(m);
@@ -472,18 +466,20 @@ pfem_status pfem_batch_create(pfem_ctx* ctx, int32_t n, pfem_mesh* const* meshes
     delete b;
     throw;
   }
+  ctx_ref(b->ctx);
   *out = b;
   PFEM_TRY_END
 }
 
 void pfem_batch_destroy(pfem_batch* b) {
   if (b == nullptr) return;
-  (void)hipSetDevice(b->ctx->c.device);
-  (void)hipStreamSynchronize(b->ctx->c.stream);
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipStreamSynchronize(b->ctx->stream);
   if (b->work) (void)hipFree(b->work);
   if (b->part) (void)hipFree(b->part);
   if (b->counters) (void)hipFree(b->counters);
   if (b->outs) (void)hipFree(b->outs);
+  ctx_unref(b->ctx);
   delete b;
 }
 
@@ -522,7 +518,7 @@ pfem_status pfem_batch_energy(pfem_batch* b, int prec, const void* u, double* en
   require(b != nullptr && u != nullptr && energies_dev != nullptr, PFEM_E_INVALID_ARG,
           "NULL argument");
   check_prec(prec);
-  Ctx* ctx = &b->ctx->c;
+  Ctx* ctx = b->ctx;
   PFEM_HIP(hipSetDevice(ctx->device));
   std::vector<Task> ts = batch_tasks(b, prec, u, nullptr, nullptr, 0);
   const Task* td = static_cast<const Task*>(ctx->ring.put(ts.data(), ts.size() * sizeof(Task)));
@@ -535,7 +531,7 @@ static pfem_status batch_elem(pfem_batch* b, int prec, int mask, int op, const v
                               const void* v, void* y) {
   require(b != nullptr && y != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
   check_prec(prec);
-  Ctx* ctx = &b->ctx->c;
+  Ctx* ctx = b->ctx;
   PFEM_HIP(hipSetDevice(ctx->device));
   std::vector<Task> ts = batch_tasks(b, prec, u, v, y, mask);
   for (Task& t : ts) t.red.part = nullptr;

@@ -423,6 +423,7 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   md.dim = m->dim;
   md.model = m->model;
   md.nonlinear = m->nonlinear ? 1 : 0;
+  ctx_ref(ctx);
   m->ctx = ctx;
   m->uploaded = true;
 }
@@ -460,7 +461,9 @@ void CallScratch::release() {
 }
 
 void mesh_release_device(pfem_mesh* m) {
-  if (m->ctx != nullptr && m->ctx->stream != nullptr) (void)hipStreamSynchronize(m->ctx->stream);
+  const bool held = m->uploaded;
+  if (held && m->ctx != nullptr && m->ctx->stream != nullptr)
+    (void)hipStreamSynchronize(m->ctx->stream);
   m->solve_state.reset();
   m->scratch.release();
   MeshDevBuffers& d = m->dev;
@@ -471,6 +474,10 @@ void mesh_release_device(pfem_mesh* m) {
   d = MeshDevBuffers{};
   m->md = MeshDev{};
   m->uploaded = false;
+  if (held) {
+    ctx_unref(m->ctx);
+    m->ctx = nullptr;
+  }
 }
 
 int64_t mesh_device_bytes(const pfem_mesh* m) {

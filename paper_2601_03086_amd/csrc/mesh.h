@@ -115,7 +115,7 @@ struct pfem_mesh {
 };
 
 struct pfem_ctx {
-  pfem::Ctx c;
+  pfem::Ctx* c = nullptr;
 };
 
 namespace pfem {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <string>
@@ -131,6 +132,7 @@ class ArgRing {
 };
 
 struct Ctx {
+  std::atomic<int> refs{1};   // handle + every uploaded mesh / batch
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -144,6 +146,11 @@ struct Ctx {
   void timing_end(int fam, hipEvent_t a);
   void drain_timing();
 };
+
+// Contexts live until their handle and every mesh or batch using them are
+// released, whatever order the caller destroys them in.
+void ctx_ref(Ctx* c);
+void ctx_unref(Ctx* c);
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on ctx->stream.  `tasks_dev` points to n_tasks Task

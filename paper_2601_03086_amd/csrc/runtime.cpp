@@ -57,6 +57,23 @@ void* ArgRing::put(const void* src, size_t n) {
   return dev_ + off;
 }
 
+// ---------------------------------------------------------------- context
+void ctx_ref(Ctx* c) { c->refs.fetch_add(1); }
+
+void ctx_unref(Ctx* c) {
+  if (c == nullptr || c->refs.fetch_sub(1) != 1) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream != nullptr) (void)hipStreamSynchronize(c->stream);
+  c->ring.release();
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream != nullptr) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
 // ---------------------------------------------------------------- timing
 void Ctx::timing_begin(int fam, hipEvent_t* a) {
   (void)fam;

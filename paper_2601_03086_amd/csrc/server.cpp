@@ -38,7 +38,7 @@ struct Req {
 }  // namespace
 
 struct pfem_server {
-  Ctx c;
+  Ctx* c = nullptr;   // own stream and descriptor ring on the caller's device
   int64_t budget = 0;
   int max_slots = 0;
   std::thread worker;
@@ -74,7 +74,7 @@ void pfem_server::admit(Req* r) {
     ++it->second;
     r->server_uploaded = true;
   } else if (!m->uploaded) {
-    mesh_upload(m, &c);
+    mesh_upload(m, c);
     mesh_refs[m] = 1;
     r->server_uploaded = true;
   }
@@ -83,13 +83,13 @@ void pfem_server::admit(Req* r) {
   const double* u0_int = nullptr;
   if (r->has_u0) {
     PFEM_HIP(hipMemcpyAsync(r->slot.st->g64, r->u0.data(), m->n_dof() * 8,
-                            hipMemcpyHostToDevice, c.stream));
-    launch_permute(&c, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, true, r->slot.st->g64,
+                            hipMemcpyHostToDevice, c->stream));
+    launch_permute(c, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, true, r->slot.st->g64,
                    r->slot.st->aux64);
-    PFEM_HIP(hipStreamSynchronize(c.stream));   // u0 host buffer may be released below
+    PFEM_HIP(hipStreamSynchronize(c->stream));   // u0 host buffer may be released below
     u0_int = r->slot.st->aux64;
   }
-  slot_begin(&c, &r->slot, u0_int);
+  slot_begin(c, &r->slot, u0_int);
   r->admitted = true;
   r->t_admit = now();
 }
@@ -98,11 +98,11 @@ void pfem_server::complete(Req* r) {
   pfem_mesh* m = r->m;
   if (r->slot.st != nullptr) {
     r->u_out.resize(m->n_dof());
-    launch_permute(&c, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, false, r->slot.st->x64,
+    launch_permute(c, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, false, r->slot.st->x64,
                    r->slot.st->g64);
     PFEM_HIP(hipMemcpyAsync(r->u_out.data(), r->slot.st->g64, m->n_dof() * 8,
-                            hipMemcpyDeviceToHost, c.stream));
-    PFEM_HIP(hipStreamSynchronize(c.stream));
+                            hipMemcpyDeviceToHost, c->stream));
+    PFEM_HIP(hipStreamSynchronize(c->stream));
   }
   r->rep = r->slot.rep;
   r->rep.status = r->cancel ? PFEM_E_CANCELLED : r->slot.status;
@@ -118,7 +118,7 @@ void pfem_server::complete(Req* r) {
 }
 
 void pfem_server::run() {
-  (void)hipSetDevice(c.device);
+  (void)hipSetDevice(c->device);
   for (;;) {
     std::vector<Req*> to_admit;
     std::vector<Req*> cancelled_live;
@@ -182,7 +182,7 @@ void pfem_server::run() {
       for (Req* r : snapshot) slots.push_back(&r->slot);
       if (!slots.empty()) {
         int64_t nl = 0;
-        engine_tick(&c, slots, &nl);
+        engine_tick(c, slots, &nl);
         std::lock_guard<std::mutex> lk(mu);
         ++steps;
         launches += nl;
@@ -226,17 +226,19 @@ pfem_status pfem_server_create(pfem_ctx* ctx, int64_t hbm_budget_bytes, int32_t 
     require(ctx != nullptr && out != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
     require(hbm_budget_bytes > 0 && max_slots > 0, PFEM_E_INVALID_ARG, "bad budget or slots");
     *out = nullptr;
-    const int device = ctx->c.device;
+    const int device = ctx->c->device;
     PFEM_HIP(hipSetDevice(device));
     pfem_server* s = new pfem_server();
-    s->c.device = device;
+    s->c = new Ctx();
+    s->c->device = device;
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
     try {
-      PFEM_HIP(hipStreamCreateWithFlags(&s->c.stream, hipStreamNonBlocking));
-      s->c.own_stream = true;
-      s->c.ring.init(16u << 20, s->c.stream);
+      PFEM_HIP(hipStreamCreateWithFlags(&s->c->stream, hipStreamNonBlocking));
+      s->c->own_stream = true;
+      s->c->ring.init(16u << 20, s->c->stream);
     } catch (...) {
+      ctx_unref(s->c);
       delete s;
       throw;
     }
@@ -391,8 +393,8 @@ void pfem_server_destroy(pfem_server* s) {
   }
   s->cv.notify_all();
   if (s->worker.joinable()) s->worker.join();
-  (void)hipSetDevice(s->c.device);
-  (void)hipStreamSynchronize(s->c.stream);
+  (void)hipSetDevice(s->c->device);
+  (void)hipStreamSynchronize(s->c->stream);
   for (Req* r : s->live) {
     try {
       slot_free(&r->slot);
@@ -406,8 +408,7 @@ void pfem_server_destroy(pfem_server* s) {
     }
   }
   for (auto& kv : s->all) delete kv.second;
-  s->c.ring.release();
-  if (s->c.own_stream) (void)hipStreamDestroy(s->c.stream);
+  ctx_unref(s->c);
   delete s;
 }
 
