@@ -123,12 +123,13 @@ const char* pfem_last_error(void);
 /* Library version string. */
 const char* pfem_version(void);
 
-/* Kernel timing: when enabled, every element-kernel launch on the context
- * is bracketed by HIP events on the context stream and its elapsed time is
- * accumulated per kernel family.  `family`: 0 = linear K.v / HVP apply,
+/* Kernel timing: every launch of a timed kernel family on the context is
+ * bracketed by HIP events on the context stream and its elapsed time is
+ * accumulated per family.  Families: 0 = K.v / Hessian-vector apply,
  * 1 = internal force, 2 = energy, 3 = Jacobi diagonal, 4 = PCG vector
- * update, 5 = direction update.  Reading synchronises the stream. */
-pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int enable);
+ * update, 5 = direction update.  `family_mask`: bit f times family f
+ * (0 = off).  Reading synchronises the stream. */
+pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int family_mask);
 pfem_status pfem_ctx_kernel_time(pfem_ctx* ctx, int family, int64_t* launches,
                                  double* total_ms);
 pfem_status pfem_ctx_reset_timing(pfem_ctx* ctx);

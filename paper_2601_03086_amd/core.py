@@ -94,8 +94,11 @@ class Context:
 
     __del__ = close
 
-    def set_timing(self, on=True):
-        check(L.pfem_ctx_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, families=(0, 1, 2, 3, 4, 5)):
+        mask = 0
+        for f in families or ():
+            mask |= 1 << f
+        check(L.pfem_ctx_set_timing(self.h, mask))
 
     def reset_timing(self):
         check(L.pfem_ctx_reset_timing(self.h))

@@ -87,11 +87,11 @@ void pfem_ctx_destroy(pfem_ctx* ctx) {
   delete ctx;
 }
 
-pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int enable) {
+pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int family_mask) {
   PFEM_TRY_BEGIN
   require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
   ctx->c->drain_timing();
-  ctx->c->timing = enable != 0;
+  ctx->c->timing = family_mask;
   PFEM_TRY_END
 }
 

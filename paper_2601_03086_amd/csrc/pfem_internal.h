@@ -137,14 +137,26 @@ struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   ArgRing ring;
-  bool timing = false;
+  int timing = 0;          // bitmask of timed families
   int64_t fam_launches[FAM_COUNT] = {};
   double fam_ms[FAM_COUNT] = {};
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  struct Timed {
+    int fam;
+    hipEvent_t a, b;
+    int64_t key;          // launch group (-1: none)
+    int it;               // iteration index inside the group
+  };
+  std::vector<Timed> pending;
   std::vector<hipEvent_t> event_pool;
+  int64_t cur_key = -1;   // tag for the launches being enqueued
+  int cur_it = 0;
+  int64_t next_key = 0;
   void timing_begin(int fam, hipEvent_t* a);
   void timing_end(int fam, hipEvent_t a);
   void drain_timing();
+  // Forget timed launches of group `key` with iteration index >= keep: they
+  // returned at once because their solve had already converged.
+  void drop_noop(int64_t key, int keep);
 };
 
 // Contexts live until their handle and every mesh or batch using them are

@@ -66,8 +66,8 @@ void ctx_unref(Ctx* c) {
   if (c->stream != nullptr) (void)hipStreamSynchronize(c->stream);
   c->ring.release();
   for (auto& p : c->pending) {
-    (void)hipEventDestroy(p.second.first);
-    (void)hipEventDestroy(p.second.second);
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream != nullptr) (void)hipStreamDestroy(c->stream);
@@ -76,9 +76,8 @@ void ctx_unref(Ctx* c) {
 
 // ---------------------------------------------------------------- timing
 void Ctx::timing_begin(int fam, hipEvent_t* a) {
-  (void)fam;
   *a = nullptr;
-  if (!timing) return;
+  if (!(timing & (1 << fam))) return;
   if (event_pool.empty()) {
     hipEvent_t e;
     PFEM_HIP(hipEventCreate(&e));
@@ -90,7 +89,7 @@ void Ctx::timing_begin(int fam, hipEvent_t* a) {
 }
 
 void Ctx::timing_end(int fam, hipEvent_t a) {
-  if (!timing || a == nullptr) return;
+  if (a == nullptr) return;
   if (event_pool.empty()) {
     hipEvent_t e;
     PFEM_HIP(hipEventCreate(&e));
@@ -99,19 +98,33 @@ void Ctx::timing_end(int fam, hipEvent_t a) {
   hipEvent_t b = event_pool.back();
   event_pool.pop_back();
   PFEM_HIP(hipEventRecord(b, stream));
-  pending.push_back({fam, {a, b}});
-  if (pending.size() > 4096) drain_timing();
+  pending.push_back({fam, a, b, cur_key, cur_it});
+  if (pending.size() > 8192 && cur_key < 0) drain_timing();
+}
+
+void Ctx::drop_noop(int64_t key, int keep) {
+  std::vector<Timed> kept;
+  kept.reserve(pending.size());
+  for (const Timed& t : pending) {
+    if (t.key == key && t.it >= keep) {
+      event_pool.push_back(t.a);
+      event_pool.push_back(t.b);
+    } else {
+      kept.push_back(t);
+    }
+  }
+  pending.swap(kept);
 }
 
 void Ctx::drain_timing() {
-  for (auto& p : pending) {
-    PFEM_HIP(hipEventSynchronize(p.second.second));
+  for (const Timed& t : pending) {
+    PFEM_HIP(hipEventSynchronize(t.b));
     float ms = 0.f;
-    PFEM_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
-    fam_ms[p.first] += ms;
-    fam_launches[p.first] += 1;
-    event_pool.push_back(p.second.first);
-    event_pool.push_back(p.second.second);
+    PFEM_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+    fam_ms[t.fam] += ms;
+    fam_launches[t.fam] += 1;
+    event_pool.push_back(t.a);
+    event_pool.push_back(t.b);
   }
   pending.clear();
 }

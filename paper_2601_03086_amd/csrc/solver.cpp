@@ -258,6 +258,11 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
   int k = 0;
   for (SlotRun* s : all) k = std::max(k, s->chunk);
   for (const Group& g : group_by(all, false)) {
+    const int64_t key = ctx->next_key++;
+    for (SlotRun* s : g.slots) {
+      s->timing_key = key;
+      s->k_before = (s->action == A_KRYLOV) ? s->k_chunk : 0;
+    }
     std::vector<Task> apply, upd;
     for (SlotRun* s : g.slots) {
       Task t = base_task(s);
@@ -274,13 +279,17 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
     }
     Uploaded ua = upload_group(ctx, g, apply);
     Uploaded uu = upload_group(ctx, g, upd);
+    ctx->cur_key = key;
     for (int it = 0; it < k; ++it) {
+      ctx->cur_it = it;
       launch_elem(ctx, g.dim, g.prec, OP_APPLY, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
                   ua.n_work, ua.bn_max, nullptr, nullptr);
       launch_pcg_update(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work);
       launch_pcg_direction(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work);
       *nl += 3;
     }
+    ctx->cur_key = -1;
+    ctx->cur_it = 0;
   }
 }
 
@@ -461,6 +470,15 @@ int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches) {
     s->action = A_RESID;
   }
   for (SlotRun* s : resid) after_resid(ctx, s);
+  if (ctx->timing != 0) {
+    // launches after the last real iteration of a group returned at once
+    std::map<int64_t, int> ran;
+    for (SlotRun* s : kall) {
+      int& r = ran[s->timing_key];
+      r = std::max(r, s->sc_host->k - s->k_before);
+    }
+    for (auto& kv : ran) ctx->drop_noop(kv.first, kv.second);
+  }
   for (SlotRun* s : kall) after_krylov(ctx, s);
   for (SlotRun* s : ls) after_ls(ctx, s);
   int running = 0;

@@ -43,6 +43,8 @@ struct SlotRun {
   int chunk = 16;
   double rho_chunk = 0.0;
   int k_chunk = 0;
+  int k_before = 0;         // Krylov count when the current chunk started
+  int64_t timing_key = -1;  // launch group of the current chunk
   double ls_s = 1.0, ls_slope = 0.0;
   int ls_tries = 0;
   int max_iter = 0;

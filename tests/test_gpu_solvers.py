@@ -100,8 +100,11 @@ def test_device_io_matches_host_io(ctx):
     uh, rh, _ = m.solve(u0=u0, tol=1e-9, prec="fp32")
     ut, rt, _ = m.solve(u0=torch.tensor(u0, device="cuda"), tol=1e-9, prec="fp32",
                         device_io=True)
-    assert rh["kv_count"] == rt["kv_count"]
-    assert rel(ut.cpu().numpy(), uh) <= 1e-12
+    # the owner scatter accumulates in LDS with atomics, so FP32 Krylov runs
+    # are reproducible to rounding, not bit for bit
+    assert abs(rh["kv_count"] - rt["kv_count"]) <= 0.05 * rh["kv_count"]
+    assert rt["status"] == 0 and rt["rel_residual_final"] <= 1e-9
+    assert rel(ut.cpu().numpy(), uh) <= 1e-7
 
 
 def _small_box(seed=81, n=5, steps=4, uz=0.3):
