@@ -136,7 +136,7 @@ def setup(args):
     from paper_2601_03086_amd import core
     prob = c2_problem()
     ctx = core.Context(0)
-    mesh = core.Mesh.from_problem(ctx, prob)
+    mesh = core.Mesh.from_problem(ctx, prob, getattr(args, "block_nodes", 0) or 0)
     # reference (untimed): device FP64 solve at 1e-11, then 1% smooth noise
     uref, rep, _ = mesh.solve(tol=1e-11, prec="fp64", device_io=True)
     u0 = synth.warm_start_guess(uref.cpu().numpy(), prob.coords, prob.dir_nodes, seed=3002)
@@ -160,6 +160,36 @@ def run_kv_only(n):
     print(json.dumps({"kv_launches": n, "copy_bytes": a.numel() * 4}))
 
 
+def run_kv_sweep(sizes):
+    """Average K.v time (FP32 and FP64, internal layout) per owner-block size."""
+    import torch
+    from paper_2601_03086_amd import core
+    prob = c2_problem()
+    ctx = core.Context(0)
+    b_alg = alg_bytes_kv(prob.n_elems, prob.n_nodes, 2)
+    for bn in sizes:
+        mesh = core.Mesh.from_problem(ctx, prob, bn)
+        for prec in ("fp32", "fp64"):
+            dt = torch.float32 if prec == "fp32" else torch.float64
+            x = mesh.permute(torch.randn(prob.n_dof, dtype=dt, device="cuda"), True, prec)
+            y = torch.empty_like(x)
+            for _ in range(20):
+                mesh.apply_K(x, prec=prec, layout="internal", out=y)
+            ctx.set_timing([FAM_APPLY])
+            ctx.reset_timing()
+            for _ in range(200):
+                mesh.apply_K(x, prec=prec, layout="internal", out=y)
+            n, ms = ctx.kernel_time(FAM_APPLY)
+            ctx.set_timing(())
+            us = ms / n * 1e3
+            print(json.dumps({"block_nodes": mesh.info["block_nodes"], "prec": prec,
+                              "blocks": mesh.info["n_blocks"],
+                              "visits_per_elem": round(mesh.info["owner_elem_visits"] / prob.n_elems, 3),
+                              "avg_us": round(us, 3),
+                              "alg_GBps": round(b_alg / (us * 1e-6) / 1e9, 1)}), flush=True)
+        mesh.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +199,9 @@ def main():
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--kv-only", type=int, default=0)
     ap.add_argument("--parse-pmc", default=None)
+    ap.add_argument("--kv-sweep", default=None,
+                    help="comma-separated owner-block sizes to time K.v with")
+    ap.add_argument("--block-nodes", type=int, default=0)
     args = ap.parse_args()
     if args.cpu_baseline_worker:
         cpu_baseline_worker()
@@ -183,6 +216,9 @@ def main():
         sys.exit(2)
     if args.kv_only:
         run_kv_only(args.kv_only)
+        return
+    if args.kv_sweep:
+        run_kv_sweep([int(s) for s in args.kv_sweep.split(",")])
         return
     import torch
     t_setup = time.perf_counter()

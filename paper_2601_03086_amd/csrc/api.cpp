@@ -17,7 +17,6 @@ struct pfem_batch {
   int n_work = 0;
   int2* work = nullptr;               // persistent device work table
   double* part = nullptr;             // per mesh: n_blocks * kRedSlots
-  unsigned* counters = nullptr;       // per mesh: 16 words
   double* outs = nullptr;             // per mesh: kRedSlots
   std::vector<int64_t> part_off;
 };
@@ -257,9 +256,10 @@ pfem_status pfem_mesh_query_int(const pfem_mesh* m, int which, int32_t* out, int
     case PFEM_Q_FREE_INDEX: src = &m->free_index; break;
     case PFEM_Q_BLOCKS:
       for (const int4& b : m->blocks) {
+        const int first = b.w > b.z ? std::min(b.x, m->halo[b.z]) : b.x;
+        tmp.push_back(first);
         tmp.push_back(b.x);
         tmp.push_back(b.y);
-        tmp.push_back(b.z);
       }
       src = &tmp;
       break;
@@ -342,7 +342,6 @@ static void elem_call(pfem_mesh* m, int prec, int layout, int scatter, int mask,
   t.y = yi;
   t.mask = mask;
   t.active = 1;
-  t.finisher = FIN_STORE;
   t.s = inv_diag;
   t.fscale = 1.0;
   if (scatter == PFEM_SCATTER_OWNER) {
@@ -405,12 +404,11 @@ pfem_status pfem_energy(pfem_mesh* m, int prec, int layout, const void* u, doubl
   t.u = ui;
   t.active = 1;
   t.fscale = 1.0;
-  t.finisher = FIN_STORE;
   t.red.part = m->scratch.part;
-  t.red.counter = m->scratch.counter;
   t.red.out = m->scratch.out;
   const Task* td = static_cast<const Task*>(ctx->ring.put(&t, sizeof(Task)));
   launch_energy(ctx, m->dim, prec, false, td, m->dev.work, m->n_blocks);
+  launch_reduce_store(ctx, td, 1);
   launch_energy_out(ctx, m->scratch.out, energy_dev, 1, kRedSlots);
   PFEM_TRY_END
 }
@@ -455,13 +453,10 @@ pfem_status pfem_batch_create(pfem_ctx* ctx, int32_t n, pfem_mesh* const* meshes
     PFEM_HIP(hipMalloc((void**)&b->work, w.size() * sizeof(int2)));
     PFEM_HIP(hipMemcpy(b->work, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice));
     PFEM_HIP(hipMalloc((void**)&b->part, std::max<int64_t>(poff, 1) * 8));
-    PFEM_HIP(hipMalloc((void**)&b->counters, (size_t)n * 64));
-    PFEM_HIP(hipMemset(b->counters, 0, (size_t)n * 64));
     PFEM_HIP(hipMalloc((void**)&b->outs, (size_t)n * kRedSlots * 8));
   } catch (...) {
     if (b->work) (void)hipFree(b->work);
     if (b->part) (void)hipFree(b->part);
-    if (b->counters) (void)hipFree(b->counters);
     if (b->outs) (void)hipFree(b->outs);
     delete b;
     throw;
@@ -477,7 +472,6 @@ void pfem_batch_destroy(pfem_batch* b) {
   (void)hipStreamSynchronize(b->ctx->stream);
   if (b->work) (void)hipFree(b->work);
   if (b->part) (void)hipFree(b->part);
-  if (b->counters) (void)hipFree(b->counters);
   if (b->outs) (void)hipFree(b->outs);
   ctx_unref(b->ctx);
   delete b;
@@ -504,9 +498,7 @@ static std::vector<Task> batch_tasks(pfem_batch* b, int prec, const void* u, con
     t.mask = mask;
     t.active = 1;
     t.fscale = 1.0;
-    t.finisher = FIN_STORE;
     t.red.part = b->part + b->part_off[i];
-    t.red.counter = b->counters + 16 * i;
     t.red.out = b->outs + kRedSlots * i;
     ts.push_back(t);
   }
@@ -523,6 +515,7 @@ pfem_status pfem_batch_energy(pfem_batch* b, int prec, const void* u, double* en
   std::vector<Task> ts = batch_tasks(b, prec, u, nullptr, nullptr, 0);
   const Task* td = static_cast<const Task*>(ctx->ring.put(ts.data(), ts.size() * sizeof(Task)));
   launch_energy(ctx, b->dim, prec, false, td, b->work, b->n_work);
+  launch_reduce_store(ctx, td, (int)b->meshes.size());
   launch_energy_out(ctx, b->outs, energies_dev, (int)b->meshes.size(), kRedSlots);
   PFEM_TRY_END
 }

@@ -23,16 +23,16 @@ namespace pfem {
 template <int D, typename T>
 __device__ __forceinline__ void load_nodal(const T* __restrict__ p, int n, T (&o)[D]) {
   if constexpr (D == 2 && sizeof(T) == 4) {
-    const float2 q = *reinterpret_cast<const float2*>(p + (size_t)n * 2);
+    const pf2 q = ldg(reinterpret_cast<const pf2*>(p + (size_t)n * 2));
     o[0] = q.x;
     o[1] = q.y;
   } else if constexpr (D == 2 && sizeof(T) == 8) {
-    const double2 q = *reinterpret_cast<const double2*>(p + (size_t)n * 2);
+    const pd2 q = ldg(reinterpret_cast<const pd2*>(p + (size_t)n * 2));
     o[0] = q.x;
     o[1] = q.y;
   } else {
 #pragma unroll
-    for (int i = 0; i < D; ++i) o[i] = p[(size_t)n * D + i];
+    for (int i = 0; i < D; ++i) o[i] = ldg(p + (size_t)n * D + i);
   }
 }
 
@@ -40,24 +40,24 @@ template <int D>
 __device__ __forceinline__ void load_conn(const int32_t* __restrict__ conn, int e,
                                           int (&nd)[D + 1]) {
   if constexpr (D == 3) {
-    const int4 q = *reinterpret_cast<const int4*>(conn + (size_t)e * 4);
+    const pi4 q = ldg(reinterpret_cast<const pi4*>(conn + (size_t)e * 4));
     nd[0] = q.x;
     nd[1] = q.y;
     nd[2] = q.z;
     nd[3] = q.w;
   } else {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) nd[a] = conn[(size_t)e * 3 + a];
+    for (int a = 0; a < 3; ++a) nd[a] = ldg(conn + (size_t)e * 3 + a);
   }
 }
 
 template <typename T>
 __device__ __forceinline__ T mat_mu(const MeshDev& m, int e) {
-  if constexpr (sizeof(T) == 4) return m.mu32[e]; else return m.mu64[e];
+  if constexpr (sizeof(T) == 4) return ldg(m.mu32 + e); else return ldg(m.mu64 + e);
 }
 template <typename T>
 __device__ __forceinline__ T mat_lam(const MeshDev& m, int e) {
-  if constexpr (sizeof(T) == 4) return m.lam32[e]; else return m.lam64[e];
+  if constexpr (sizeof(T) == 4) return ldg(m.lam32 + e); else return ldg(m.lam64 + e);
 }
 
 // Element output for one op; y[a][i] is the contribution to node a, comp i.
@@ -125,7 +125,7 @@ __device__ __forceinline__ void element_output(const MeshDev& m, const T* __rest
     if (OP == OP_APPLY && (mask & PFEM_MASK_IN)) {
 #pragma unroll
       for (int a = 0; a <= D; ++a) {
-        const int bits = m.dmask[nd[a]];
+        const int bits = ldg(m.dmask + nd[a]);
 #pragma unroll
         for (int i = 0; i < D; ++i)
           if (bits & (1 << i)) vv[a][i] = T(0);
@@ -157,7 +157,7 @@ __device__ __forceinline__ void element_output(const MeshDev& m, const T* __rest
     if (mask & PFEM_MASK_IN) {
 #pragma unroll
       for (int a = 0; a <= D; ++a) {
-        const int bits = m.dmask[nd[a]];
+        const int bits = ldg(m.dmask + nd[a]);
 #pragma unroll
         for (int i = 0; i < D; ++i)
           if (bits & (1 << i)) vv[a][i] = T(0);
@@ -171,6 +171,9 @@ __device__ __forceinline__ void element_output(const MeshDev& m, const T* __rest
 }
 
 // ------------------------------------------------------------ owner kernel
+// Workgroup = (task, node block).  Elements visited: the block's own sorted
+// range (smallest node inside the block) followed by its halo list
+// (elements owned by earlier blocks that reach into it).
 template <int D, typename T, int OP>
 __global__ void __launch_bounds__(kThreads)
 k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
@@ -178,12 +181,12 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   const int2 wk = work[blockIdx.x];
   const Task* tp = tasks + wk.x;
   if (!tp->active) return;
-  if (tp->finisher == FIN_PQ && tp->sc->state != 0) return;
+  if (tp->pcg && ldg(&tp->sc->state) != 0) return;
   const MeshDev m = tp->m;
   const int blk = wk.y;
   const int n0 = blk * m.bn;
   const int nloc = min(m.bn, m.n_nodes - n0);
-  const int4 br = m.blocks[blk];
+  const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
   T* acc = reinterpret_cast<T*>(smem_raw);
   const int nown = nloc * D;
   for (int i = threadIdx.x; i < nown; i += kThreads) acc[i] = T(0);
@@ -191,13 +194,12 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   const T* U = static_cast<const T*>(tp->u);
   const T* V = static_cast<const T*>(tp->v);
   const int mask = tp->mask;
-  for (int e = br.x + (int)threadIdx.x; e < br.z; e += kThreads) {
+  const int n_own = br.y - br.x;
+  const int total = n_own + (br.w - br.z);
+  for (int t = threadIdx.x; t < total; t += kThreads) {
+    const int e = t < n_own ? br.x + t : ldg(m.halo + br.z + (t - n_own));
     int nd[D + 1];
     load_conn<D>(m.conn, e, nd);
-    bool touch = false;
-#pragma unroll
-    for (int a = 0; a <= D; ++a) touch |= (unsigned)(nd[a] - n0) < (unsigned)nloc;
-    if (!touch) continue;
     T y[D + 1][D];
     element_output<D, T, OP>(m, U, V, mask, e, nd, y);
 #pragma unroll
@@ -217,19 +219,19 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   for (int i = threadIdx.x; i < nown; i += kThreads) {
     const size_t gi = g0 + i;
     T val = acc[i];
-    const bool con = (m.dmask[n0 + i / D] >> (i % D)) & 1;
-    if (OP == OP_FORCE) val -= (T)(tp->fscale * m.fext[gi]);
+    const bool con = (ldg(m.dmask + n0 + i / D) >> (i % D)) & 1;
+    if (OP == OP_FORCE) val -= (T)(tp->fscale * ldg(m.fext + gi));
     if (OP == OP_DIAG) {
       if (con) val = T(1);
       else if (tp->s != 0.0) val = T(1) / val;   // inverse diagonal for PCG
     } else if ((mask & PFEM_MASK_OUT) && con) {
       val = T(0);
     }
-    Y[gi] = val;
-    if (W != nullptr) part[0] += (double)val * (double)W[gi];
+    stg(Y + gi, val);
+    if (W != nullptr) part[0] += (double)val * (double)ldg(W + gi);
     part[1] += (double)val * (double)val;
   }
-  reduce_finish(tp, blk, m.n_blocks, part);
+  write_partials(tp->red, m.n_blocks, blk, part, 0, 2);
 }
 
 // -------------------------------------------------- alternative scatters
@@ -260,7 +262,7 @@ __global__ void __launch_bounds__(kThreads) k_colored(Task t, int c0, int c1) {
   T* Y = static_cast<T*>(t.y);
   for (int k = c0 + blockIdx.x * kThreads + threadIdx.x; k < c1;
        k += gridDim.x * kThreads) {
-    const int e = m.colored[k];
+    const int e = ldg(m.colored + k);
     int nd[D + 1];
     load_conn<D>(m.conn, e, nd);
     T y[D + 1][D];
@@ -281,16 +283,16 @@ __global__ void __launch_bounds__(kThreads) k_alt_fixup(Task t) {
   const size_t n = (size_t)m.n_nodes * D;
   for (size_t g = (size_t)blockIdx.x * kThreads + threadIdx.x; g < n;
        g += (size_t)gridDim.x * kThreads) {
-    const bool con = (m.dmask[g / D] >> (g % D)) & 1;
-    T val = Y[g];
-    if (OP == OP_FORCE) val -= (T)(t.fscale * m.fext[g]);
+    const bool con = (ldg(m.dmask + g / D) >> (g % D)) & 1;
+    T val = ldg(Y + g);
+    if (OP == OP_FORCE) val -= (T)(t.fscale * ldg(m.fext + g));
     if (OP == OP_DIAG) {
       if (con) val = T(1);
       else if (t.s != 0.0) val = T(1) / val;
     } else if ((t.mask & PFEM_MASK_OUT) && con) {
       val = T(0);
     }
-    Y[g] = val;
+    stg(Y + g, val);
   }
 }
 
@@ -310,13 +312,13 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   const int blk = wk.y;
   const int n0 = blk * m.bn;
   const int nloc = min(m.bn, m.n_nodes - n0);
-  const int4 br = m.blocks[blk];
+  const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
   const TU* U = static_cast<const TU*>(tp->u);
   const TV* V = static_cast<const TV*>(tp->v);
   const double s = tp->s;
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
   using T = TU;   // element arithmetic type
-  for (int e = br.y + (int)threadIdx.x; e < br.z; e += kThreads) {
+  for (int e = br.x + (int)threadIdx.x; e < br.y; e += kThreads) {
     int nd[D + 1];
     load_conn<D>(m.conn, e, nd);
     Geo<D, T> g;
@@ -389,18 +391,14 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   // - f_ext . u   (or - s f_ext . v for the difference)
   const size_t g0 = (size_t)n0 * D;
   for (int i = threadIdx.x; i < nloc * D; i += kThreads) {
-    const double f = tp->fscale * m.fext[g0 + i];
-    if (DIFF) part[0] -= s * f * (double)V[g0 + i];
-    else part[0] -= f * (double)U[g0 + i];
+    const double f = tp->fscale * ldg(m.fext + g0 + i);
+    if (DIFF) part[0] -= s * f * (double)ldg(V + g0 + i);
+    else part[0] -= f * (double)ldg(U + g0 + i);
   }
-  reduce_finish(tp, blk, m.n_blocks, part);
+  write_partials(tp->red, m.n_blocks, blk, part, 0, 2);
 }
 
 // ---------------------------------------------------------------- launchers
-static int smem_bytes(int dim, int prec, int bn) {
-  return bn * dim * (prec == PFEM_FP64 ? 8 : 4);
-}
-
 template <int D, typename T>
 static void launch_owner_typed(Ctx* ctx, int op, const Task* tasks, const int2* work,
                                int n_work, int bn_max) {

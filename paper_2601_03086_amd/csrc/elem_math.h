@@ -16,6 +16,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "pfem_internal.h"
+
 namespace pfem {
 
 template <int D>
@@ -35,15 +37,26 @@ template <int D, typename T>
 __device__ __forceinline__ void load_geometry(const double* __restrict__ X,
                                               const int (&nd)[D + 1],
                                               Geo<D, T>& g) {
-  double x0[D];
+  double x[D + 1][D];
+  if constexpr (D == 2) {
 #pragma unroll
-  for (int i = 0; i < D; ++i) x0[i] = X[(size_t)nd[0] * D + i];
+    for (int a = 0; a <= D; ++a) {
+      const pd2 q = ldg(reinterpret_cast<const pd2*>(X + (size_t)nd[a] * 2));
+      x[a][0] = q.x;
+      x[a][1] = q.y;
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a <= D; ++a)
+#pragma unroll
+      for (int i = 0; i < D; ++i) x[a][i] = ldg(X + (size_t)nd[a] * D + i);
+  }
   T e[D][D];
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int i = 0; i < D; ++i)
-      e[a][i] = (T)(X[(size_t)nd[a + 1] * D + i] - x0[i]);
+      e[a][i] = (T)(x[a + 1][i] - x[0][i]);
   if constexpr (D == 2) {
     g.c[0][0] = e[1][1];
     g.c[0][1] = -e[1][0];

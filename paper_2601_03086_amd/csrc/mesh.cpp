@@ -325,37 +325,47 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
   require(bn <= block_nodes_max(), PFEM_E_INVALID_ARG, "block_nodes too large");
   m->bn = bn;
   m->n_blocks = (int)((N + bn - 1) / bn);
-  m->blocks.assign(m->n_blocks, make_int4(-1, 0, 0, 0));
-  for (int64_t s = 0; s < NE; ++s)
+  const int nb = m->n_blocks;
+  // owned range of block b: elements whose smallest node lies in b (the
+  // sort makes it contiguous); halo of b: elements owned by an earlier
+  // block that have a node in b, in increasing sorted position.
+  std::vector<int> own_begin(nb + 1, (int)NE);
+  std::vector<std::vector<int32_t>> halo(nb);
+  for (int64_t s = NE - 1; s >= 0; --s) {
+    int32_t mn = m->conn_int[s * nv];
+    for (int a = 1; a < nv; ++a) mn = std::min(mn, m->conn_int[s * nv + a]);
+    own_begin[mn / bn] = (int)s;
+  }
+  for (int b = nb - 1; b >= 0; --b)   // blocks that own nothing start where the next starts
+    if (own_begin[b] > own_begin[b + 1]) own_begin[b] = own_begin[b + 1];
+  for (int64_t s = 0; s < NE; ++s) {
+    int bl[4];
+    int32_t mn = m->conn_int[s * nv];
+    for (int a = 1; a < nv; ++a) mn = std::min(mn, m->conn_int[s * nv + a]);
+    const int ob = mn / bn;
+    int nbl = 0;
     for (int a = 0; a < nv; ++a) {
       const int b = m->conn_int[s * nv + a] / bn;
-      if (m->blocks[b].x < 0) m->blocks[b].x = (int)s;
+      if (b == ob) continue;
+      bool seen = false;
+      for (int k = 0; k < nbl; ++k) seen |= bl[k] == b;
+      if (!seen) bl[nbl++] = b;
     }
-  {
-    int64_t s = 0;
-    for (int b = 0; b < m->n_blocks; ++b) {
-      const int32_t n0 = b * bn;
-      // elements are sorted by their smallest node id
-      while (s < NE && m->conn_int[s * nv] >= 0) {
-        int32_t mn = m->conn_int[s * nv];
-        for (int a = 1; a < nv; ++a) mn = std::min(mn, m->conn_int[s * nv + a]);
-        if (mn >= n0) break;
-        ++s;
-      }
-      m->blocks[b].y = (int)s;
-    }
-    for (int b = 0; b < m->n_blocks; ++b)
-      m->blocks[b].z = (b + 1 < m->n_blocks) ? m->blocks[b + 1].y : (int)NE;
-    m->owner_visits = 0;
-    for (int b = 0; b < m->n_blocks; ++b) {
-      require(m->blocks[b].x >= 0 && m->blocks[b].x <= m->blocks[b].y, PFEM_E_INVALID_MESH,
-              "internal: block without elements");
-      m->owner_visits += m->blocks[b].z - m->blocks[b].x;
-    }
+    for (int k = 0; k < nbl; ++k) halo[bl[k]].push_back((int32_t)s);
+  }
+  m->blocks.assign(nb, make_int4(0, 0, 0, 0));
+  m->halo.clear();
+  m->owner_visits = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int h0 = (int)m->halo.size();
+    m->halo.insert(m->halo.end(), halo[b].begin(), halo[b].end());
+    m->blocks[b] = make_int4(own_begin[b], own_begin[b + 1], h0, (int)m->halo.size());
+    m->owner_visits += (own_begin[b + 1] - own_begin[b]) + (int64_t)halo[b].size();
+    require(own_begin[b + 1] > own_begin[b] || !halo[b].empty(), PFEM_E_INVALID_MESH,
+            "internal: node block touched by no element");
   }
   // work table: consecutive blocks on the same XCD (workgroup i runs on
   // XCD i % 8 when dispatched round-robin)
-  const int nb = m->n_blocks;
   m->work.resize(nb);
   {
     int cnt[8], pre[8];
@@ -395,6 +405,7 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
     d.lam64 = upload(m->lam_int, d.bytes);
     d.dmask = upload(m->dmask, d.bytes);
     d.blocks = upload(m->blocks, d.bytes);
+    d.halo = upload(m->halo, d.bytes);
     d.fext = upload(m->fext_int, d.bytes);
     d.ubar = upload(m->ubar_int, d.bytes);
     d.colored = upload(m->colored, d.bytes);
@@ -413,6 +424,7 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   md.lam64 = d.lam64;
   md.dmask = d.dmask;
   md.blocks = d.blocks;
+  md.halo = d.halo;
   md.fext = d.fext;
   md.ubar = d.ubar;
   md.colored = d.colored;
@@ -437,8 +449,6 @@ void CallScratch::ensure(int64_t nd, int nb) {
   PFEM_HIP(hipMalloc(&zero64, nd * 8));
   PFEM_HIP(hipMemset(zero64, 0, nd * 8));
   PFEM_HIP(hipMalloc((void**)&part, (size_t)std::max(nb, 1) * kRedSlots * 8));
-  PFEM_HIP(hipMalloc((void**)&counter, 64));
-  PFEM_HIP(hipMemset(counter, 0, 64));
   PFEM_HIP(hipMalloc((void**)&out, kRedSlots * 8));
   n_dof = nd;
   n_blocks = nb;
@@ -450,11 +460,9 @@ void CallScratch::release() {
   if (out64) (void)hipFree(out64);
   if (zero64) (void)hipFree(zero64);
   if (part) (void)hipFree(part);
-  if (counter) (void)hipFree(counter);
   if (out) (void)hipFree(out);
   in64 = v64 = out64 = zero64 = nullptr;
   part = nullptr;
-  counter = nullptr;
   out = nullptr;
   n_dof = 0;
   n_blocks = 0;
@@ -468,7 +476,7 @@ void mesh_release_device(pfem_mesh* m) {
   m->scratch.release();
   MeshDevBuffers& d = m->dev;
   void* ptrs[] = {d.X, d.conn, d.mu32, d.lam32, d.mu64, d.lam64, d.dmask, d.blocks,
-                  d.fext, d.ubar, d.colored, d.perm, d.work};
+                  d.halo, d.fext, d.ubar, d.colored, d.perm, d.work};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
   d = MeshDevBuffers{};
@@ -484,8 +492,8 @@ int64_t mesh_device_bytes(const pfem_mesh* m) {
   const int64_t N = m->n_nodes, NE = m->n_elems, D = m->dim;
   auto r = [](int64_t b) { return std::max<int64_t>(b, 1); };
   return r(N * D * 8) + r(NE * (D + 1) * 4) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
-         r((int64_t)m->n_blocks * 16) + 2 * r(N * D * 8) + r(NE * 4) + r(N * 4) +
-         r((int64_t)m->n_blocks * 8);
+         r((int64_t)m->n_blocks * 16) + r((int64_t)m->halo.size() * 4) + 2 * r(N * D * 8) +
+         r(NE * 4) + r(N * 4) + r((int64_t)m->n_blocks * 8);
 }
 
 int64_t solve_bytes(const pfem_mesh* m, int prec) {

@@ -22,12 +22,10 @@ struct SolveState {
   void* q = nullptr;
   void* minv = nullptr;
   void* u32 = nullptr;      // float32 copy of the state (FP32 Neo-Hookean HVP)
-  double* part = nullptr;   // n_blocks * kRedSlots
-  unsigned* counter = nullptr;
+  double* part = nullptr;   // kRedSlots * n_blocks
   Scalars* sc = nullptr;
   double* hist = nullptr;
   int64_t hist_cap = 0;
-  double* red_out = nullptr;   // kRedSlots doubles for FIN_STORE reductions
   int64_t bytes = 0;
   void alloc(int prec, int64_t n_dof, int n_blocks, int64_t hist_cap, bool nonlinear);
   void release();
@@ -43,6 +41,7 @@ struct MeshDevBuffers {
   double* lam64 = nullptr;
   uint8_t* dmask = nullptr;
   int4* blocks = nullptr;
+  int32_t* halo = nullptr;
   double* fext = nullptr;
   double* ubar = nullptr;
   int32_t* colored = nullptr;
@@ -58,7 +57,6 @@ struct CallScratch {
   void* out64 = nullptr;
   void* zero64 = nullptr;   // all-zero state (K = K_T(0))
   double* part = nullptr;
-  unsigned* counter = nullptr;
   double* out = nullptr;
   int64_t n_dof = 0;
   int n_blocks = 0;
@@ -92,7 +90,8 @@ struct pfem_mesh {
   std::vector<int32_t> free_index;  // caller DOF -> free rank or -1
   std::vector<int> color_ptr;       // colour CSR
   std::vector<int32_t> colored;     // sorted element ids grouped by colour
-  std::vector<int4> blocks;
+  std::vector<int4> blocks;         // (own begin, own end, halo begin, halo end)
+  std::vector<int32_t> halo;        // halo element lists of all blocks
   std::vector<int2> work;           // single-mesh work table
   int bn = 0, n_blocks = 0, n_colors = 0;
   int64_t n_free = 0, bw_in = 0, bw_rcm = 0, owner_visits = 0;

@@ -46,7 +46,8 @@ struct MeshDev {
   const double* mu64;     // n_elems
   const double* lam64;    // n_elems
   const uint8_t* dmask;   // n_nodes, bit c set when component c is Dirichlet
-  const int4* blocks;     // n_blocks: (first touching elem, first owned elem, end, 0)
+  const int4* blocks;     // n_blocks: (first owned elem, end owned, halo begin, halo end)
+  const int32_t* halo;    // elements owned by earlier blocks that touch a block
   const double* fext;     // n_dof, internal order
   const double* ubar;     // n_dof, final Dirichlet values, 0 on free DOFs
   const int32_t* colored; // n_elems: sorted element ids grouped by colour
@@ -54,24 +55,29 @@ struct MeshDev {
   int32_t dim, model, nonlinear, pad;
 };
 
-// Reduction bookkeeping of one task in one launch.
+// Partial sums of one task: slot k of block b at part[k * n_blocks + b].
+// The kernel after the producing one (or a one-workgroup reduction kernel)
+// sums them in block order, so no workgroup waits for another and no fence
+// is needed.
 struct RedDev {
-  double* part;           // n_blocks * kRedSlots partial sums
-  unsigned* counter;      // finished-block counter (reset by the last block)
+  double* part;           // kRedSlots * n_blocks partial sums
   double* out;            // reduced sums land here (kRedSlots doubles)
 };
 
-// Per-slot scalars of the Krylov state machine (device-resident).
+// Per-slot scalars of the Krylov state machine (device-resident).  Values a
+// kernel reads while its own block 0 may update them are double-buffered by
+// iteration parity (rz2).
 struct Scalars {
-  double rz, pq, rr, alpha, beta;
+  double rz2[2];          // r.M^-1 r after an even / odd number of iterations
+  double pq, rr, alpha, beta;
   double rho;             // latest |r| / den
   double den;             // |r_f(lifted)| (denominator of the relative residual)
   double target2;         // stop when |r|^2 <= target2
   double bnorm;           // |r| at inner start
-  double red[kRedSlots];  // last reduction outputs
+  double red[kRedSlots];  // outputs of one-workgroup reductions
   int32_t k;              // Krylov iterations done in the current inner solve
   int32_t kmax;           // cap for the current inner solve
-  int32_t state;          // 0 running, 1 converged, 2 max-iter, 3 breakdown, 4 negative curvature
+  int32_t state;          // 0 running, 1 converged, 2 max-iter, 3 breakdown
   int32_t hist_len, hist_cap, total_k, pad0, pad1;
 };
 
@@ -93,15 +99,10 @@ struct Task {
   double fscale;          // load factor applied to f_ext (load steps)
   int32_t mask;           // PFEM_MASK_* bits
   int32_t active;         // 0: every workgroup of this task returns at once
-  int32_t finisher;       // what the last block does with the reduction
+  int32_t k_base;         // Krylov iterations done before this chunk (PCG)
+  int32_t hist_base;      // history index of iteration 0 of this inner solve (PCG)
+  int32_t pcg;            // 1: PCG apply (returns at once unless state == 0)
   int32_t pad;
-};
-
-enum Finisher {
-  FIN_STORE = 0,          // copy sums[0..1] to red.out[0..1]
-  FIN_PQ = 1,             // sums[0] = p.q -> alpha (PCG)
-  FIN_RZ = 2,             // sums = (r.z, r.r) -> beta, rho, state (PCG)
-  FIN_INIT = 3            // sums = (r.z, r.r) at inner start -> rz, bnorm (PCG)
 };
 
 // Element-kernel operations.
@@ -175,11 +176,13 @@ void launch_energy(Ctx* ctx, int dim, int prec, bool diff,
                    const Task* tasks_dev, const int2* work_dev, int n_work);
 // PCG vector passes over owned node blocks.
 void launch_pcg_init(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
-                     const int2* work_dev, int n_work);
+                     const int2* work_dev, int n_work, int n_tasks);
 void launch_pcg_update(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
-                       const int2* work_dev, int n_work);
+                       const int2* work_dev, int n_work, int it);
 void launch_pcg_direction(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
-                          const int2* work_dev, int n_work);
+                          const int2* work_dev, int n_work, int it);
+// One workgroup per task: red.out[0..1] = sums of partial slots 0 and 1.
+void launch_reduce_store(Ctx* ctx, const Task* tasks_dev, int n_tasks);
 void launch_dot(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
                 const int2* work_dev, int n_work);
 void launch_set_scalars(Ctx* ctx, Scalars* sc, double den, double target2, int kmax,
@@ -197,6 +200,28 @@ void launch_axpy_state(Ctx* ctx, int prec, const MeshDev& m, double* out,
 // out = scale * ubar on Dirichlet DOFs, keep others of `base` (or 0 if base null)
 void launch_lift(Ctx* ctx, const MeshDev& m, double* out, const double* base,
                  double scale);
+
+// Device-side access through the global address space: pointers read from
+// descriptor structs are generic, and generic (flat) accesses make the
+// compiler wait on both the vector and the LDS/scalar counters.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PFEM_GLOBAL __attribute__((address_space(1)))
+#else
+#define PFEM_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *(const PFEM_GLOBAL T*)p;
+}
+// Native vector types: HIP's float2/double2/int4 wrappers copy through
+// generic references, which would turn a global load back into a flat one.
+typedef float pf2 __attribute__((ext_vector_type(2)));
+typedef double pd2 __attribute__((ext_vector_type(2)));
+typedef int pi4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ void stg(T* p, T v) {
+  *(PFEM_GLOBAL T*)p = v;
+}
 
 // Host-side helpers.
 int block_nodes_max();  // largest block size the kernels accept

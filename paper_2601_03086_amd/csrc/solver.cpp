@@ -28,8 +28,6 @@ void SolveState::alloc(int pr, int64_t nd, int nb, int64_t hcap, bool nonlinear)
   A(&minv, nd * s);
   if (nonlinear && pr == PFEM_FP32) A(&u32, nd * 4);
   A((void**)&part, (size_t)std::max(nb, 1) * kRedSlots * 8);
-  A((void**)&counter, 64);
-  PFEM_HIP(hipMemset(counter, 0, 64));
   A((void**)&sc, sizeof(Scalars));
   PFEM_HIP(hipMemset(sc, 0, sizeof(Scalars)));
   hist_cap = std::max<int64_t>(hcap, 0);
@@ -40,13 +38,12 @@ void SolveState::alloc(int pr, int64_t nd, int nb, int64_t hcap, bool nonlinear)
 }
 
 void SolveState::release() {
-  void* ptrs[] = {x64, g64, aux64, d, r, p, q, minv, u32, part, counter, sc, hist};
+  void* ptrs[] = {x64, g64, aux64, d, r, p, q, minv, u32, part, sc, hist};
   for (void* ptr : ptrs)
     if (ptr != nullptr) (void)hipFree(ptr);
   x64 = g64 = aux64 = nullptr;
   d = r = p = q = minv = u32 = nullptr;
   part = nullptr;
-  counter = nullptr;
   sc = nullptr;
   hist = nullptr;
   bytes = 0;
@@ -87,10 +84,10 @@ static Task base_task(SlotRun* s) {
   t.p = s->st->p;
   t.d = s->st->d;
   t.red.part = s->st->part;
-  t.red.counter = s->st->counter;
   t.red.out = &s->st->sc->red[0];
   t.mask = PFEM_MASK_OUT;
-  t.finisher = FIN_STORE;
+  t.k_base = s->k_before;
+  t.hist_base = s->hist_base;
   t.fscale = (double)s->step / s->n_steps;   // load step n applies n / N_f of the load
   return t;
 }
@@ -192,6 +189,7 @@ void slot_begin(Ctx* ctx, SlotRun* s, const double* u0_dev) {
     launch_lift(ctx, m->md, s->st->x64, nullptr, scale);
   launch_lift(ctx, m->md, s->st->aux64, nullptr, scale);
   launch_set_scalars(ctx, s->st->sc, 1.0, 0.0, 0, true, true);
+  s->hist_len_host = 0;
   s->action = A_DEN;
 }
 
@@ -209,12 +207,23 @@ static void do_force(Ctx* ctx, const std::vector<SlotRun*>& v, bool at_lift, int
     Uploaded u = upload_group(ctx, g, ts);
     launch_elem(ctx, g.dim, PFEM_FP64, OP_FORCE, PFEM_SCATTER_OWNER, u.tasks, u.work,
                 u.n_work, u.bn_max, nullptr, nullptr);
-    ++*nl;
+    launch_reduce_store(ctx, u.tasks, (int)ts.size());
+    *nl += 2;
   }
 }
 
 static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
                       const std::vector<SlotRun*>& all, int64_t* nl) {
+  // chunk bookkeeping: iterations done so far and where history goes
+  for (SlotRun* s : all) {
+    if (s->action == A_KRYLOV_START) {
+      s->k_before = 0;
+      const int64_t h0 = s->hist_len_host;
+      s->hist_base = (h0 == 0 && s->st->hist_cap > 0) ? 1 : (int)h0;
+    } else {
+      s->k_before = s->sc_host->k;
+    }
+  }
   // diagonal + init for the slots that start an inner solve
   if (!start.empty()) {
     std::vector<SlotRun*> need_diag;
@@ -246,12 +255,11 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
       for (SlotRun* s : g.slots) {
         Task t = base_task(s);
         t.u = s->st->g64;
-        t.finisher = FIN_INIT;
         ts.push_back(t);
       }
       Uploaded u = upload_group(ctx, g, ts);
-      launch_pcg_init(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work);
-      ++*nl;
+      launch_pcg_init(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work, (int)ts.size());
+      *nl += 2;
     }
   }
   // chunk of iterations for every Krylov slot
@@ -259,10 +267,7 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
   for (SlotRun* s : all) k = std::max(k, s->chunk);
   for (const Group& g : group_by(all, false)) {
     const int64_t key = ctx->next_key++;
-    for (SlotRun* s : g.slots) {
-      s->timing_key = key;
-      s->k_before = (s->action == A_KRYLOV) ? s->k_chunk : 0;
-    }
+    for (SlotRun* s : g.slots) s->timing_key = key;
     std::vector<Task> apply, upd;
     for (SlotRun* s : g.slots) {
       Task t = base_task(s);
@@ -270,11 +275,11 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
       t.v = s->st->p;
       t.y = s->st->q;
       t.w = s->st->p;
-      t.finisher = FIN_PQ;
+      t.pcg = 1;
       apply.push_back(t);
       Task t2 = base_task(s);
       t2.y = s->st->q;
-      t2.finisher = FIN_RZ;
+      t2.pcg = 1;
       upd.push_back(t2);
     }
     Uploaded ua = upload_group(ctx, g, apply);
@@ -284,8 +289,8 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
       ctx->cur_it = it;
       launch_elem(ctx, g.dim, g.prec, OP_APPLY, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
                   ua.n_work, ua.bn_max, nullptr, nullptr);
-      launch_pcg_update(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work);
-      launch_pcg_direction(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work);
+      launch_pcg_update(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
+      launch_pcg_direction(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
       *nl += 3;
     }
     ctx->cur_key = -1;
@@ -308,7 +313,8 @@ static void do_linesearch(Ctx* ctx, const std::vector<SlotRun*>& v, int64_t* nl)
     }
     Uploaded u = upload_group(ctx, g, ts);
     launch_dot(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work);
-    ++*nl;
+    launch_reduce_store(ctx, u.tasks, (int)ts.size());
+    *nl += 2;
   }
   for (const Group& g : group_by(v, false)) {   // Pi(x + s d) - Pi(x) -> red[0], #inverted -> red[1]
     std::vector<Task> ts;
@@ -321,7 +327,8 @@ static void do_linesearch(Ctx* ctx, const std::vector<SlotRun*>& v, int64_t* nl)
     }
     Uploaded u = upload_group(ctx, g, ts);
     launch_energy(ctx, g.dim, g.prec, true, u.tasks, u.work, u.n_work);
-    ++*nl;
+    launch_reduce_store(ctx, u.tasks, (int)ts.size());
+    *nl += 2;
   }
 }
 
@@ -464,6 +471,7 @@ int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches) {
                             ctx->stream));
   PFEM_HIP(hipStreamSynchronize(ctx->stream));
   if (launches) *launches += nl;
+  for (SlotRun* s : touched) s->hist_len_host = s->sc_host->hist_len;
   for (SlotRun* s : den) {
     const double dn = std::sqrt(s->sc_host->red[1]);
     s->den = dn > 0 ? dn : 1.0;

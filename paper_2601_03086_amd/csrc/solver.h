@@ -44,6 +44,8 @@ struct SlotRun {
   double rho_chunk = 0.0;
   int k_chunk = 0;
   int k_before = 0;         // Krylov count when the current chunk started
+  int hist_base = 0;        // history index of iteration 0 of the inner solve
+  int64_t hist_len_host = 0;
   int64_t timing_key = -1;  // launch group of the current chunk
   double ls_s = 1.0, ls_slope = 0.0;
   int ls_tries = 0;

@@ -2,16 +2,17 @@
 //
 // PCG (Saad, Alg. 9.1, with the Jacobi preconditioner M = diag A; App. B
 // iteration U^(k+1) = phi(U^(k))) solves A d = r0 for the correction d.  One
-// iteration is three launches over the owned node blocks of every live
-// task:
-//   apply      q = A p            fused with p.q, alpha = rz / pq   (element kernel)
-//   update     d += alpha p, r -= alpha q, fused with r.M^-1 r and r.r;
-//              beta, the relative residual, the history entry and the
-//              convergence flag are set by the last workgroup
-//   direction  p = M^-1 r + beta p
-// z = M^-1 r is never stored.  Every kernel returns at once for a task whose
-// state is no longer "running", so the host can queue several iterations
-// before it looks at the flags.
+// iteration is three launches over the owned node blocks of every live task:
+//   apply      q = A p; partials of p.q                     (element kernel)
+//   update     pq from the apply partials; alpha = rz / pq;
+//              d += alpha p, r -= alpha q; partials of r.M^-1 r and r.r
+//   direction  rz', rr from the update partials; beta = rz' / rz; the
+//              convergence test; p = M^-1 r + beta p
+// Every workgroup sums the previous kernel's partials itself (fixed order),
+// so the scalars never leave the device and no workgroup waits for another.
+// Block 0 of a task records the scalars, the residual history and the
+// state; the next launch returns at once for a task that left "running".
+// z = M^-1 r is never stored.
 #include "pfem_internal.h"
 #include "reduce.h"
 
@@ -26,7 +27,7 @@ __device__ __forceinline__ void block_range(const Task* tp, int blk, size_t& g0,
 }
 
 // r = -g (g: float64 gradient at the outer iterate, Dirichlet-masked);
-// d = 0; p = M^-1 r.  Reduction: (r.M^-1 r, r.r) -> FIN_INIT.
+// d = 0; p = M^-1 r.  Partials: slot 1 = r.M^-1 r, slot 2 = r.r.
 template <int D, typename T>
 __global__ void __launch_bounds__(kThreads)
 k_pcg_init(const Task* __restrict__ tasks, const int2* __restrict__ work) {
@@ -44,27 +45,71 @@ k_pcg_init(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < n; i += kThreads) {
     const size_t g = g0 + i;
-    const T r = (T)(-G[g]);
-    const T z = Mi[g] * r;
-    R[g] = r;
-    P[g] = z;
-    Dd[g] = T(0);
-    part[0] += (double)r * (double)z;
-    part[1] += (double)r * (double)r;
+    const T r = (T)(-ldg(G + g));
+    const T z = ldg(Mi + g) * r;
+    stg(R + g, r);
+    stg(P + g, z);
+    stg(Dd + g, T(0));
+    part[1] += (double)r * (double)z;
+    part[2] += (double)r * (double)r;
   }
-  reduce_finish(tp, wk.y, tp->m.n_blocks, part);
+  write_partials(tp->red, tp->m.n_blocks, wk.y, part, 1, 3);
+}
+
+// One workgroup per task: scalars at the start of an inner solve.
+__global__ void __launch_bounds__(kThreads) k_pcg_init_finish(const Task* __restrict__ tasks) {
+  const Task* tp = tasks + blockIdx.x;
+  if (!tp->active) return;
+  double rz, rr;
+  sum_slots2(tp->red.part, tp->m.n_blocks, 1, 2, rz, rr);
+  if (threadIdx.x != 0) return;
+  Scalars* sc = tp->sc;
+  sc->rz2[0] = rz;
+  sc->rr = rr;
+  sc->bnorm = sqrt(rr);
+  sc->rho = sqrt(rr) / sc->den;
+  sc->k = 0;
+  if (tp->hist != nullptr && sc->hist_len == 0 && sc->hist_cap > 0) {
+    tp->hist[0] = sc->rho;
+    sc->hist_len = 1;
+  }
+  if (!(rr == rr) || !(rz == rz))
+    sc->state = 3;
+  else if (rr <= sc->target2)
+    sc->state = 1;
+  else if (!(rz > 0.0))
+    sc->state = 3;
+  else if (sc->kmax <= 0)
+    sc->state = 2;
+  else
+    sc->state = 0;
 }
 
 template <int D, typename T>
 __global__ void __launch_bounds__(kThreads)
-k_pcg_update(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+k_pcg_update(const Task* __restrict__ tasks, const int2* __restrict__ work, int it) {
   const int2 wk = work[blockIdx.x];
   const Task* tp = tasks + wk.x;
   if (!tp->active) return;
-  const Scalars* sc = tp->sc;
-  if (sc->state != 0) return;
-  const T alpha = (T)sc->alpha;
-  const double alpha64 = sc->alpha;
+  Scalars* sc = tp->sc;
+  if (ldg(&sc->state) != 0) return;
+  const int nb = tp->m.n_blocks;
+  double pq, unused;
+  sum_slots2(tp->red.part, nb, 0, 0, pq, unused);
+  const int j = tp->k_base + it;
+  if (!(pq > 0.0)) {   // breakdown (not SPD) or NaN: nothing moves
+    if (wk.y == 0 && threadIdx.x == 0) {
+      sc->pq = pq;
+      sc->state = 3;
+    }
+    return;
+  }
+  const double alpha64 = ldg(&sc->rz2[j & 1]) / pq;
+  const T alpha = (T)alpha64;
+  if (wk.y == 0 && threadIdx.x == 0) {
+    sc->pq = pq;
+    sc->alpha = alpha64;
+  }
   size_t g0;
   int n;
   block_range<D>(tp, wk.y, g0, n);
@@ -76,26 +121,56 @@ k_pcg_update(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < n; i += kThreads) {
     const size_t g = g0 + i;
-    const T p = P[g];
-    const T r = R[g] - alpha * Q[g];
-    R[g] = r;
-    if constexpr (sizeof(T) == 8) Dd[g] += alpha64 * p;
-    else Dd[g] += alpha * p;
-    part[0] += (double)r * (double)Mi[g] * (double)r;
-    part[1] += (double)r * (double)r;
+    const T p = ldg(P + g);
+    const T r = ldg(R + g) - alpha * ldg(Q + g);
+    stg(R + g, r);
+    if constexpr (sizeof(T) == 8) stg(Dd + g, ldg(Dd + g) + alpha64 * p);
+    else stg(Dd + g, ldg(Dd + g) + alpha * p);
+    part[1] += (double)r * (double)ldg(Mi + g) * (double)r;
+    part[2] += (double)r * (double)r;
   }
-  reduce_finish(tp, wk.y, tp->m.n_blocks, part);
+  write_partials(tp->red, nb, wk.y, part, 1, 3);   // slot 0 is still being read
 }
 
 template <int D, typename T>
 __global__ void __launch_bounds__(kThreads)
-k_pcg_direction(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+k_pcg_direction(const Task* __restrict__ tasks, const int2* __restrict__ work, int it) {
   const int2 wk = work[blockIdx.x];
   const Task* tp = tasks + wk.x;
   if (!tp->active) return;
-  const Scalars* sc = tp->sc;
-  if (sc->state != 0) return;
-  const T beta = (T)sc->beta;
+  Scalars* sc = tp->sc;
+  if (ldg(&sc->state) != 0) return;
+  const int nb = tp->m.n_blocks;
+  double rz, rr;
+  sum_slots2(tp->red.part, nb, 1, 2, rz, rr);
+  const int j = tp->k_base + it;
+  const double beta64 = rz / ldg(&sc->rz2[j & 1]);
+  int state = 0;
+  if (!(rr == rr) || !(rz == rz))
+    state = 3;
+  else if (rr <= ldg(&sc->target2))
+    state = 1;
+  else if (!(rz > 0.0))
+    state = 3;
+  else if (j + 1 >= ldg(&sc->kmax))
+    state = 2;
+  if (wk.y == 0 && threadIdx.x == 0) {
+    sc->rz2[(j + 1) & 1] = rz;
+    sc->rr = rr;
+    sc->beta = beta64;
+    const double rho = sqrt(rr) / sc->den;
+    sc->rho = rho;
+    sc->k = j + 1;
+    sc->total_k += 1;
+    const int h = tp->hist_base + j;
+    if (tp->hist != nullptr && h < sc->hist_cap) {
+      tp->hist[h] = rho;
+      sc->hist_len = h + 1;
+    }
+    if (state != 0) sc->state = state;
+  }
+  if (state != 0) return;
+  const T beta = (T)beta64;
   size_t g0;
   int n;
   block_range<D>(tp, wk.y, g0, n);
@@ -104,11 +179,11 @@ k_pcg_direction(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   T* P = static_cast<T*>(tp->p);
   for (int i = threadIdx.x; i < n; i += kThreads) {
     const size_t g = g0 + i;
-    P[g] = Mi[g] * R[g] + beta * P[g];
+    stg(P + g, ldg(Mi + g) * ldg(R + g) + beta * ldg(P + g));
   }
 }
 
-// red.out = (u . v, 0, 0, 0) over owned DOFs; u float64, v kernel type.
+// Partials of u . v (u float64, v kernel type) in slot 0.
 template <int D, typename T>
 __global__ void __launch_bounds__(kThreads)
 k_dot(const Task* __restrict__ tasks, const int2* __restrict__ work) {
@@ -121,43 +196,63 @@ k_dot(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   const double* A = static_cast<const double*>(tp->u);
   const T* B = static_cast<const T*>(tp->v);
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < n; i += kThreads) part[0] += A[g0 + i] * (double)B[g0 + i];
-  reduce_finish(tp, wk.y, tp->m.n_blocks, part);
+  for (int i = threadIdx.x; i < n; i += kThreads)
+    part[0] += ldg(A + g0 + i) * (double)ldg(B + g0 + i);
+  write_partials(tp->red, tp->m.n_blocks, wk.y, part, 0, 1);
 }
 
-#define PFEM_VEC_LAUNCH(KERNEL, FAM)                                                  \
+// One workgroup per task: red.out[0..1] = totals of partial slots 0 and 1.
+__global__ void __launch_bounds__(kThreads) k_reduce_store(const Task* __restrict__ tasks) {
+  const Task* tp = tasks + blockIdx.x;
+  if (!tp->active) return;
+  double s0, s1;
+  sum_slots2(tp->red.part, tp->m.n_blocks, 0, 1, s0, s1);
+  if (threadIdx.x == 0) {
+    tp->red.out[0] = s0;
+    tp->red.out[1] = s1;
+  }
+}
+
+#define PFEM_VEC_LAUNCH(KERNEL, FAM, ...)                                              \
   do {                                                                                \
     if (n_work <= 0) return;                                                          \
     hipEvent_t ev = nullptr;                                                          \
     ctx->timing_begin(FAM, &ev);                                                      \
     dim3 grid(n_work), block(kThreads);                                               \
     if (dim == 2 && prec == PFEM_FP32)                                                \
-      hipLaunchKernelGGL((KERNEL<2, float>), grid, block, 0, ctx->stream, tasks, work); \
+      hipLaunchKernelGGL((KERNEL<2, float>), grid, block, 0, ctx->stream, __VA_ARGS__);  \
     else if (dim == 2)                                                                \
-      hipLaunchKernelGGL((KERNEL<2, double>), grid, block, 0, ctx->stream, tasks, work); \
+      hipLaunchKernelGGL((KERNEL<2, double>), grid, block, 0, ctx->stream, __VA_ARGS__); \
     else if (prec == PFEM_FP32)                                                       \
-      hipLaunchKernelGGL((KERNEL<3, float>), grid, block, 0, ctx->stream, tasks, work); \
+      hipLaunchKernelGGL((KERNEL<3, float>), grid, block, 0, ctx->stream, __VA_ARGS__);  \
     else                                                                              \
-      hipLaunchKernelGGL((KERNEL<3, double>), grid, block, 0, ctx->stream, tasks, work); \
+      hipLaunchKernelGGL((KERNEL<3, double>), grid, block, 0, ctx->stream, __VA_ARGS__); \
     PFEM_HIP(hipGetLastError());                                                      \
     ctx->timing_end(FAM, ev);                                                         \
   } while (0)
 
 void launch_pcg_init(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
-                     int n_work) {
-  PFEM_VEC_LAUNCH(k_pcg_init, FAM_UPDATE);
+                     int n_work, int n_tasks) {
+  PFEM_VEC_LAUNCH(k_pcg_init, FAM_UPDATE, tasks, work);
+  hipLaunchKernelGGL(k_pcg_init_finish, dim3(n_tasks), dim3(kThreads), 0, ctx->stream, tasks);
+  PFEM_HIP(hipGetLastError());
 }
 void launch_pcg_update(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
-                       int n_work) {
-  PFEM_VEC_LAUNCH(k_pcg_update, FAM_UPDATE);
+                       int n_work, int it) {
+  PFEM_VEC_LAUNCH(k_pcg_update, FAM_UPDATE, tasks, work, it);
 }
 void launch_pcg_direction(Ctx* ctx, int dim, int prec, const Task* tasks,
-                          const int2* work, int n_work) {
-  PFEM_VEC_LAUNCH(k_pcg_direction, FAM_DIRECTION);
+                          const int2* work, int n_work, int it) {
+  PFEM_VEC_LAUNCH(k_pcg_direction, FAM_DIRECTION, tasks, work, it);
 }
 void launch_dot(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
                 int n_work) {
-  PFEM_VEC_LAUNCH(k_dot, FAM_UPDATE);
+  PFEM_VEC_LAUNCH(k_dot, FAM_UPDATE, tasks, work);
+}
+void launch_reduce_store(Ctx* ctx, const Task* tasks, int n_tasks) {
+  if (n_tasks <= 0) return;
+  hipLaunchKernelGGL(k_reduce_store, dim3(n_tasks), dim3(kThreads), 0, ctx->stream, tasks);
+  PFEM_HIP(hipGetLastError());
 }
 
 __global__ void k_set_scalars(Scalars* sc, double den, double target2, int kmax,
@@ -180,7 +275,7 @@ void launch_set_scalars(Ctx* ctx, Scalars* sc, double den, double target2, int k
   PFEM_HIP(hipGetLastError());
 }
 
-// energies from FIN_STORE pairs (value, #inverted): +inf where any J <= 0.
+// energies from (value, #inverted) pairs: +inf where any J <= 0.
 __global__ void k_energy_out(const double* red, double* out, int n, int stride) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = red[(size_t)i * stride + 1] > 0.5 ? __builtin_inf() : red[(size_t)i * stride];

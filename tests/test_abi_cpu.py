@@ -93,13 +93,16 @@ def test_owner_blocks_cover_every_touch(bn):
     assert blk[0, 1] == 0 and blk[-1, 2] == p.n_elems
     assert np.all(blk[1:, 1] == blk[:-1, 2])
     owner = sconn.min(axis=1) // bn
+    visits = 0
     for b in range(nb):
         touching = np.nonzero(np.any(sconn // bn == b, axis=1))[0]
+        visits += touching.size
         assert touching.min() == blk[b, 0]
         assert touching.max() < blk[b, 2]
         own = np.nonzero(owner == b)[0]
         assert own.size == 0 or (own.min() == blk[b, 1] and own.max() == blk[b, 2] - 1)
-    assert m.info["owner_elem_visits"] == int((blk[:, 2] - blk[:, 0]).sum())
+    # every element is visited once per block it touches, and no more
+    assert m.info["owner_elem_visits"] == visits
 
 
 def test_invalid_meshes_rejected():
