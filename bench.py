@@ -249,6 +249,17 @@ def main():
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     n_apply, ms_apply = ctx.kernel_time(FAM_APPLY)
+    # per-family breakdown from two extra solves with every family timed
+    ctx.set_timing(range(6))
+    ctx.reset_timing()
+    for _ in range(2):
+        mesh.solve(u0=u0, **opts)
+    fam_names = ["apply", "force", "energy", "diag", "update", "direction"]
+    breakdown = {}
+    for f, nm in enumerate(fam_names):
+        n_f, ms_f = ctx.kernel_time(f)
+        if n_f:
+            breakdown[nm] = {"launches_per_solve": n_f / 2, "avg_us": round(ms_f / n_f * 1e3, 3)}
     ctx.set_timing(())
     assert all(r["status"] == 0 and r["rel_residual_final"] <= 1e-8 for r in reps), reps[-1]
     value = kv_total * prob.n_dof / t / 1e9
@@ -293,6 +304,7 @@ def main():
         "solve_latency_ms": {"p50": round(lat_sorted[len(lat) // 2] * 1e3, 3),
                              "p99": round(lat_sorted[min(len(lat) - 1,
                                                          int(0.99 * len(lat)))] * 1e3, 3)},
+        "kernel_breakdown": breakdown,
         "kv_per_solve_warm": kv_total / args.steps,
         "kv_per_solve_zero": rz["kv_count"],
         "outer_sweeps_warm": reps[-1]["outer_sweeps"],

@@ -15,7 +15,9 @@ struct pfem_batch {
   int dim = 0;
   int bn_max = 0;
   int n_work = 0;
-  int2* work = nullptr;               // persistent device work table
+  int2* work = nullptr;               // persistent device work table (all meshes)
+  int n_work_kind[2] = {0, 0};        // linear / Neo-Hookean sub-tables
+  int2* work_kind[2] = {nullptr, nullptr};
   double* part = nullptr;             // per mesh: n_blocks * kRedSlots
   double* outs = nullptr;             // per mesh: kRedSlots
   std::vector<int64_t> part_off;
@@ -346,10 +348,11 @@ static void elem_call(pfem_mesh* m, int prec, int layout, int scatter, int mask,
   t.fscale = 1.0;
   if (scatter == PFEM_SCATTER_OWNER) {
     const Task* td = static_cast<const Task*>(ctx->ring.put(&t, sizeof(Task)));
-    launch_elem(ctx, m->dim, prec, op, PFEM_SCATTER_OWNER, td, m->dev.work, m->n_blocks, m->bn,
-                nullptr, nullptr);
+    launch_elem(ctx, m->dim, prec, op, m->nonlinear, PFEM_SCATTER_OWNER, td, m->dev.work,
+                m->n_blocks, m->bn, nullptr, nullptr);
   } else {
-    launch_elem(ctx, m->dim, prec, op, scatter, nullptr, nullptr, 0, m->bn, &t, &m->color_ptr);
+    launch_elem(ctx, m->dim, prec, op, m->nonlinear, scatter, nullptr, nullptr, 0, m->bn, &t,
+                &m->color_ptr);
   }
   if (layout == PFEM_LAYOUT_USER)
     launch_permute(ctx, prec, m->dim, m->dev.perm, m->n_nodes, false, yi, y);
@@ -440,22 +443,40 @@ pfem_status pfem_batch_create(pfem_ctx* ctx, int32_t n, pfem_mesh* const* meshes
       poff += (int64_t)m->n_blocks * kRedSlots;
       total += m->n_blocks;
     }
-    std::vector<int2> nat;
+    auto remap = [](const std::vector<int2>& nat) {
+      const int total = (int)nat.size();
+      std::vector<int2> w(total);
+      int cnt[8], pre[8];
+      for (int k = 0; k < 8; ++k) cnt[k] = std::max((total - k + 7) / 8, 0);
+      pre[0] = 0;
+      for (int k = 1; k < 8; ++k) pre[k] = pre[k - 1] + cnt[k - 1];
+      for (int i = 0; i < total; ++i) w[i] = nat[pre[i % 8] + i / 8];
+      return w;
+    };
+    std::vector<int2> all_nat, kind_nat[2];
     for (int i = 0; i < n; ++i)
-      for (int k = 0; k < meshes[i]->n_blocks; ++k) nat.push_back(make_int2(i, k));
-    std::vector<int2> w(total);
-    int cnt[8], pre[8];
-    for (int k = 0; k < 8; ++k) cnt[k] = std::max((total - k + 7) / 8, 0);
-    pre[0] = 0;
-    for (int k = 1; k < 8; ++k) pre[k] = pre[k - 1] + cnt[k - 1];
-    for (int i = 0; i < total; ++i) w[i] = nat[pre[i % 8] + i / 8];
+      for (int k = 0; k < meshes[i]->n_blocks; ++k) {
+        all_nat.push_back(make_int2(i, k));
+        kind_nat[meshes[i]->nonlinear ? 1 : 0].push_back(make_int2(i, k));
+      }
+    std::vector<int2> w = remap(all_nat);
     b->n_work = total;
     PFEM_HIP(hipMalloc((void**)&b->work, w.size() * sizeof(int2)));
     PFEM_HIP(hipMemcpy(b->work, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice));
+    for (int kd = 0; kd < 2; ++kd) {
+      if (kind_nat[kd].empty()) continue;
+      std::vector<int2> wk = remap(kind_nat[kd]);
+      b->n_work_kind[kd] = (int)wk.size();
+      PFEM_HIP(hipMalloc((void**)&b->work_kind[kd], wk.size() * sizeof(int2)));
+      PFEM_HIP(hipMemcpy(b->work_kind[kd], wk.data(), wk.size() * sizeof(int2),
+                         hipMemcpyHostToDevice));
+    }
     PFEM_HIP(hipMalloc((void**)&b->part, std::max<int64_t>(poff, 1) * 8));
     PFEM_HIP(hipMalloc((void**)&b->outs, (size_t)n * kRedSlots * 8));
   } catch (...) {
     if (b->work) (void)hipFree(b->work);
+    for (int kd = 0; kd < 2; ++kd)
+      if (b->work_kind[kd]) (void)hipFree(b->work_kind[kd]);
     if (b->part) (void)hipFree(b->part);
     if (b->outs) (void)hipFree(b->outs);
     delete b;
@@ -471,6 +492,8 @@ void pfem_batch_destroy(pfem_batch* b) {
   (void)hipSetDevice(b->ctx->device);
   (void)hipStreamSynchronize(b->ctx->stream);
   if (b->work) (void)hipFree(b->work);
+  for (int kd = 0; kd < 2; ++kd)
+    if (b->work_kind[kd]) (void)hipFree(b->work_kind[kd]);
   if (b->part) (void)hipFree(b->part);
   if (b->outs) (void)hipFree(b->outs);
   ctx_unref(b->ctx);
@@ -529,8 +552,10 @@ static pfem_status batch_elem(pfem_batch* b, int prec, int mask, int op, const v
   std::vector<Task> ts = batch_tasks(b, prec, u, v, y, mask);
   for (Task& t : ts) t.red.part = nullptr;
   const Task* td = static_cast<const Task*>(ctx->ring.put(ts.data(), ts.size() * sizeof(Task)));
-  launch_elem(ctx, b->dim, prec, op, PFEM_SCATTER_OWNER, td, b->work, b->n_work, b->bn_max,
-              nullptr, nullptr);
+  for (int kd = 0; kd < 2; ++kd)
+    if (b->n_work_kind[kd] > 0)
+      launch_elem(ctx, b->dim, prec, op, kd == 1, PFEM_SCATTER_OWNER, td, b->work_kind[kd],
+                  b->n_work_kind[kd], b->bn_max, nullptr, nullptr);
   return PFEM_OK;
 }
 

@@ -60,18 +60,52 @@ __device__ __forceinline__ T mat_lam(const MeshDev& m, int e) {
   if constexpr (sizeof(T) == 4) return ldg(m.lam32 + e); else return ldg(m.lam64 + e);
 }
 
+// Everything one element needs, gathered before any arithmetic so that all
+// of its loads are in flight together.
+template <int D, typename T, int OP, bool NL>
+struct ElemIn {
+  double x[D + 1][D];
+  T u[D + 1][D];   // state (Neo-Hookean) or input of the linear force
+  T v[D + 1][D];   // direction of the apply
+  T mu, lam;
+};
+
+template <int D, typename T, int OP, bool NL>
+__device__ __forceinline__ void load_elem(const MeshDev& m, const T* __restrict__ U,
+                                          const T* __restrict__ V, int mask, int e,
+                                          const int (&nd)[D + 1], ElemIn<D, T, OP, NL>& in) {
+  load_coords<D>(m.X, nd, in.x);
+  in.mu = mat_mu<T>(m, e);
+  in.lam = mat_lam<T>(m, e);
+  if constexpr (NL || OP == OP_FORCE) {
+#pragma unroll
+    for (int a = 0; a <= D; ++a) load_nodal<D, T>(U, nd[a], in.u[a]);
+  }
+  if constexpr (OP == OP_APPLY) {
+#pragma unroll
+    for (int a = 0; a <= D; ++a) load_nodal<D, T>(V, nd[a], in.v[a]);
+    if (mask & PFEM_MASK_IN) {
+#pragma unroll
+      for (int a = 0; a <= D; ++a) {
+        const int bits = ldg(m.dmask + nd[a]);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+          if (bits & (1 << i)) in.v[a][i] = T(0);
+      }
+    }
+  }
+}
+
 // Element output for one op; y[a][i] is the contribution to node a, comp i.
-template <int D, typename T, int OP>
-__device__ __forceinline__ void element_output(const MeshDev& m, const T* __restrict__ U,
-                                               const T* __restrict__ V, int mask, int e,
-                                               const int (&nd)[D + 1], T (&y)[D + 1][D]) {
+template <int D, typename T, int OP, bool NL>
+__device__ __forceinline__ void element_compute(const ElemIn<D, T, OP, NL>& in,
+                                                T (&y)[D + 1][D]) {
   Geo<D, T> g;
-  load_geometry<D, T>(m.X, nd, g);
-  const T mu = mat_mu<T>(m, e);
-  const T lam = mat_lam<T>(m, e);
+  geometry<D, T>(in.x, g);
+  const T mu = in.mu, lam = in.lam;
   const T adet = g.det < T(0) ? -g.det : g.det;
   const T s_sym = T(1) / (T(Fact<D>::v) * adet);       // vol / det^2
-  if (OP == OP_DIAG) {
+  if constexpr (OP == OP_DIAG) {
     T cc[D + 1][D];
 #pragma unroll
     for (int i = 0; i < D; ++i) cc[0][i] = T(0);
@@ -82,7 +116,7 @@ __device__ __forceinline__ void element_output(const MeshDev& m, const T* __rest
         cc[a][i] = g.c[a - 1][i];
         cc[0][i] -= g.c[a - 1][i];
       }
-    if (!m.nonlinear) {
+    if constexpr (!NL) {
 #pragma unroll
       for (int a = 0; a <= D; ++a) {
         T n2 = T(0);
@@ -92,11 +126,8 @@ __device__ __forceinline__ void element_output(const MeshDev& m, const T* __rest
         for (int i = 0; i < D; ++i) y[a][i] = s_sym * (mu * n2 + (lam + mu) * cc[a][i] * cc[a][i]);
       }
     } else {
-      T uu[D + 1][D];
-#pragma unroll
-      for (int a = 0; a <= D; ++a) load_nodal<D, T>(U, nd[a], uu[a]);
       T Ht[D][D];
-      grad_tilde<D, T>(uu, g, Ht);
+      grad_tilde<D, T>(in.u, g, Ht);
       NHState<D, T> st;
       nh_state<D, T>(Ht, T(1) / g.det, st);
       const T coef = (T)((double)lam + (double)mu - (double)lam * st.lnJ);
@@ -114,67 +145,61 @@ __device__ __forceinline__ void element_output(const MeshDev& m, const T* __rest
         }
       }
     }
-    return;
-  }
-  if (!m.nonlinear) {
+  } else if constexpr (!NL) {
     // K v (OP_APPLY) or K u (OP_FORCE, f_ext subtracted by the caller)
-    T vv[D + 1][D];
-    const T* src = (OP == OP_APPLY) ? V : U;
-#pragma unroll
-    for (int a = 0; a <= D; ++a) load_nodal<D, T>(src, nd[a], vv[a]);
-    if (OP == OP_APPLY && (mask & PFEM_MASK_IN)) {
-#pragma unroll
-      for (int a = 0; a <= D; ++a) {
-        const int bits = ldg(m.dmask + nd[a]);
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-          if (bits & (1 << i)) vv[a][i] = T(0);
-      }
-    }
     T M[D][D], S[D][D];
-    grad_tilde<D, T>(vv, g, M);
+    if constexpr (OP == OP_APPLY) grad_tilde<D, T>(in.v, g, M);
+    else grad_tilde<D, T>(in.u, g, M);
     linear_stress_tilde<D, T>(M, mu, lam, S);
     scatter_rows<D, T>(S, g, s_sym, y);
-    return;
-  }
-  // Neo-Hookean
-  T uu[D + 1][D];
-#pragma unroll
-  for (int a = 0; a <= D; ++a) load_nodal<D, T>(U, nd[a], uu[a]);
-  T Ht[D][D];
-  grad_tilde<D, T>(uu, g, Ht);
-  NHState<D, T> st;
-  nh_state<D, T>(Ht, T(1) / g.det, st);
-  if (OP == OP_FORCE) {
-    T P[D][D];
-    nh_piola<D, T>(st, mu, lam, P);
-    const T s_sgn = (g.det < T(0) ? T(-1) : T(1)) / T(Fact<D>::v);   // vol / det
-    scatter_rows<D, T>(P, g, s_sgn, y);
   } else {
-    T vv[D + 1][D];
-#pragma unroll
-    for (int a = 0; a <= D; ++a) load_nodal<D, T>(V, nd[a], vv[a]);
-    if (mask & PFEM_MASK_IN) {
-#pragma unroll
-      for (int a = 0; a <= D; ++a) {
-        const int bits = ldg(m.dmask + nd[a]);
-#pragma unroll
-        for (int i = 0; i < D; ++i)
-          if (bits & (1 << i)) vv[a][i] = T(0);
-      }
+    T Ht[D][D];
+    grad_tilde<D, T>(in.u, g, Ht);
+    NHState<D, T> st;
+    nh_state<D, T>(Ht, T(1) / g.det, st);
+    if constexpr (OP == OP_FORCE) {
+      T P[D][D];
+      nh_piola<D, T>(st, mu, lam, P);
+      const T s_sgn = (g.det < T(0) ? T(-1) : T(1)) / T(Fact<D>::v);   // vol / det
+      scatter_rows<D, T>(P, g, s_sgn, y);
+    } else {
+      T dF[D][D], dP[D][D];
+      grad_tilde<D, T>(in.v, g, dF);
+      nh_dpiola<D, T>(st, mu, lam, dF, dP);
+      scatter_rows<D, T>(dP, g, s_sym, y);
     }
-    T dF[D][D], dP[D][D];
-    grad_tilde<D, T>(vv, g, dF);
-    nh_dpiola<D, T>(st, mu, lam, dF, dP);
-    scatter_rows<D, T>(dP, g, s_sym, y);
+  }
+}
+
+template <int D, typename T, int OP, bool NL>
+__device__ __forceinline__ void element_output(const MeshDev& m, const T* __restrict__ U,
+                                               const T* __restrict__ V, int mask, int e,
+                                               const int (&nd)[D + 1], T (&y)[D + 1][D]) {
+  ElemIn<D, T, OP, NL> in;
+  load_elem<D, T, OP, NL>(m, U, V, mask, e, nd, in);
+  element_compute<D, T, OP, NL>(in, y);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void lds_accumulate(T* acc, const int (&nd)[D + 1], int n0,
+                                               int nloc, const T (&y)[D + 1][D]) {
+#pragma unroll
+  for (int a = 0; a <= D; ++a) {
+    const int ln = nd[a] - n0;
+    if ((unsigned)ln < (unsigned)nloc) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) atomicAdd(&acc[ln * D + i], y[a][i]);
+    }
   }
 }
 
 // ------------------------------------------------------------ owner kernel
 // Workgroup = (task, node block).  Elements visited: the block's own sorted
 // range (smallest node inside the block) followed by its halo list
-// (elements owned by earlier blocks that reach into it).
-template <int D, typename T, int OP>
+// (elements owned by earlier blocks that reach into it).  Each thread keeps
+// two elements in flight: both connectivity rows are loaded, then all
+// gathers of both elements, then the arithmetic.
+template <int D, typename T, int OP, bool NL>
 __global__ void __launch_bounds__(kThreads)
 k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -196,19 +221,23 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   const int mask = tp->mask;
   const int n_own = br.y - br.x;
   const int total = n_own + (br.w - br.z);
-  for (int t = threadIdx.x; t < total; t += kThreads) {
-    const int e = t < n_own ? br.x + t : ldg(m.halo + br.z + (t - n_own));
-    int nd[D + 1];
-    load_conn<D>(m.conn, e, nd);
+  for (int t0 = threadIdx.x; t0 < total; t0 += 2 * kThreads) {
+    const int t1 = t0 + kThreads;
+    const bool two = t1 < total;
+    const int e0 = t0 < n_own ? br.x + t0 : ldg(m.halo + br.z + (t0 - n_own));
+    const int e1 = !two ? e0 : (t1 < n_own ? br.x + t1 : ldg(m.halo + br.z + (t1 - n_own)));
+    int nd0[D + 1], nd1[D + 1];
+    load_conn<D>(m.conn, e0, nd0);
+    load_conn<D>(m.conn, e1, nd1);
+    ElemIn<D, T, OP, NL> in0, in1;
+    load_elem<D, T, OP, NL>(m, U, V, mask, e0, nd0, in0);
+    load_elem<D, T, OP, NL>(m, U, V, mask, e1, nd1, in1);
     T y[D + 1][D];
-    element_output<D, T, OP>(m, U, V, mask, e, nd, y);
-#pragma unroll
-    for (int a = 0; a <= D; ++a) {
-      const int ln = nd[a] - n0;
-      if ((unsigned)ln < (unsigned)nloc) {
-#pragma unroll
-        for (int i = 0; i < D; ++i) atomicAdd(&acc[ln * D + i], y[a][i]);
-      }
+    element_compute<D, T, OP, NL>(in0, y);
+    lds_accumulate<D, T>(acc, nd0, n0, nloc, y);
+    if (two) {
+      element_compute<D, T, OP, NL>(in1, y);
+      lds_accumulate<D, T>(acc, nd1, n0, nloc, y);
     }
   }
   __syncthreads();
@@ -235,7 +264,7 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
 }
 
 // -------------------------------------------------- alternative scatters
-template <int D, typename T, int OP>
+template <int D, typename T, int OP, bool NL>
 __global__ void __launch_bounds__(kThreads) k_atomic(Task t) {
   const MeshDev& m = t.m;
   const T* U = static_cast<const T*>(t.u);
@@ -246,7 +275,7 @@ __global__ void __launch_bounds__(kThreads) k_atomic(Task t) {
     int nd[D + 1];
     load_conn<D>(m.conn, e, nd);
     T y[D + 1][D];
-    element_output<D, T, OP>(m, U, V, t.mask, e, nd, y);
+    element_output<D, T, OP, NL>(m, U, V, t.mask, e, nd, y);
 #pragma unroll
     for (int a = 0; a <= D; ++a)
 #pragma unroll
@@ -254,7 +283,7 @@ __global__ void __launch_bounds__(kThreads) k_atomic(Task t) {
   }
 }
 
-template <int D, typename T, int OP>
+template <int D, typename T, int OP, bool NL>
 __global__ void __launch_bounds__(kThreads) k_colored(Task t, int c0, int c1) {
   const MeshDev& m = t.m;
   const T* U = static_cast<const T*>(t.u);
@@ -266,7 +295,7 @@ __global__ void __launch_bounds__(kThreads) k_colored(Task t, int c0, int c1) {
     int nd[D + 1];
     load_conn<D>(m.conn, e, nd);
     T y[D + 1][D];
-    element_output<D, T, OP>(m, U, V, t.mask, e, nd, y);
+    element_output<D, T, OP, NL>(m, U, V, t.mask, e, nd, y);
 #pragma unroll
     for (int a = 0; a <= D; ++a)
 #pragma unroll
@@ -399,32 +428,32 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
 }
 
 // ---------------------------------------------------------------- launchers
-template <int D, typename T>
+template <int D, typename T, bool NL>
 static void launch_owner_typed(Ctx* ctx, int op, const Task* tasks, const int2* work,
                                int n_work, int bn_max) {
   const size_t sm = (size_t)bn_max * D * sizeof(T);
   dim3 grid(n_work), block(kThreads);
   switch (op) {
     case OP_APPLY:
-      hipLaunchKernelGGL((k_owner<D, T, OP_APPLY>), grid, block, sm, ctx->stream, tasks, work);
+      hipLaunchKernelGGL((k_owner<D, T, OP_APPLY, NL>), grid, block, sm, ctx->stream, tasks, work);
       break;
     case OP_FORCE:
-      hipLaunchKernelGGL((k_owner<D, T, OP_FORCE>), grid, block, sm, ctx->stream, tasks, work);
+      hipLaunchKernelGGL((k_owner<D, T, OP_FORCE, NL>), grid, block, sm, ctx->stream, tasks, work);
       break;
     default:
-      hipLaunchKernelGGL((k_owner<D, T, OP_DIAG>), grid, block, sm, ctx->stream, tasks, work);
+      hipLaunchKernelGGL((k_owner<D, T, OP_DIAG, NL>), grid, block, sm, ctx->stream, tasks, work);
       break;
   }
 }
 
-template <int D, typename T>
+template <int D, typename T, bool NL>
 static void launch_alt_typed(Ctx* ctx, int op, int mode, const Task& t,
                              const std::vector<int>* color_ptr) {
   const int ne = t.m.n_elems;
   const int grid = std::max(1, std::min((ne + kThreads - 1) / kThreads, 4096));
   launch_fill(ctx, sizeof(T) == 8 ? PFEM_FP64 : PFEM_FP32, t.y, (int64_t)t.m.n_nodes * D, 0.0);
   if (mode == PFEM_SCATTER_ATOMIC) {
-#define PFEM_ATOMIC(OPV) hipLaunchKernelGGL((k_atomic<D, T, OPV>), dim3(grid), dim3(kThreads), 0, ctx->stream, t)
+#define PFEM_ATOMIC(OPV) hipLaunchKernelGGL((k_atomic<D, T, OPV, NL>), dim3(grid), dim3(kThreads), 0, ctx->stream, t)
     if (op == OP_APPLY) PFEM_ATOMIC(OP_APPLY);
     else if (op == OP_FORCE) PFEM_ATOMIC(OP_FORCE);
     else PFEM_ATOMIC(OP_DIAG);
@@ -435,7 +464,7 @@ static void launch_alt_typed(Ctx* ctx, int op, int mode, const Task& t,
       const int cnt = cp[c + 1] - cp[c];
       if (cnt <= 0) continue;
       const int g = std::max(1, std::min((cnt + kThreads - 1) / kThreads, 4096));
-#define PFEM_COLOR(OPV) hipLaunchKernelGGL((k_colored<D, T, OPV>), dim3(g), dim3(kThreads), 0, ctx->stream, t, cp[c], cp[c + 1])
+#define PFEM_COLOR(OPV) hipLaunchKernelGGL((k_colored<D, T, OPV, NL>), dim3(g), dim3(kThreads), 0, ctx->stream, t, cp[c], cp[c + 1])
       if (op == OP_APPLY) PFEM_COLOR(OP_APPLY);
       else if (op == OP_FORCE) PFEM_COLOR(OP_FORCE);
       else PFEM_COLOR(OP_DIAG);
@@ -455,25 +484,37 @@ static int family_of(int op) {
   return op == OP_APPLY ? FAM_APPLY : (op == OP_FORCE ? FAM_FORCE : FAM_DIAG);
 }
 
-void launch_elem(Ctx* ctx, int dim, int prec, int op, int scatter_mode,
+template <bool NL>
+static void dispatch_owner(Ctx* ctx, int dim, int prec, int op, const Task* t, const int2* w,
+                           int n, int bn) {
+  if (dim == 2 && prec == PFEM_FP32) launch_owner_typed<2, float, NL>(ctx, op, t, w, n, bn);
+  else if (dim == 2) launch_owner_typed<2, double, NL>(ctx, op, t, w, n, bn);
+  else if (prec == PFEM_FP32) launch_owner_typed<3, float, NL>(ctx, op, t, w, n, bn);
+  else launch_owner_typed<3, double, NL>(ctx, op, t, w, n, bn);
+}
+
+template <bool NL>
+static void dispatch_alt(Ctx* ctx, int dim, int prec, int op, int mode, const Task& t,
+                         const std::vector<int>* cp) {
+  if (dim == 2 && prec == PFEM_FP32) launch_alt_typed<2, float, NL>(ctx, op, mode, t, cp);
+  else if (dim == 2) launch_alt_typed<2, double, NL>(ctx, op, mode, t, cp);
+  else if (prec == PFEM_FP32) launch_alt_typed<3, float, NL>(ctx, op, mode, t, cp);
+  else launch_alt_typed<3, double, NL>(ctx, op, mode, t, cp);
+}
+
+void launch_elem(Ctx* ctx, int dim, int prec, int op, bool nonlinear, int scatter_mode,
                  const Task* tasks_dev, const int2* work_dev, int n_work, int bn_max,
                  const Task* host_task_for_alt, const std::vector<int>* color_ptr) {
   hipEvent_t ev = nullptr;
   ctx->timing_begin(family_of(op), &ev);
   if (scatter_mode == PFEM_SCATTER_OWNER) {
     if (n_work > 0) {
-      if (dim == 2 && prec == PFEM_FP32) launch_owner_typed<2, float>(ctx, op, tasks_dev, work_dev, n_work, bn_max);
-      else if (dim == 2) launch_owner_typed<2, double>(ctx, op, tasks_dev, work_dev, n_work, bn_max);
-      else if (prec == PFEM_FP32) launch_owner_typed<3, float>(ctx, op, tasks_dev, work_dev, n_work, bn_max);
-      else launch_owner_typed<3, double>(ctx, op, tasks_dev, work_dev, n_work, bn_max);
+      if (nonlinear) dispatch_owner<true>(ctx, dim, prec, op, tasks_dev, work_dev, n_work, bn_max);
+      else dispatch_owner<false>(ctx, dim, prec, op, tasks_dev, work_dev, n_work, bn_max);
     }
   } else {
-    const Task& t = *host_task_for_alt;
-    const std::vector<int>* cp = color_ptr;
-    if (dim == 2 && prec == PFEM_FP32) launch_alt_typed<2, float>(ctx, op, scatter_mode, t, cp);
-    else if (dim == 2) launch_alt_typed<2, double>(ctx, op, scatter_mode, t, cp);
-    else if (prec == PFEM_FP32) launch_alt_typed<3, float>(ctx, op, scatter_mode, t, cp);
-    else launch_alt_typed<3, double>(ctx, op, scatter_mode, t, cp);
+    if (nonlinear) dispatch_alt<true>(ctx, dim, prec, op, scatter_mode, *host_task_for_alt, color_ptr);
+    else dispatch_alt<false>(ctx, dim, prec, op, scatter_mode, *host_task_for_alt, color_ptr);
   }
   PFEM_HIP(hipGetLastError());
   ctx->timing_end(family_of(op), ev);

@@ -33,11 +33,9 @@ struct Geo {
   T det;       // signed det J
 };
 
-template <int D, typename T>
-__device__ __forceinline__ void load_geometry(const double* __restrict__ X,
-                                              const int (&nd)[D + 1],
-                                              Geo<D, T>& g) {
-  double x[D + 1][D];
+template <int D>
+__device__ __forceinline__ void load_coords(const double* __restrict__ X,
+                                            const int (&nd)[D + 1], double (&x)[D + 1][D]) {
   if constexpr (D == 2) {
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
@@ -51,6 +49,10 @@ __device__ __forceinline__ void load_geometry(const double* __restrict__ X,
 #pragma unroll
       for (int i = 0; i < D; ++i) x[a][i] = ldg(X + (size_t)nd[a] * D + i);
   }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void geometry(const double (&x)[D + 1][D], Geo<D, T>& g) {
   T e[D][D];
 #pragma unroll
   for (int a = 0; a < D; ++a)
@@ -75,6 +77,14 @@ __device__ __forceinline__ void load_geometry(const double* __restrict__ X,
     }
     g.det = e[0][0] * g.c[0][0] + e[0][1] * g.c[0][1] + e[0][2] * g.c[0][2];
   }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void load_geometry(const double* __restrict__ X,
+                                              const int (&nd)[D + 1], Geo<D, T>& g) {
+  double x[D + 1][D];
+  load_coords<D>(X, nd, x);
+  geometry<D, T>(x, g);
 }
 
 // Gradient-like tensor M_ij = sum_{a>=1} (v_a - v_0)_i c_a,j.

@@ -168,7 +168,7 @@ void ctx_unref(Ctx* c);
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on ctx->stream.  `tasks_dev` points to n_tasks Task
 // structs in device memory; `work_dev` to n_work (task, block) pairs.
-void launch_elem(Ctx* ctx, int dim, int prec, int op, int scatter_mode,
+void launch_elem(Ctx* ctx, int dim, int prec, int op, bool nonlinear, int scatter_mode,
                  const Task* tasks_dev, const int2* work_dev, int n_work,
                  int bn_max, const Task* host_task_for_alt,
                  const std::vector<int>* color_ptr);

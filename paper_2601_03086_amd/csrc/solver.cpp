@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <tuple>
 
 namespace pfem {
 
@@ -94,17 +95,19 @@ static Task base_task(SlotRun* s) {
 
 struct Group {
   int dim, prec;
+  bool nl;
   std::vector<SlotRun*> slots;
 };
 
-// Groups slots by (dim, precision) so one templated launch covers a group.
+// Groups slots by (dim, precision, model kind) so one templated launch
+// covers a group.
 static std::vector<Group> group_by(const std::vector<SlotRun*>& v, bool force_fp64) {
-  std::map<std::pair<int, int>, Group> g;
+  std::map<std::tuple<int, int, int>, Group> g;
   for (SlotRun* s : v) {
     const int pr = force_fp64 ? PFEM_FP64 : s->prec;
-    auto key = std::make_pair(s->m->dim, pr);
+    auto key = std::make_tuple(s->m->dim, pr, s->nl ? 1 : 0);
     auto it = g.find(key);
-    if (it == g.end()) it = g.emplace(key, Group{s->m->dim, pr, {}}).first;
+    if (it == g.end()) it = g.emplace(key, Group{s->m->dim, pr, s->nl, {}}).first;
     it->second.slots.push_back(s);
   }
   std::vector<Group> out;
@@ -205,7 +208,7 @@ static void do_force(Ctx* ctx, const std::vector<SlotRun*>& v, bool at_lift, int
       ts.push_back(t);
     }
     Uploaded u = upload_group(ctx, g, ts);
-    launch_elem(ctx, g.dim, PFEM_FP64, OP_FORCE, PFEM_SCATTER_OWNER, u.tasks, u.work,
+    launch_elem(ctx, g.dim, PFEM_FP64, OP_FORCE, g.nl, PFEM_SCATTER_OWNER, u.tasks, u.work,
                 u.n_work, u.bn_max, nullptr, nullptr);
     launch_reduce_store(ctx, u.tasks, (int)ts.size());
     *nl += 2;
@@ -246,7 +249,7 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
         s->minv_valid = true;
       }
       Uploaded u = upload_group(ctx, g, ts);
-      launch_elem(ctx, g.dim, g.prec, OP_DIAG, PFEM_SCATTER_OWNER, u.tasks, u.work, u.n_work,
+      launch_elem(ctx, g.dim, g.prec, OP_DIAG, g.nl, PFEM_SCATTER_OWNER, u.tasks, u.work, u.n_work,
                   u.bn_max, nullptr, nullptr);
       ++*nl;
     }
@@ -287,7 +290,7 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
     ctx->cur_key = key;
     for (int it = 0; it < k; ++it) {
       ctx->cur_it = it;
-      launch_elem(ctx, g.dim, g.prec, OP_APPLY, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
+      launch_elem(ctx, g.dim, g.prec, OP_APPLY, g.nl, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
                   ua.n_work, ua.bn_max, nullptr, nullptr);
       launch_pcg_update(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
       launch_pcg_direction(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
