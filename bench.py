@@ -190,6 +190,60 @@ def run_kv_sweep(sizes):
         mesh.close()
 
 
+def run_kv_large(spec, reps=50):
+    """K.v at working sets far beyond the caches: structured-topology plates
+    and boxes with jittered interior nodes and a random node relabelling
+    (so the library's RCM does the ordering work).  spec: "2d:NX,3d:NX"."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2601_03086_amd import core
+    ctx = core.Context(0)
+    for item in spec.split(","):
+        kind, n = item.split(":")
+        n = int(n)
+        t0 = time.perf_counter()
+        if kind == "2d":
+            prob = synth.structured_plate(n, n, seed=7)
+        else:
+            prob = synth.structured_box(n, n, 4 * n, seed=7)
+        t_gen = time.perf_counter() - t0
+        print(f"# generated {kind} {prob.n_elems} elements in {t_gen:.1f}s", file=sys.stderr,
+              flush=True)
+        t0 = time.perf_counter()
+        mesh = core.Mesh.from_problem(ctx, prob)
+        t_prep = time.perf_counter() - t0
+        print(f"# preprocessed in {t_prep:.1f}s", file=sys.stderr, flush=True)
+        d = prob.dim
+        for prec in ("fp32", "fp64"):
+            s = 4 if prec == "fp32" else 8
+            dt = torch.float32 if prec == "fp32" else torch.float64
+            x = mesh.permute(torch.randn(prob.n_dof, dtype=dt, device="cuda"), True, prec)
+            y = torch.empty_like(x)
+            for _ in range(5):
+                mesh.apply_K(x, prec=prec, layout="internal", out=y)
+            ctx.set_timing([FAM_APPLY])
+            ctx.reset_timing()
+            for _ in range(reps):
+                mesh.apply_K(x, prec=prec, layout="internal", out=y)
+            nl, ms = ctx.kernel_time(FAM_APPLY)
+            ctx.set_timing(())
+            us = ms / nl * 1e3
+            b_alg = alg_bytes_kv(prob.n_elems, prob.n_nodes, d, s=s, s_m=s)
+            print(json.dumps({
+                "mesh": f"{kind} {prob.n_elems} elems {prob.n_nodes} nodes",
+                "prec": prec, "block_nodes": mesh.info["block_nodes"],
+                "visits_per_elem": round(mesh.info["owner_elem_visits"] / prob.n_elems, 3),
+                "alg_bytes": b_alg, "avg_us": round(us, 2),
+                "alg_GBps": round(b_alg / (us * 1e-6) / 1e9, 1),
+                "frac_hbm": round(b_alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "GDOF_s": round(prob.n_dof / (us * 1e-6) / 1e9, 2),
+                "gen_s": round(t_gen, 1), "prep_s": round(t_prep, 1)}), flush=True)
+            del x, y
+        mesh.close()
+        del prob
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +256,8 @@ def main():
     ap.add_argument("--kv-sweep", default=None,
                     help="comma-separated owner-block sizes to time K.v with")
     ap.add_argument("--block-nodes", type=int, default=0)
+    ap.add_argument("--kv-large", default=None,
+                    help='e.g. "2d:2000,3d:60": K.v roofline sweep on large meshes')
     args = ap.parse_args()
     if args.cpu_baseline_worker:
         cpu_baseline_worker()
@@ -219,6 +275,9 @@ def main():
         return
     if args.kv_sweep:
         run_kv_sweep([int(s) for s in args.kv_sweep.split(",")])
+        return
+    if args.kv_large:
+        run_kv_large(args.kv_large)
         return
     import torch
     t_setup = time.perf_counter()
