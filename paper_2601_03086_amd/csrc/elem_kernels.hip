@@ -14,6 +14,8 @@
 //
 // Alternatives for comparison: a device-wide atomic scatter over all
 // elements, and a colour-by-colour deterministic scatter.
+#include <type_traits>
+
 #include "elem_math.h"
 #include "pfem_internal.h"
 #include "reduce.h"
@@ -180,18 +182,25 @@ __device__ __forceinline__ void element_output(const MeshDev& m, const T* __rest
   element_compute<D, T, OP, NL>(in, y);
 }
 
-template <int D, typename T>
-__device__ __forceinline__ void lds_accumulate(T* acc, const int (&nd)[D + 1], int n0,
+template <int D, typename T, typename A>
+__device__ __forceinline__ void lds_accumulate(A* acc, const int (&nd)[D + 1], int n0,
                                                int nloc, const T (&y)[D + 1][D]) {
 #pragma unroll
   for (int a = 0; a <= D; ++a) {
     const int ln = nd[a] - n0;
     if ((unsigned)ln < (unsigned)nloc) {
 #pragma unroll
-      for (int i = 0; i < D; ++i) atomicAdd(&acc[ln * D + i], y[a][i]);
+      for (int i = 0; i < D; ++i) atomicAdd(&acc[ln * D + i], (A)y[a][i]);
     }
   }
 }
+
+// LDS accumulator type of the owner kernel.
+#ifndef PFEM_ACC_F64
+#define PFEM_ACC_F64 1
+#endif
+template <typename T>
+using AccT = typename std::conditional<PFEM_ACC_F64 != 0, double, T>::type;
 
 // ------------------------------------------------------------ owner kernel
 // Workgroup = (task, node block).  Elements visited: the block's own sorted
@@ -212,9 +221,10 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   const int n0 = blk * m.bn;
   const int nloc = min(m.bn, m.n_nodes - n0);
   const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
-  T* acc = reinterpret_cast<T*>(smem_raw);
+  using A = AccT<T>;
+  A* acc = reinterpret_cast<A*>(smem_raw);
   const int nown = nloc * D;
-  for (int i = threadIdx.x; i < nown; i += kThreads) acc[i] = T(0);
+  for (int i = threadIdx.x; i < nown; i += kThreads) acc[i] = A(0);
   __syncthreads();
   const T* U = static_cast<const T*>(tp->u);
   const T* V = static_cast<const T*>(tp->v);
@@ -234,10 +244,10 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
     load_elem<D, T, OP, NL>(m, U, V, mask, e1, nd1, in1);
     T y[D + 1][D];
     element_compute<D, T, OP, NL>(in0, y);
-    lds_accumulate<D, T>(acc, nd0, n0, nloc, y);
+    lds_accumulate<D, T, A>(acc, nd0, n0, nloc, y);
     if (two) {
       element_compute<D, T, OP, NL>(in1, y);
-      lds_accumulate<D, T>(acc, nd1, n0, nloc, y);
+      lds_accumulate<D, T, A>(acc, nd1, n0, nloc, y);
     }
   }
   __syncthreads();
@@ -247,7 +257,7 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   const size_t g0 = (size_t)n0 * D;
   for (int i = threadIdx.x; i < nown; i += kThreads) {
     const size_t gi = g0 + i;
-    T val = acc[i];
+    T val = (T)acc[i];
     const bool con = (ldg(m.dmask + n0 + i / D) >> (i % D)) & 1;
     if (OP == OP_FORCE) val -= (T)(tp->fscale * ldg(m.fext + gi));
     if (OP == OP_DIAG) {
@@ -431,7 +441,7 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
 template <int D, typename T, bool NL>
 static void launch_owner_typed(Ctx* ctx, int op, const Task* tasks, const int2* work,
                                int n_work, int bn_max) {
-  const size_t sm = (size_t)bn_max * D * sizeof(T);
+  const size_t sm = (size_t)bn_max * D * sizeof(AccT<T>);
   dim3 grid(n_work), block(kThreads);
   switch (op) {
     case OP_APPLY:
