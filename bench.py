@@ -144,9 +144,19 @@ def setup(args):
     return prob, ctx, mesh, u0_dev
 
 
-def run_kv_only(n):
+def run_kv_only(n, mesh_spec=None):
     import torch
-    prob, ctx, mesh, u0 = setup(None)
+    if mesh_spec:
+        import synth
+        from paper_2601_03086_amd import core
+        kind, nx = mesh_spec.split(":")
+        nx = int(nx)
+        prob = (synth.structured_plate(nx, nx, seed=7) if kind == "2d"
+                else synth.structured_box(nx, nx, 4 * nx, seed=7))
+        ctx = core.Context(0)
+        mesh = core.Mesh.from_problem(ctx, prob)
+    else:
+        prob, ctx, mesh, u0 = setup(None)
     x = mesh.permute(torch.randn(prob.n_dof, dtype=torch.float32, device="cuda"),
                      True, "fp32")
     y = torch.empty_like(x)
@@ -256,6 +266,7 @@ def main():
     ap.add_argument("--kv-sweep", default=None,
                     help="comma-separated owner-block sizes to time K.v with")
     ap.add_argument("--block-nodes", type=int, default=0)
+    ap.add_argument("--kv-mesh", default=None, help='mesh for --kv-only, e.g. "3d:40"')
     ap.add_argument("--kv-large", default=None,
                     help='e.g. "2d:2000,3d:60": K.v roofline sweep on large meshes')
     args = ap.parse_args()
@@ -271,7 +282,7 @@ def main():
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.kv_only:
-        run_kv_only(args.kv_only)
+        run_kv_only(args.kv_only, args.kv_mesh)
         return
     if args.kv_sweep:
         run_kv_sweep([int(s) for s in args.kv_sweep.split(",")])

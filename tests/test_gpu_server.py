@@ -1,0 +1,120 @@
+"""Serving: continuous batching of solve requests on one GPU.
+
+Each request's result is the same alone and in the mix (within the solve
+tolerance), admission never exceeds the memory budget or the slot count,
+and cancellation / oversize requests are reported.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import solve as osolve
+from tests.gpu_util import rel, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch_cuda()
+    from paper_2601_03086_amd import core
+    c = core.Context(0)
+    yield c
+    c.close()
+
+
+def _requests():
+    reqs = []
+    for k in range(4):
+        p = synth.plate_problem(200 + k, 300 + k, 400 + k, n_holes=3,
+                                target_tris=2000 + 1500 * k)
+        ud, _ = osolve.solve_linear(p, method="direct")
+        u0 = synth.warm_start_guess(ud, p.coords, p.dir_nodes, seed=500 + k)
+        reqs.append((p, u0 if k % 2 == 0 else None, ud))
+    for k in range(2):
+        p = synth.box_problem(600 + k, 700 + k, n_per_unit=4, n_voids=2, uz=0.2,
+                              n_load_steps=2)
+        reqs.append((p, None, None))
+    return reqs
+
+
+def _wait(srv, ids, timeout=120.0):
+    done = set()
+    t0 = time.time()
+    while len(done) < len(ids):
+        done.update(srv.poll())
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"server finished {len(done)} of {len(ids)}")
+        time.sleep(0.002)
+    return done
+
+
+def test_alone_equals_in_the_mix(ctx):
+    from paper_2601_03086_amd import core
+    reqs = _requests()
+    host_meshes = [core.Mesh.from_problem(None, p) for p, _, _ in reqs]
+    dev_meshes = [core.Mesh.from_problem(ctx, p) for p, _, _ in reqs]
+    opts = dict(tol=1e-9, prec="fp32", n_load_steps=2)
+    alone = [m.solve(u0=u0, **opts) for m, (_, u0, _) in zip(dev_meshes, reqs)]
+    budget = 64 << 20
+    srv = core.Server(ctx, budget, max_slots=3)
+    for i, (m, (_, u0, _)) in enumerate(zip(host_meshes, reqs)):
+        srv.submit(i, m, u0=u0, **opts)
+    _wait(srv, list(range(len(reqs))))
+    st = srv.stats()
+    assert st["peak_live"] <= 3 and st["peak_bytes"] <= budget
+    assert st["completed"] == len(reqs)
+    for i, (p, u0, ud) in enumerate(reqs):
+        u, r = srv.result(i)
+        ua, ra, _ = alone[i]
+        print(i, r["status_name"], r["kv_count"], ra["kv_count"], flush=True)
+        assert r["status"] == 0 and ra["status"] == 0
+        assert r["rel_residual_final"] <= 1e-9
+        assert rel(u, ua) <= 1e-6
+        if ud is not None:
+            assert rel(u, ud) <= 1e-6
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+    srv.close()
+
+
+def test_admission_waits_for_memory(ctx):
+    """A budget that fits one request at a time serialises the stream."""
+    from paper_2601_03086_amd import core
+    reqs = _requests()[:3]
+    host = [core.Mesh.from_problem(None, p) for p, _, _ in reqs]
+    need = max(m.info["device_bytes"] + m.info["solve_bytes_fp32"] for m in host)
+    srv = core.Server(ctx, need + 1024, max_slots=8)
+    for i, m in enumerate(host):
+        srv.submit(i, m, u0=reqs[i][1], tol=1e-8, prec="fp32")
+    _wait(srv, [0, 1, 2])
+    st = srv.stats()
+    assert st["peak_live"] == 1 and st["peak_bytes"] <= need + 1024
+    times = [srv.result(i)[1] for i in range(3)]
+    for a, b in zip(times, times[1:]):
+        assert b["t_admit"] >= a["t_done"] - 1e-3
+    srv.close()
+
+
+def test_oversize_and_cancel(ctx):
+    from paper_2601_03086_amd import _lib as L
+    from paper_2601_03086_amd import core
+    p = synth.plate_problem(801, 802, 803, n_holes=4, target_tris=30000)
+    m = core.Mesh.from_problem(None, p)
+    srv = core.Server(ctx, 1 << 20, max_slots=2)       # 1 MiB: too small
+    with pytest.raises(L.PfemError) as ei:
+        srv.submit(0, m, tol=1e-8)
+    assert ei.value.status == L.PFEM_E_OOM
+    srv.close()
+    srv = core.Server(ctx, 1 << 30, max_slots=1)
+    srv.submit(1, m, tol=1e-13, prec="fp64", max_iter=10 ** 7)   # long
+    srv.submit(2, m, tol=1e-8)                                   # queued behind it
+    time.sleep(0.05)
+    srv.cancel(1)
+    srv.cancel(2)
+    _wait(srv, [1, 2], timeout=60)
+    for i in (1, 2):
+        _, r = srv.result(i)
+        assert r["status"] == L.PFEM_E_CANCELLED
+    srv.close()
