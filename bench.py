@@ -156,7 +156,10 @@ def run_kv_only(n, mesh_spec=None):
         ctx = core.Context(0)
         mesh = core.Mesh.from_problem(ctx, prob)
     else:
-        prob, ctx, mesh, u0 = setup(None)
+        from paper_2601_03086_amd import core
+        prob = c2_problem()
+        ctx = core.Context(0)
+        mesh = core.Mesh.from_problem(ctx, prob)
     x = mesh.permute(torch.randn(prob.n_dof, dtype=torch.float32, device="cuda"),
                      True, "fp32")
     y = torch.empty_like(x)
