@@ -9,15 +9,17 @@ from a synthetic network prediction (reference solution + 1% smooth noise).
 Inputs are resident in device memory before the timed region.
 
 value = sum over timed solves of (K.v products * n_dof) / wall time, in
-GDOF/s.  The roofline object describes the K.v kernel alone: algorithmic
-bytes per launch divided by its average launch time measured with HIP
+GDOF/s.  The PCG runs in its fused form: one launch per iteration does the
+element pass (K.v) and every vector update.  The roofline object
+describes that kernel: algorithmic bytes per launch (K.v inputs plus the
+fused vector pass) divided by its average launch time, measured with HIP
 events on the library stream during the timed solves.
 
 Other modes (not the default line):
-  --kv-only N        N back-to-back K.v launches (for rocprofv3 counters)
+  --kv-only N        N back-to-back K.v launches, or with --kv-kernel fused
+                     about N fused PCG iterations (for rocprofv3 counters)
   --parse-pmc DIR    turn rocprofv3 FETCH_SIZE / WRITE_SIZE CSVs into the
                      traffic summary under profiles/
-  --serve            serving-stream measurement (see --serve-requests)
 """
 import argparse
 import glob
@@ -34,10 +36,12 @@ sys.path.insert(0, ROOT)
 METRIC = ("Matrix-free K·v GDOF/s (% HBM roofline); solves/s + p99 latency at "
           "1e-8 rel")
 HBM_PEAK_GBS = 8000.0
-FAM_APPLY, FAM_FORCE, FAM_ENERGY, FAM_DIAG, FAM_UPDATE, FAM_DIRECTION = range(6)
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "kv_fp32_plate200k_traffic.json")
+FAM_APPLY, FAM_FORCE, FAM_ENERGY, FAM_DIAG, FAM_UPDATE, FAM_DIRECTION, FAM_FUSED = range(7)
+FAM_NAMES = ["apply", "force", "energy", "diag", "update", "direction", "fused_iter"]
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pcg_iter_fp32_plate200k_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2601_03086_amd", "csrc", "elem_kernels.hip")
-KERNEL_NAME = "k_owner<2, float, 0>"
+KERNEL_NAME = "k_fcg<2, float, false>"
+KERNEL_MATCH = "k_fcg<2, float, false>"
 
 
 def kernel_hash():
@@ -56,6 +60,14 @@ def alg_bytes_kv(n_elems, n_nodes, dim, s=4, s_m=4):
     """Algorithmic bytes of one K.v: connectivity, one material value per
     element, coordinates, x read and y written once."""
     return 4 * (dim + 1) * n_elems + s_m * n_elems + 3 * dim * s * n_nodes
+
+
+def alg_bytes_fused(n_elems, n_nodes, dim, s=4, s_m=4):
+    """Algorithmic bytes of one fused PCG iteration: connectivity, one
+    material value per element and the coordinates, each once; the node
+    records {r, w, s, M^-1} read once and {r, w, s} written once; p and d
+    read and written once."""
+    return 4 * (dim + 1) * n_elems + s_m * n_elems + (1 + 4 + 3 + 4) * dim * s * n_nodes
 
 
 # --------------------------------------------------------------- CPU baseline
@@ -109,8 +121,8 @@ def parse_pmc(out_dir):
             name = row.get("Kernel_Name", "")
             ctr = row.get("Counter_Name", "")
             v = float(row.get("Counter_Value", 0))
-            if "k_owner" in name and "float" in name and "0>" in name:
-                key = "kv"
+            if KERNEL_MATCH in name:
+                key = "kernel"
             elif "copy" in name.lower() or "elementwise" in name.lower():
                 key = "copy"
             else:
@@ -144,7 +156,10 @@ def setup(args):
     return prob, ctx, mesh, u0_dev
 
 
-def run_kv_only(n, mesh_spec=None):
+def run_kv_only(n, mesh_spec=None, kernel="owner"):
+    """n launches of the K.v owner kernel (kernel="owner") or about n fused
+    PCG iterations of a capped zero-start FP32 solve (kernel="fused"), then
+    five 256 MiB copies that calibrate byte counters."""
     import torch
     if mesh_spec:
         import synth
@@ -160,11 +175,14 @@ def run_kv_only(n, mesh_spec=None):
         prob = c2_problem()
         ctx = core.Context(0)
         mesh = core.Mesh.from_problem(ctx, prob)
-    x = mesh.permute(torch.randn(prob.n_dof, dtype=torch.float32, device="cuda"),
-                     True, "fp32")
-    y = torch.empty_like(x)
-    for _ in range(n):
-        mesh.apply_K(x, prec="fp32", layout="internal", out=y)
+    if kernel == "fused":
+        mesh.solve(u0=None, tol=1e-8, prec="fp32", max_iter=n, history_cap=1)
+    else:
+        x = mesh.permute(torch.randn(prob.n_dof, dtype=torch.float32, device="cuda"),
+                         True, "fp32")
+        y = torch.empty_like(x)
+        for _ in range(n):
+            mesh.apply_K(x, prec="fp32", layout="internal", out=y)
     a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")   # 256 MiB copy
     b = torch.empty_like(a)
     for _ in range(5):
@@ -270,6 +288,8 @@ def main():
                     help="comma-separated owner-block sizes to time K.v with")
     ap.add_argument("--block-nodes", type=int, default=0)
     ap.add_argument("--kv-mesh", default=None, help='mesh for --kv-only, e.g. "3d:40"')
+    ap.add_argument("--kv-kernel", default="owner", choices=["owner", "fused"],
+                    help="--kv-only: K.v launches or fused PCG iterations")
     ap.add_argument("--kv-large", default=None,
                     help='e.g. "2d:2000,3d:60": K.v roofline sweep on large meshes')
     args = ap.parse_args()
@@ -285,7 +305,7 @@ def main():
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.kv_only:
-        run_kv_only(args.kv_only, args.kv_mesh)
+        run_kv_only(args.kv_only, args.kv_mesh, args.kv_kernel)
         return
     if args.kv_sweep:
         run_kv_sweep([int(s) for s in args.kv_sweep.split(",")])
@@ -306,7 +326,9 @@ def main():
         mesh.solve(u0=u0, **opts)
     # zero-start reference solve (not timed in the headline)
     _, rz, _ = mesh.solve(u0=None, **opts)
-    ctx.set_timing([FAM_APPLY])
+    # the dominant kernel's duration: HIP events around one launch in 16 of
+    # the timed solves (sampling keeps the event pairs from perturbing them)
+    ctx.set_timing([FAM_FUSED], sample_every=16)
     ctx.reset_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -321,23 +343,32 @@ def main():
         reps.append(rep)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    n_apply, ms_apply = ctx.kernel_time(FAM_APPLY)
+    n_apply, ms_apply = ctx.kernel_time(FAM_FUSED)
     # per-family breakdown from two extra solves with every family timed
-    ctx.set_timing(range(6))
+    ctx.set_timing(range(7))
     ctx.reset_timing()
     for _ in range(2):
         mesh.solve(u0=u0, **opts)
-    fam_names = ["apply", "force", "energy", "diag", "update", "direction"]
     breakdown = {}
-    for f, nm in enumerate(fam_names):
+    for f, nm in enumerate(FAM_NAMES):
         n_f, ms_f = ctx.kernel_time(f)
         if n_f:
             breakdown[nm] = {"launches_per_solve": n_f / 2, "avg_us": round(ms_f / n_f * 1e3, 3)}
     ctx.set_timing(())
+    # the same warm solves with the three-launch PCG loop, for comparison
+    torch.cuda.synchronize()
+    tc0 = time.perf_counter()
+    n_cls = max(2, args.steps // 4)
+    kv_cls = 0
+    for _ in range(n_cls):
+        _, rc, _ = mesh.solve(u0=u0, krylov="classic", **opts)
+        kv_cls += rc["kv_count"]
+    torch.cuda.synchronize()
+    t_cls = time.perf_counter() - tc0
     assert all(r["status"] == 0 and r["rel_residual_final"] <= 1e-8 for r in reps), reps[-1]
     value = kv_total * prob.n_dof / t / 1e9
     avg_ms = ms_apply / max(n_apply, 1)
-    b_alg = alg_bytes_kv(prob.n_elems, prob.n_nodes, 2)
+    b_alg = alg_bytes_fused(prob.n_elems, prob.n_nodes, 2)
     achieved = b_alg / (avg_ms * 1e-3) / 1e9
     lat_sorted = sorted(lat)
     res = {
@@ -378,6 +409,9 @@ def main():
                              "p99": round(lat_sorted[min(len(lat) - 1,
                                                          int(0.99 * len(lat)))] * 1e3, 3)},
         "kernel_breakdown": breakdown,
+        "classic_pcg": {"ms_per_solve": round(t_cls / n_cls * 1e3, 3),
+                        "GDOF_s": round(kv_cls * prob.n_dof / t_cls / 1e9, 3),
+                        "kv_per_solve": kv_cls / n_cls},
         "kv_per_solve_warm": kv_total / args.steps,
         "kv_per_solve_zero": rz["kv_count"],
         "outer_sweeps_warm": reps[-1]["outer_sweeps"],

@@ -127,9 +127,13 @@ const char* pfem_version(void);
  * bracketed by HIP events on the context stream and its elapsed time is
  * accumulated per family.  Families: 0 = K.v / Hessian-vector apply,
  * 1 = internal force, 2 = energy, 3 = Jacobi diagonal, 4 = PCG vector
- * update, 5 = direction update.  `family_mask`: bit f times family f
+ * update, 5 = direction update, 6 = pipelined PCG iteration (matvec and
+ * vector updates in one launch).  `family_mask`: bit f times family f
  * (0 = off).  Reading synchronises the stream. */
 pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int family_mask);
+/* Time only every `every`-th launch of each timed family (default 1), so
+ * that the event pairs barely perturb a long launch sequence. */
+pfem_status pfem_ctx_set_timing_sample(pfem_ctx* ctx, int every);
 pfem_status pfem_ctx_kernel_time(pfem_ctx* ctx, int family, int64_t* launches,
                                  double* total_ms);
 pfem_status pfem_ctx_reset_timing(pfem_ctx* ctx);
@@ -234,6 +238,17 @@ pfem_status pfem_batch_hvp(pfem_batch* b, int prec, int mask, const void* u,
                            const void* v, void* y);
 
 /* --------------------------------------------------------------- solves */
+/* PCG formulations (same Krylov iterates in exact arithmetic):
+ * CLASSIC  three launches per iteration (apply; update; direction), the
+ *          textbook recurrences (Saad, Alg. 9.1);
+ * FUSED    one launch per iteration: the Chronopoulos-Gear form, whose two
+ *          inner products come from one phase, with the pointwise vector
+ *          update evaluated by every workgroup at the nodes it gathers, so
+ *          the element pass and all vector updates share a kernel (one
+ *          extra matvec per inner solve, w = A u at the start);
+ * AUTO     FUSED in FP32 mode, CLASSIC in FP64 mode. */
+enum { PFEM_KRYLOV_AUTO = 0, PFEM_KRYLOV_CLASSIC = 1, PFEM_KRYLOV_FUSED = 2 };
+
 typedef struct {
   double tol;           /* relative residual target |r_f| / |r_f(lifted)| (App. B) */
   double tol_fine;      /* skip iterating if the guess is already below (Sec. 'Warm-start'); 0 = off */
@@ -243,6 +258,7 @@ typedef struct {
   int32_t prec;         /* PFEM_FP64 or PFEM_FP32 (FP32 Krylov, FP64 outer residual) */
   int32_t record_history;
   double inner_rtol;    /* FP32 mode: residual reduction per refinement sweep; 0 = 1e-4 */
+  int32_t krylov;       /* PFEM_KRYLOV_*: PCG formulation of the inner solves */
 } pfem_solve_opts;
 
 typedef struct {

@@ -28,6 +28,7 @@ PFEM_LIN_PLANE_STRESS, PFEM_LIN_PLANE_STRAIN, PFEM_LIN_3D = 0, 1, 2
 PFEM_NH_PLANE_STRAIN, PFEM_NH_3D = 3, 4
 PFEM_PARAM_E_NU, PFEM_PARAM_LAME = 0, 1
 PFEM_FP64, PFEM_FP32 = 0, 1
+PFEM_KRYLOV_AUTO, PFEM_KRYLOV_CLASSIC, PFEM_KRYLOV_FUSED = 0, 1, 2
 PFEM_SCATTER_OWNER, PFEM_SCATTER_COLORED, PFEM_SCATTER_ATOMIC = 0, 1, 2
 PFEM_LAYOUT_USER, PFEM_LAYOUT_INTERNAL = 0, 1
 PFEM_MASK_NONE, PFEM_MASK_OUT, PFEM_MASK_IN = 0, 1, 2
@@ -51,7 +52,8 @@ class pfem_mesh_info(C.Structure):
 class pfem_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("tol_fine", C.c_double), ("max_iter", C.c_int32),
                 ("n_load_steps", C.c_int32), ("max_newton", C.c_int32), ("prec", C.c_int32),
-                ("record_history", C.c_int32), ("inner_rtol", C.c_double)]
+                ("record_history", C.c_int32), ("inner_rtol", C.c_double),
+                ("krylov", C.c_int32)]
 
 
 class pfem_solve_report(C.Structure):
@@ -85,6 +87,7 @@ PROTOTYPES = {
     "pfem_last_error": (C.c_char_p, []),
     "pfem_version": (C.c_char_p, []),
     "pfem_ctx_set_timing": (_I32, [_VP, C.c_int]),
+    "pfem_ctx_set_timing_sample": (_I32, [_VP, C.c_int]),
     "pfem_ctx_kernel_time": (_I32, [_VP, C.c_int, C.POINTER(_I64), C.POINTER(_D)]),
     "pfem_ctx_reset_timing": (_I32, [_VP]),
     "pfem_ctx_synchronize": (_I32, [_VP]),

@@ -56,6 +56,8 @@ PREC = {"fp64": L.PFEM_FP64, "fp32": L.PFEM_FP32, L.PFEM_FP64: L.PFEM_FP64,
 SCATTER = {"owner": L.PFEM_SCATTER_OWNER, "colored": L.PFEM_SCATTER_COLORED,
            "atomic": L.PFEM_SCATTER_ATOMIC}
 LAYOUT = {"user": L.PFEM_LAYOUT_USER, "internal": L.PFEM_LAYOUT_INTERNAL}
+KRYLOV = {"auto": L.PFEM_KRYLOV_AUTO, "classic": L.PFEM_KRYLOV_CLASSIC,
+          "fused": L.PFEM_KRYLOV_FUSED}
 
 
 def _ptr(a):
@@ -94,10 +96,11 @@ class Context:
 
     __del__ = close
 
-    def set_timing(self, families=(0, 1, 2, 3, 4, 5)):
+    def set_timing(self, families=(0, 1, 2, 3, 4, 5, 6), sample_every=1):
         mask = 0
         for f in families or ():
             mask |= 1 << f
+        check(L.pfem_ctx_set_timing_sample(self.h, int(sample_every)))
         check(L.pfem_ctx_set_timing(self.h, mask))
 
     def reset_timing(self):
@@ -234,7 +237,7 @@ class Mesh:
     # ------------------------------------------------------------ solve
     @staticmethod
     def opts(tol=1e-8, prec="fp32", tol_fine=0.0, max_iter=0, n_load_steps=10,
-             max_newton=50, record_history=1, inner_rtol=1e-4):
+             max_newton=50, record_history=1, inner_rtol=1e-4, krylov="auto"):
         o = L.pfem_solve_opts()
         L.pfem_solve_opts_default(C.byref(o))
         o.tol = tol
@@ -245,6 +248,7 @@ class Mesh:
         o.prec = PREC[prec]
         o.record_history = record_history
         o.inner_rtol = inner_rtol
+        o.krylov = KRYLOV[krylov]
         return o
 
     @_on_stream

@@ -96,6 +96,16 @@ pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int family_mask) {
   PFEM_TRY_END
 }
 
+pfem_status pfem_ctx_set_timing_sample(pfem_ctx* ctx, int every) {
+  PFEM_TRY_BEGIN
+  require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
+  require(every >= 1, PFEM_E_INVALID_ARG, "sampling interval must be >= 1");
+  ctx->c->drain_timing();
+  ctx->c->sample_every = every;
+  for (int i = 0; i < FAM_COUNT; ++i) ctx->c->fam_seen[i] = 0;
+  PFEM_TRY_END
+}
+
 pfem_status pfem_ctx_kernel_time(pfem_ctx* ctx, int family, int64_t* launches,
                                  double* total_ms) {
   PFEM_TRY_BEGIN
@@ -238,8 +248,8 @@ pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* o) {
   o->bandwidth_rcm = m->bw_rcm;
   o->owner_elem_visits = m->owner_visits;
   o->device_bytes = m->finalized ? mesh_device_bytes(m) : 0;
-  o->solve_bytes_fp32 = m->finalized ? solve_bytes(m, PFEM_FP32) : 0;
-  o->solve_bytes_fp64 = m->finalized ? solve_bytes(m, PFEM_FP64) : 0;
+  o->solve_bytes_fp32 = m->finalized ? solve_bytes(m, PFEM_FP32, true) : 0;
+  o->solve_bytes_fp64 = m->finalized ? solve_bytes(m, PFEM_FP64, false) : 0;
   o->f_ext_norm = m->fext_norm;
   PFEM_TRY_END
 }
@@ -588,6 +598,7 @@ void pfem_solve_opts_default(pfem_solve_opts* o) {
   o->prec = PFEM_FP32;
   o->record_history = 1;
   o->inner_rtol = 1e-4;
+  o->krylov = PFEM_KRYLOV_AUTO;
 }
 
 pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o, double* u_out,
@@ -599,6 +610,8 @@ pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
   require(o->tol > 0 && std::isfinite(o->tol), PFEM_E_INVALID_ARG, "tol must be > 0");
   require(o->prec == PFEM_FP64 || o->prec == PFEM_FP32, PFEM_E_INVALID_ARG, "bad precision");
   require(history_cap >= 0, PFEM_E_INVALID_ARG, "history_cap < 0");
+  require(o->krylov >= PFEM_KRYLOV_AUTO && o->krylov <= PFEM_KRYLOV_FUSED,
+          PFEM_E_INVALID_ARG, "bad krylov formulation");
   Ctx* ctx = m->ctx;
   const int64_t nd = m->n_dof();
   const int64_t hcap = (o->record_history && history) ? history_cap : 0;
@@ -606,10 +619,11 @@ pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
   // (re)use the mesh's cached solver state
   std::unique_ptr<SolveState>& cached = m->solve_state;
   const int prec = o->prec;
-  if (!cached || cached->prec != prec || cached->hist_cap < hcap) {
+  const bool fused = krylov_fused(*o);
+  if (!cached || cached->prec != prec || cached->hist_cap < hcap || cached->fused != fused) {
     cached.reset();
     cached.reset(new SolveState());
-    cached->alloc(prec, nd, m->n_blocks, std::max<int64_t>(hcap, 1024), m->nonlinear);
+    cached->alloc(prec, nd, m->n_blocks, std::max<int64_t>(hcap, 1024), m->nonlinear, fused);
   }
   SlotRun s;
   s.m = m;

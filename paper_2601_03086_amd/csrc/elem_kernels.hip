@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "elem_math.h"
+#include "fcg_record.h"
 #include "pfem_internal.h"
 #include "reduce.h"
 
@@ -64,18 +65,20 @@ __device__ __forceinline__ T mat_lam(const MeshDev& m, int e) {
 
 // Everything one element needs, gathered before any arithmetic so that all
 // of its loads are in flight together.
-template <int D, typename T, int OP, bool NL>
+template <int D, typename T, int OP, bool NL, bool FUSED = false>
 struct ElemIn {
   double x[D + 1][D];
   T u[D + 1][D];   // state (Neo-Hookean) or input of the linear force
   T v[D + 1][D];   // direction of the apply
+  T rec[FUSED ? D + 1 : 1][FUSED ? 4 * D : 1];   // fused PCG records
   T mu, lam;
 };
 
-template <int D, typename T, int OP, bool NL>
+template <int D, typename T, int OP, bool NL, bool FUSED = false>
 __device__ __forceinline__ void load_elem(const MeshDev& m, const T* __restrict__ U,
                                           const T* __restrict__ V, int mask, int e,
-                                          const int (&nd)[D + 1], ElemIn<D, T, OP, NL>& in) {
+                                          const int (&nd)[D + 1],
+                                          ElemIn<D, T, OP, NL, FUSED>& in) {
   load_coords<D>(m.X, nd, in.x);
   in.mu = mat_mu<T>(m, e);
   in.lam = mat_lam<T>(m, e);
@@ -83,7 +86,10 @@ __device__ __forceinline__ void load_elem(const MeshDev& m, const T* __restrict_
 #pragma unroll
     for (int a = 0; a <= D; ++a) load_nodal<D, T>(U, nd[a], in.u[a]);
   }
-  if constexpr (OP == OP_APPLY) {
+  if constexpr (FUSED) {
+#pragma unroll
+    for (int a = 0; a <= D; ++a) load_record<D, T>(V, nd[a], in.rec[a]);
+  } else if constexpr (OP == OP_APPLY) {
 #pragma unroll
     for (int a = 0; a <= D; ++a) load_nodal<D, T>(V, nd[a], in.v[a]);
     if (mask & PFEM_MASK_IN) {
@@ -98,9 +104,23 @@ __device__ __forceinline__ void load_elem(const MeshDev& m, const T* __restrict_
   }
 }
 
-// Element output for one op; y[a][i] is the contribution to node a, comp i.
+// Fused PCG: the apply direction u' at the element's nodes from their records.
 template <int D, typename T, int OP, bool NL>
-__device__ __forceinline__ void element_compute(const ElemIn<D, T, OP, NL>& in,
+__device__ __forceinline__ void fcg_direction(ElemIn<D, T, OP, NL, true>& in, T alpha, T beta) {
+#pragma unroll
+  for (int a = 0; a <= D; ++a)
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      T s, rn, un;
+      fcg_step<T>(in.rec[a][c], in.rec[a][D + c], in.rec[a][2 * D + c], in.rec[a][3 * D + c],
+                  alpha, beta, s, rn, un);
+      in.v[a][c] = un;
+    }
+}
+
+// Element output for one op; y[a][i] is the contribution to node a, comp i.
+template <int D, typename T, int OP, bool NL, bool FUSED>
+__device__ __forceinline__ void element_compute(const ElemIn<D, T, OP, NL, FUSED>& in,
                                                 T (&y)[D + 1][D]) {
   Geo<D, T> g;
   geometry<D, T>(in.x, g);
@@ -179,7 +199,7 @@ __device__ __forceinline__ void element_output(const MeshDev& m, const T* __rest
                                                const int (&nd)[D + 1], T (&y)[D + 1][D]) {
   ElemIn<D, T, OP, NL> in;
   load_elem<D, T, OP, NL>(m, U, V, mask, e, nd, in);
-  element_compute<D, T, OP, NL>(in, y);
+  element_compute<D, T, OP, NL, false>(in, y);
 }
 
 template <int D, typename T, typename A>
@@ -207,7 +227,42 @@ using AccT = typename std::conditional<PFEM_ACC_F64 != 0, double, T>::type;
 // range (smallest node inside the block) followed by its halo list
 // (elements owned by earlier blocks that reach into it).  Each thread keeps
 // two elements in flight: both connectivity rows are loaded, then all
-// gathers of both elements, then the arithmetic.
+// gathers of both elements, then the arithmetic.  On return acc[] holds the
+// block's owned DOFs (all threads synchronised).
+template <int D, typename T, int OP, bool NL, typename A, bool FUSED = false>
+__device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __restrict__ U,
+                                                 const T* __restrict__ V, int mask,
+                                                 const pi4 br, int n0, int nloc, A* acc,
+                                                 T alpha = T(0), T beta = T(0)) {
+  const int nown = nloc * D;
+  for (int i = threadIdx.x; i < nown; i += kThreads) acc[i] = A(0);
+  __syncthreads();
+  const int n_own = br.y - br.x;
+  const int total = n_own + (br.w - br.z);
+  for (int t0 = threadIdx.x; t0 < total; t0 += 2 * kThreads) {
+    const int t1 = t0 + kThreads;
+    const bool two = t1 < total;
+    const int e0 = t0 < n_own ? br.x + t0 : ldg(m.halo + br.z + (t0 - n_own));
+    const int e1 = !two ? e0 : (t1 < n_own ? br.x + t1 : ldg(m.halo + br.z + (t1 - n_own)));
+    int nd0[D + 1], nd1[D + 1];
+    load_conn<D>(m.conn, e0, nd0);
+    load_conn<D>(m.conn, e1, nd1);
+    ElemIn<D, T, OP, NL, FUSED> in0, in1;
+    load_elem<D, T, OP, NL, FUSED>(m, U, V, mask, e0, nd0, in0);
+    load_elem<D, T, OP, NL, FUSED>(m, U, V, mask, e1, nd1, in1);
+    T y[D + 1][D];
+    if constexpr (FUSED) fcg_direction<D, T, OP, NL>(in0, alpha, beta);
+    element_compute<D, T, OP, NL, FUSED>(in0, y);
+    lds_accumulate<D, T, A>(acc, nd0, n0, nloc, y);
+    if (two) {
+      if constexpr (FUSED) fcg_direction<D, T, OP, NL>(in1, alpha, beta);
+      element_compute<D, T, OP, NL, FUSED>(in1, y);
+      lds_accumulate<D, T, A>(acc, nd1, n0, nloc, y);
+    }
+  }
+  __syncthreads();
+}
+
 template <int D, typename T, int OP, bool NL>
 __global__ void __launch_bounds__(kThreads)
 k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
@@ -224,33 +279,10 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   using A = AccT<T>;
   A* acc = reinterpret_cast<A*>(smem_raw);
   const int nown = nloc * D;
-  for (int i = threadIdx.x; i < nown; i += kThreads) acc[i] = A(0);
-  __syncthreads();
   const T* U = static_cast<const T*>(tp->u);
   const T* V = static_cast<const T*>(tp->v);
   const int mask = tp->mask;
-  const int n_own = br.y - br.x;
-  const int total = n_own + (br.w - br.z);
-  for (int t0 = threadIdx.x; t0 < total; t0 += 2 * kThreads) {
-    const int t1 = t0 + kThreads;
-    const bool two = t1 < total;
-    const int e0 = t0 < n_own ? br.x + t0 : ldg(m.halo + br.z + (t0 - n_own));
-    const int e1 = !two ? e0 : (t1 < n_own ? br.x + t1 : ldg(m.halo + br.z + (t1 - n_own)));
-    int nd0[D + 1], nd1[D + 1];
-    load_conn<D>(m.conn, e0, nd0);
-    load_conn<D>(m.conn, e1, nd1);
-    ElemIn<D, T, OP, NL> in0, in1;
-    load_elem<D, T, OP, NL>(m, U, V, mask, e0, nd0, in0);
-    load_elem<D, T, OP, NL>(m, U, V, mask, e1, nd1, in1);
-    T y[D + 1][D];
-    element_compute<D, T, OP, NL>(in0, y);
-    lds_accumulate<D, T, A>(acc, nd0, n0, nloc, y);
-    if (two) {
-      element_compute<D, T, OP, NL>(in1, y);
-      lds_accumulate<D, T, A>(acc, nd1, n0, nloc, y);
-    }
-  }
-  __syncthreads();
+  owner_accumulate<D, T, OP, NL, A>(m, U, V, mask, br, n0, nloc, acc);
   T* Y = static_cast<T*>(tp->y);
   const T* W = static_cast<const T*>(tp->w);
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
@@ -270,7 +302,135 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
     if (W != nullptr) part[0] += (double)val * (double)ldg(W + gi);
     part[1] += (double)val * (double)val;
   }
-  write_partials(tp->red, m.n_blocks, blk, part, 0, 2);
+  // an apply only reports y.w (slot 0): PCG init kernels own slots 1 and 2
+  write_partials(tp->red, m.n_blocks, blk, part, 0, OP == OP_APPLY ? 1 : 2);
+}
+
+// ----------------------------------------------------- fused PCG iteration
+// Jacobi-PCG in the Chronopoulos-Gear form (one inner-product phase per
+// iteration; same iterates as the textbook loop in exact arithmetic), with
+// one launch per iteration j:
+//   gamma_j = r.u, delta_j = w.u, |r|^2      partials of launch j-1 (u = M^-1 r, w = A u)
+//   beta_j = gamma_j / gamma_{j-1}, alpha_j = gamma_j / (delta_j - beta_j gamma_j / alpha_{j-1})
+//   s = w + beta s, r' = r - alpha s, u' = M^-1 r'        at every gathered node
+//   w' = A u'                                            element pass, owner scatter
+//   p = u + beta p, d += alpha p                         owned DOFs
+// The point update is pointwise, so a workgroup evaluates u' itself at the
+// nodes its elements touch -- from a per-node record {r, w, s, M^-1} of the
+// previous launch -- instead of waiting for the owner of the node; owners
+// then write the new record to the other parity buffer.  Partial sums
+// alternate between two slot sets by parity of j.  Unlike the pipelined
+// (Ghysels-Vanroose) form, no recurrence replaces the matvec, which keeps
+// the float32 iteration as stable as the textbook loop.
+template <int D, typename T, bool NL>
+__global__ void __launch_bounds__(kThreads)
+k_fcg(const Task* __restrict__ tasks, const int2* __restrict__ work, int it) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  Scalars* sc = tp->sc;
+  if (ldg(&sc->state) != 0) return;
+  const MeshDev m = tp->m;
+  const int blk = wk.y;
+  const int nb = m.n_blocks;
+  const int j = tp->k_base + it;
+  const double* part_in = tp->red.part + (size_t)(j & 1) * kRedSlots * nb;
+  double delta, gamma, rr;
+  sum_slots3(part_in, nb, delta, gamma, rr);
+  int state = 0;
+  double alpha64 = 0.0, beta64 = 0.0;
+  if (!(rr == rr) || !(gamma == gamma) || !(delta == delta)) {
+    state = 3;
+  } else if (rr <= ldg(&sc->target2)) {
+    state = 1;
+  } else if (!(gamma > 0.0)) {
+    state = 3;
+  } else if (j >= ldg(&sc->kmax)) {
+    state = 2;
+  } else {
+    double den = delta;
+    if (j > 0) {
+      beta64 = gamma / ldg(&sc->pg[(j - 1) & 1]);
+      den = delta - beta64 * gamma / ldg(&sc->pa[(j - 1) & 1]);
+    }
+    if (!(den > 0.0)) state = 3;   // not SPD along this direction
+    else alpha64 = gamma / den;
+  }
+  if (blk == 0 && threadIdx.x == 0) {
+    sc->rr = rr;
+    const double rho = sqrt(rr) / sc->den;
+    sc->rho = rho;
+    if (j > 0) {   // residual after j iterations
+      const int h = tp->hist_base + j - 1;
+      if (tp->hist != nullptr && h < sc->hist_cap) {
+        tp->hist[h] = rho;
+        sc->hist_len = h + 1;
+      }
+    }
+    if (state == 0) {
+      sc->pa[j & 1] = alpha64;
+      sc->pg[j & 1] = gamma;
+      sc->alpha = alpha64;
+      sc->beta = beta64;
+      sc->k = j + 1;
+      sc->total_k += 1;
+    } else {
+      sc->k = j;
+      sc->state = state;
+    }
+  }
+  if (state != 0) return;
+  const int n0 = blk * m.bn;
+  const int nloc = min(m.bn, m.n_nodes - n0);
+  const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
+  using A = AccT<T>;
+  A* acc = reinterpret_cast<A*>(smem_raw);
+  const T alpha = (T)alpha64, beta = (T)beta64;
+  const T* U = static_cast<const T*>(tp->u);
+  const T* Rin = static_cast<const T*>(tp->rec[j & 1]);
+  owner_accumulate<D, T, OP_APPLY, NL, A, true>(m, U, Rin, 0, br, n0, nloc, acc, alpha, beta);
+  T* Rout = static_cast<T*>(tp->rec[(j + 1) & 1]);
+  T* P = static_cast<T*>(tp->p);
+  T* Dd = static_cast<T*>(tp->d);
+  const bool first = j == 0;
+  double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
+  for (int ln = threadIdx.x; ln < nloc; ln += kThreads) {
+    const int n = n0 + ln;
+    const int bits = ldg(m.dmask + n);
+    T rc[4 * D], out[4 * D];
+    load_record<D, T>(Rin, n, rc);
+    T pv[D], dv[D];
+    load_nodal<D, T>(P, n, pv);
+    load_nodal<D, T>(Dd, n, dv);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const T r = rc[c], w = rc[D + c], so = rc[2 * D + c], mi = rc[3 * D + c];
+      T s, rn, un;
+      fcg_step<T>(r, w, so, mi, alpha, beta, s, rn, un);
+      const T ui = mi * r;
+      const T p = first ? ui : fma_t(beta, pv[c], ui);
+      pv[c] = p;
+      if constexpr (sizeof(T) == 8) dv[c] = dv[c] + alpha64 * p;
+      else dv[c] = fma_t(alpha, p, dv[c]);
+      const T wn = ((bits >> c) & 1) ? T(0) : (T)acc[ln * D + c];
+      out[c] = rn;
+      out[D + c] = wn;
+      out[2 * D + c] = s;
+      out[3 * D + c] = mi;
+      part[0] += (double)wn * (double)un;
+      part[1] += (double)rn * (double)un;
+      part[2] += (double)rn * (double)rn;
+    }
+    store_record<D, T>(Rout, n, out);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      stg(P + (size_t)n * D + c, pv[c]);
+      stg(Dd + (size_t)n * D + c, dv[c]);
+    }
+  }
+  RedDev outp{tp->red.part + (size_t)((j + 1) & 1) * kRedSlots * nb, nullptr};
+  write_partials(outp, nb, blk, part, 0, 3);
 }
 
 // -------------------------------------------------- alternative scatters
@@ -551,6 +711,32 @@ void launch_energy(Ctx* ctx, int dim, int prec, bool diff, const Task* tasks_dev
   }
   PFEM_HIP(hipGetLastError());
   ctx->timing_end(FAM_ENERGY, ev);
+}
+
+void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nl, const Task* tasks,
+                     const int2* work, int n_work, int bn_max, int it) {
+  if (n_work <= 0) return;
+  hipEvent_t ev = nullptr;
+  ctx->timing_begin(FAM_FUSED, &ev);
+  dim3 grid(n_work), block(kThreads);
+  hipStream_t s = ctx->stream;
+  const size_t s32 = (size_t)bn_max * dim * sizeof(AccT<float>);
+  const size_t s64 = (size_t)bn_max * dim * sizeof(AccT<double>);
+#define PFEM_FCG(DD, TT, NLV, SM) hipLaunchKernelGGL((k_fcg<DD, TT, NLV>), grid, block, SM, s, tasks, work, it)
+  if (!nl) {
+    if (dim == 2 && prec == PFEM_FP32) PFEM_FCG(2, float, false, s32);
+    else if (dim == 2) PFEM_FCG(2, double, false, s64);
+    else if (prec == PFEM_FP32) PFEM_FCG(3, float, false, s32);
+    else PFEM_FCG(3, double, false, s64);
+  } else {
+    if (dim == 2 && prec == PFEM_FP32) PFEM_FCG(2, float, true, s32);
+    else if (dim == 2) PFEM_FCG(2, double, true, s64);
+    else if (prec == PFEM_FP32) PFEM_FCG(3, float, true, s32);
+    else PFEM_FCG(3, double, true, s64);
+  }
+#undef PFEM_FCG
+  PFEM_HIP(hipGetLastError());
+  ctx->timing_end(FAM_FUSED, ev);
 }
 
 int block_nodes_max() { return 4096; }

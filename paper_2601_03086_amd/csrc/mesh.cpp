@@ -496,11 +496,15 @@ int64_t mesh_device_bytes(const pfem_mesh* m) {
          r(NE * 4) + r(N * 4) + r((int64_t)m->n_blocks * 8);
 }
 
-int64_t solve_bytes(const pfem_mesh* m, int prec) {
+int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg) {
   const int64_t nd = m->n_dof();
   const int64_t s = prec == PFEM_FP64 ? 8 : 4;
-  return 3 * nd * 8 + 6 * nd * s + (int64_t)m->n_blocks * kRedSlots * 8 + 4096 +
-         (int64_t)8 * 65536;
+  return 3 * nd * 8 + (6 + (fused_pcg ? 9 : 0)) * nd * s +
+         (int64_t)m->n_blocks * 2 * kRedSlots * 8 + 4096 + (int64_t)8 * 65536;
+}
+
+bool krylov_fused(const pfem_solve_opts& o) {
+  return o.krylov == PFEM_KRYLOV_FUSED || (o.krylov == PFEM_KRYLOV_AUTO && o.prec == PFEM_FP32);
 }
 
 }  // namespace pfem

@@ -22,12 +22,16 @@ struct SolveState {
   void* q = nullptr;
   void* minv = nullptr;
   void* u32 = nullptr;      // float32 copy of the state (FP32 Neo-Hookean HVP)
-  double* part = nullptr;   // kRedSlots * n_blocks
+  bool fused = false;       // fused PCG records present
+  void* rec[2] = {nullptr, nullptr};   // fused PCG: {r, w, s, M^-1} per node, by parity
+  void* tmp = nullptr;
+  double* part = nullptr;   // 2 * kRedSlots * n_blocks (two slot sets)
   Scalars* sc = nullptr;
   double* hist = nullptr;
   int64_t hist_cap = 0;
   int64_t bytes = 0;
-  void alloc(int prec, int64_t n_dof, int n_blocks, int64_t hist_cap, bool nonlinear);
+  void alloc(int prec, int64_t n_dof, int n_blocks, int64_t hist_cap, bool nonlinear,
+             bool fused_pcg);
   void release();
   ~SolveState() { release(); }
 };
@@ -122,7 +126,10 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes);
 void mesh_upload(pfem_mesh* m, Ctx* ctx);
 void mesh_release_device(pfem_mesh* m);
 int64_t mesh_device_bytes(const pfem_mesh* m);
-int64_t solve_bytes(const pfem_mesh* m, int prec);
+int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg);
+// Whether a solve with these options runs the fused (one launch per
+// iteration) PCG.
+bool krylov_fused(const pfem_solve_opts& o);
 void lame_from_params(int model, int param_kind, double p0, double p1, double* mu,
                       double* lam);
 uint32_t fmix32(uint32_t h);

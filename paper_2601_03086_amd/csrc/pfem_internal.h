@@ -75,6 +75,7 @@ struct Scalars {
   double target2;         // stop when |r|^2 <= target2
   double bnorm;           // |r| at inner start
   double red[kRedSlots];  // outputs of one-workgroup reductions
+  double pa[2], pg[2];    // fused PCG: alpha_j and gamma_j by parity of j
   int32_t k;              // Krylov iterations done in the current inner solve
   int32_t kmax;           // cap for the current inner solve
   int32_t state;          // 0 running, 1 converged, 2 max-iter, 3 breakdown
@@ -103,6 +104,11 @@ struct Task {
   int32_t hist_base;      // history index of iteration 0 of this inner solve (PCG)
   int32_t pcg;            // 1: PCG apply (returns at once unless state == 0)
   int32_t pad;
+  // Fused PCG: per-node records {r, w, s, M^-1} (4 * dim values, kernel
+  // precision) by iteration parity -- launch j gathers rec[j & 1] and its
+  // owners write rec[(j + 1) & 1] -- and a scratch vector for the start.
+  void* rec[2];
+  void* tmp;
 };
 
 // Element-kernel operations.
@@ -110,7 +116,7 @@ enum ElemOp { OP_APPLY = 0, OP_FORCE = 1, OP_DIAG = 2 };
 
 // Kernel timing families (pfem_ctx_kernel_time).
 enum Family { FAM_APPLY = 0, FAM_FORCE = 1, FAM_ENERGY = 2, FAM_DIAG = 3,
-              FAM_UPDATE = 4, FAM_DIRECTION = 5, FAM_COUNT = 6 };
+              FAM_UPDATE = 4, FAM_DIRECTION = 5, FAM_FUSED = 6, FAM_COUNT = 7 };
 
 // ----------------------------------------------------- launch descriptors
 struct Ctx;
@@ -139,6 +145,8 @@ struct Ctx {
   bool own_stream = false;
   ArgRing ring;
   int timing = 0;          // bitmask of timed families
+  int sample_every = 1;    // time one launch in this many per family
+  int64_t fam_seen[FAM_COUNT] = {};
   int64_t fam_launches[FAM_COUNT] = {};
   double fam_ms[FAM_COUNT] = {};
   struct Timed {
@@ -181,6 +189,17 @@ void launch_pcg_update(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
                        const int2* work_dev, int n_work, int it);
 void launch_pcg_direction(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
                           const int2* work_dev, int n_work, int it);
+// Fused PCG (one element launch per iteration).  init: r = -g into rec[0]
+// (s = 0, M^-1 copied), p = u = M^-1 r, d = 0, partials (r.u, r.r) in slots
+// 1, 2; the caller then applies tmp = A p (partial in slot 0), calls
+// init_w (w of rec[0] = tmp) and the classic init_finish.
+void launch_fcg_init(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
+                     const int2* work_dev, int n_work);
+void launch_fcg_init_w(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
+                       const int2* work_dev, int n_work);
+void launch_pcg_init_finish(Ctx* ctx, const Task* tasks_dev, int n_tasks);
+void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nonlinear, const Task* tasks_dev,
+                     const int2* work_dev, int n_work, int bn_max, int it);
 // One workgroup per task: red.out[0..1] = sums of partial slots 0 and 1.
 void launch_reduce_store(Ctx* ctx, const Task* tasks_dev, int n_tasks);
 void launch_dot(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
@@ -216,6 +235,7 @@ __device__ __forceinline__ T ldg(const T* p) {
 // Native vector types: HIP's float2/double2/int4 wrappers copy through
 // generic references, which would turn a global load back into a flat one.
 typedef float pf2 __attribute__((ext_vector_type(2)));
+typedef float pf4 __attribute__((ext_vector_type(4)));
 typedef double pd2 __attribute__((ext_vector_type(2)));
 typedef int pi4 __attribute__((ext_vector_type(4)));
 template <typename T>

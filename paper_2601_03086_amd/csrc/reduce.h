@@ -66,4 +66,19 @@ __device__ __forceinline__ void sum_slots2(const double* part, int nb, int k0, i
   s1 = v[1];
 }
 
+// Totals of slots 0, 1, 2 over all blocks (fixed order), in every thread.
+__device__ __forceinline__ void sum_slots3(const double* part, int nb, double& s0,
+                                           double& s1, double& s2) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
+    v[0] += ldg(part + b);
+    v[1] += ldg(part + (size_t)nb + b);
+    v[2] += ldg(part + (size_t)2 * nb + b);
+  }
+  block_sum_all<3>(v);
+  s0 = v[0];
+  s1 = v[1];
+  s2 = v[2];
+}
+
 }  // namespace pfem

@@ -78,6 +78,7 @@ void ctx_unref(Ctx* c) {
 void Ctx::timing_begin(int fam, hipEvent_t* a) {
   *a = nullptr;
   if (!(timing & (1 << fam))) return;
+  if (fam_seen[fam]++ % sample_every != 0) return;
   if (event_pool.empty()) {
     hipEvent_t e;
     PFEM_HIP(hipEventCreate(&e));

@@ -63,8 +63,8 @@ struct pfem_server {
   void complete(Req* r);
 };
 
-static int64_t req_bytes(const pfem_mesh* m, int prec) {
-  return (m->uploaded ? 0 : mesh_device_bytes(m)) + solve_bytes(m, prec);
+static int64_t req_bytes(const pfem_mesh* m, const pfem_solve_opts& o) {
+  return (m->uploaded ? 0 : mesh_device_bytes(m)) + solve_bytes(m, o.prec, krylov_fused(o));
 }
 
 void pfem_server::admit(Req* r) {
@@ -263,13 +263,15 @@ pfem_status pfem_server_submit(pfem_server* s, pfem_mesh* m, const double* u0,
     require(m->finalized, PFEM_E_STATE, "mesh not finalized");
     require(o->tol > 0, PFEM_E_INVALID_ARG, "tol must be > 0");
     require(o->prec == PFEM_FP64 || o->prec == PFEM_FP32, PFEM_E_INVALID_ARG, "bad precision");
+    require(o->krylov >= PFEM_KRYLOV_AUTO && o->krylov <= PFEM_KRYLOV_FUSED,
+            PFEM_E_INVALID_ARG, "bad krylov formulation");
     Req* r = new Req();
     r->id = req_id;
     r->m = m;
     r->o = *o;
     r->has_u0 = u0 != nullptr;
     if (u0) r->u0.assign(u0, u0 + m->n_dof());
-    r->bytes = req_bytes(m, o->prec);
+    r->bytes = req_bytes(m, *o);
     {
       std::lock_guard<std::mutex> lk(s->mu);
       if (s->all.count(req_id)) {

@@ -9,8 +9,10 @@
 namespace pfem {
 
 // ------------------------------------------------------------ state memory
-void SolveState::alloc(int pr, int64_t nd, int nb, int64_t hcap, bool nonlinear) {
+void SolveState::alloc(int pr, int64_t nd, int nb, int64_t hcap, bool nonlinear,
+                       bool fused_pcg) {
   prec = pr;
+  fused = fused_pcg;
   n_dof = nd;
   n_blocks = nb;
   const size_t s = pr == PFEM_FP64 ? 8 : 4;
@@ -28,7 +30,12 @@ void SolveState::alloc(int pr, int64_t nd, int nb, int64_t hcap, bool nonlinear)
   A(&q, nd * s);
   A(&minv, nd * s);
   if (nonlinear && pr == PFEM_FP32) A(&u32, nd * 4);
-  A((void**)&part, (size_t)std::max(nb, 1) * kRedSlots * 8);
+  if (fused_pcg) {
+    A(&rec[0], 4 * nd * s);
+    A(&rec[1], 4 * nd * s);
+    A(&tmp, nd * s);
+  }
+  A((void**)&part, (size_t)std::max(nb, 1) * 2 * kRedSlots * 8);
   A((void**)&sc, sizeof(Scalars));
   PFEM_HIP(hipMemset(sc, 0, sizeof(Scalars)));
   hist_cap = std::max<int64_t>(hcap, 0);
@@ -39,11 +46,12 @@ void SolveState::alloc(int pr, int64_t nd, int nb, int64_t hcap, bool nonlinear)
 }
 
 void SolveState::release() {
-  void* ptrs[] = {x64, g64, aux64, d, r, p, q, minv, u32, part, sc, hist};
+  void* ptrs[] = {x64, g64, aux64, d, r, p, q, minv, u32, rec[0], rec[1], tmp, part, sc, hist};
   for (void* ptr : ptrs)
     if (ptr != nullptr) (void)hipFree(ptr);
   x64 = g64 = aux64 = nullptr;
   d = r = p = q = minv = u32 = nullptr;
+  rec[0] = rec[1] = tmp = nullptr;
   part = nullptr;
   sc = nullptr;
   hist = nullptr;
@@ -57,7 +65,7 @@ void slot_alloc(SlotRun* s, pfem_mesh* m, const pfem_solve_opts& o, int64_t hist
   s->nl = m->nonlinear;
   s->st = new SolveState();
   try {
-    s->st->alloc(s->prec, m->n_dof(), m->n_blocks, hist_cap, m->nonlinear);
+    s->st->alloc(s->prec, m->n_dof(), m->n_blocks, hist_cap, m->nonlinear, krylov_fused(o));
     PFEM_HIP(hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault));
   } catch (...) {
     delete s->st;
@@ -86,6 +94,9 @@ static Task base_task(SlotRun* s) {
   t.d = s->st->d;
   t.red.part = s->st->part;
   t.red.out = &s->st->sc->red[0];
+  t.rec[0] = s->st->rec[0];
+  t.rec[1] = s->st->rec[1];
+  t.tmp = s->st->tmp;
   t.mask = PFEM_MASK_OUT;
   t.k_base = s->k_before;
   t.hist_base = s->hist_base;
@@ -96,18 +107,20 @@ static Task base_task(SlotRun* s) {
 struct Group {
   int dim, prec;
   bool nl;
+  bool fused;
   std::vector<SlotRun*> slots;
 };
 
-// Groups slots by (dim, precision, model kind) so one templated launch
-// covers a group.
+// Groups slots by (dim, precision, model kind, PCG formulation) so one
+// templated launch covers a group.
 static std::vector<Group> group_by(const std::vector<SlotRun*>& v, bool force_fp64) {
-  std::map<std::tuple<int, int, int>, Group> g;
+  std::map<std::tuple<int, int, int, int>, Group> g;
   for (SlotRun* s : v) {
     const int pr = force_fp64 ? PFEM_FP64 : s->prec;
-    auto key = std::make_tuple(s->m->dim, pr, s->nl ? 1 : 0);
+    const bool fused = !force_fp64 && s->st->fused;
+    auto key = std::make_tuple(s->m->dim, pr, s->nl ? 1 : 0, fused ? 1 : 0);
     auto it = g.find(key);
-    if (it == g.end()) it = g.emplace(key, Group{s->m->dim, pr, s->nl, {}}).first;
+    if (it == g.end()) it = g.emplace(key, Group{s->m->dim, pr, s->nl, fused, {}}).first;
     it->second.slots.push_back(s);
   }
   std::vector<Group> out;
@@ -235,7 +248,8 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
         launch_cast(ctx, true, s->st->x64, s->st->u32, s->m->n_dof());
       if (s->nl || !s->minv_valid) need_diag.push_back(s);
       launch_set_scalars(ctx, s->st->sc, s->den, inner_target(s) * inner_target(s),
-                         std::max(0, s->max_iter - s->rep.kv_count), false, false);
+                         std::max(0, s->max_iter - s->rep.kv_count - (s->st->fused ? 1 : 0)),
+                         false, false);
     }
     for (const Group& g : group_by(need_diag, false)) {
       std::vector<Task> ts;
@@ -261,8 +275,29 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
         ts.push_back(t);
       }
       Uploaded u = upload_group(ctx, g, ts);
-      launch_pcg_init(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work, (int)ts.size());
-      *nl += 2;
+      if (!g.fused) {
+        launch_pcg_init(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work, (int)ts.size());
+        *nl += 2;
+        continue;
+      }
+      // fused start: records {r, 0, 0, M^-1}, p = u = M^-1 r, d = 0;
+      // tmp = A u (+ partial w.u); w of the records = tmp
+      launch_fcg_init(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work);
+      std::vector<Task> ta;
+      for (SlotRun* s : g.slots) {
+        Task t = base_task(s);
+        t.u = s->nl ? (s->prec == PFEM_FP32 ? s->st->u32 : (void*)s->st->x64) : nullptr;
+        t.v = s->st->p;
+        t.y = s->st->tmp;
+        t.w = s->st->p;
+        ta.push_back(t);
+      }
+      Uploaded ua = upload_group(ctx, g, ta);
+      launch_elem(ctx, g.dim, g.prec, OP_APPLY, g.nl, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
+                  ua.n_work, ua.bn_max, nullptr, nullptr);
+      launch_fcg_init_w(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work);
+      launch_pcg_init_finish(ctx, u.tasks, (int)ts.size());
+      *nl += 4;
     }
   }
   // chunk of iterations for every Krylov slot
@@ -286,8 +321,18 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
       upd.push_back(t2);
     }
     Uploaded ua = upload_group(ctx, g, apply);
-    Uploaded uu = upload_group(ctx, g, upd);
     ctx->cur_key = key;
+    if (g.fused) {
+      for (int it = 0; it < k; ++it) {
+        ctx->cur_it = it;
+        launch_fcg_iter(ctx, g.dim, g.prec, g.nl, ua.tasks, ua.work, ua.n_work, ua.bn_max, it);
+        *nl += 1;
+      }
+      ctx->cur_key = -1;
+      ctx->cur_it = 0;
+      continue;
+    }
+    Uploaded uu = upload_group(ctx, g, upd);
     for (int it = 0; it < k; ++it) {
       ctx->cur_it = it;
       launch_elem(ctx, g.dim, g.prec, OP_APPLY, g.nl, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
@@ -400,7 +445,8 @@ static void after_krylov(Ctx* ctx, SlotRun* s) {
     s->action = A_KRYLOV;
     return;
   }
-  s->rep.kv_count += h.k;
+  // the fused start applies A once more (w = A u) before iteration 0
+  s->rep.kv_count += h.k + (s->st->fused ? 1 : 0);
   s->rep.pcg_iters += h.k;
   s->rep.outer_sweeps += 1;
   if (h.state == 3 && (!s->nl || h.k == 0)) {
@@ -409,7 +455,9 @@ static void after_krylov(Ctx* ctx, SlotRun* s) {
       return;
     }
     // negative curvature on the first step: preconditioned steepest descent
-    PFEM_HIP(hipMemcpyAsync(s->st->d, s->st->p, s->m->n_dof() * (s->prec == PFEM_FP64 ? 8 : 4),
+    // (M^-1 r: the first direction of both formulations, held in p)
+    PFEM_HIP(hipMemcpyAsync(s->st->d, s->st->p,
+                            s->m->n_dof() * (s->prec == PFEM_FP64 ? 8 : 4),
                             hipMemcpyDeviceToDevice, ctx->stream));
   }
   if (!s->nl) {

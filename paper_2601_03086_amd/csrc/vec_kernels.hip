@@ -12,8 +12,10 @@
 // so the scalars never leave the device and no workgroup waits for another.
 // Block 0 of a task records the scalars, the residual history and the
 // state; the next launch returns at once for a task that left "running".
-// z = M^-1 r is never stored.
+// z = M^-1 r is never stored.  The fused variant (one element launch per
+// iteration) lives with the element kernels; its start-up passes are here.
 #include "pfem_internal.h"
+#include "fcg_record.h"
 #include "reduce.h"
 
 namespace pfem {
@@ -54,6 +56,67 @@ k_pcg_init(const Task* __restrict__ tasks, const int2* __restrict__ work) {
     part[2] += (double)r * (double)r;
   }
   write_partials(tp->red, tp->m.n_blocks, wk.y, part, 1, 3);
+}
+
+// Fused PCG start: r = -g; record {r, w = 0, s = 0, M^-1} of parity 0;
+// p = u = M^-1 r (the vector the start-up apply multiplies); d = 0.
+// Partials: slot 1 = r.u, slot 2 = r.r.
+template <int D, typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fcg_init(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  const int n0 = wk.y * tp->m.bn;
+  const int nloc = min(tp->m.bn, tp->m.n_nodes - n0);
+  const double* G = static_cast<const double*>(tp->u);
+  const T* Mi = static_cast<const T*>(tp->minv);
+  T* Rec = static_cast<T*>(tp->rec[0]);
+  T* P = static_cast<T*>(tp->p);
+  T* Dd = static_cast<T*>(tp->d);
+  double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
+  for (int ln = threadIdx.x; ln < nloc; ln += kThreads) {
+    const int n = n0 + ln;
+    T o[4 * D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const size_t g = (size_t)n * D + c;
+      const T r = (T)(-ldg(G + g));
+      const T mi = ldg(Mi + g);
+      const T u = mi * r;
+      o[c] = r;
+      o[D + c] = T(0);
+      o[2 * D + c] = T(0);
+      o[3 * D + c] = mi;
+      stg(P + g, u);
+      stg(Dd + g, T(0));
+      part[1] += (double)r * (double)u;
+      part[2] += (double)r * (double)r;
+    }
+    store_record<D, T>(Rec, n, o);
+  }
+  write_partials(tp->red, tp->m.n_blocks, wk.y, part, 1, 3);
+}
+
+// Fused PCG start, after tmp = A u: w of the parity-0 records = tmp.
+template <int D, typename T>
+__global__ void __launch_bounds__(kThreads)
+k_fcg_init_w(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  const int n0 = wk.y * tp->m.bn;
+  const int nloc = min(tp->m.bn, tp->m.n_nodes - n0);
+  T* Rec = static_cast<T*>(tp->rec[0]);
+  const T* W = static_cast<const T*>(tp->tmp);
+  for (int ln = threadIdx.x; ln < nloc; ln += kThreads) {
+    const int n = n0 + ln;
+    T o[4 * D];
+    load_record<D, T>(Rec, n, o);
+#pragma unroll
+    for (int c = 0; c < D; ++c) o[D + c] = ldg(W + (size_t)n * D + c);
+    store_record<D, T>(Rec, n, o);
+  }
 }
 
 // One workgroup per task: scalars at the start of an inner solve.
@@ -236,6 +299,19 @@ void launch_pcg_init(Ctx* ctx, int dim, int prec, const Task* tasks, const int2*
   PFEM_VEC_LAUNCH(k_pcg_init, FAM_UPDATE, tasks, work);
   hipLaunchKernelGGL(k_pcg_init_finish, dim3(n_tasks), dim3(kThreads), 0, ctx->stream, tasks);
   PFEM_HIP(hipGetLastError());
+}
+void launch_pcg_init_finish(Ctx* ctx, const Task* tasks, int n_tasks) {
+  if (n_tasks <= 0) return;
+  hipLaunchKernelGGL(k_pcg_init_finish, dim3(n_tasks), dim3(kThreads), 0, ctx->stream, tasks);
+  PFEM_HIP(hipGetLastError());
+}
+void launch_fcg_init(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
+                     int n_work) {
+  PFEM_VEC_LAUNCH(k_fcg_init, FAM_UPDATE, tasks, work);
+}
+void launch_fcg_init_w(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
+                       int n_work) {
+  PFEM_VEC_LAUNCH(k_fcg_init_w, FAM_UPDATE, tasks, work);
 }
 void launch_pcg_update(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
                        int n_work, int it) {

@@ -171,3 +171,64 @@ def test_failures_reported(ctx):
     with pytest.raises(L.PfemError) as ei:
         m.solve(u0=u0, tol=1e-10, prec="fp64")
     assert ei.value.status == L.PFEM_E_BREAKDOWN
+
+
+def test_fused_pcg_matches_classic_fp64(ctx):
+    """The one-launch fused PCG runs the same Krylov iterates as the
+    three-launch loop: on C1 in FP64 the residual histories agree and the
+    fused count is one matvec (its start-up w = A u) higher per inner solve."""
+    p = synth.unit_square_c1()
+    m = _mesh(ctx, p)
+    uc, rc, hc = m.solve(tol=1e-10, prec="fp64", krylov="classic")
+    up, rp, hp = m.solve(tol=1e-10, prec="fp64", krylov="fused")
+    print("c1 classic", rc["kv_count"], "fused", rp["kv_count"], flush=True)
+    assert rc["status"] == 0 and rp["status"] == 0
+    assert abs(rp["pcg_iters"] - rc["pcg_iters"]) <= 2
+    assert rp["kv_count"] == rp["pcg_iters"] + rp["outer_sweeps"]
+    n = min(len(hc), len(hp), 60)
+    assert np.allclose(hp[:n], hc[:n], rtol=1e-5, atol=0)
+    assert rel(up, uc) <= 1e-9
+    assert _oracle_rel_residual(p, up) <= 1.01e-10
+
+
+@pytest.mark.parametrize("model", ["lin_plane_strain", "nh_plane_strain"])
+def test_fused_pcg_fp32_plate(ctx, model):
+    """FP32 mode with both formulations on a 20k-triangle plate (linear) or a
+    3k-triangle Neo-Hookean plate: same tolerance met, same solution."""
+    if model == "nh_plane_strain":
+        p = synth.plate_problem(94, 95, 96, n_holes=3, target_tris=3000, model=model)
+        p.neu_traction = p.neu_traction * 20.0
+        kw = dict(tol=1e-9, n_load_steps=3)
+        uo, ro = osolve.newton(p, tol=1e-10)
+    else:
+        p = synth.plate_problem(77, 78, 79, n_holes=6, target_tris=20000)
+        kw = dict(tol=1e-8)
+        uo, _ = osolve.solve_linear(p, method="direct")
+    m = _mesh(ctx, p)
+    out = {}
+    for kr in ("classic", "fused"):
+        u, rep, hist = m.solve(prec="fp32", krylov=kr, **kw)
+        print(model, kr, rep["kv_count"], rep["outer_sweeps"], rep["newton_iters"],
+              rep["rel_residual_final"], flush=True)
+        assert rep["status"] == 0
+        assert rep["rel_residual_final"] <= kw["tol"]
+        assert rel(u, uo) <= 1e-6
+        out[kr] = rep
+    assert out["fused"]["kv_count"] <= 1.25 * out["classic"]["kv_count"] + 10
+
+
+def test_fused_failures_reported(ctx):
+    from paper_2601_03086_amd import _lib as L
+    p = synth.unit_square_c1(n=9)
+    q = mk.make_problem("lin_plane_stress", p.coords, p.conn, E=-1.0,
+                        dir_nodes=p.dir_nodes, dir_comps=p.dir_comps,
+                        dir_values=p.dir_values, facets=p.neu_facets,
+                        traction=p.neu_traction)
+    with pytest.raises(L.PfemError) as ei:
+        _mesh(ctx, q).solve(tol=1e-10, prec="fp32", krylov="fused")
+    assert ei.value.status == L.PFEM_E_BREAKDOWN
+    # cap of 5 matvecs: the start-up product and 4 iterations
+    m = _mesh(ctx, p)
+    u, rep, hist = m.solve(tol=1e-14, prec="fp64", max_iter=5, krylov="fused")
+    assert rep["status_name"] == "NOT_CONVERGED"
+    assert rep["kv_count"] == 5 and rep["pcg_iters"] == 4 and len(hist) == 5
