@@ -111,9 +111,16 @@ def cpu_baseline():
 
 
 # ------------------------------------------------------------------ traffic
+def _short_kernel(name):
+    import re
+    m = re.match(r"(?:void )?(?:pfem::)?([A-Za-z_0-9]+)(<[^()]*>)?", name)
+    return (m.group(1) + (m.group(2) or "")) if m else name[:40]
+
+
 def parse_pmc(out_dir):
-    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the K.v kernel
-    and of a plain copy of known size, from rocprofv3 counter CSVs."""
+    """Mean counter value per dispatch, by kernel and counter, from the
+    rocprofv3 counter CSVs under out_dir (pfem kernels, and device copies
+    of at least 100000 KiB, which calibrate the byte counters)."""
     import csv
     vals = {}
     for f in glob.glob(os.path.join(out_dir, "**", "*counter_collection.csv"), recursive=True):
@@ -121,14 +128,14 @@ def parse_pmc(out_dir):
             name = row.get("Kernel_Name", "")
             ctr = row.get("Counter_Name", "")
             v = float(row.get("Counter_Value", 0))
-            if KERNEL_MATCH in name:
-                key = "kernel"
-            elif "copy" in name.lower() or "elementwise" in name.lower():
-                key = "copy"
+            if "copyBuffer" in name and ctr in ("FETCH_SIZE", "WRITE_SIZE") and v > 100000:
+                key = "copy_256MiB"
+            elif "pfem::" in name:
+                key = _short_kernel(name)
             else:
                 continue
             vals.setdefault((key, ctr), []).append(v)
-    return {f"{k}:{c}": sum(v) / len(v) for (k, c), v in vals.items()}
+    return {f"{k} | {c}": round(sum(v) / len(v), 3) for (k, c), v in sorted(vals.items())}
 
 
 def traffic_entry():

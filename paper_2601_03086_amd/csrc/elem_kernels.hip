@@ -229,18 +229,18 @@ using AccT = typename std::conditional<PFEM_ACC_F64 != 0, double, T>::type;
 // two elements in flight: both connectivity rows are loaded, then all
 // gathers of both elements, then the arithmetic.  On return acc[] holds the
 // block's owned DOFs (all threads synchronised).
-template <int D, typename T, int OP, bool NL, typename A, bool FUSED = false>
+template <int D, typename T, int OP, bool NL, typename A, bool FUSED = false, int NT = kThreads>
 __device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __restrict__ U,
                                                  const T* __restrict__ V, int mask,
                                                  const pi4 br, int n0, int nloc, A* acc,
                                                  T alpha = T(0), T beta = T(0)) {
   const int nown = nloc * D;
-  for (int i = threadIdx.x; i < nown; i += kThreads) acc[i] = A(0);
+  for (int i = threadIdx.x; i < nown; i += NT) acc[i] = A(0);
   __syncthreads();
   const int n_own = br.y - br.x;
   const int total = n_own + (br.w - br.z);
-  for (int t0 = threadIdx.x; t0 < total; t0 += 2 * kThreads) {
-    const int t1 = t0 + kThreads;
+  for (int t0 = threadIdx.x; t0 < total; t0 += 2 * NT) {
+    const int t1 = t0 + NT;
     const bool two = t1 < total;
     const int e0 = t0 < n_own ? br.x + t0 : ldg(m.halo + br.z + (t0 - n_own));
     const int e1 = !two ? e0 : (t1 < n_own ? br.x + t1 : ldg(m.halo + br.z + (t1 - n_own)));
@@ -322,22 +322,36 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
 // alternate between two slot sets by parity of j.  Unlike the pipelined
 // (Ghysels-Vanroose) form, no recurrence replaces the matvec, which keeps
 // the float32 iteration as stable as the textbook loop.
-template <int D, typename T, bool NL>
-__global__ void __launch_bounds__(kThreads)
-k_fcg(const Task* __restrict__ tasks, const int2* __restrict__ work, int it) {
+template <int D, typename T, bool NL, int NT>
+__device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int blk, int it) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int2 wk = work[blockIdx.x];
-  const Task* tp = tasks + wk.x;
-  if (!tp->active) return;
   Scalars* sc = tp->sc;
-  if (ldg(&sc->state) != 0) return;
   const MeshDev m = tp->m;
-  const int blk = wk.y;
   const int nb = m.n_blocks;
   const int j = tp->k_base + it;
+  const int n0 = blk * m.bn;
+  const int nloc = min(m.bn, m.n_nodes - n0);
+  const T* Rin = static_cast<const T*>(tp->rec[j & 1]);
+  T* P = static_cast<T*>(tp->p);
+  T* Dd = static_cast<T*>(tp->d);
+  // Loads that do not depend on the step scalars go out first, so that
+  // their latency overlaps the reduction of the partial sums: the run
+  // state, the block's visit ranges and this thread's first owned node.
+  const int state_in = ldg(&sc->state);
+  const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
+  const int ln0 = threadIdx.x;
+  T rc0[4 * D], pv0[D], dv0[D];
+  int bits0 = 0;
+  if (ln0 < nloc) {
+    load_record<D, T>(Rin, n0 + ln0, rc0);
+    load_nodal<D, T>(P, n0 + ln0, pv0);
+    load_nodal<D, T>(Dd, n0 + ln0, dv0);
+    bits0 = ldg(m.dmask + n0 + ln0);
+  }
   const double* part_in = tp->red.part + (size_t)(j & 1) * kRedSlots * nb;
   double delta, gamma, rr;
-  sum_slots3(part_in, nb, delta, gamma, rr);
+  sum_slots3<NT>(part_in, nb, delta, gamma, rr);
+  if (state_in != 0) return;
   int state = 0;
   double alpha64 = 0.0, beta64 = 0.0;
   if (!(rr == rr) || !(gamma == gamma) || !(delta == delta)) {
@@ -381,28 +395,34 @@ k_fcg(const Task* __restrict__ tasks, const int2* __restrict__ work, int it) {
     }
   }
   if (state != 0) return;
-  const int n0 = blk * m.bn;
-  const int nloc = min(m.bn, m.n_nodes - n0);
-  const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
   using A = AccT<T>;
   A* acc = reinterpret_cast<A*>(smem_raw);
   const T alpha = (T)alpha64, beta = (T)beta64;
   const T* U = static_cast<const T*>(tp->u);
-  const T* Rin = static_cast<const T*>(tp->rec[j & 1]);
-  owner_accumulate<D, T, OP_APPLY, NL, A, true>(m, U, Rin, 0, br, n0, nloc, acc, alpha, beta);
+  owner_accumulate<D, T, OP_APPLY, NL, A, true, NT>(m, U, Rin, 0, br, n0, nloc, acc, alpha,
+                                                    beta);
   T* Rout = static_cast<T*>(tp->rec[(j + 1) & 1]);
-  T* P = static_cast<T*>(tp->p);
-  T* Dd = static_cast<T*>(tp->d);
   const bool first = j == 0;
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
-  for (int ln = threadIdx.x; ln < nloc; ln += kThreads) {
+  for (int ln = ln0; ln < nloc; ln += NT) {
     const int n = n0 + ln;
-    const int bits = ldg(m.dmask + n);
-    T rc[4 * D], out[4 * D];
-    load_record<D, T>(Rin, n, rc);
-    T pv[D], dv[D];
-    load_nodal<D, T>(P, n, pv);
-    load_nodal<D, T>(Dd, n, dv);
+    T rc[4 * D], out[4 * D], pv[D], dv[D];
+    int bits;
+    if (ln == ln0) {
+#pragma unroll
+      for (int q = 0; q < 4 * D; ++q) rc[q] = rc0[q];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        pv[c] = pv0[c];
+        dv[c] = dv0[c];
+      }
+      bits = bits0;
+    } else {
+      load_record<D, T>(Rin, n, rc);
+      load_nodal<D, T>(P, n, pv);
+      load_nodal<D, T>(Dd, n, dv);
+      bits = ldg(m.dmask + n);
+    }
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       const T r = rc[c], w = rc[D + c], so = rc[2 * D + c], mi = rc[3 * D + c];
@@ -430,7 +450,17 @@ k_fcg(const Task* __restrict__ tasks, const int2* __restrict__ work, int it) {
     }
   }
   RedDev outp{tp->red.part + (size_t)((j + 1) & 1) * kRedSlots * nb, nullptr};
-  write_partials(outp, nb, blk, part, 0, 3);
+  write_partials<NT>(outp, nb, blk, part, 0, 3);
+}
+
+// Batched form: workgroup -> (task, node block) through the work table.
+template <int D, typename T, bool NL, int NT>
+__global__ void __launch_bounds__(NT)
+k_fcg(const Task* __restrict__ tasks, const int2* __restrict__ work, int it) {
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  fcg_iteration<D, T, NL, NT>(tp, wk.y, it);
 }
 
 // -------------------------------------------------- alternative scatters
@@ -713,26 +743,38 @@ void launch_energy(Ctx* ctx, int dim, int prec, bool diff, const Task* tasks_dev
   ctx->timing_end(FAM_ENERGY, ev);
 }
 
+// Threads per workgroup of the fused iteration: enough that every thread
+// evaluates about one element visit in a single round of dependent loads
+// where the registers allow (2D linear), fewer where the element state is
+// larger.
+#ifndef PFEM_FCG_NT2
+#define PFEM_FCG_NT2 256
+#endif
+#ifndef PFEM_FCG_NT3
+#define PFEM_FCG_NT3 256
+#endif
+
 void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nl, const Task* tasks,
                      const int2* work, int n_work, int bn_max, int it) {
   if (n_work <= 0) return;
   hipEvent_t ev = nullptr;
   ctx->timing_begin(FAM_FUSED, &ev);
-  dim3 grid(n_work), block(kThreads);
   hipStream_t s = ctx->stream;
   const size_t s32 = (size_t)bn_max * dim * sizeof(AccT<float>);
   const size_t s64 = (size_t)bn_max * dim * sizeof(AccT<double>);
-#define PFEM_FCG(DD, TT, NLV, SM) hipLaunchKernelGGL((k_fcg<DD, TT, NLV>), grid, block, SM, s, tasks, work, it)
+  dim3 grid(n_work);
+#define PFEM_FCG(DD, TT, NLV, SM, NTV) \
+  hipLaunchKernelGGL((k_fcg<DD, TT, NLV, NTV>), grid, dim3(NTV), SM, s, tasks, work, it)
   if (!nl) {
-    if (dim == 2 && prec == PFEM_FP32) PFEM_FCG(2, float, false, s32);
-    else if (dim == 2) PFEM_FCG(2, double, false, s64);
-    else if (prec == PFEM_FP32) PFEM_FCG(3, float, false, s32);
-    else PFEM_FCG(3, double, false, s64);
+    if (dim == 2 && prec == PFEM_FP32) PFEM_FCG(2, float, false, s32, PFEM_FCG_NT2);
+    else if (dim == 2) PFEM_FCG(2, double, false, s64, 256);
+    else if (prec == PFEM_FP32) PFEM_FCG(3, float, false, s32, PFEM_FCG_NT3);
+    else PFEM_FCG(3, double, false, s64, 256);
   } else {
-    if (dim == 2 && prec == PFEM_FP32) PFEM_FCG(2, float, true, s32);
-    else if (dim == 2) PFEM_FCG(2, double, true, s64);
-    else if (prec == PFEM_FP32) PFEM_FCG(3, float, true, s32);
-    else PFEM_FCG(3, double, true, s64);
+    if (dim == 2 && prec == PFEM_FP32) PFEM_FCG(2, float, true, s32, 256);
+    else if (dim == 2) PFEM_FCG(2, double, true, s64, 256);
+    else if (prec == PFEM_FP32) PFEM_FCG(3, float, true, s32, 256);
+    else PFEM_FCG(3, double, true, s64, 256);
   }
 #undef PFEM_FCG
   PFEM_HIP(hipGetLastError());

@@ -319,8 +319,12 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
   // 7. owner node blocks
   int bn = block_nodes;
   if (bn <= 0) {
+    // about 1200 blocks on large meshes (fills the chip, bounds the halo
+    // revisits), at least 256 nodes per block on small ones: the fused PCG
+    // launch sums every block's partials in every block, which grows with
+    // the square of the block count
     const int64_t target = 1200;
-    bn = (int)std::min<int64_t>(2048, std::max<int64_t>(64, ((N / target) + 31) / 32 * 32));
+    bn = (int)std::min<int64_t>(2048, std::max<int64_t>(256, ((N / target) + 31) / 32 * 32));
   }
   require(bn <= block_nodes_max(), PFEM_E_INVALID_ARG, "block_nodes too large");
   m->bn = bn;

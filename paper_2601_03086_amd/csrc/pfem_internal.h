@@ -36,6 +36,13 @@ inline void require(bool ok, pfem_status code, const std::string& msg) {
   if (!ok) throw Error{code, msg};
 }
 
+// Native vector types: HIP's float2/double2/int4 wrappers copy through
+// generic references, which would turn a global load back into a flat one.
+typedef float pf2 __attribute__((ext_vector_type(2)));
+typedef float pf4 __attribute__((ext_vector_type(4)));
+typedef double pd2 __attribute__((ext_vector_type(2)));
+typedef int pi4 __attribute__((ext_vector_type(4)));
+
 // ------------------------------------------------------- device descriptors
 // Everything a kernel needs to know about one finalized mesh (POD).
 struct MeshDev {
@@ -232,12 +239,6 @@ template <typename T>
 __device__ __forceinline__ T ldg(const T* p) {
   return *(const PFEM_GLOBAL T*)p;
 }
-// Native vector types: HIP's float2/double2/int4 wrappers copy through
-// generic references, which would turn a global load back into a flat one.
-typedef float pf2 __attribute__((ext_vector_type(2)));
-typedef float pf4 __attribute__((ext_vector_type(4)));
-typedef double pd2 __attribute__((ext_vector_type(2)));
-typedef int pi4 __attribute__((ext_vector_type(4)));
 template <typename T>
 __device__ __forceinline__ void stg(T* p, T v) {
   *(PFEM_GLOBAL T*)p = v;

@@ -19,10 +19,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum of v over the workgroup, returned to every thread.
-template <int NS>
+// Sum of v over the workgroup (NT threads), returned to every thread.
+template <int NS, int NT = kThreads>
 __device__ __forceinline__ void block_sum_all(double (&v)[NS]) {
-  __shared__ double sm[NS * (kThreads / 64)];
+  __shared__ double sm[NS * (NT / 64)];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
 #pragma unroll
@@ -37,17 +37,18 @@ __device__ __forceinline__ void block_sum_all(double (&v)[NS]) {
   for (int k = 0; k < NS; ++k) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) s += sm[w * NS + k];
+    for (int w = 0; w < NT / 64; ++w) s += sm[w * NS + k];
     v[k] = s;
   }
 }
 
 // Store this workgroup's partials of slots [k0, k1).  A kernel must never
 // store a slot that other workgroups of the same launch are still reading.
+template <int NT = kThreads>
 __device__ __forceinline__ void write_partials(const RedDev& red, int nb, int blk,
                                                double (&v)[kRedSlots], int k0, int k1) {
   if (red.part == nullptr) return;
-  block_sum_all<kRedSlots>(v);
+  block_sum_all<kRedSlots, NT>(v);
   if (threadIdx.x == 0) {
     for (int k = k0; k < k1; ++k) stg(red.part + (size_t)k * nb + blk, v[k]);
   }
@@ -67,15 +68,16 @@ __device__ __forceinline__ void sum_slots2(const double* part, int nb, int k0, i
 }
 
 // Totals of slots 0, 1, 2 over all blocks (fixed order), in every thread.
+template <int NT = kThreads>
 __device__ __forceinline__ void sum_slots3(const double* part, int nb, double& s0,
                                            double& s1, double& s2) {
   double v[3] = {0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nb; b += kThreads) {
+  for (int b = threadIdx.x; b < nb; b += NT) {
     v[0] += ldg(part + b);
     v[1] += ldg(part + (size_t)nb + b);
     v[2] += ldg(part + (size_t)2 * nb + b);
   }
-  block_sum_all<3>(v);
+  block_sum_all<3, NT>(v);
   s0 = v[0];
   s1 = v[1];
   s2 = v[2];
