@@ -333,9 +333,10 @@ def main():
         mesh.solve(u0=u0, **opts)
     # zero-start reference solve (not timed in the headline)
     _, rz, _ = mesh.solve(u0=None, **opts)
-    # the dominant kernel's duration: HIP events around one launch in 16 of
-    # the timed solves (sampling keeps the event pairs from perturbing them)
-    ctx.set_timing([FAM_FUSED], sample_every=16)
+    # the dominant kernel's duration: HIP events around each chunk of
+    # consecutive fused-iteration launches of the timed solves (chunks that
+    # ran past convergence are discarded), divided by the launches in it
+    ctx.set_timing([FAM_FUSED])
     ctx.reset_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -127,12 +127,13 @@ const char* pfem_version(void);
  * bracketed by HIP events on the context stream and its elapsed time is
  * accumulated per family.  Families: 0 = K.v / Hessian-vector apply,
  * 1 = internal force, 2 = energy, 3 = Jacobi diagonal, 4 = PCG vector
- * update, 5 = direction update, 6 = pipelined PCG iteration (matvec and
- * vector updates in one launch).  `family_mask`: bit f times family f
- * (0 = off).  Reading synchronises the stream. */
+ * update, 5 = direction update, 6 = fused PCG iteration (matvec and
+ * vector updates in one launch; timed per chunk of consecutive launches,
+ * chunks that ran past convergence discarded).  `family_mask`: bit f times
+ * family f (0 = off).  Reading synchronises the stream. */
 pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int family_mask);
-/* Time only every `every`-th launch of each timed family (default 1), so
- * that the event pairs barely perturb a long launch sequence. */
+/* Time only every `every`-th launch of each per-launch timed family
+ * (default 1), so that the event pairs barely perturb a long sequence. */
 pfem_status pfem_ctx_set_timing_sample(pfem_ctx* ctx, int every);
 pfem_status pfem_ctx_kernel_time(pfem_ctx* ctx, int family, int64_t* launches,
                                  double* total_ms);

@@ -757,8 +757,6 @@ void launch_energy(Ctx* ctx, int dim, int prec, bool diff, const Task* tasks_dev
 void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nl, const Task* tasks,
                      const int2* work, int n_work, int bn_max, int it) {
   if (n_work <= 0) return;
-  hipEvent_t ev = nullptr;
-  ctx->timing_begin(FAM_FUSED, &ev);
   hipStream_t s = ctx->stream;
   const size_t s32 = (size_t)bn_max * dim * sizeof(AccT<float>);
   const size_t s64 = (size_t)bn_max * dim * sizeof(AccT<double>);
@@ -778,7 +776,6 @@ void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nl, const Task* tasks,
   }
 #undef PFEM_FCG
   PFEM_HIP(hipGetLastError());
-  ctx->timing_end(FAM_FUSED, ev);
 }
 
 int block_nodes_max() { return 4096; }

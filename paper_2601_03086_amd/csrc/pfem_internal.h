@@ -161,6 +161,7 @@ struct Ctx {
     hipEvent_t a, b;
     int64_t key;          // launch group (-1: none)
     int it;               // iteration index inside the group
+    int count;            // launches between the two events
   };
   std::vector<Timed> pending;
   std::vector<hipEvent_t> event_pool;
@@ -169,9 +170,14 @@ struct Ctx {
   int64_t next_key = 0;
   void timing_begin(int fam, hipEvent_t* a);
   void timing_end(int fam, hipEvent_t a);
+  // One event pair around `count` consecutive launches of one family (no
+  // sampling): the average per launch excludes the event overhead.
+  void timing_begin_run(int fam, hipEvent_t* a);
+  void timing_end_run(int fam, hipEvent_t a, int count);
   void drain_timing();
-  // Forget timed launches of group `key` with iteration index >= keep: they
-  // returned at once because their solve had already converged.
+  // Forget timed launches of group `key` with iteration index >= keep (and
+  // runs that include one): they returned at once because their solve had
+  // already converged.
   void drop_noop(int64_t key, int keep);
 };
 

@@ -89,7 +89,22 @@ void Ctx::timing_begin(int fam, hipEvent_t* a) {
   PFEM_HIP(hipEventRecord(*a, stream));
 }
 
-void Ctx::timing_end(int fam, hipEvent_t a) {
+void Ctx::timing_end(int fam, hipEvent_t a) { timing_end_run(fam, a, 1); }
+
+void Ctx::timing_begin_run(int fam, hipEvent_t* a) {
+  *a = nullptr;
+  if (!(timing & (1 << fam))) return;
+  if (event_pool.empty()) {
+    hipEvent_t e;
+    PFEM_HIP(hipEventCreate(&e));
+    event_pool.push_back(e);
+  }
+  *a = event_pool.back();
+  event_pool.pop_back();
+  PFEM_HIP(hipEventRecord(*a, stream));
+}
+
+void Ctx::timing_end_run(int fam, hipEvent_t a, int count) {
   if (a == nullptr) return;
   if (event_pool.empty()) {
     hipEvent_t e;
@@ -99,7 +114,7 @@ void Ctx::timing_end(int fam, hipEvent_t a) {
   hipEvent_t b = event_pool.back();
   event_pool.pop_back();
   PFEM_HIP(hipEventRecord(b, stream));
-  pending.push_back({fam, a, b, cur_key, cur_it});
+  pending.push_back({fam, a, b, cur_key, count > 1 ? 0 : cur_it, count});
   if (pending.size() > 8192 && cur_key < 0) drain_timing();
 }
 
@@ -107,7 +122,7 @@ void Ctx::drop_noop(int64_t key, int keep) {
   std::vector<Timed> kept;
   kept.reserve(pending.size());
   for (const Timed& t : pending) {
-    if (t.key == key && t.it >= keep) {
+    if (t.key == key && t.it + t.count > keep) {
       event_pool.push_back(t.a);
       event_pool.push_back(t.b);
     } else {
@@ -123,7 +138,7 @@ void Ctx::drain_timing() {
     float ms = 0.f;
     PFEM_HIP(hipEventElapsedTime(&ms, t.a, t.b));
     fam_ms[t.fam] += ms;
-    fam_launches[t.fam] += 1;
+    fam_launches[t.fam] += t.count;
     event_pool.push_back(t.a);
     event_pool.push_back(t.b);
   }

@@ -323,11 +323,14 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
     Uploaded ua = upload_group(ctx, g, apply);
     ctx->cur_key = key;
     if (g.fused) {
+      // the chunk is timed as one run of k launches
+      hipEvent_t ev = nullptr;
+      ctx->timing_begin_run(FAM_FUSED, &ev);
       for (int it = 0; it < k; ++it) {
-        ctx->cur_it = it;
         launch_fcg_iter(ctx, g.dim, g.prec, g.nl, ua.tasks, ua.work, ua.n_work, ua.bn_max, it);
         *nl += 1;
       }
+      ctx->timing_end_run(FAM_FUSED, ev, k);
       ctx->cur_key = -1;
       ctx->cur_it = 0;
       continue;
