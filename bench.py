@@ -18,8 +18,11 @@ events on the library stream during the timed solves.
 Other modes (not the default line):
   --kv-only N        N back-to-back K.v launches, or with --kv-kernel fused
                      about N fused PCG iterations (for rocprofv3 counters)
-  --parse-pmc DIR    turn rocprofv3 FETCH_SIZE / WRITE_SIZE CSVs into the
-                     traffic summary under profiles/
+  --parse-pmc DIR    mean counter values per kernel from rocprofv3 CSVs
+  --config NAME      c1 | c3 | c4 | sweep | rotate | serve: the other
+                     workloads (unit square, 3D Neo-Hookean box, 64-mesh
+                     batch, K.v size sweep, rotating-buffer K.v, serving
+                     stream), one JSON line each
 """
 import argparse
 import glob
@@ -29,6 +32,8 @@ import os
 import subprocess
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -145,6 +150,331 @@ def traffic_entry():
     if d.get("kernel_hash") != kernel_hash():
         return None   # kernel changed since the counters were taken
     return d.get("traffic_bytes_per_launch")
+
+
+# ------------------------------------------------------- per-config legs
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _kv_rate(ctx, mesh, prec, reps=100, trials=5, warm=10, hvp_state=None):
+    """Median over trials of the average K.v (or HVP at hvp_state) time in
+    microseconds, internal layout, events around `reps` back-to-back launches."""
+    import torch
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    x = mesh.permute(torch.randn(mesh.n_dof, dtype=dt, device="cuda"), True, prec)
+    y = torch.empty_like(x)
+    u = None
+    if hvp_state is not None:
+        u = mesh.permute(torch.as_tensor(hvp_state, dtype=dt, device="cuda"), True, prec)
+    call = ((lambda: mesh.hvp(u, x, prec=prec, layout="internal", out=y)) if u is not None
+            else (lambda: mesh.apply_K(x, prec=prec, layout="internal", out=y)))
+    for _ in range(warm):
+        call()
+    ts = []
+    for _ in range(trials):
+        ctx.set_timing([FAM_APPLY])
+        ctx.reset_timing()
+        for _ in range(reps):
+            call()
+        n, ms = ctx.kernel_time(FAM_APPLY)
+        ts.append(ms / n * 1e3)
+    ctx.set_timing(())
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def _timed_solve(mesh, **kw):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, rep, _ = mesh.solve(**kw)
+    torch.cuda.synchronize()
+    return u, rep, time.perf_counter() - t0
+
+
+def run_c1():
+    """Unit square, FP64: solves from zero and from a warm start to 1e-10,
+    and the FP64 K.v rate."""
+    import synth
+    import torch
+    from paper_2601_03086_amd import core
+    prob = synth.unit_square_c1()
+    ctx = core.Context(0)
+    mesh = core.Mesh.from_problem(ctx, prob)
+    uref, _, _ = mesh.solve(tol=1e-12, prec="fp64", device_io=True)
+    u0 = synth.warm_start_guess(uref.cpu().numpy(), prob.coords, prob.dir_nodes, seed=11)
+    out = {"config": "C1 unit square, 2048 triangles, plane stress, FP64 PCG to 1e-10"}
+    for name, guess in (("zero", None), ("warm", u0)):
+        best = None
+        for _ in range(5):
+            _, rep, t = _timed_solve(mesh, u0=guess, tol=1e-10, prec="fp64", history_cap=1)
+            best = t if best is None else min(best, t)
+        out[name] = {"ms": round(best * 1e3, 3), "kv": rep["kv_count"],
+                     "rel_residual_initial": rep["rel_residual_initial"]}
+    us = _kv_rate(ctx, mesh, "fp64")
+    out["kv_fp64_us"] = round(us, 3)
+    out["kv_fp64_GDOF_s"] = round(prob.n_dof / us * 1e-3, 3)
+    print(json.dumps(out), flush=True)
+
+
+def run_c3():
+    """3D Neo-Hookean box, about 1e6 tets: FP32 HVP rate at the solution;
+    zero-start (10 load steps) and warm-start (final step) FP32 Newton
+    solves to 1e-8 next to the FP64 reference solve."""
+    import synth
+    import torch
+    from paper_2601_03086_amd import core
+    t0 = time.perf_counter()
+    prob = synth.box_problem(3, 1003)
+    _log(f"# C3 box: {prob.n_elems} tets, {prob.n_dof} DOFs, generated in "
+         f"{time.perf_counter() - t0:.1f}s")
+    ctx = core.Context(0)
+    t0 = time.perf_counter()
+    mesh = core.Mesh.from_problem(ctx, prob)
+    _log(f"# preprocessed + uploaded in {time.perf_counter() - t0:.1f}s, "
+         f"{mesh.info['n_blocks']} blocks of {mesh.info['block_nodes']}")
+    uref, rref, tref = _timed_solve(mesh, tol=1e-10, prec="fp64", n_load_steps=10,
+                                    device_io=True, history_cap=1)
+    _log(f"# FP64 reference (zero start, 10 load steps, 1e-10): {tref:.2f}s "
+         f"{rref['newton_iters']} Newton, {rref['kv_count']} HVP")
+    uref_h = uref.cpu().numpy()
+    u0 = synth.warm_start_guess(uref_h, prob.coords, prob.dir_nodes, seed=3003)
+    out = {"config": f"C3 Neo-Hookean box, {prob.n_elems} tets / {prob.n_dof} DOFs",
+           "fp64_zero_1e-10": {"s": round(tref, 3), "newton": rref["newton_iters"],
+                               "hvp": rref["kv_count"], "status": rref["status_name"]}}
+    for name, guess in (("zero", None), ("warm", u0)):
+        u, rep, t = _timed_solve(mesh, u0=guess, tol=1e-8, prec="fp32", n_load_steps=10,
+                                 history_cap=1)
+        err = float(np.linalg.norm(u - uref_h) / np.linalg.norm(uref_h))
+        out[f"fp32_{name}_1e-8"] = {
+            "s": round(t, 3), "newton": rep["newton_iters"], "hvp": rep["kv_count"],
+            "load_steps": rep["load_steps_done"], "line_search_evals": rep["line_search_evals"],
+            "rel_residual_initial": rep["rel_residual_initial"],
+            "rel_residual_final": rep["rel_residual_final"], "rel_err_vs_ref": err,
+            "status": rep["status_name"],
+            "hvp_GDOF_s_in_solve": round(rep["kv_count"] * prob.n_dof / t / 1e9, 3)}
+        _log(f"# FP32 {name}: {t:.2f}s {rep['newton_iters']} Newton {rep['kv_count']} HVP")
+    us = _kv_rate(ctx, mesh, "fp32", hvp_state=uref_h)
+    b = alg_bytes_kv(prob.n_elems, prob.n_nodes, 3) + 3 * 4 * prob.n_nodes
+    out["hvp_fp32_us"] = round(us, 2)
+    out["hvp_fp32_GDOF_s"] = round(prob.n_dof / us * 1e-3, 2)
+    out["hvp_fp32_alg_GBps"] = round(b / us * 1e-3, 1)
+    us_lin = _kv_rate(ctx, mesh, "fp32")
+    out["note"] = "HVP timed at the reference solution; K.v below is the HVP at u = 0"
+    out["hvp_at_zero_fp32_us"] = round(us_lin, 2)
+    print(json.dumps(out), flush=True)
+
+
+def run_c4():
+    """64 plates (5k-20k triangles, alternating linear / Neo-Hookean): the
+    differentiable energy, its gradient and an HVP of the whole batch, one
+    launch per kernel family."""
+    import synth
+    import torch
+    from paper_2601_03086_amd import _lib as L, core
+    members = synth.batch_c4(64)
+    ctx = core.Context(0)
+    meshes = [core.Mesh.from_problem(ctx, p) for p, _ in members]
+    b = core.Batch(ctx, meshes)
+    perms = [m.query(L.PFEM_Q_PERM) for m in meshes]
+    parts = []
+    for (p, u), pr in zip(members, perms):
+        o = np.empty_like(u, dtype=np.float64)
+        o.reshape(-1, 2)[pr] = u.reshape(-1, 2)
+        parts.append(o)
+    u = torch.tensor(np.concatenate(parts), device="cuda", dtype=torch.float32)
+    v = torch.randn_like(u)
+    n_dof = b.n_dof
+    n_el = sum(p.n_elems for p, _ in members)
+    res = {"config": f"C4 batch: 64 plates, {n_el} triangles, {n_dof} DOFs, FP32"}
+    for name, fn in (("energy", lambda: b.energy(u)), ("force", lambda: b.force(u)),
+                     ("hvp", lambda: b.hvp(u, v))):
+        for _ in range(5):
+            fn()
+        ts = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(ctx.stream)
+            for _ in range(20):
+                fn()
+            e1.record(ctx.stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / 20 * 1e3)
+        ts.sort()
+        us = ts[2]
+        res[name] = {"us": round(us, 2), "GDOF_s": round(n_dof / us * 1e-3, 2)}
+    res["fwd_bwd_hvp_us"] = round(sum(res[k]["us"] for k in ("energy", "force", "hvp")), 2)
+    print(json.dumps(res), flush=True)
+
+
+def run_sweep(spec):
+    """K.v roofline sweep over generator meshes of the given sizes
+    ("2d:2e5,3d:1e6,..." = element counts)."""
+    import torch
+    import synth
+    from paper_2601_03086_amd import core
+    ctx = core.Context(0)
+    for item in spec.split(","):
+        kind, n = item.split(":")
+        n = float(n)
+        t0 = time.perf_counter()
+        if kind == "2d":
+            nx = int(round((n / 2) ** 0.5))
+            prob = synth.structured_plate(nx, nx, seed=7)
+        else:
+            nx = int(round((n / 24) ** (1 / 3)))
+            prob = synth.structured_box(nx, nx, 4 * nx, seed=7)
+        _log(f"# {kind} {prob.n_elems} elements generated in {time.perf_counter() - t0:.1f}s")
+        t0 = time.perf_counter()
+        mesh = core.Mesh.from_problem(ctx, prob)
+        _log(f"# preprocessed + uploaded in {time.perf_counter() - t0:.1f}s")
+        d = prob.dim
+        for prec in ("fp32", "fp64"):
+            s = 4 if prec == "fp32" else 8
+            us = _kv_rate(ctx, mesh, prec, reps=50, trials=5, warm=5)
+            b_alg = alg_bytes_kv(prob.n_elems, prob.n_nodes, d, s=s, s_m=s)
+            print(json.dumps({
+                "mesh": f"{kind} {prob.n_elems} elems {prob.n_nodes} nodes", "prec": prec,
+                "block_nodes": mesh.info["block_nodes"],
+                "visits_per_elem": round(mesh.info["owner_elem_visits"] / prob.n_elems, 3),
+                "alg_bytes": b_alg, "avg_us": round(us, 2),
+                "alg_GBps": round(b_alg / us * 1e-3, 1),
+                "frac_hbm": round(b_alg / us * 1e-3 / HBM_PEAK_GBS, 4),
+                "GDOF_s": round(prob.n_dof / us * 1e-3, 2)}), flush=True)
+        mesh.close()
+        del prob, mesh
+        torch.cuda.empty_cache()
+
+
+def run_rotate(copies, kind="c2"):
+    """K.v over `copies` distinct device copies of the plate (or the 3D box),
+    applied round-robin so that no copy is in a cache when it is applied."""
+    import torch
+    import synth
+    from paper_2601_03086_amd import core
+    ctx = core.Context(0)
+    prob = c2_problem() if kind == "c2" else synth.box_problem(3, 1003, model="lin_3d")
+    meshes, xs, ys = [], [], []
+    t0 = time.perf_counter()
+    for i in range(copies):
+        m = core.Mesh.from_problem(ctx, prob)
+        meshes.append(m)
+        xs.append(m.permute(torch.randn(prob.n_dof, dtype=torch.float32, device="cuda"),
+                            True, "fp32"))
+        ys.append(torch.empty_like(xs[-1]))
+        if i % 16 == 15:
+            _log(f"# {i + 1} copies in {time.perf_counter() - t0:.1f}s")
+    d = prob.dim
+    b_alg = alg_bytes_kv(prob.n_elems, prob.n_nodes, d)
+    ws = b_alg * copies
+    for r in range(2):
+        for m, x, y in zip(meshes, xs, ys):
+            m.apply_K(x, prec="fp32", layout="internal", out=y)
+    ts = []
+    for _ in range(5):
+        ctx.set_timing([FAM_APPLY])
+        ctx.reset_timing()
+        for r in range(3):
+            for m, x, y in zip(meshes, xs, ys):
+                m.apply_K(x, prec="fp32", layout="internal", out=y)
+        n, ms = ctx.kernel_time(FAM_APPLY)
+        ts.append(ms / n * 1e3)
+    ctx.set_timing(())
+    ts.sort()
+    us = ts[2]
+    print(json.dumps({"mesh": f"{kind} x {copies} copies", "working_set_alg_bytes": ws,
+                      "avg_us": round(us, 2), "alg_GBps": round(b_alg / us * 1e-3, 1),
+                      "frac_hbm": round(b_alg / us * 1e-3 / HBM_PEAK_GBS, 4),
+                      "GDOF_s": round(prob.n_dof / us * 1e-3, 2)}), flush=True)
+
+
+def run_serve(n_requests=512, rate=200.0, pool=24, budget_gb=96, max_slots=64):
+    """Serving stream: Poisson arrivals replayed open-loop into the server;
+    requests drawn from a pool of distinct meshes (70% plates, 30% 3D
+    Neo-Hookean boxes, 1e4-5e5 elements), each with a warm start
+    (reference + 1% smooth noise); tol 1e-8, FP32 mode.  Baselines: the
+    pool's requests solved one at a time from zero and from the warm start."""
+    import torch
+    import synth
+    from paper_2601_03086_amd import core
+    ctx = core.Context(0)
+    descs = synth.serving_stream(n_requests=pool, rate=rate)
+    probs, hmeshes, guesses, refs = [], [], [], []
+    t0 = time.perf_counter()
+    for dsc in descs:
+        p = synth.serving_problem(dsc)
+        probs.append(p)
+        dm = core.Mesh.from_problem(ctx, p)
+        kw = dict(tol=1e-10, prec="fp64", history_cap=1)
+        if p.nonlinear:
+            kw["n_load_steps"] = p.n_load_steps
+        uref, rr, _ = dm.solve(**kw)
+        dm.close()
+        refs.append(rr)
+        guesses.append(synth.warm_start_guess(uref, p.coords, p.dir_nodes, seed=dsc["seed"] + 7))
+        hmeshes.append(core.Mesh.from_problem(None, p))
+        _log(f"# pool {len(probs)}/{pool}: {dsc['kind']} {p.n_elems} elems, ref "
+             f"{rr['status_name']} ({time.perf_counter() - t0:.0f}s)")
+    opts = dict(tol=1e-8, prec="fp32")
+
+    def solve_kw(p):
+        return dict(opts, n_load_steps=p.n_load_steps) if p.nonlinear else dict(opts)
+
+    # baselines: one at a time on a device mesh (uploaded beforehand)
+    base = {}
+    for name in ("zero", "warm"):
+        tt, kv = 0.0, 0
+        for i, p in enumerate(probs):
+            dm = core.Mesh.from_problem(ctx, p)
+            _, rep, t = _timed_solve(dm, u0=guesses[i] if name == "warm" else None,
+                                     history_cap=1, **solve_kw(p))
+            dm.close()
+            tt += t
+            kv += rep["kv_count"]
+        base[name] = {"mean_ms": round(tt / len(probs) * 1e3, 2), "solves_per_s":
+                      round(len(probs) / tt, 2), "kv_mean": kv / len(probs)}
+        _log(f"# sequential {name}: {tt / len(probs) * 1e3:.1f} ms per request")
+    # the stream
+    arrivals = synth.serving_stream(n_requests=n_requests, rate=rate)
+    srv = core.Server(ctx, int(budget_gb * (1 << 30)), max_slots=max_slots)
+    t_start = time.perf_counter()
+    done, results = set(), {}
+    nxt = 0
+    while len(done) < n_requests:
+        now = time.perf_counter() - t_start
+        while nxt < n_requests and arrivals[nxt]["t_arrive"] <= now:
+            i = nxt % pool
+            srv.submit(nxt, hmeshes[i], u0=guesses[i], **solve_kw(probs[i]))
+            nxt += 1
+        for rid in srv.poll():
+            done.add(rid)
+            _, r = srv.result(rid)
+            results[rid] = r
+        if len(done) and len(done) % 64 == 0 and len(done) != getattr(run_serve, "_last", -1):
+            run_serve._last = len(done)
+            _log(f"# stream: {len(done)}/{n_requests} done at {now:.1f}s")
+        time.sleep(0.0005)
+    st = srv.stats()
+    srv.close()
+    lat = sorted(r["t_done"] - r["t_submit"] for r in results.values())
+    t_first = min(r["t_submit"] for r in results.values())
+    t_last = max(r["t_done"] for r in results.values())
+    ok = sum(1 for r in results.values() if r["status"] in (0, 2))
+    worst = max(r["rel_residual_final"] for r in results.values())
+    print(json.dumps({
+        "config": f"C5 serving stream: {n_requests} requests from a pool of {pool} meshes "
+                  f"(plates and 3D Neo-Hookean boxes, 1e4-5e5 elements), Poisson arrivals "
+                  f"{rate}/s, warm starts, tol 1e-8, FP32 mode",
+        "offered_per_s": rate, "achieved_solves_per_s": round(n_requests / (t_last - t_first), 2),
+        "latency_ms": {"p50": round(lat[len(lat) // 2] * 1e3, 1),
+                       "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))] * 1e3, 1),
+                       "max": round(lat[-1] * 1e3, 1)},
+        "ok": ok, "worst_rel_residual": worst, "peak_live": st["peak_live"],
+        "peak_bytes": st["peak_bytes"], "launches": st["launches"],
+        "sequential_zero": base["zero"], "sequential_warm": base["warm"]}), flush=True)
 
 
 # --------------------------------------------------------------------- main
@@ -299,6 +629,15 @@ def main():
                     help="--kv-only: K.v launches or fused PCG iterations")
     ap.add_argument("--kv-large", default=None,
                     help='e.g. "2d:2000,3d:60": K.v roofline sweep on large meshes')
+    ap.add_argument("--config", default=None,
+                    choices=["c1", "c3", "c4", "sweep", "rotate", "serve"],
+                    help="other workloads (one JSON line each, not the headline)")
+    ap.add_argument("--sizes", default="2d:2e5,2d:1e6,2d:4e6,2d:1.6e7,3d:1e6,3d:4e6,3d:1.6e7",
+                    help="--config sweep sizes (element counts)")
+    ap.add_argument("--copies", type=int, default=192, help="--config rotate copies")
+    ap.add_argument("--requests", type=int, default=512, help="--config serve")
+    ap.add_argument("--rate", type=float, default=200.0, help="--config serve arrivals/s")
+    ap.add_argument("--pool", type=int, default=24, help="--config serve distinct meshes")
     args = ap.parse_args()
     if args.cpu_baseline_worker:
         cpu_baseline_worker()
@@ -319,6 +658,12 @@ def main():
         return
     if args.kv_large:
         run_kv_large(args.kv_large)
+        return
+    if args.config:
+        {"c1": run_c1, "c3": run_c3, "c4": run_c4,
+         "sweep": lambda: run_sweep(args.sizes),
+         "rotate": lambda: run_rotate(args.copies),
+         "serve": lambda: run_serve(args.requests, args.rate, args.pool)}[args.config]()
         return
     import torch
     t_setup = time.perf_counter()

@@ -17,7 +17,11 @@
   load-step Dirichlet values, load-step tractions); the step
   length s follows Armijo backtracking on the total potential (factor 1/2,
   sufficient-decrease constant 1e-4, at most 20 halvings), rejecting any
-  trial state with J <= 0; no load-step predictor.
+  trial state with J <= 0; an energy change within the float64 rounding
+  level of its summed terms (64 eps times their magnitudes) counts as
+  inconclusive and the step is taken, because near convergence a Newton
+  step lowers the energy by O(|r|^2), below what the sum resolves; no
+  load-step predictor.
 """
 import numpy as np
 import scipy.sparse.linalg as spla
@@ -113,6 +117,19 @@ def _residual_free(m, u):
     return m.gradient(u)[m.free_dofs]
 
 
+def _energy_change(m, psi0, u, ut):
+    """Pi(ut) - Pi(u) summed element by element, and the sum of the
+    magnitudes of its terms (the scale of its rounding error).  +inf if an
+    element of ut has J <= 0."""
+    psit = m.energy_density(ut)
+    if not np.all(np.isfinite(psit)):
+        return np.inf, 0.0
+    w = m.f_ext * (ut - u)
+    de = float(np.sum(m.vol * (psit - psi0)) - np.sum(w))
+    size = float(np.sum(m.vol * (np.abs(psi0) + np.abs(psit))) + np.sum(np.abs(w)))
+    return de, size
+
+
 def newton(prob, u0=None, tol=1e-8, n_load_steps=None, max_newton=50,
            linear_solver="direct", lin_tol=1e-12, armijo_c=1e-4,
            max_halvings=20):
@@ -155,15 +172,19 @@ def newton(prob, u0=None, tol=1e-8, n_load_steps=None, max_newton=50,
                 delta = spla.spsolve(KT, -r)
             else:
                 delta, _, _, _ = pcg(KT.tocsr(), -r, None, lin_tol)
-            e0 = m.energy(u)
+            psi0 = m.energy_density(u)
             slope = r @ delta
             s = 1.0
             ok = False
             for _ in range(max_halvings + 1):
                 ut = u.copy()
                 ut[fr] += s * delta
-                et = m.energy(ut)
-                if np.isfinite(et) and et - e0 <= armijo_c * s * slope:
+                de, size = _energy_change(m, psi0, u, ut)
+                # Armijo; a change within the rounding level of the summed
+                # terms is inconclusive and the step is taken (the residual
+                # test then decides convergence)
+                if np.isfinite(de) and (de <= armijo_c * s * slope
+                                        or abs(de) <= 64 * np.finfo(float).eps * size):
                     ok = True
                     break
                 s *= 0.5

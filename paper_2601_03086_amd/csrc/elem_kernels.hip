@@ -529,8 +529,10 @@ __global__ void __launch_bounds__(kThreads) k_alt_fixup(Task t) {
 // Pi = sum_e vol_e Psi_e - f_ext . u over the elements a block owns (each
 // element once) and the DOFs it owns.  With DIFF the kernel returns
 // Pi(u + s v) - Pi(u) accumulated element by element in float64 (no
-// cancellation between two large totals), and counts elements with J <= 0
-// at the trial state.  red.out = (energy or difference, #inverted, 0, 0).
+// cancellation between two large totals), counts elements with J <= 0 at
+// the trial state, and sums the magnitudes of the terms (slot 2) so the
+// caller knows the rounding level of the difference.  Partials: (energy or
+// difference, #inverted, sum of |terms|).
 template <int D, typename TU, typename TV, bool DIFF>
 __global__ void __launch_bounds__(kThreads)
 k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
@@ -611,6 +613,7 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
         part[1] += 1.0;
       } else {
         part[0] += vol * (psi1 - psi0);
+        part[2] += vol * (fabs(psi0) + fabs(psi1));   // size of the summed terms
       }
     } else {
       if (psi0 == __builtin_inf()) part[1] += 1.0;
@@ -621,10 +624,15 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   const size_t g0 = (size_t)n0 * D;
   for (int i = threadIdx.x; i < nloc * D; i += kThreads) {
     const double f = tp->fscale * ldg(m.fext + g0 + i);
-    if (DIFF) part[0] -= s * f * (double)ldg(V + g0 + i);
-    else part[0] -= f * (double)ldg(U + g0 + i);
+    if (DIFF) {
+      const double w = s * f * (double)ldg(V + g0 + i);
+      part[0] -= w;
+      part[2] += fabs(w);
+    } else {
+      part[0] -= f * (double)ldg(U + g0 + i);
+    }
   }
-  write_partials(tp->red, m.n_blocks, blk, part, 0, 2);
+  write_partials(tp->red, m.n_blocks, blk, part, 0, DIFF ? 3 : 2);
 }
 
 // ---------------------------------------------------------------- launchers

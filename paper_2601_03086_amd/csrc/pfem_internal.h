@@ -83,6 +83,7 @@ struct Scalars {
   double bnorm;           // |r| at inner start
   double red[kRedSlots];  // outputs of one-workgroup reductions
   double pa[2], pg[2];    // fused PCG: alpha_j and gamma_j by parity of j
+  double lsred[2];        // line search: slope g.d (first trial)
   int32_t k;              // Krylov iterations done in the current inner solve
   int32_t kmax;           // cap for the current inner solve
   int32_t state;          // 0 running, 1 converged, 2 max-iter, 3 breakdown
@@ -213,8 +214,9 @@ void launch_fcg_init_w(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
 void launch_pcg_init_finish(Ctx* ctx, const Task* tasks_dev, int n_tasks);
 void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nonlinear, const Task* tasks_dev,
                      const int2* work_dev, int n_work, int bn_max, int it);
-// One workgroup per task: red.out[0..1] = sums of partial slots 0 and 1.
-void launch_reduce_store(Ctx* ctx, const Task* tasks_dev, int n_tasks);
+// One workgroup per task: red.out[0..n_slots-1] = sums of partial slots
+// 0..n_slots-1 (n_slots 2 or 3).
+void launch_reduce_store(Ctx* ctx, const Task* tasks_dev, int n_tasks, int n_slots = 2);
 void launch_dot(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
                 const int2* work_dev, int n_work);
 void launch_set_scalars(Ctx* ctx, Scalars* sc, double den, double target2, int kmax,

@@ -264,15 +264,18 @@ k_dot(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   write_partials(tp->red, tp->m.n_blocks, wk.y, part, 0, 1);
 }
 
-// One workgroup per task: red.out[0..1] = totals of partial slots 0 and 1.
+// One workgroup per task: red.out[0..NS-1] = totals of partial slots 0..NS-1.
+template <int NS>
 __global__ void __launch_bounds__(kThreads) k_reduce_store(const Task* __restrict__ tasks) {
   const Task* tp = tasks + blockIdx.x;
   if (!tp->active) return;
-  double s0, s1;
-  sum_slots2(tp->red.part, tp->m.n_blocks, 0, 1, s0, s1);
+  double s0, s1, s2 = 0.0;
+  if constexpr (NS == 3) sum_slots3(tp->red.part, tp->m.n_blocks, s0, s1, s2);
+  else sum_slots2(tp->red.part, tp->m.n_blocks, 0, 1, s0, s1);
   if (threadIdx.x == 0) {
     tp->red.out[0] = s0;
     tp->red.out[1] = s1;
+    if constexpr (NS == 3) tp->red.out[2] = s2;
   }
 }
 
@@ -325,9 +328,12 @@ void launch_dot(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work
                 int n_work) {
   PFEM_VEC_LAUNCH(k_dot, FAM_UPDATE, tasks, work);
 }
-void launch_reduce_store(Ctx* ctx, const Task* tasks, int n_tasks) {
+void launch_reduce_store(Ctx* ctx, const Task* tasks, int n_tasks, int n_slots) {
   if (n_tasks <= 0) return;
-  hipLaunchKernelGGL(k_reduce_store, dim3(n_tasks), dim3(kThreads), 0, ctx->stream, tasks);
+  if (n_slots == 3)
+    hipLaunchKernelGGL(k_reduce_store<3>, dim3(n_tasks), dim3(kThreads), 0, ctx->stream, tasks);
+  else
+    hipLaunchKernelGGL(k_reduce_store<2>, dim3(n_tasks), dim3(kThreads), 0, ctx->stream, tasks);
   PFEM_HIP(hipGetLastError());
 }
 

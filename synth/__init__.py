@@ -10,11 +10,12 @@ Every generator takes an explicit integer seed and uses
 ``numpy.random.Generator(PCG64(seed))``.
 """
 from .problems import (Problem, MODELS, unit_square_c1, plate_problem,
-                       box_problem, batch_c4, serving_stream,
-                       structured_plate, structured_box)
+                       box_problem, c4_member, batch_c4, serving_stream,
+                       serving_problem, structured_plate, structured_box)
 from .fields import rff_field, lifting_weight, warm_start_guess
 
 __all__ = ["Problem", "MODELS", "unit_square_c1", "plate_problem",
-           "box_problem", "batch_c4", "serving_stream", "structured_plate",
+           "box_problem", "c4_member", "batch_c4", "serving_stream",
+           "serving_problem", "structured_plate",
            "structured_box", "rff_field", "lifting_weight",
            "warm_start_guess"]

@@ -339,6 +339,32 @@ def test_newton_load_steps_and_warm_start():
     assert repw["steps"][0]["newton_iters"] < total_zero
 
 
+def test_newton_reaches_tolerances_below_energy_resolution():
+    """Near convergence the energy decrease of a Newton step (O(|r|^2)) is
+    below float64 resolution of the total potential; the line search must
+    still let Newton reach a 1e-13 residual (quadratic convergence), and
+    the result must equal the one at 1e-10 to that accuracy."""
+    coords, conn = mk.patch_3d(3, seed=21, dims=(1.0, 1.0, 2.0))
+    z0 = np.nonzero(coords[:, 2] == 0)[0]
+    z2 = np.nonzero(coords[:, 2] == 2.0)[0]
+    dn = np.concatenate([np.repeat(z0, 3), z2])
+    dc = np.concatenate([np.tile([0, 1, 2], z0.size), np.full(z2.size, 2)])
+    dv = np.concatenate([np.zeros(3 * z0.size), np.full(z2.size, 0.4)])
+    prob = mk.make_problem("nh_3d", coords, conn, param_kind="lame",
+                           p0=np.where(np.arange(conn.shape[0]) % 2 == 0, 1.0, 10.0),
+                           p1=np.where(np.arange(conn.shape[0]) % 2 == 0, 4.0, 40.0),
+                           dir_nodes=dn, dir_comps=dc, dir_values=dv, n_load_steps=2)
+    u13, rep = solve.newton(prob, tol=1e-13)
+    assert rep["status"] == 0
+    hist = rep["steps"][-1]["history"]
+    assert hist[-1] <= 1e-13
+    # quadratic convergence in the last steps: each residual ~ previous^2
+    big = [h for h in hist if h < 1e-2]
+    assert len(big) >= 2 and big[-1] <= 1e3 * big[-2] ** 2 + 1e-15
+    u10, _ = solve.newton(prob, tol=1e-10)
+    assert np.linalg.norm(u13 - u10) <= 1e-8 * np.linalg.norm(u13)
+
+
 # -------------------------------------------------------- preprocessing
 def test_fmix32_published_vectors():
     """MurmurHash3_x86_32 of the empty key with seed s is fmix32(s); the
