@@ -215,6 +215,11 @@ __device__ __forceinline__ void lds_accumulate(A* acc, const int (&nd)[D + 1], i
   }
 }
 
+// Element visits in flight per thread in the fused 2D linear iteration.
+#ifndef PFEM_FCG_EIF
+#define PFEM_FCG_EIF 2
+#endif
+
 // LDS accumulator type of the owner kernel.
 #ifndef PFEM_ACC_F64
 #define PFEM_ACC_F64 1
@@ -229,7 +234,8 @@ using AccT = typename std::conditional<PFEM_ACC_F64 != 0, double, T>::type;
 // two elements in flight: both connectivity rows are loaded, then all
 // gathers of both elements, then the arithmetic.  On return acc[] holds the
 // block's owned DOFs (all threads synchronised).
-template <int D, typename T, int OP, bool NL, typename A, bool FUSED = false, int NT = kThreads>
+template <int D, typename T, int OP, bool NL, typename A, bool FUSED = false, int NT = kThreads,
+          int EIF = 2>
 __device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __restrict__ U,
                                                  const T* __restrict__ V, int mask,
                                                  const pi4 br, int n0, int nloc, A* acc,
@@ -239,25 +245,31 @@ __device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __re
   __syncthreads();
   const int n_own = br.y - br.x;
   const int total = n_own + (br.w - br.z);
-  for (int t0 = threadIdx.x; t0 < total; t0 += 2 * NT) {
-    const int t1 = t0 + NT;
-    const bool two = t1 < total;
-    const int e0 = t0 < n_own ? br.x + t0 : ldg(m.halo + br.z + (t0 - n_own));
-    const int e1 = !two ? e0 : (t1 < n_own ? br.x + t1 : ldg(m.halo + br.z + (t1 - n_own)));
-    int nd0[D + 1], nd1[D + 1];
-    load_conn<D>(m.conn, e0, nd0);
-    load_conn<D>(m.conn, e1, nd1);
-    ElemIn<D, T, OP, NL, FUSED> in0, in1;
-    load_elem<D, T, OP, NL, FUSED>(m, U, V, mask, e0, nd0, in0);
-    load_elem<D, T, OP, NL, FUSED>(m, U, V, mask, e1, nd1, in1);
+  // EIF visits in flight per thread: all connectivity rows, then all
+  // gathers, then the arithmetic (a slot past the end repeats slot 0's
+  // loads and is skipped)
+  for (int t0 = threadIdx.x; t0 < total; t0 += EIF * NT) {
+    int e[EIF], nd[EIF][D + 1];
+    bool on[EIF];
+#pragma unroll
+    for (int q = 0; q < EIF; ++q) {
+      const int t = t0 + q * NT;
+      on[q] = t < total;
+      const int tt = on[q] ? t : t0;
+      e[q] = tt < n_own ? br.x + tt : ldg(m.halo + br.z + (tt - n_own));
+    }
+#pragma unroll
+    for (int q = 0; q < EIF; ++q) load_conn<D>(m.conn, e[q], nd[q]);
+    ElemIn<D, T, OP, NL, FUSED> in[EIF];
+#pragma unroll
+    for (int q = 0; q < EIF; ++q) load_elem<D, T, OP, NL, FUSED>(m, U, V, mask, e[q], nd[q], in[q]);
     T y[D + 1][D];
-    if constexpr (FUSED) fcg_direction<D, T, OP, NL>(in0, alpha, beta);
-    element_compute<D, T, OP, NL, FUSED>(in0, y);
-    lds_accumulate<D, T, A>(acc, nd0, n0, nloc, y);
-    if (two) {
-      if constexpr (FUSED) fcg_direction<D, T, OP, NL>(in1, alpha, beta);
-      element_compute<D, T, OP, NL, FUSED>(in1, y);
-      lds_accumulate<D, T, A>(acc, nd1, n0, nloc, y);
+#pragma unroll
+    for (int q = 0; q < EIF; ++q) {
+      if (q > 0 && !on[q]) continue;
+      if constexpr (FUSED) fcg_direction<D, T, OP, NL>(in[q], alpha, beta);
+      element_compute<D, T, OP, NL, FUSED>(in[q], y);
+      lds_accumulate<D, T, A>(acc, nd[q], n0, nloc, y);
     }
   }
   __syncthreads();
@@ -325,48 +337,67 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
 template <int D, typename T, bool NL, int NT>
 __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int blk, int it) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  // The latency of this launch is a chain of dependent memory round trips,
+  // so every load is issued as early as its address allows and none waits
+  // behind a branch: descriptor fields (both parity buffers, selected
+  // afterwards), then the run scalars, the block's visit ranges, the
+  // previous partial sums and this thread's first owned node together.
   Scalars* sc = tp->sc;
   const MeshDev m = tp->m;
   const int nb = m.n_blocks;
   const int j = tp->k_base + it;
   const int n0 = blk * m.bn;
   const int nloc = min(m.bn, m.n_nodes - n0);
-  const T* Rin = static_cast<const T*>(tp->rec[j & 1]);
+  const T* R0 = static_cast<const T*>(tp->rec[0]);
+  const T* R1 = static_cast<const T*>(tp->rec[1]);
+  const T* Rin = (j & 1) ? R1 : R0;
   T* P = static_cast<T*>(tp->p);
   T* Dd = static_cast<T*>(tp->d);
-  // Loads that do not depend on the step scalars go out first, so that
-  // their latency overlaps the reduction of the partial sums: the run
-  // state, the block's visit ranges and this thread's first owned node.
-  const int state_in = ldg(&sc->state);
-  const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
-  const int ln0 = threadIdx.x;
-  T rc0[4 * D], pv0[D], dv0[D];
-  int bits0 = 0;
-  if (ln0 < nloc) {
-    load_record<D, T>(Rin, n0 + ln0, rc0);
-    load_nodal<D, T>(P, n0 + ln0, pv0);
-    load_nodal<D, T>(Dd, n0 + ln0, dv0);
-    bits0 = ldg(m.dmask + n0 + ln0);
-  }
   const double* part_in = tp->red.part + (size_t)(j & 1) * kRedSlots * nb;
-  double delta, gamma, rr;
-  sum_slots3<NT>(part_in, nb, delta, gamma, rr);
-  if (state_in != 0) return;
+  const int state_in = ldg(&sc->state);
+  const double target2 = ldg(&sc->target2);
+  const int kmax = ldg(&sc->kmax);
+  const double pg_prev = ldg(&sc->pg[(j + 1) & 1]);   // gamma_{j-1}
+  const double pa_prev = ldg(&sc->pa[(j + 1) & 1]);   // alpha_{j-1}
+  const int active = tp->active;
+  const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
+  // branch-free: out-of-range threads load a valid neighbour and discard it
+  const int pb = min((int)threadIdx.x, nb - 1);
+  double pv_in[3];
+  pv_in[0] = ldg(part_in + pb);
+  pv_in[1] = ldg(part_in + (size_t)nb + pb);
+  pv_in[2] = ldg(part_in + (size_t)2 * nb + pb);
+  if ((int)threadIdx.x >= nb) pv_in[0] = pv_in[1] = pv_in[2] = 0.0;
+  const int ln0 = threadIdx.x;
+  const int lnc = min(ln0, nloc - 1);
+  T rc0[4 * D], pv0[D], dv0[D];
+  load_record<D, T>(Rin, n0 + lnc, rc0);
+  load_nodal<D, T>(P, n0 + lnc, pv0);
+  load_nodal<D, T>(Dd, n0 + lnc, dv0);
+  const int bits0 = ldg(m.dmask + n0 + lnc);
+  for (int b = (int)threadIdx.x + NT; b < nb; b += NT) {   // more blocks than threads
+    pv_in[0] += ldg(part_in + b);
+    pv_in[1] += ldg(part_in + (size_t)nb + b);
+    pv_in[2] += ldg(part_in + (size_t)2 * nb + b);
+  }
+  block_sum_all<3, NT>(pv_in);
+  const double delta = pv_in[0], gamma = pv_in[1], rr = pv_in[2];
+  if (state_in != 0 || !active) return;
   int state = 0;
   double alpha64 = 0.0, beta64 = 0.0;
   if (!(rr == rr) || !(gamma == gamma) || !(delta == delta)) {
     state = 3;
-  } else if (rr <= ldg(&sc->target2)) {
+  } else if (rr <= target2) {
     state = 1;
   } else if (!(gamma > 0.0)) {
     state = 3;
-  } else if (j >= ldg(&sc->kmax)) {
+  } else if (j >= kmax) {
     state = 2;
   } else {
     double den = delta;
     if (j > 0) {
-      beta64 = gamma / ldg(&sc->pg[(j - 1) & 1]);
-      den = delta - beta64 * gamma / ldg(&sc->pa[(j - 1) & 1]);
+      beta64 = gamma / pg_prev;
+      den = delta - beta64 * gamma / pa_prev;
     }
     if (!(den > 0.0)) state = 3;   // not SPD along this direction
     else alpha64 = gamma / den;
@@ -399,8 +430,8 @@ __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int b
   A* acc = reinterpret_cast<A*>(smem_raw);
   const T alpha = (T)alpha64, beta = (T)beta64;
   const T* U = static_cast<const T*>(tp->u);
-  owner_accumulate<D, T, OP_APPLY, NL, A, true, NT>(m, U, Rin, 0, br, n0, nloc, acc, alpha,
-                                                    beta);
+  owner_accumulate<D, T, OP_APPLY, NL, A, true, NT, (D == 2 && !NL) ? PFEM_FCG_EIF : 2>(
+      m, U, Rin, 0, br, n0, nloc, acc, alpha, beta);
   T* Rout = static_cast<T*>(tp->rec[(j + 1) & 1]);
   const bool first = j == 0;
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
@@ -458,9 +489,7 @@ template <int D, typename T, bool NL, int NT>
 __global__ void __launch_bounds__(NT)
 k_fcg(const Task* __restrict__ tasks, const int2* __restrict__ work, int it) {
   const int2 wk = work[blockIdx.x];
-  const Task* tp = tasks + wk.x;
-  if (!tp->active) return;
-  fcg_iteration<D, T, NL, NT>(tp, wk.y, it);
+  fcg_iteration<D, T, NL, NT>(tasks + wk.x, wk.y, it);
 }
 
 // -------------------------------------------------- alternative scatters
