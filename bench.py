@@ -287,7 +287,11 @@ def run_c4():
     v = torch.randn_like(u)
     n_dof = b.n_dof
     n_el = sum(p.n_elems for p, _ in members)
-    res = {"config": f"C4 batch: 64 plates, {n_el} triangles, {n_dof} DOFs, FP32"}
+    res = {"config": f"C4 batch: 64 plates, {n_el} triangles, {n_dof} DOFs, FP32; "
+                     "calls issued on the library stream"}
+    torch.cuda.synchronize()
+    stream_ctx = torch.cuda.stream(ctx.stream)
+    stream_ctx.__enter__()
     for name, fn in (("energy", lambda: b.energy(u)), ("force", lambda: b.force(u)),
                      ("hvp", lambda: b.hvp(u, v))):
         for _ in range(5):
@@ -306,6 +310,7 @@ def run_c4():
         ts.sort()
         us = ts[2]
         res[name] = {"us": round(us, 2), "GDOF_s": round(n_dof / us * 1e-3, 2)}
+    stream_ctx.__exit__(None, None, None)
     res["fwd_bwd_hvp_us"] = round(sum(res[k]["us"] for k in ("energy", "force", "hvp")), 2)
     print(json.dumps(res), flush=True)
 

@@ -35,6 +35,8 @@ def _on_stream(fn):
     def wrap(self, *a, **kw):
         ctx = self.ctx
         cur = torch.cuda.current_stream(ctx.device)
+        if cur == ctx.stream:        # caller already runs on the library stream
+            return fn(self, *a, **kw)
         ctx.stream.wait_stream(cur)
         try:
             # staging copies made by the wrapper run on the library stream too

@@ -21,6 +21,10 @@ struct pfem_batch {
   double* part = nullptr;             // per mesh: n_blocks * kRedSlots
   double* outs = nullptr;             // per mesh: kRedSlots
   std::vector<int64_t> part_off;
+  // persistent task tables with relocatable operands (u, v, y = DOF offset
+  // of each mesh), with and without partial sums
+  pfem::Task* tasks_red = nullptr;
+  pfem::Task* tasks_plain = nullptr;
 };
 
 namespace pfem {
@@ -483,12 +487,34 @@ pfem_status pfem_batch_create(pfem_ctx* ctx, int32_t n, pfem_mesh* const* meshes
     }
     PFEM_HIP(hipMalloc((void**)&b->part, std::max<int64_t>(poff, 1) * 8));
     PFEM_HIP(hipMalloc((void**)&b->outs, (size_t)n * kRedSlots * 8));
+    std::vector<Task> ts;
+    for (int i = 0; i < n; ++i) {
+      Task t{};
+      t.m = b->meshes[i]->md;
+      const uintptr_t off = (uintptr_t)b->offsets[i];
+      t.u = reinterpret_cast<const void*>(off);
+      t.v = reinterpret_cast<const void*>(off);
+      t.y = reinterpret_cast<void*>(off);
+      t.active = 1;
+      t.fscale = 1.0;
+      t.red.part = b->part + b->part_off[i];
+      t.red.out = b->outs + kRedSlots * i;
+      ts.push_back(t);
+    }
+    PFEM_HIP(hipMalloc((void**)&b->tasks_red, ts.size() * sizeof(Task)));
+    PFEM_HIP(hipMemcpy(b->tasks_red, ts.data(), ts.size() * sizeof(Task), hipMemcpyHostToDevice));
+    for (Task& t : ts) t.red.part = nullptr;
+    PFEM_HIP(hipMalloc((void**)&b->tasks_plain, ts.size() * sizeof(Task)));
+    PFEM_HIP(hipMemcpy(b->tasks_plain, ts.data(), ts.size() * sizeof(Task),
+                       hipMemcpyHostToDevice));
   } catch (...) {
     if (b->work) (void)hipFree(b->work);
     for (int kd = 0; kd < 2; ++kd)
       if (b->work_kind[kd]) (void)hipFree(b->work_kind[kd]);
     if (b->part) (void)hipFree(b->part);
     if (b->outs) (void)hipFree(b->outs);
+    if (b->tasks_red) (void)hipFree(b->tasks_red);
+    if (b->tasks_plain) (void)hipFree(b->tasks_plain);
     delete b;
     throw;
   }
@@ -506,6 +532,8 @@ void pfem_batch_destroy(pfem_batch* b) {
     if (b->work_kind[kd]) (void)hipFree(b->work_kind[kd]);
   if (b->part) (void)hipFree(b->part);
   if (b->outs) (void)hipFree(b->outs);
+  if (b->tasks_red) (void)hipFree(b->tasks_red);
+  if (b->tasks_plain) (void)hipFree(b->tasks_plain);
   ctx_unref(b->ctx);
   delete b;
 }
@@ -517,27 +545,6 @@ pfem_status pfem_batch_offsets(const pfem_batch* b, int64_t* offsets) {
   PFEM_TRY_END
 }
 
-static std::vector<Task> batch_tasks(pfem_batch* b, int prec, const void* u, const void* v,
-                                     void* y, int mask) {
-  const size_t s = prec == PFEM_FP64 ? 8 : 4;
-  std::vector<Task> ts;
-  for (size_t i = 0; i < b->meshes.size(); ++i) {
-    Task t{};
-    t.m = b->meshes[i]->md;
-    const size_t off = (size_t)b->offsets[i] * s;
-    t.u = u ? static_cast<const char*>(u) + off : nullptr;
-    t.v = v ? static_cast<const char*>(v) + off : nullptr;
-    t.y = y ? static_cast<char*>(y) + off : nullptr;
-    t.mask = mask;
-    t.active = 1;
-    t.fscale = 1.0;
-    t.red.part = b->part + b->part_off[i];
-    t.red.out = b->outs + kRedSlots * i;
-    ts.push_back(t);
-  }
-  return ts;
-}
-
 pfem_status pfem_batch_energy(pfem_batch* b, int prec, const void* u, double* energies_dev) {
   PFEM_TRY_BEGIN
   require(b != nullptr && u != nullptr && energies_dev != nullptr, PFEM_E_INVALID_ARG,
@@ -545,27 +552,26 @@ pfem_status pfem_batch_energy(pfem_batch* b, int prec, const void* u, double* en
   check_prec(prec);
   Ctx* ctx = b->ctx;
   PFEM_HIP(hipSetDevice(ctx->device));
-  std::vector<Task> ts = batch_tasks(b, prec, u, nullptr, nullptr, 0);
-  const Task* td = static_cast<const Task*>(ctx->ring.put(ts.data(), ts.size() * sizeof(Task)));
-  launch_energy(ctx, b->dim, prec, false, td, b->work, b->n_work);
-  launch_reduce_store(ctx, td, (int)b->meshes.size());
+  const BaseArgs ba{u, nullptr, nullptr, 1, 0};
+  launch_energy(ctx, b->dim, prec, false, b->tasks_red, b->work, b->n_work, &ba);
+  launch_reduce_store(ctx, b->tasks_red, (int)b->meshes.size());
   launch_energy_out(ctx, b->outs, energies_dev, (int)b->meshes.size(), kRedSlots);
   PFEM_TRY_END
 }
 
+// One launch per model kind (the kinds compile to different kernels); the
+// task table is persistent, so a call uploads nothing.
 static pfem_status batch_elem(pfem_batch* b, int prec, int mask, int op, const void* u,
                               const void* v, void* y) {
   require(b != nullptr && y != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
   check_prec(prec);
   Ctx* ctx = b->ctx;
   PFEM_HIP(hipSetDevice(ctx->device));
-  std::vector<Task> ts = batch_tasks(b, prec, u, v, y, mask);
-  for (Task& t : ts) t.red.part = nullptr;
-  const Task* td = static_cast<const Task*>(ctx->ring.put(ts.data(), ts.size() * sizeof(Task)));
+  const BaseArgs ba{u, v, y, 1, mask};
   for (int kd = 0; kd < 2; ++kd)
     if (b->n_work_kind[kd] > 0)
-      launch_elem(ctx, b->dim, prec, op, kd == 1, PFEM_SCATTER_OWNER, td, b->work_kind[kd],
-                  b->n_work_kind[kd], b->bn_max, nullptr, nullptr);
+      launch_elem(ctx, b->dim, prec, op, kd == 1, PFEM_SCATTER_OWNER, b->tasks_plain,
+                  b->work_kind[kd], b->n_work_kind[kd], b->bn_max, nullptr, nullptr, &ba);
   return PFEM_OK;
 }
 

@@ -277,7 +277,7 @@ __device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __re
 
 template <int D, typename T, int OP, bool NL>
 __global__ void __launch_bounds__(kThreads)
-k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work, const BaseArgs ba) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 wk = work[blockIdx.x];
   const Task* tp = tasks + wk.x;
@@ -291,11 +291,11 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   using A = AccT<T>;
   A* acc = reinterpret_cast<A*>(smem_raw);
   const int nown = nloc * D;
-  const T* U = static_cast<const T*>(tp->u);
-  const T* V = static_cast<const T*>(tp->v);
-  const int mask = tp->mask;
+  const T* U = operand<const T>(const_cast<void*>(tp->u), const_cast<void*>(ba.u), ba.rel);
+  const T* V = operand<const T>(const_cast<void*>(tp->v), const_cast<void*>(ba.v), ba.rel);
+  const int mask = ba.rel ? ba.mask : tp->mask;
   owner_accumulate<D, T, OP, NL, A>(m, U, V, mask, br, n0, nloc, acc);
-  T* Y = static_cast<T*>(tp->y);
+  T* Y = operand<T>(tp->y, ba.y, ba.rel);
   const T* W = static_cast<const T*>(tp->w);
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
   const size_t g0 = (size_t)n0 * D;
@@ -564,7 +564,7 @@ __global__ void __launch_bounds__(kThreads) k_alt_fixup(Task t) {
 // difference, #inverted, sum of |terms|).
 template <int D, typename TU, typename TV, bool DIFF>
 __global__ void __launch_bounds__(kThreads)
-k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work, const BaseArgs ba) {
   const int2 wk = work[blockIdx.x];
   const Task* tp = tasks + wk.x;
   if (!tp->active) return;
@@ -573,8 +573,8 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   const int n0 = blk * m.bn;
   const int nloc = min(m.bn, m.n_nodes - n0);
   const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
-  const TU* U = static_cast<const TU*>(tp->u);
-  const TV* V = static_cast<const TV*>(tp->v);
+  const TU* U = operand<const TU>(const_cast<void*>(tp->u), const_cast<void*>(ba.u), ba.rel);
+  const TV* V = operand<const TV>(const_cast<void*>(tp->v), const_cast<void*>(ba.v), ba.rel);
   const double s = tp->s;
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
   using T = TU;   // element arithmetic type
@@ -667,18 +667,18 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work) {
 // ---------------------------------------------------------------- launchers
 template <int D, typename T, bool NL>
 static void launch_owner_typed(Ctx* ctx, int op, const Task* tasks, const int2* work,
-                               int n_work, int bn_max) {
+                               int n_work, int bn_max, const BaseArgs& ba) {
   const size_t sm = (size_t)bn_max * D * sizeof(AccT<T>);
   dim3 grid(n_work), block(kThreads);
   switch (op) {
     case OP_APPLY:
-      hipLaunchKernelGGL((k_owner<D, T, OP_APPLY, NL>), grid, block, sm, ctx->stream, tasks, work);
+      hipLaunchKernelGGL((k_owner<D, T, OP_APPLY, NL>), grid, block, sm, ctx->stream, tasks, work, ba);
       break;
     case OP_FORCE:
-      hipLaunchKernelGGL((k_owner<D, T, OP_FORCE, NL>), grid, block, sm, ctx->stream, tasks, work);
+      hipLaunchKernelGGL((k_owner<D, T, OP_FORCE, NL>), grid, block, sm, ctx->stream, tasks, work, ba);
       break;
     default:
-      hipLaunchKernelGGL((k_owner<D, T, OP_DIAG, NL>), grid, block, sm, ctx->stream, tasks, work);
+      hipLaunchKernelGGL((k_owner<D, T, OP_DIAG, NL>), grid, block, sm, ctx->stream, tasks, work, ba);
       break;
   }
 }
@@ -723,11 +723,11 @@ static int family_of(int op) {
 
 template <bool NL>
 static void dispatch_owner(Ctx* ctx, int dim, int prec, int op, const Task* t, const int2* w,
-                           int n, int bn) {
-  if (dim == 2 && prec == PFEM_FP32) launch_owner_typed<2, float, NL>(ctx, op, t, w, n, bn);
-  else if (dim == 2) launch_owner_typed<2, double, NL>(ctx, op, t, w, n, bn);
-  else if (prec == PFEM_FP32) launch_owner_typed<3, float, NL>(ctx, op, t, w, n, bn);
-  else launch_owner_typed<3, double, NL>(ctx, op, t, w, n, bn);
+                           int n, int bn, const BaseArgs& ba) {
+  if (dim == 2 && prec == PFEM_FP32) launch_owner_typed<2, float, NL>(ctx, op, t, w, n, bn, ba);
+  else if (dim == 2) launch_owner_typed<2, double, NL>(ctx, op, t, w, n, bn, ba);
+  else if (prec == PFEM_FP32) launch_owner_typed<3, float, NL>(ctx, op, t, w, n, bn, ba);
+  else launch_owner_typed<3, double, NL>(ctx, op, t, w, n, bn, ba);
 }
 
 template <bool NL>
@@ -741,13 +741,15 @@ static void dispatch_alt(Ctx* ctx, int dim, int prec, int op, int mode, const Ta
 
 void launch_elem(Ctx* ctx, int dim, int prec, int op, bool nonlinear, int scatter_mode,
                  const Task* tasks_dev, const int2* work_dev, int n_work, int bn_max,
-                 const Task* host_task_for_alt, const std::vector<int>* color_ptr) {
+                 const Task* host_task_for_alt, const std::vector<int>* color_ptr,
+                 const BaseArgs* rel) {
   hipEvent_t ev = nullptr;
   ctx->timing_begin(family_of(op), &ev);
+  const BaseArgs ba = rel != nullptr ? *rel : BaseArgs{nullptr, nullptr, nullptr, 0, 0};
   if (scatter_mode == PFEM_SCATTER_OWNER) {
     if (n_work > 0) {
-      if (nonlinear) dispatch_owner<true>(ctx, dim, prec, op, tasks_dev, work_dev, n_work, bn_max);
-      else dispatch_owner<false>(ctx, dim, prec, op, tasks_dev, work_dev, n_work, bn_max);
+      if (nonlinear) dispatch_owner<true>(ctx, dim, prec, op, tasks_dev, work_dev, n_work, bn_max, ba);
+      else dispatch_owner<false>(ctx, dim, prec, op, tasks_dev, work_dev, n_work, bn_max, ba);
     }
   } else {
     if (nonlinear) dispatch_alt<true>(ctx, dim, prec, op, scatter_mode, *host_task_for_alt, color_ptr);
@@ -758,23 +760,24 @@ void launch_elem(Ctx* ctx, int dim, int prec, int op, bool nonlinear, int scatte
 }
 
 void launch_energy(Ctx* ctx, int dim, int prec, bool diff, const Task* tasks_dev,
-                   const int2* work_dev, int n_work) {
+                   const int2* work_dev, int n_work, const BaseArgs* rel) {
   if (n_work <= 0) return;
+  const BaseArgs ba = rel != nullptr ? *rel : BaseArgs{nullptr, nullptr, nullptr, 0, 0};
   hipEvent_t ev = nullptr;
   ctx->timing_begin(FAM_ENERGY, &ev);
   dim3 grid(n_work), block(kThreads);
   hipStream_t s = ctx->stream;
   // diff: u is float64 state, v is the increment in `prec`
   if (!diff) {
-    if (dim == 2 && prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<2, float, float, false>), grid, block, 0, s, tasks_dev, work_dev);
-    else if (dim == 2) hipLaunchKernelGGL((k_energy<2, double, double, false>), grid, block, 0, s, tasks_dev, work_dev);
-    else if (prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<3, float, float, false>), grid, block, 0, s, tasks_dev, work_dev);
-    else hipLaunchKernelGGL((k_energy<3, double, double, false>), grid, block, 0, s, tasks_dev, work_dev);
+    if (dim == 2 && prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<2, float, float, false>), grid, block, 0, s, tasks_dev, work_dev, ba);
+    else if (dim == 2) hipLaunchKernelGGL((k_energy<2, double, double, false>), grid, block, 0, s, tasks_dev, work_dev, ba);
+    else if (prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<3, float, float, false>), grid, block, 0, s, tasks_dev, work_dev, ba);
+    else hipLaunchKernelGGL((k_energy<3, double, double, false>), grid, block, 0, s, tasks_dev, work_dev, ba);
   } else {
-    if (dim == 2 && prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<2, double, float, true>), grid, block, 0, s, tasks_dev, work_dev);
-    else if (dim == 2) hipLaunchKernelGGL((k_energy<2, double, double, true>), grid, block, 0, s, tasks_dev, work_dev);
-    else if (prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<3, double, float, true>), grid, block, 0, s, tasks_dev, work_dev);
-    else hipLaunchKernelGGL((k_energy<3, double, double, true>), grid, block, 0, s, tasks_dev, work_dev);
+    if (dim == 2 && prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<2, double, float, true>), grid, block, 0, s, tasks_dev, work_dev, ba);
+    else if (dim == 2) hipLaunchKernelGGL((k_energy<2, double, double, true>), grid, block, 0, s, tasks_dev, work_dev, ba);
+    else if (prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<3, double, float, true>), grid, block, 0, s, tasks_dev, work_dev, ba);
+    else hipLaunchKernelGGL((k_energy<3, double, double, true>), grid, block, 0, s, tasks_dev, work_dev, ba);
   }
   PFEM_HIP(hipGetLastError());
   ctx->timing_end(FAM_ENERGY, ev);

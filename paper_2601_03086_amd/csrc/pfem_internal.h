@@ -119,6 +119,23 @@ struct Task {
   void* tmp;
 };
 
+// Relocatable operands.  With rel != 0 the u, v, y fields of every task of
+// a launch hold element offsets instead of pointers, and the base pointers
+// and the mask come with the launch: a batch of meshes keeps one persistent
+// device task table instead of uploading one per call.
+struct BaseArgs {
+  const void* u;
+  const void* v;
+  void* y;
+  int32_t rel;
+  int32_t mask;
+};
+
+template <typename T>
+__host__ __device__ inline T* operand(void* field, void* base, int rel) {
+  return rel ? static_cast<T*>(base) + reinterpret_cast<uintptr_t>(field) : static_cast<T*>(field);
+}
+
 // Element-kernel operations.
 enum ElemOp { OP_APPLY = 0, OP_FORCE = 1, OP_DIAG = 2 };
 
@@ -193,9 +210,10 @@ void ctx_unref(Ctx* c);
 void launch_elem(Ctx* ctx, int dim, int prec, int op, bool nonlinear, int scatter_mode,
                  const Task* tasks_dev, const int2* work_dev, int n_work,
                  int bn_max, const Task* host_task_for_alt,
-                 const std::vector<int>* color_ptr);
+                 const std::vector<int>* color_ptr, const BaseArgs* rel = nullptr);
 void launch_energy(Ctx* ctx, int dim, int prec, bool diff,
-                   const Task* tasks_dev, const int2* work_dev, int n_work);
+                   const Task* tasks_dev, const int2* work_dev, int n_work,
+                   const BaseArgs* rel = nullptr);
 // PCG vector passes over owned node blocks.
 void launch_pcg_init(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
                      const int2* work_dev, int n_work, int n_tasks);
