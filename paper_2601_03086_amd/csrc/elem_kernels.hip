@@ -58,8 +58,11 @@ template <typename T>
 __device__ __forceinline__ T mat_mu(const MeshDev& m, int e) {
   if constexpr (sizeof(T) == 4) return ldg(m.mu32 + e); else return ldg(m.mu64 + e);
 }
+// lambda of element e given its mu: one multiply when the mesh has a
+// uniform lambda / mu ratio (one material value per element to stream)
 template <typename T>
-__device__ __forceinline__ T mat_lam(const MeshDev& m, int e) {
+__device__ __forceinline__ T mat_lam(const MeshDev& m, int e, T mu) {
+  if (m.lam_uniform) return (T)m.lam_ratio * mu;
   if constexpr (sizeof(T) == 4) return ldg(m.lam32 + e); else return ldg(m.lam64 + e);
 }
 
@@ -81,7 +84,7 @@ __device__ __forceinline__ void load_elem(const MeshDev& m, const T* __restrict_
                                           ElemIn<D, T, OP, NL, FUSED>& in) {
   load_coords<D>(m.X, nd, in.x);
   in.mu = mat_mu<T>(m, e);
-  in.lam = mat_lam<T>(m, e);
+  in.lam = mat_lam<T>(m, e, in.mu);
   if constexpr (NL || OP == OP_FORCE) {
 #pragma unroll
     for (int a = 0; a <= D; ++a) load_nodal<D, T>(U, nd[a], in.u[a]);
@@ -584,7 +587,7 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work, const Ba
     Geo<D, T> g;
     load_geometry<D, T>(m.X, nd, g);
     const T mu = mat_mu<T>(m, e);
-    const T lam = mat_lam<T>(m, e);
+    const T lam = mat_lam<T>(m, e, mu);
     const T adet = g.det < T(0) ? -g.det : g.det;
     const double vol = (double)adet / Fact<D>::v;
     T uu[D + 1][D];

@@ -439,6 +439,19 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   md.dim = m->dim;
   md.model = m->model;
   md.nonlinear = m->nonlinear ? 1 : 0;
+  // uniform lambda / mu ratio (uniform Poisson ratio): kernels stream mu only
+  md.lam_uniform = 0;
+  md.lam_ratio = 0.0;
+  if (m->n_elems > 0 && m->mu_int[0] != 0.0) {
+    const double r = m->lam_int[0] / m->mu_int[0];
+    bool uni = std::isfinite(r);
+    for (int64_t s = 0; uni && s < m->n_elems; ++s)
+      uni = std::fabs(m->lam_int[s] - r * m->mu_int[s]) <= 2e-15 * std::fabs(m->lam_int[s]);
+    if (uni) {
+      md.lam_uniform = 1;
+      md.lam_ratio = r;
+    }
+  }
   ctx_ref(ctx);
   m->ctx = ctx;
   m->uploaded = true;

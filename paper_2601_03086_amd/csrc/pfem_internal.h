@@ -59,7 +59,9 @@ struct MeshDev {
   const double* ubar;     // n_dof, final Dirichlet values, 0 on free DOFs
   const int32_t* colored; // n_elems: sorted element ids grouped by colour
   int32_t n_nodes, n_elems, n_blocks, bn;
-  int32_t dim, model, nonlinear, pad;
+  int32_t dim, model, nonlinear;
+  int32_t lam_uniform;    // 1: lambda = lam_ratio * mu on every element (lam arrays unread)
+  double lam_ratio;
 };
 
 // Partial sums of one task: slot k of block b at part[k * n_blocks + b].
