@@ -70,7 +70,7 @@ __device__ __forceinline__ T mat_lam(const MeshDev& m, int e, T mu) {
 // of its loads are in flight together.
 template <int D, typename T, int OP, bool NL, bool FUSED = false>
 struct ElemIn {
-  double x[D + 1][D];
+  ElemX<D, T> x;
   T u[D + 1][D];   // state (Neo-Hookean) or input of the linear force
   T v[D + 1][D];   // direction of the apply
   T rec[FUSED ? D + 1 : 1][FUSED ? 4 * D : 1];   // fused PCG records
@@ -82,7 +82,7 @@ __device__ __forceinline__ void load_elem(const MeshDev& m, const T* __restrict_
                                           const T* __restrict__ V, int mask, int e,
                                           const int (&nd)[D + 1],
                                           ElemIn<D, T, OP, NL, FUSED>& in) {
-  load_coords<D>(m.X, nd, in.x);
+  load_elem_x<D, T>(m, nd, in.x);
   in.mu = mat_mu<T>(m, e);
   in.lam = mat_lam<T>(m, e, in.mu);
   if constexpr (NL || OP == OP_FORCE) {
@@ -123,10 +123,11 @@ __device__ __forceinline__ void fcg_direction(ElemIn<D, T, OP, NL, true>& in, T 
 
 // Element output for one op; y[a][i] is the contribution to node a, comp i.
 template <int D, typename T, int OP, bool NL, bool FUSED>
-__device__ __forceinline__ void element_compute(const ElemIn<D, T, OP, NL, FUSED>& in,
+__device__ __forceinline__ void element_compute(const MeshDev& m,
+                                                const ElemIn<D, T, OP, NL, FUSED>& in,
                                                 T (&y)[D + 1][D]) {
   Geo<D, T> g;
-  geometry<D, T>(in.x, g);
+  geometry_x<D, T>(m, in.x, g);
   const T mu = in.mu, lam = in.lam;
   const T adet = g.det < T(0) ? -g.det : g.det;
   const T s_sym = T(1) / (T(Fact<D>::v) * adet);       // vol / det^2
@@ -202,7 +203,7 @@ __device__ __forceinline__ void element_output(const MeshDev& m, const T* __rest
                                                const int (&nd)[D + 1], T (&y)[D + 1][D]) {
   ElemIn<D, T, OP, NL> in;
   load_elem<D, T, OP, NL>(m, U, V, mask, e, nd, in);
-  element_compute<D, T, OP, NL, false>(in, y);
+  element_compute<D, T, OP, NL, false>(m, in, y);
 }
 
 template <int D, typename T, typename A>
@@ -271,7 +272,7 @@ __device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __re
     for (int q = 0; q < EIF; ++q) {
       if (q > 0 && !on[q]) continue;
       if constexpr (FUSED) fcg_direction<D, T, OP, NL>(in[q], alpha, beta);
-      element_compute<D, T, OP, NL, FUSED>(in[q], y);
+      element_compute<D, T, OP, NL, FUSED>(m, in[q], y);
       lds_accumulate<D, T, A>(acc, nd[q], n0, nloc, y);
     }
   }
@@ -585,7 +586,7 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work, const Ba
     int nd[D + 1];
     load_conn<D>(m.conn, e, nd);
     Geo<D, T> g;
-    load_geometry<D, T>(m.X, nd, g);
+    load_geometry<D, T>(m, nd, g);
     const T mu = mat_mu<T>(m, e);
     const T lam = mat_lam<T>(m, e, mu);
     const T adet = g.det < T(0) ? -g.det : g.det;

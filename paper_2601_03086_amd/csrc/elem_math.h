@@ -5,9 +5,12 @@
 // shape-function gradients grad N_a = c_a / det J, where c_a are the
 // cofactor rows (2D: c_1 = (e2y, -e2x), c_2 = (-e1y, e1x); 3D:
 // c_1 = e2 x e3, c_2 = e3 x e1, c_3 = e1 x e2) and grad N_0 = -sum_a grad N_a.
-// The element measure is |det J| / D!.  Coordinates are float64 and the
-// differences are taken in float64 before rounding to the kernel type, so
-// the geometry keeps its relative accuracy on small elements.
+// The element measure is |det J| / D!.  float64 kernels read float64
+// coordinates and difference them in float64.  float32 kernels read 32-bit
+// fixed-point coordinates (X = lo + q * step over the mesh's bounding box,
+// step = extent / (2^32 - 1)): the edge q_a - q_0 is an exact integer, so
+// the geometry keeps the relative accuracy of float32 on small elements
+// far from the origin, at half the bytes of float64 coordinates.
 //
 // Every nodal output y_a is formed from the unnormalised c_a; vol/det^2 =
 // 1/(D! |det|) and vol/det = sign(det)/D! carry the normalisation, so each
@@ -51,6 +54,62 @@ __device__ __forceinline__ void load_coords(const double* __restrict__ X,
   }
 }
 
+template <int D>
+__device__ __forceinline__ void load_coords_q(const uint32_t* __restrict__ Xq,
+                                              const int (&nd)[D + 1], uint32_t (&x)[D + 1][D]) {
+#pragma unroll
+  for (int a = 0; a <= D; ++a) {
+    if constexpr (D == 2) {
+      typedef unsigned int pu2 __attribute__((ext_vector_type(2)));
+      const pu2 q = ldg(reinterpret_cast<const pu2*>(Xq + (size_t)nd[a] * 2));
+      x[a][0] = q.x;
+      x[a][1] = q.y;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) x[a][i] = ldg(Xq + (size_t)nd[a] * 3 + i);
+    }
+  }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void geometry_from_edges(const T (&e)[D][D], Geo<D, T>& g);
+
+// Coordinates of an element as the kernel type reads them.
+template <int D, typename T>
+struct ElemX {
+  double x[D + 1][D];
+};
+template <int D>
+struct ElemX<D, float> {
+  uint32_t q[D + 1][D];
+};
+
+template <int D, typename T>
+__device__ __forceinline__ void load_elem_x(const MeshDev& m, const int (&nd)[D + 1],
+                                            ElemX<D, T>& x) {
+  if constexpr (sizeof(T) == 4) load_coords_q<D>(m.Xq, nd, x.q);
+  else load_coords<D>(m.X, nd, x.x);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void geometry_x(const MeshDev& m, const ElemX<D, T>& x,
+                                           Geo<D, T>& g) {
+  T e[D][D];
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+        e[a][i] = (float)(int)(x.q[a + 1][i] - x.q[0][i]) * m.qscale[i];
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int i = 0; i < D; ++i) e[a][i] = (T)(x.x[a + 1][i] - x.x[0][i]);
+  }
+  geometry_from_edges<D, T>(e, g);
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void geometry(const double (&x)[D + 1][D], Geo<D, T>& g) {
   T e[D][D];
@@ -59,6 +118,11 @@ __device__ __forceinline__ void geometry(const double (&x)[D + 1][D], Geo<D, T>&
 #pragma unroll
     for (int i = 0; i < D; ++i)
       e[a][i] = (T)(x[a + 1][i] - x[0][i]);
+  geometry_from_edges<D, T>(e, g);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void geometry_from_edges(const T (&e)[D][D], Geo<D, T>& g) {
   if constexpr (D == 2) {
     g.c[0][0] = e[1][1];
     g.c[0][1] = -e[1][0];
@@ -80,11 +144,11 @@ __device__ __forceinline__ void geometry(const double (&x)[D + 1][D], Geo<D, T>&
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void load_geometry(const double* __restrict__ X,
-                                              const int (&nd)[D + 1], Geo<D, T>& g) {
-  double x[D + 1][D];
-  load_coords<D>(X, nd, x);
-  geometry<D, T>(x, g);
+__device__ __forceinline__ void load_geometry(const MeshDev& m, const int (&nd)[D + 1],
+                                              Geo<D, T>& g) {
+  ElemX<D, T> x;
+  load_elem_x<D, T>(m, nd, x);
+  geometry_x<D, T>(m, x, g);
 }
 
 // Gradient-like tensor M_ij = sum_{a>=1} (v_a - v_0)_i c_a,j.

@@ -400,8 +400,27 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   d.bytes = 0;
   std::vector<float> mu32(m->mu_int.begin(), m->mu_int.end());
   std::vector<float> lam32(m->lam_int.begin(), m->lam_int.end());
+  // 32-bit fixed-point coordinates over the bounding box (float32 kernels)
+  const int D = m->dim;
+  std::vector<uint32_t> xq(m->X_int.size());
+  float qscale[3] = {1.f, 1.f, 1.f};
+  for (int i = 0; i < D; ++i) {
+    double lo = 0.0, hi = 0.0;
+    for (int64_t n = 0; n < m->n_nodes; ++n) {
+      const double v = m->X_int[n * D + i];
+      if (n == 0 || v < lo) lo = v;
+      if (n == 0 || v > hi) hi = v;
+    }
+    const double step = hi > lo ? (hi - lo) / 4294967295.0 : 1.0;
+    qscale[i] = (float)step;
+    for (int64_t n = 0; n < m->n_nodes; ++n) {
+      const double t = std::round((m->X_int[n * D + i] - lo) / step);
+      xq[n * D + i] = (uint32_t)std::min(std::max(t, 0.0), 4294967295.0);
+    }
+  }
   try {
     d.X = upload(m->X_int, d.bytes);
+    d.Xq = upload(xq, d.bytes);
     d.conn = upload(m->conn_int, d.bytes);
     d.mu32 = upload(mu32, d.bytes);
     d.lam32 = upload(lam32, d.bytes);
@@ -421,6 +440,8 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   }
   MeshDev& md = m->md;
   md.X = d.X;
+  md.Xq = d.Xq;
+  for (int i = 0; i < 3; ++i) md.qscale[i] = qscale[i];
   md.conn = d.conn;
   md.mu32 = d.mu32;
   md.lam32 = d.lam32;
@@ -492,7 +513,7 @@ void mesh_release_device(pfem_mesh* m) {
   m->solve_state.reset();
   m->scratch.release();
   MeshDevBuffers& d = m->dev;
-  void* ptrs[] = {d.X, d.conn, d.mu32, d.lam32, d.mu64, d.lam64, d.dmask, d.blocks,
+  void* ptrs[] = {d.X, d.Xq, d.conn, d.mu32, d.lam32, d.mu64, d.lam64, d.dmask, d.blocks,
                   d.halo, d.fext, d.ubar, d.colored, d.perm, d.work};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
@@ -508,7 +529,7 @@ void mesh_release_device(pfem_mesh* m) {
 int64_t mesh_device_bytes(const pfem_mesh* m) {
   const int64_t N = m->n_nodes, NE = m->n_elems, D = m->dim;
   auto r = [](int64_t b) { return std::max<int64_t>(b, 1); };
-  return r(N * D * 8) + r(NE * (D + 1) * 4) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
+  return r(N * D * 8) + r(N * D * 4) + r(NE * (D + 1) * 4) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
          r((int64_t)m->n_blocks * 16) + r((int64_t)m->halo.size() * 4) + 2 * r(N * D * 8) +
          r(NE * 4) + r(N * 4) + r((int64_t)m->n_blocks * 8);
 }

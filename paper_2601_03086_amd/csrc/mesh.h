@@ -38,6 +38,7 @@ struct SolveState {
 
 struct MeshDevBuffers {
   double* X = nullptr;
+  uint32_t* Xq = nullptr;
   int32_t* conn = nullptr;
   float* mu32 = nullptr;
   float* lam32 = nullptr;

@@ -47,6 +47,8 @@ typedef int pi4 __attribute__((ext_vector_type(4)));
 // Everything a kernel needs to know about one finalized mesh (POD).
 struct MeshDev {
   const double* X;        // n_nodes * dim, internal node order
+  const uint32_t* Xq;     // n_nodes * dim fixed-point coordinates (float32 kernels):
+                          // X = lo + q * qscale, per dimension
   const int32_t* conn;    // n_elems * (dim+1), sorted element order, internal ids
   const float* mu32;      // n_elems
   const float* lam32;     // n_elems
@@ -62,6 +64,8 @@ struct MeshDev {
   int32_t dim, model, nonlinear;
   int32_t lam_uniform;    // 1: lambda = lam_ratio * mu on every element (lam arrays unread)
   double lam_ratio;
+  float qscale[3];        // fixed-point coordinate step per dimension
+  int32_t pad2;
 };
 
 // Partial sums of one task: slot k of block b at part[k * n_blocks + b].
