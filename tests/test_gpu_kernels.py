@@ -22,8 +22,24 @@ def ctx():
     c.close()
 
 
+def _varied_ratio(p, seed):
+    """Same mesh with a Poisson ratio (or lambda / mu) that varies per
+    element, so the kernels read both material arrays."""
+    rng = np.random.default_rng(seed)
+    if p.param_kind == "E_nu":
+        p.p1 = rng.uniform(0.15, 0.45, size=p.n_elems)
+    else:
+        p.p1 = p.p0 * rng.uniform(1.0, 6.0, size=p.n_elems)
+    p.name = p.name + "_varied"
+    return p
+
+
 def _problems():
     return {
+        "plate_nu": _varied_ratio(synth.plate_problem(71, 72, 73, n_holes=4, target_tris=5000,
+                                                      model="lin_plane_strain"), 1),
+        "box_nh_lam": _varied_ratio(synth.box_problem(74, 75, n_per_unit=5, n_voids=3,
+                                                      n_load_steps=2), 2),
         "c1": synth.unit_square_c1(),
         "plate_lin": synth.plate_problem(61, 62, 63, n_holes=5, target_tris=6000,
                                          model="lin_plane_strain"),
@@ -43,7 +59,7 @@ def _mesh(ctx, name, bn=0):
     return core.Mesh.from_problem(ctx, PROBS[name], bn)
 
 
-@pytest.mark.parametrize("name", ["c1", "plate_lin", "box_lin"])
+@pytest.mark.parametrize("name", ["c1", "plate_lin", "box_lin", "plate_nu"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("scatter", ["owner", "colored", "atomic"])
 @pytest.mark.parametrize("bn", [0, 32])
@@ -88,7 +104,7 @@ def test_apply_K_masks_and_internal_layout(ctx, prec):
     assert bound_rel(y, K @ v, abs(K) @ abs(v)) <= TOL[prec]
 
 
-@pytest.mark.parametrize("name", ["plate_nh", "box_nh"])
+@pytest.mark.parametrize("name", ["plate_nh", "box_nh", "box_nh_lam"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("bn", [0, 40])
 def test_hvp_force_energy_diag_nh(ctx, name, prec, bn):
