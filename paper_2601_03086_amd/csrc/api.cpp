@@ -252,7 +252,9 @@ pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* o) {
   o->bandwidth_rcm = m->bw_rcm;
   o->owner_elem_visits = m->owner_visits;
   o->device_bytes = m->finalized ? mesh_device_bytes(m) : 0;
-  o->solve_bytes_fp32 = m->finalized ? solve_bytes(m, PFEM_FP32, true) : 0;
+  pfem_solve_opts d32;
+  pfem_solve_opts_default(&d32);   // FP32 mode, AUTO formulation
+  o->solve_bytes_fp32 = m->finalized ? solve_bytes(m, PFEM_FP32, krylov_fused(d32, m)) : 0;
   o->solve_bytes_fp64 = m->finalized ? solve_bytes(m, PFEM_FP64, false) : 0;
   o->f_ext_norm = m->fext_norm;
   PFEM_TRY_END
@@ -625,7 +627,7 @@ pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
   // (re)use the mesh's cached solver state
   std::unique_ptr<SolveState>& cached = m->solve_state;
   const int prec = o->prec;
-  const bool fused = krylov_fused(*o);
+  const bool fused = krylov_fused(*o, m);
   if (!cached || cached->prec != prec || cached->hist_cap < hcap || cached->fused != fused) {
     cached.reset();
     cached.reset(new SolveState());

@@ -130,7 +130,7 @@ int64_t mesh_device_bytes(const pfem_mesh* m);
 int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg);
 // Whether a solve with these options runs the fused (one launch per
 // iteration) PCG.
-bool krylov_fused(const pfem_solve_opts& o);
+bool krylov_fused(const pfem_solve_opts& o, const pfem_mesh* m);
 void lame_from_params(int model, int param_kind, double p0, double p1, double* mu,
                       double* lam);
 uint32_t fmix32(uint32_t h);

@@ -64,7 +64,7 @@ struct pfem_server {
 };
 
 static int64_t req_bytes(const pfem_mesh* m, const pfem_solve_opts& o) {
-  return (m->uploaded ? 0 : mesh_device_bytes(m)) + solve_bytes(m, o.prec, krylov_fused(o));
+  return (m->uploaded ? 0 : mesh_device_bytes(m)) + solve_bytes(m, o.prec, krylov_fused(o, m));
 }
 
 void pfem_server::admit(Req* r) {

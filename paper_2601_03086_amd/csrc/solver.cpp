@@ -65,7 +65,7 @@ void slot_alloc(SlotRun* s, pfem_mesh* m, const pfem_solve_opts& o, int64_t hist
   s->nl = m->nonlinear;
   s->st = new SolveState();
   try {
-    s->st->alloc(s->prec, m->n_dof(), m->n_blocks, hist_cap, m->nonlinear, krylov_fused(o));
+    s->st->alloc(s->prec, m->n_dof(), m->n_blocks, hist_cap, m->nonlinear, krylov_fused(o, m));
     PFEM_HIP(hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault));
   } catch (...) {
     delete s->st;
