@@ -41,6 +41,36 @@ __device__ __forceinline__ void load_nodal(const T* __restrict__ p, int n, T (&o
 
 template <int D>
 __device__ __forceinline__ void load_conn(const int32_t* __restrict__ conn, int e,
+                                          int (&nd)[D + 1]);
+
+// Element e's nodes: packed (smallest node + 16-bit offsets, 8 bytes in 2D,
+// 12 in 3D) when the mesh fits, else plain int32 rows.  Measured on large
+// meshes: packing pays in 2D and in 3D float64, while 3D float32 is faster
+// with one 16-byte load of the plain row.
+template <int D, typename T>
+__device__ __forceinline__ void load_conn(const MeshDev& m, int e, int (&nd)[D + 1]) {
+  if ((D == 2 || sizeof(T) == 8) && m.conn_packed) {
+    if constexpr (D == 2) {
+      typedef unsigned int pu2 __attribute__((ext_vector_type(2)));
+      const pu2 q = ldg(reinterpret_cast<const pu2*>(m.connp + (size_t)e * 2));
+      nd[0] = (int)q.x;
+      nd[1] = (int)(q.x + (q.y & 0xffffu));
+      nd[2] = (int)(q.x + (q.y >> 16));
+    } else {
+      const uint32_t* p = m.connp + (size_t)e * 3;
+      const uint32_t a = ldg(p), b = ldg(p + 1), c = ldg(p + 2);
+      nd[0] = (int)a;
+      nd[1] = (int)(a + (b & 0xffffu));
+      nd[2] = (int)(a + (b >> 16));
+      nd[3] = (int)(a + c);
+    }
+  } else {
+    load_conn<D>(m.conn, e, nd);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void load_conn(const int32_t* __restrict__ conn, int e,
                                           int (&nd)[D + 1]) {
   if constexpr (D == 3) {
     const pi4 q = ldg(reinterpret_cast<const pi4*>(conn + (size_t)e * 4));
@@ -263,7 +293,7 @@ __device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __re
       e[q] = tt < n_own ? br.x + tt : ldg(m.halo + br.z + (tt - n_own));
     }
 #pragma unroll
-    for (int q = 0; q < EIF; ++q) load_conn<D>(m.conn, e[q], nd[q]);
+    for (int q = 0; q < EIF; ++q) load_conn<D, T>(m, e[q], nd[q]);
     ElemIn<D, T, OP, NL, FUSED> in[EIF];
 #pragma unroll
     for (int q = 0; q < EIF; ++q) load_elem<D, T, OP, NL, FUSED>(m, U, V, mask, e[q], nd[q], in[q]);
@@ -506,7 +536,7 @@ __global__ void __launch_bounds__(kThreads) k_atomic(Task t) {
   for (int e = blockIdx.x * kThreads + threadIdx.x; e < m.n_elems;
        e += gridDim.x * kThreads) {
     int nd[D + 1];
-    load_conn<D>(m.conn, e, nd);
+    load_conn<D, T>(m, e, nd);
     T y[D + 1][D];
     element_output<D, T, OP, NL>(m, U, V, t.mask, e, nd, y);
 #pragma unroll
@@ -526,7 +556,7 @@ __global__ void __launch_bounds__(kThreads) k_colored(Task t, int c0, int c1) {
        k += gridDim.x * kThreads) {
     const int e = ldg(m.colored + k);
     int nd[D + 1];
-    load_conn<D>(m.conn, e, nd);
+    load_conn<D, T>(m, e, nd);
     T y[D + 1][D];
     element_output<D, T, OP, NL>(m, U, V, t.mask, e, nd, y);
 #pragma unroll
@@ -584,7 +614,7 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work, const Ba
   using T = TU;   // element arithmetic type
   for (int e = br.x + (int)threadIdx.x; e < br.y; e += kThreads) {
     int nd[D + 1];
-    load_conn<D>(m.conn, e, nd);
+    load_conn<D, T>(m, e, nd);
     Geo<D, T> g;
     load_geometry<D, T>(m, nd, g);
     const T mu = mat_mu<T>(m, e);

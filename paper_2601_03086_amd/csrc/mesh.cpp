@@ -418,9 +418,32 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
       xq[n * D + i] = (uint32_t)std::min(std::max(t, 0.0), 4294967295.0);
     }
   }
+  // packed connectivity: smallest node first, 16-bit offsets of the others
+  const int nv = D + 1;
+  const int pw = D == 2 ? 2 : 3;
+  bool packable = true;
+  std::vector<uint32_t> cp((size_t)m->n_elems * pw);
+  for (int64_t s = 0; packable && s < m->n_elems; ++s) {
+    const int32_t* c = &m->conn_int[s * nv];
+    int amin = 0;
+    for (int a = 1; a < nv; ++a)
+      if (c[a] < c[amin]) amin = a;
+    uint32_t off[3];
+    for (int k = 1; k < nv; ++k) {
+      const int64_t dlt = (int64_t)c[(amin + k) % nv] - c[amin];
+      if (dlt > 65535) packable = false;
+      off[k - 1] = (uint32_t)dlt;
+    }
+    uint32_t* o = &cp[s * pw];
+    o[0] = (uint32_t)c[amin];
+    o[1] = (off[0] & 0xffffu) | ((off[1] & 0xffffu) << 16);
+    if (D == 3) o[2] = off[2];
+  }
+  if (!packable) cp.clear();
   try {
     d.X = upload(m->X_int, d.bytes);
     d.Xq = upload(xq, d.bytes);
+    d.connp = upload(cp, d.bytes);
     d.conn = upload(m->conn_int, d.bytes);
     d.mu32 = upload(mu32, d.bytes);
     d.lam32 = upload(lam32, d.bytes);
@@ -441,6 +464,8 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   MeshDev& md = m->md;
   md.X = d.X;
   md.Xq = d.Xq;
+  md.connp = d.connp;
+  md.conn_packed = packable ? 1 : 0;
   for (int i = 0; i < 3; ++i) md.qscale[i] = qscale[i];
   md.conn = d.conn;
   md.mu32 = d.mu32;
@@ -513,7 +538,7 @@ void mesh_release_device(pfem_mesh* m) {
   m->solve_state.reset();
   m->scratch.release();
   MeshDevBuffers& d = m->dev;
-  void* ptrs[] = {d.X, d.Xq, d.conn, d.mu32, d.lam32, d.mu64, d.lam64, d.dmask, d.blocks,
+  void* ptrs[] = {d.X, d.Xq, d.conn, d.connp, d.mu32, d.lam32, d.mu64, d.lam64, d.dmask, d.blocks,
                   d.halo, d.fext, d.ubar, d.colored, d.perm, d.work};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
@@ -529,7 +554,7 @@ void mesh_release_device(pfem_mesh* m) {
 int64_t mesh_device_bytes(const pfem_mesh* m) {
   const int64_t N = m->n_nodes, NE = m->n_elems, D = m->dim;
   auto r = [](int64_t b) { return std::max<int64_t>(b, 1); };
-  return r(N * D * 8) + r(N * D * 4) + r(NE * (D + 1) * 4) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
+  return r(N * D * 8) + r(N * D * 4) + r(NE * (D + 1) * 4) + r(NE * (D == 2 ? 8 : 12)) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
          r((int64_t)m->n_blocks * 16) + r((int64_t)m->halo.size() * 4) + 2 * r(N * D * 8) +
          r(NE * 4) + r(N * 4) + r((int64_t)m->n_blocks * 8);
 }

@@ -40,6 +40,7 @@ struct MeshDevBuffers {
   double* X = nullptr;
   uint32_t* Xq = nullptr;
   int32_t* conn = nullptr;
+  uint32_t* connp = nullptr;
   float* mu32 = nullptr;
   float* lam32 = nullptr;
   double* mu64 = nullptr;

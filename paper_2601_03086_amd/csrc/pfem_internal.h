@@ -50,6 +50,10 @@ struct MeshDev {
   const uint32_t* Xq;     // n_nodes * dim fixed-point coordinates (float32 kernels):
                           // X = lo + q * qscale, per dimension
   const int32_t* conn;    // n_elems * (dim+1), sorted element order, internal ids
+  const uint32_t* connp;  // packed connectivity (conn_packed): per element the
+                          // smallest node, then 16-bit offsets of the others
+                          // (2 words in 2D, 3 in 3D); node order inside the
+                          // element rotated so the smallest comes first
   const float* mu32;      // n_elems
   const float* lam32;     // n_elems
   const double* mu64;     // n_elems
@@ -63,9 +67,9 @@ struct MeshDev {
   int32_t n_nodes, n_elems, n_blocks, bn;
   int32_t dim, model, nonlinear;
   int32_t lam_uniform;    // 1: lambda = lam_ratio * mu on every element (lam arrays unread)
+  int32_t conn_packed;    // 1: kernels read connp (every offset fits 16 bits)
   double lam_ratio;
   float qscale[3];        // fixed-point coordinate step per dimension
-  int32_t pad2;
 };
 
 // Partial sums of one task: slot k of block b at part[k * n_blocks + b].
