@@ -260,7 +260,8 @@ typedef struct {
   int32_t max_newton;   /* per load step; 0 = 50 */
   int32_t prec;         /* PFEM_FP64 or PFEM_FP32 (FP32 Krylov, FP64 outer residual) */
   int32_t record_history;
-  double inner_rtol;    /* FP32 mode: residual reduction per refinement sweep; 0 = 1e-4 */
+  double inner_rtol;    /* FP32 mode: residual reduction per refinement sweep;
+                           0 = automatic (1e-4 for FUSED, 1e-3 for CLASSIC) */
   int32_t krylov;       /* PFEM_KRYLOV_*: PCG formulation of the inner solves */
 } pfem_solve_opts;
 

@@ -239,7 +239,7 @@ class Mesh:
     # ------------------------------------------------------------ solve
     @staticmethod
     def opts(tol=1e-8, prec="fp32", tol_fine=0.0, max_iter=0, n_load_steps=10,
-             max_newton=50, record_history=1, inner_rtol=1e-4, krylov="auto"):
+             max_newton=50, record_history=1, inner_rtol=0.0, krylov="auto"):
         o = L.pfem_solve_opts()
         L.pfem_solve_opts_default(C.byref(o))
         o.tol = tol

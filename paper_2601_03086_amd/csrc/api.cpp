@@ -605,7 +605,7 @@ void pfem_solve_opts_default(pfem_solve_opts* o) {
   o->max_newton = 50;
   o->prec = PFEM_FP32;
   o->record_history = 1;
-  o->inner_rtol = 1e-4;
+  o->inner_rtol = 0.0;   // automatic (by PCG formulation)
   o->krylov = PFEM_KRYLOV_AUTO;
 }
 
