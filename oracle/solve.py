@@ -20,8 +20,11 @@
   trial state with J <= 0; an energy change within the float64 rounding
   level of its summed terms (64 eps times their magnitudes) counts as
   inconclusive and the step is taken, because near convergence a Newton
-  step lowers the energy by O(|r|^2), below what the sum resolves; no
-  load-step predictor.
+  step lowers the energy by O(|r|^2), below what the sum resolves; each
+  load step after the first starts from the previous converged state
+  scaled to the new load fraction (a linear predictor: moving only the
+  prescribed DOFs would stretch the element layer next to the loaded
+  boundary by the whole increment).
 """
 import numpy as np
 import scipy.sparse.linalg as spla
@@ -150,10 +153,14 @@ def newton(prob, u0=None, tol=1e-8, n_load_steps=None, max_newton=50,
         steps = [nls]
     out = []
     status = 0
+    prev = None
     for n in steps:
         scale = n / nls
         m.f_ext = scale * f_full
+        if prev is not None:       # predictor: previous state scaled to this load
+            u = u * (n / prev)
         u[m.dir_dofs] = scale * m.dir_vals
+        prev = n
         den = np.linalg.norm(_residual_free(m, m.lifted(scale)))
         hist = []
         it = 0

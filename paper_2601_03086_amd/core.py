@@ -273,7 +273,11 @@ class Mesh:
         r = rep.as_dict()
         r["status_name"] = L.STATUS_NAMES.get(rep.status, rep.status)
         if st < 0:
-            check(st)
+            try:
+                check(st)
+            except L.PfemError as e:   # keep what the failed solve reported
+                e.report, e.u, e.history = r, u, hist[:rep.history_len].copy()
+                raise
         return u, r, hist[:rep.history_len].copy()
 
 

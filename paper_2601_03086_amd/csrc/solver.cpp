@@ -409,7 +409,11 @@ static void after_resid(Ctx* ctx, SlotRun* s) {
     if (s->nl && s->step < s->n_steps) {
       s->step += 1;
       const double scale = (double)s->step / s->n_steps;
-      launch_lift(ctx, s->m->md, s->st->x64, s->st->x64, scale);
+      // predictor: the converged state scaled to the new load fraction
+      // (exact for a linear response; the Dirichlet DOFs land exactly on
+      // the new values), instead of moving only the prescribed DOFs
+      launch_axpy_state(ctx, PFEM_FP64, s->m->md, s->st->x64, nullptr, s->st->x64,
+                        (double)s->step / (s->step - 1), true, scale);
       launch_lift(ctx, s->m->md, s->st->aux64, nullptr, scale);
       s->newton_in_step = 0;
       s->first_resid = false;
