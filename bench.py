@@ -49,6 +49,17 @@ KERNEL_NAME = "k_fcg<2, float, false>"
 KERNEL_MATCH = "k_fcg<2, float, false>"
 
 
+
+# internal node numbering and owner-block size of every mesh the benchmark
+# builds ("blocks" / "rcm"; 0 = automatic block size)
+ORDER = "blocks"
+BLOCK_NODES = 0
+
+
+def new_mesh(ctx, prob, bn=0):
+    from paper_2601_03086_amd import core
+    return core.Mesh.from_problem(ctx, prob, bn, ORDER)
+
 def kernel_hash():
     h = hashlib.sha256()
     for f in ("elem_kernels.hip", "elem_math.h", "reduce.h", "pfem_internal.h"):
@@ -201,7 +212,7 @@ def run_c1():
     from paper_2601_03086_amd import core
     prob = synth.unit_square_c1()
     ctx = core.Context(0)
-    mesh = core.Mesh.from_problem(ctx, prob)
+    mesh = new_mesh(ctx, prob)
     uref, _, _ = mesh.solve(tol=1e-12, prec="fp64", device_io=True)
     u0 = synth.warm_start_guess(uref.cpu().numpy(), prob.coords, prob.dir_nodes, seed=11)
     out = {"config": "C1 unit square, 2048 triangles, plane stress, FP64 PCG to 1e-10"}
@@ -231,7 +242,7 @@ def run_c3():
          f"{time.perf_counter() - t0:.1f}s")
     ctx = core.Context(0)
     t0 = time.perf_counter()
-    mesh = core.Mesh.from_problem(ctx, prob)
+    mesh = new_mesh(ctx, prob)
     _log(f"# preprocessed + uploaded in {time.perf_counter() - t0:.1f}s, "
          f"{mesh.info['n_blocks']} blocks of {mesh.info['block_nodes']}")
     uref, rref, tref = _timed_solve(mesh, tol=1e-10, prec="fp64", n_load_steps=10,
@@ -275,7 +286,7 @@ def run_c4():
     from paper_2601_03086_amd import _lib as L, core
     members = synth.batch_c4(64)
     ctx = core.Context(0)
-    meshes = [core.Mesh.from_problem(ctx, p) for p, _ in members]
+    meshes = [new_mesh(ctx, p) for p, _ in members]
     b = core.Batch(ctx, meshes)
     perms = [m.query(L.PFEM_Q_PERM) for m in meshes]
     parts = []
@@ -349,7 +360,7 @@ def run_sweep(spec):
             prob = synth.structured_box(nx, nx, 4 * nx, seed=7)
         _log(f"# {kind} {prob.n_elems} elements generated in {time.perf_counter() - t0:.1f}s")
         t0 = time.perf_counter()
-        mesh = core.Mesh.from_problem(ctx, prob)
+        mesh = new_mesh(ctx, prob)
         _log(f"# preprocessed + uploaded in {time.perf_counter() - t0:.1f}s")
         d = prob.dim
         for prec in ("fp32", "fp64"):
@@ -380,7 +391,7 @@ def run_rotate(copies, kind="c2"):
     meshes, xs, ys = [], [], []
     t0 = time.perf_counter()
     for i in range(copies):
-        m = core.Mesh.from_problem(ctx, prob)
+        m = new_mesh(ctx, prob)
         meshes.append(m)
         xs.append(m.permute(torch.randn(prob.n_dof, dtype=torch.float32, device="cuda"),
                             True, "fp32"))
@@ -427,7 +438,7 @@ def run_serve(n_requests=512, rate=200.0, pool=24, budget_gb=96, max_slots=64):
     for dsc in descs:
         p = synth.serving_problem(dsc)
         probs.append(p)
-        dm = core.Mesh.from_problem(ctx, p)
+        dm = new_mesh(ctx, p)
         kw = dict(tol=1e-10, prec="fp64", history_cap=1)
         if p.nonlinear:
             kw["n_load_steps"] = p.n_load_steps
@@ -435,7 +446,7 @@ def run_serve(n_requests=512, rate=200.0, pool=24, budget_gb=96, max_slots=64):
         dm.close()
         refs.append(rr)
         guesses.append(synth.warm_start_guess(uref, p.coords, p.dir_nodes, seed=dsc["seed"] + 7))
-        hmeshes.append(core.Mesh.from_problem(None, p))
+        hmeshes.append(new_mesh(None, p))
         _log(f"# pool {len(probs)}/{pool}: {dsc['kind']} {p.n_elems} elems, ref "
              f"{rr['status_name']} ({time.perf_counter() - t0:.0f}s)")
     opts = dict(tol=1e-8, prec="fp32")
@@ -448,7 +459,7 @@ def run_serve(n_requests=512, rate=200.0, pool=24, budget_gb=96, max_slots=64):
     for name in ("zero", "warm"):
         tt, kv = 0.0, 0
         for i, p in enumerate(probs):
-            dm = core.Mesh.from_problem(ctx, p)
+            dm = new_mesh(ctx, p)
             _, rep, t = _timed_solve(dm, u0=guesses[i] if name == "warm" else None,
                                      history_cap=1, **solve_kw(p))
             dm.close()
@@ -505,7 +516,7 @@ def setup(args):
     from paper_2601_03086_amd import core
     prob = c2_problem()
     ctx = core.Context(0)
-    mesh = core.Mesh.from_problem(ctx, prob, getattr(args, "block_nodes", 0) or 0)
+    mesh = new_mesh(ctx, prob, getattr(args, "block_nodes", 0) or 0)
     # reference (untimed): device FP64 solve at 1e-11, then 1% smooth noise
     uref, rep, hist = mesh.solve(tol=1e-11, prec="fp64", device_io=True)
     u0 = synth.warm_start_guess(uref.cpu().numpy(), prob.coords, prob.dir_nodes, seed=3002)
@@ -553,12 +564,12 @@ def run_kv_only(n, mesh_spec=None, kernel="owner"):
         prob = (synth.structured_plate(nx, nx, seed=7) if kind == "2d"
                 else synth.structured_box(nx, nx, 4 * nx, seed=7))
         ctx = core.Context(0)
-        mesh = core.Mesh.from_problem(ctx, prob)
+        mesh = new_mesh(ctx, prob)
     else:
         from paper_2601_03086_amd import core
         prob = c2_problem()
         ctx = core.Context(0)
-        mesh = core.Mesh.from_problem(ctx, prob)
+        mesh = new_mesh(ctx, prob)
     if kernel == "fused":
         mesh.solve(u0=None, tol=1e-8, prec="fp32", max_iter=n, history_cap=1)
     else:
@@ -583,7 +594,7 @@ def run_kv_sweep(sizes):
     ctx = core.Context(0)
     b_alg = alg_bytes_kv(prob.n_elems, prob.n_nodes, 2)
     for bn in sizes:
-        mesh = core.Mesh.from_problem(ctx, prob, bn)
+        mesh = new_mesh(ctx, prob, bn)
         for prec in ("fp32", "fp64"):
             dt = torch.float32 if prec == "fp32" else torch.float64
             x = mesh.permute(torch.randn(prob.n_dof, dtype=dt, device="cuda"), True, prec)
@@ -598,6 +609,7 @@ def run_kv_sweep(sizes):
             ctx.set_timing(())
             us = ms / n * 1e3
             print(json.dumps({"block_nodes": mesh.info["block_nodes"], "prec": prec,
+                              "order": ORDER,
                               "blocks": mesh.info["n_blocks"],
                               "visits_per_elem": round(mesh.info["owner_elem_visits"] / prob.n_elems, 3),
                               "avg_us": round(us, 3),
@@ -626,7 +638,7 @@ def run_kv_large(spec, reps=50):
         print(f"# generated {kind} {prob.n_elems} elements in {t_gen:.1f}s", file=sys.stderr,
               flush=True)
         t0 = time.perf_counter()
-        mesh = core.Mesh.from_problem(ctx, prob)
+        mesh = new_mesh(ctx, prob, BLOCK_NODES)
         t_prep = time.perf_counter() - t0
         print(f"# preprocessed in {t_prep:.1f}s", file=sys.stderr, flush=True)
         d = prob.dim
@@ -647,7 +659,8 @@ def run_kv_large(spec, reps=50):
             b_alg = alg_bytes_kv(prob.n_elems, prob.n_nodes, d, s=s, s_m=s)
             print(json.dumps({
                 "mesh": f"{kind} {prob.n_elems} elems {prob.n_nodes} nodes",
-                "prec": prec, "block_nodes": mesh.info["block_nodes"],
+                "prec": prec, "block_nodes": mesh.info["block_nodes"], "order": ORDER,
+                "bandwidth": mesh.info["bandwidth_rcm"],
                 "visits_per_elem": round(mesh.info["owner_elem_visits"] / prob.n_elems, 3),
                 "alg_bytes": b_alg, "avg_us": round(us, 2),
                 "alg_GBps": round(b_alg / (us * 1e-6) / 1e9, 1),
@@ -671,6 +684,8 @@ def main():
     ap.add_argument("--kv-sweep", default=None,
                     help="comma-separated owner-block sizes to time K.v with")
     ap.add_argument("--block-nodes", type=int, default=0)
+    ap.add_argument("--order", default="blocks", choices=["blocks", "rcm"],
+                    help="internal node numbering of every mesh")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"],
                     help="solve precision (fp32: FP32 Krylov + FP64 refinement)")
     ap.add_argument("--kv-mesh", default=None, help='mesh for --kv-only, e.g. "3d:40"')
@@ -688,6 +703,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="--config serve arrivals/s")
     ap.add_argument("--pool", type=int, default=24, help="--config serve distinct meshes")
     args = ap.parse_args()
+    global ORDER, BLOCK_NODES
+    ORDER, BLOCK_NODES = args.order, args.block_nodes
     if args.cpu_baseline_worker:
         cpu_baseline_worker()
         return
@@ -696,7 +713,7 @@ def main():
         print(json.dumps(d, indent=1))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build never uses a second GPU); "
+        print(f"bench.py measures one GPU only (the library has no multi-GPU path); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.kv_only:

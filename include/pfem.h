@@ -25,8 +25,8 @@
  *     next call on the same thread).  No C++ exception crosses the ABI.
  *   - Indices are 0-based int32.  A DOF index is g = node * dim + comp in
  *     the CALLER's node numbering unless a call takes PFEM_LAYOUT_INTERNAL,
- *     in which case vectors are in the library's reverse-Cuthill-McKee node
- *     order (see pfem_mesh_query_int(PFEM_Q_PERM)).
+ *     in which case vectors are in the library's internal node order (see
+ *     pfem_mesh_set_node_order and pfem_mesh_query_int(PFEM_Q_PERM)).
  *   - Input arrays are caller-owned and copied during the call.  Handles are
  *     library-owned and released with the matching *_destroy.  Output
  *     buffers are caller-owned.
@@ -99,7 +99,7 @@ enum {
 
 /* Integer query hooks (bit-exact preprocessing results). */
 enum {
-  PFEM_Q_PERM = 0,            /* n_nodes: new (RCM) id of each caller node */
+  PFEM_Q_PERM = 0,            /* n_nodes: internal id of each caller node */
   PFEM_Q_ELEM_ORDER = 1,      /* n_elems: caller element index at each sorted position */
   PFEM_Q_COLOR = 2,           /* n_elems: colour of each sorted element */
   PFEM_Q_FREE_INDEX = 3,      /* n_nodes*dim: rank among free DOFs (caller numbering) or -1 */
@@ -168,16 +168,30 @@ pfem_status pfem_mesh_set_dirichlet(pfem_mesh* m, int64_t n, const int32_t* node
  * f_ext puts t |facet| / n_f on each facet node (App. B, f_ext integral). */
 pfem_status pfem_mesh_set_neumann(pfem_mesh* m, int64_t n_facets,
                                   const int32_t* facet_nodes, const double* traction);
-/* Validate and preprocess: RCM numbering, element sort, colouring, free-DOF
- * map, node blocks; upload to the device when the mesh has a context.
- * block_nodes: nodes per owner block (0 = automatic). */
+/* Internal node numbering (not in the paper, which names no ordering; it
+ * decides how many elements straddle two owner blocks and so how often the
+ * element kernels evaluate an element):
+ *   PFEM_ORDER_BLOCKS (default): reverse Cuthill-McKee, cut into bands about
+ *     as many breadth-first levels thick as a block is wide, each band cut
+ *     into compact blocks of block_nodes nodes by recursive coordinate
+ *     bisection;
+ *   PFEM_ORDER_RCM: reverse Cuthill-McKee alone (blocks are runs of RCM
+ *     positions).
+ * Must be called before pfem_mesh_finalize (PFEM_E_STATE after); an unknown
+ * value is PFEM_E_INVALID_ARG. */
+enum { PFEM_ORDER_BLOCKS = 0, PFEM_ORDER_RCM = 1 };
+pfem_status pfem_mesh_set_node_order(pfem_mesh* m, int order);
+/* Validate and preprocess: node numbering, element sort, colouring,
+ * free-DOF map, node blocks; upload to the device when the mesh has a
+ * context.  block_nodes: nodes per owner block (0 = automatic). */
 pfem_status pfem_mesh_finalize(pfem_mesh* m, int block_nodes);
 
 typedef struct {
   int32_t dim, model;
   int64_t n_nodes, n_elems, n_dof, n_free;
   int32_t n_colors, n_blocks, block_nodes;
-  int64_t bandwidth_in, bandwidth_rcm;     /* max |i-j| over element node pairs */
+  int64_t bandwidth_in, bandwidth_rcm;     /* max |i-j| over element node pairs:
+                                              caller and internal numbering */
   int64_t owner_elem_visits;                /* sum over blocks of touched range lengths */
   int64_t device_bytes;                     /* mesh arrays resident on the device */
   int64_t solve_bytes_fp32, solve_bytes_fp64;   /* extra device bytes of one solve */

@@ -8,6 +8,19 @@ readings below make "bit-exact" meaningful by removing every tie:
   unvisited node of minimum degree (ties: smallest original id); a dequeued
   node appends its unvisited neighbours sorted by (degree, original id);
   the final order is reversed.  new_id[old] = position in that order.
+* Node blocks (the default numbering; RCM alone is the other choice): the
+  RCM order is cut into bands of k * bn consecutive positions, bn the nodes
+  per owner block, and each band into blocks of bn nodes by recursive
+  coordinate bisection, so that a block is a compact patch instead of a
+  sliver of one RCM level.  With L the number of breadth-first levels of
+  the Cuthill-McKee search (summed over components), N nodes and w the
+  largest integer with w**d <= bn, k = max(1, round(w N / (L bn))) (halves
+  rounded up): a band is about as many levels thick as a block is wide.  A
+  set S of more than bn nodes is split along the axis of largest extent
+  max - min over S (smallest axis on ties), ordered by (coordinate, RCM
+  position): the first bn * floor(ceil(|S| / bn) / 2) nodes go first, each
+  part recursively; a set of at most bn nodes is one block, in RCM order.
+  new_id[old] = position in the concatenated blocks.
 * Element order: sort by (min new id of the element's nodes, the sorted
   tuple of its new ids, original element index).  Node order inside an
   element is kept.
@@ -50,13 +63,16 @@ def node_adjacency(conn, n_nodes):
     return ptr, dst
 
 
-def rcm(conn, n_nodes):
-    """Reverse Cuthill-McKee; returns new_id (old -> new), int32."""
+def cuthill_mckee(conn, n_nodes):
+    """Cuthill-McKee visiting order (list of old ids) and the number of
+    breadth-first levels, summed over the components."""
     ptr, nbr = node_adjacency(conn, n_nodes)
     deg = np.diff(ptr)
     starts = np.lexsort((np.arange(n_nodes), deg))   # by (degree, id)
     visited = np.zeros(n_nodes, dtype=bool)
+    level = np.zeros(n_nodes, dtype=np.int64)
     order = []
+    n_levels = 0
     si = 0
     while len(order) < n_nodes:
         while visited[starts[si]]:
@@ -64,18 +80,81 @@ def rcm(conn, n_nodes):
         s = int(starts[si])
         visited[s] = True
         q = deque([s])
+        depth = 0
         while q:
             v = q.popleft()
             order.append(v)
+            depth = max(depth, int(level[v]))
             nb = nbr[ptr[v]:ptr[v + 1]]
             nb = nb[~visited[nb]]
             if nb.size:
                 nb = nb[np.lexsort((nb, deg[nb]))]
                 visited[nb] = True
+                level[nb] = level[v] + 1
                 q.extend(nb.tolist())
+        n_levels += depth + 1
+    return order, n_levels
+
+
+def rcm(conn, n_nodes):
+    """Reverse Cuthill-McKee; returns new_id (old -> new), int32."""
+    order, _ = cuthill_mckee(conn, n_nodes)
     order = np.array(order[::-1], dtype=np.int64)
     new_id = np.empty(n_nodes, dtype=np.int32)
     new_id[order] = np.arange(n_nodes, dtype=np.int32)
+    return new_id
+
+
+def auto_block_nodes(n_nodes):
+    """Nodes per owner block when the caller leaves it to the library:
+    ~1200 blocks on large meshes, at least 256 and at most 2048 nodes."""
+    return int(min(2048, max(256, ((n_nodes // 1200) + 31) // 32 * 32)))
+
+
+def int_root(bn, dim):
+    """Largest integer w with w**dim <= bn."""
+    w = 1
+    while (w + 1) ** dim <= bn:
+        w += 1
+    return w
+
+
+def band_blocks(n_nodes, n_levels, bn, dim):
+    """Blocks per band, k = max(1, round(w N / (L bn))), halves up."""
+    w = int_root(bn, dim)
+    num = 2 * w * n_nodes + n_levels * bn
+    return max(1, num // (2 * n_levels * bn))
+
+
+def bisect_blocks(nodes, coords, pos, bn):
+    """Recursive coordinate bisection of ``nodes`` into blocks of bn nodes
+    (module docstring); returns the nodes in block order."""
+    nodes = np.asarray(nodes, dtype=np.int64)
+    if nodes.size <= bn:
+        return nodes[np.argsort(pos[nodes], kind="stable")]
+    x = coords[nodes]
+    ext = x.max(axis=0) - x.min(axis=0)
+    ax = int(np.argmax(ext))                 # first maximum: smallest axis
+    o = np.lexsort((pos[nodes], x[:, ax]))
+    parts = -(-nodes.size // bn)
+    left = bn * (parts // 2)
+    return np.concatenate([bisect_blocks(nodes[o[:left]], coords, pos, bn),
+                           bisect_blocks(nodes[o[left:]], coords, pos, bn)])
+
+
+def block_numbering(conn, coords, n_nodes, bn):
+    """Node-block numbering (module docstring); new_id (old -> new), int32."""
+    order, n_levels = cuthill_mckee(conn, n_nodes)
+    rcm_order = np.array(order[::-1], dtype=np.int64)
+    pos = np.empty(n_nodes, dtype=np.int64)
+    pos[rcm_order] = np.arange(n_nodes)
+    coords = np.asarray(coords, dtype=np.float64)
+    band = band_blocks(n_nodes, n_levels, bn, coords.shape[1]) * bn
+    out = [bisect_blocks(rcm_order[b0:b0 + band], coords, pos, bn)
+           for b0 in range(0, n_nodes, band)]
+    seq = np.concatenate(out)
+    new_id = np.empty(n_nodes, dtype=np.int32)
+    new_id[seq] = np.arange(n_nodes, dtype=np.int32)
     return new_id
 
 
@@ -138,14 +217,21 @@ def free_dof_map(n_nodes, dim, dir_nodes, dir_comps):
     return out
 
 
-def preprocess(prob):
-    """All bit-exact preprocessing results for a problem, as a dict."""
-    new_id = rcm(prob.conn, prob.n_nodes)
+def preprocess(prob, block_nodes=0, order="blocks"):
+    """All bit-exact preprocessing results for a problem, as a dict.
+    order: "blocks" (node blocks cut from RCM bands, the library default) or
+    "rcm"; block_nodes 0 = auto_block_nodes."""
+    bn = block_nodes or auto_block_nodes(prob.n_nodes)
+    if order == "rcm":
+        new_id = rcm(prob.conn, prob.n_nodes)
+    else:
+        new_id = block_numbering(prob.conn, prob.coords, prob.n_nodes, bn)
     eo = element_order(prob.conn, new_id)
     sconn = np.asarray(new_id)[np.asarray(prob.conn)[eo]]
     col = colour_elements(sconn, prob.n_nodes)
     fmap = free_dof_map(prob.n_nodes, prob.dim, prob.dir_nodes, prob.dir_comps)
-    return {"perm": new_id, "elem_order": eo, "color": col, "free_index": fmap}
+    return {"perm": new_id, "elem_order": eo, "color": col, "free_index": fmap,
+            "block_nodes": bn}
 
 
 def bandwidth(conn, numbering):

@@ -29,6 +29,7 @@ PFEM_NH_PLANE_STRAIN, PFEM_NH_3D = 3, 4
 PFEM_PARAM_E_NU, PFEM_PARAM_LAME = 0, 1
 PFEM_FP64, PFEM_FP32 = 0, 1
 PFEM_KRYLOV_AUTO, PFEM_KRYLOV_CLASSIC, PFEM_KRYLOV_FUSED = 0, 1, 2
+PFEM_ORDER_BLOCKS, PFEM_ORDER_RCM = 0, 1
 PFEM_SCATTER_OWNER, PFEM_SCATTER_COLORED, PFEM_SCATTER_ATOMIC = 0, 1, 2
 PFEM_LAYOUT_USER, PFEM_LAYOUT_INTERNAL = 0, 1
 PFEM_MASK_NONE, PFEM_MASK_OUT, PFEM_MASK_IN = 0, 1, 2
@@ -95,6 +96,7 @@ PROTOTYPES = {
     "pfem_mesh_set_material": (_I32, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "pfem_mesh_set_dirichlet": (_I32, [_VP, _I64, _VP, _VP, _VP]),
     "pfem_mesh_set_neumann": (_I32, [_VP, _I64, _VP, _VP]),
+    "pfem_mesh_set_node_order": (_I32, [_VP, C.c_int]),
     "pfem_mesh_finalize": (_I32, [_VP, C.c_int]),
     "pfem_mesh_get_info": (_I32, [_VP, C.POINTER(pfem_mesh_info)]),
     "pfem_mesh_query_int": (_I32, [_VP, C.c_int, _VP, _I64, C.POINTER(_I64)]),

@@ -53,6 +53,7 @@ MODEL_IDS = {"lin_plane_stress": L.PFEM_LIN_PLANE_STRESS,
              "nh_plane_strain": L.PFEM_NH_PLANE_STRAIN,
              "nh_3d": L.PFEM_NH_3D}
 PARAM_IDS = {"E_nu": L.PFEM_PARAM_E_NU, "lame": L.PFEM_PARAM_LAME}
+ORDER_IDS = {"blocks": L.PFEM_ORDER_BLOCKS, "rcm": L.PFEM_ORDER_RCM}
 PREC = {"fp64": L.PFEM_FP64, "fp32": L.PFEM_FP32, L.PFEM_FP64: L.PFEM_FP64,
         L.PFEM_FP32: L.PFEM_FP32}
 SCATTER = {"owner": L.PFEM_SCATTER_OWNER, "colored": L.PFEM_SCATTER_COLORED,
@@ -123,7 +124,7 @@ class Mesh:
 
     def __init__(self, ctx, dim, coords, conn, model, param_kind, p0, p1,
                  dir_nodes=(), dir_comps=(), dir_values=(), facets=None,
-                 traction=None, block_nodes=0):
+                 traction=None, block_nodes=0, order="blocks"):
         L.load()
         self.ctx = ctx
         self.dim = int(dim)
@@ -151,16 +152,19 @@ class Mesh:
             fa = np.ascontiguousarray(facets, dtype=np.int32)
             tr = np.ascontiguousarray(traction, dtype=np.float64)
             check(L.pfem_mesh_set_neumann(h, fa.shape[0], _ptr(fa), _ptr(tr)))
+        check(L.pfem_mesh_set_node_order(h, ORDER_IDS[order]))
         check(L.pfem_mesh_finalize(h, int(block_nodes)))
         self.info = self.get_info()
         _LIVE["mesh"].add(self)
 
     @classmethod
-    def from_problem(cls, ctx, prob, block_nodes=0):
-        """Build from any object with the fields of a problem description."""
+    def from_problem(cls, ctx, prob, block_nodes=0, order="blocks"):
+        """Build from any object with the fields of a problem description.
+        order: internal node numbering, "blocks" (default) or "rcm"."""
         return cls(ctx, prob.coords.shape[1], prob.coords, prob.conn, prob.model,
                    prob.param_kind, prob.p0, prob.p1, prob.dir_nodes, prob.dir_comps,
-                   prob.dir_values, prob.neu_facets, prob.neu_traction, block_nodes)
+                   prob.dir_values, prob.neu_facets, prob.neu_traction, block_nodes,
+                   order)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

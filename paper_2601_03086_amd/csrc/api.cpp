@@ -225,6 +225,16 @@ pfem_status pfem_mesh_set_neumann(pfem_mesh* m, int64_t n_facets, const int32_t*
   PFEM_TRY_END
 }
 
+pfem_status pfem_mesh_set_node_order(pfem_mesh* m, int order) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
+  require(!m->finalized, PFEM_E_STATE, "mesh already finalized");
+  require(order == PFEM_ORDER_BLOCKS || order == PFEM_ORDER_RCM, PFEM_E_INVALID_ARG,
+          "unknown node order");
+  m->node_order = order;
+  PFEM_TRY_END
+}
+
 pfem_status pfem_mesh_finalize(pfem_mesh* m, int block_nodes) {
   PFEM_TRY_BEGIN
   require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");

@@ -7,6 +7,16 @@
 //    smallest degree (ties: smallest caller id); a dequeued node appends its
 //    unvisited neighbours ordered by (degree, caller id); the visiting order
 //    is reversed at the end;
+//  * node blocks (default numbering): the RCM order is cut into bands of
+//    k * bn consecutive positions, k = max(1, round(w N / (L bn))) with L the
+//    number of breadth-first levels of the search (summed over components)
+//    and w the largest integer with w^d <= bn, halves rounded up; each band
+//    is cut into blocks of bn nodes by recursive coordinate bisection: a set
+//    of more than bn nodes is ordered along its axis of largest extent
+//    (smallest axis on ties) by (coordinate, RCM position) and split after
+//    bn * floor(ceil(n / bn) / 2) nodes; a set of at most bn nodes is a
+//    block, kept in RCM order.  Blocks become compact patches instead of
+//    slivers of one RCM level, so far fewer elements straddle two blocks;
 //  * elements sorted by the ascending tuple of their new node ids, ties by
 //    caller element index (so the smallest node id is non-decreasing);
 //  * colours by first fit in decreasing priority (fmix32(k ^ 0x9E3779B9), k)
@@ -121,7 +131,9 @@ static void node_graph(const pfem_mesh* m, std::vector<int64_t>& ptr,
   }
 }
 
-static void rcm(const pfem_mesh* m, std::vector<int32_t>& new_id) {
+// Cuthill-McKee visiting order; returns the number of breadth-first levels
+// summed over the components.
+static int64_t cuthill_mckee(const pfem_mesh* m, std::vector<int32_t>& q) {
   std::vector<int64_t> ptr;
   std::vector<int32_t> nbr;
   node_graph(m, ptr, nbr);
@@ -133,18 +145,21 @@ static void rcm(const pfem_mesh* m, std::vector<int32_t>& new_id) {
   std::stable_sort(starts.begin(), starts.end(),
                    [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
   std::vector<char> vis(N, 0);
-  std::vector<int32_t> q;
+  std::vector<int32_t> level(N, 0);
+  q.clear();
   q.reserve(N);
   std::vector<int32_t> tmp;
-  int64_t si = 0;
+  int64_t si = 0, n_levels = 0;
   size_t head = 0;
   while ((int64_t)q.size() < N) {
     while (vis[starts[si]]) ++si;
     const int32_t s = starts[si];
     vis[s] = 1;
     q.push_back(s);
+    int32_t depth = 0;
     while (head < q.size()) {
       const int32_t v = q[head++];
+      depth = std::max(depth, level[v]);
       tmp.clear();
       for (int64_t k = ptr[v]; k < ptr[v + 1]; ++k)
         if (!vis[nbr[k]]) tmp.push_back(nbr[k]);
@@ -153,12 +168,67 @@ static void rcm(const pfem_mesh* m, std::vector<int32_t>& new_id) {
       });
       for (int32_t w : tmp) {
         vis[w] = 1;
+        level[w] = level[v] + 1;
         q.push_back(w);
       }
     }
+    n_levels += depth + 1;
+  }
+  return n_levels;
+}
+
+// Recursive coordinate bisection of nodes[b, e) into blocks of bn nodes, in
+// place (rules in the header comment).  pos: RCM position of each node.
+static void bisect_blocks(int32_t* b, int32_t* e, const double* X, int D,
+                          const std::vector<int32_t>& pos, int bn) {
+  const int64_t n = e - b;
+  if (n <= bn) {
+    std::sort(b, e, [&](int32_t x, int32_t y) { return pos[x] < pos[y]; });
+    return;
+  }
+  double lo[3], hi[3];
+  for (int i = 0; i < D; ++i) lo[i] = hi[i] = X[(int64_t)b[0] * D + i];
+  for (const int32_t* v = b; v != e; ++v)
+    for (int i = 0; i < D; ++i) {
+      const double c = X[(int64_t)*v * D + i];
+      lo[i] = std::min(lo[i], c);
+      hi[i] = std::max(hi[i], c);
+    }
+  int ax = 0;
+  for (int i = 1; i < D; ++i)
+    if (hi[i] - lo[i] > hi[ax] - lo[ax]) ax = i;
+  const int64_t parts = (n + bn - 1) / bn;
+  const int64_t left = (int64_t)bn * (parts / 2);
+  // the left set is unique under the strict order (coordinate, position)
+  std::nth_element(b, b + left, e, [&](int32_t x, int32_t y) {
+    const double cx = X[(int64_t)x * D + ax], cy = X[(int64_t)y * D + ax];
+    return cx != cy ? cx < cy : pos[x] < pos[y];
+  });
+  bisect_blocks(b, b + left, X, D, pos, bn);
+  bisect_blocks(b + left, e, X, D, pos, bn);
+}
+
+// new_id[caller node] = internal node (RCM, or node blocks cut from RCM bands).
+static void number_nodes(const pfem_mesh* m, int bn, bool blocks,
+                         std::vector<int32_t>& new_id) {
+  const int64_t N = m->n_nodes;
+  std::vector<int32_t> q;
+  const int64_t n_levels = cuthill_mckee(m, q);
+  std::reverse(q.begin(), q.end());            // q[position] = caller node (RCM)
+  if (blocks) {
+    std::vector<int32_t> pos(N);
+    for (int64_t i = 0; i < N; ++i) pos[q[i]] = (int32_t)i;
+    int64_t w = 1;
+    auto ipow = [&](int64_t x) { int64_t r = 1; for (int i = 0; i < m->dim; ++i) r *= x; return r; };
+    while (ipow(w + 1) <= bn) ++w;
+    const int64_t k = std::max<int64_t>(1, (2 * w * N + n_levels * bn) / (2 * n_levels * bn));
+    const int64_t band = k * bn;
+    for (int64_t b0 = 0; b0 < N; b0 += band)
+      bisect_blocks(q.data() + b0, q.data() + std::min(N, b0 + band), m->coords.data(),
+                    m->dim, pos, bn);
   }
   new_id.assign(N, 0);
-  for (int64_t i = 0; i < N; ++i) new_id[q[N - 1 - i]] = (int32_t)i;
+  for (int64_t i = 0; i < N; ++i) new_id[q[i]] = (int32_t)i;
 }
 
 static int64_t bandwidth(const pfem_mesh* m, const int32_t* numbering) {
@@ -181,8 +251,18 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
   const int D = m->dim;
   const int nv = D + 1;
   const int64_t N = m->n_nodes, NE = m->n_elems;
-  // 1. RCM
-  rcm(m, m->perm);
+  // 0. nodes per owner block
+  int bn = block_nodes;
+  if (bn <= 0) {
+    // about 1200 blocks on large meshes (fills the chip), at least 256 nodes
+    // per block on small ones: the fused PCG launch sums every block's
+    // partials in every block, which grows with the square of the block count
+    const int64_t target = 1200;
+    bn = (int)std::min<int64_t>(2048, std::max<int64_t>(256, ((N / target) + 31) / 32 * 32));
+  }
+  require(bn <= block_nodes_max(), PFEM_E_INVALID_ARG, "block_nodes too large");
+  // 1. node numbering
+  number_nodes(m, bn, m->node_order == PFEM_ORDER_BLOCKS, m->perm);
   m->bw_in = bandwidth(m, nullptr);
   m->bw_rcm = bandwidth(m, m->perm.data());
   // 2. element order
@@ -317,16 +397,6 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
     m->lam_int[s] = m->lam[m->elem_order[s]];
   }
   // 7. owner node blocks
-  int bn = block_nodes;
-  if (bn <= 0) {
-    // about 1200 blocks on large meshes (fills the chip, bounds the halo
-    // revisits), at least 256 nodes per block on small ones: the fused PCG
-    // launch sums every block's partials in every block, which grows with
-    // the square of the block count
-    const int64_t target = 1200;
-    bn = (int)std::min<int64_t>(2048, std::max<int64_t>(256, ((N / target) + 31) / 32 * 32));
-  }
-  require(bn <= block_nodes_max(), PFEM_E_INVALID_ARG, "block_nodes too large");
   m->bn = bn;
   m->n_blocks = (int)((N + bn - 1) / bn);
   const int nb = m->n_blocks;

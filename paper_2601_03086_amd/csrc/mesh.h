@@ -88,6 +88,7 @@ struct pfem_mesh {
   std::vector<double> traction;
   int64_t n_facets = 0;
 
+  int node_order = PFEM_ORDER_BLOCKS;
   bool finalized = false;
   // preprocessing (bit-exact hooks)
   std::vector<int32_t> perm;        // caller node -> internal node

@@ -401,6 +401,78 @@ def test_rcm_two_components_and_ties():
     assert new_id.tolist() == exp.tolist()
 
 
+def test_cuthill_mckee_levels_hand_example():
+    """Same graph as above: component A is searched in levels {0}, {2,5},
+    {4} and component B in {1}, {3,6}: 3 + 2 levels."""
+    conn = np.array([[4, 2, 5], [2, 0, 5], [1, 3, 6]], dtype=np.int32)
+    order, levels = prep.cuthill_mckee(conn, 7)
+    assert order == [0, 2, 5, 4, 1, 3, 6]
+    assert levels == 5
+
+
+def test_band_size_hand_values():
+    assert [prep.int_root(b, d) for b, d in [(255, 2), (256, 2), (26, 3), (27, 3), (1, 3)]] == \
+        [15, 16, 2, 3, 1]
+    # k = round(w N / (L bn)): 4*1000/(10*16) = 25; 4*80/(8*16) = 2.5 -> 3 (halves up);
+    # 4*100/(8*16) = 3.125 -> 3; tiny ratios clamp to one block per band
+    assert prep.band_blocks(1000, 10, 16, 2) == 25
+    assert prep.band_blocks(80, 8, 16, 2) == 3
+    assert prep.band_blocks(100, 8, 16, 2) == 3
+    assert prep.band_blocks(10, 100, 256, 2) == 1
+    assert prep.auto_block_nodes(1000) == 256 and prep.auto_block_nodes(10 ** 6) == 864
+    assert prep.auto_block_nodes(10 ** 8) == 2048
+
+
+def test_bisect_blocks_hand_example():
+    """Eight points, blocks of two.  Top level: x and y extents tie (3), so
+    x splits; the 4 smallest (x, position) are {0,4,2,6}.  Each half has
+    x extent 1 < y extent 3, so y splits it into pairs; a block keeps the
+    RCM position order."""
+    X = np.array([[0, 0], [3, 0], [1, 1], [2, 1], [0, 2], [3, 2], [1, 3], [2, 3]], float)
+    pos = np.arange(8)
+    assert prep.bisect_blocks(np.arange(8), X, pos, 2).tolist() == [0, 2, 4, 6, 1, 3, 5, 7]
+    # reversed positions: same sets (no coordinate tie decides a split), each
+    # block in the new position order
+    pos = np.arange(8)[::-1].copy()
+    assert prep.bisect_blocks(np.arange(8), X, pos, 2).tolist() == [2, 0, 6, 4, 3, 1, 7, 5]
+    # a split through tied coordinates takes the smaller positions first;
+    # zero extent everywhere falls back to axis x
+    X = np.array([[0, 0], [0, 0], [0, 0], [1, 0]], float)
+    assert prep.bisect_blocks(np.arange(4), X, np.array([2, 0, 1, 3]), 1).tolist() == \
+        [1, 2, 0, 3]
+    # blocks of three out of seven: 3 parts -> first split after 3 nodes
+    X = np.array([[k, 0] for k in range(7)], float)
+    assert prep.bisect_blocks(np.arange(7)[::-1], X, np.arange(7), 3).tolist() == \
+        list(range(7))
+
+
+def test_block_numbering_invariants():
+    """Bands are runs of RCM positions; inside a band every block is a
+    coordinate-bisection cell: the blocks' bounding boxes do not overlap
+    in their splitting order, and the numbering is a permutation."""
+    p = synth.structured_plate(30, 24, 5)
+    bn = 32
+    new_id = prep.block_numbering(p.conn, p.coords, p.n_nodes, bn)
+    assert sorted(new_id.tolist()) == list(range(p.n_nodes))
+    order, levels = prep.cuthill_mckee(p.conn, p.n_nodes)
+    rcm_pos = np.empty(p.n_nodes, np.int64)
+    rcm_pos[np.array(order[::-1])] = np.arange(p.n_nodes)
+    band = prep.band_blocks(p.n_nodes, levels, bn, 2) * bn
+    assert band > bn
+    for b0 in range(0, p.n_nodes, band):
+        members = np.nonzero((new_id >= b0) & (new_id < b0 + band))[0]
+        assert np.array_equal(np.sort(rcm_pos[members]),
+                              np.arange(b0, min(p.n_nodes, b0 + band)))
+    # every full block is compact: its bounding box is at most 2.5x the area
+    # of bn lattice cells (30 x 24 cells on the unit square; RCM blocks,
+    # slivers of one level, reach ~11x here)
+    seq = np.argsort(new_id)
+    for b0 in range(0, p.n_nodes - bn + 1, bn):
+        x = p.coords[seq[b0:b0 + bn]]
+        ext = x.max(0) - x.min(0)
+        assert ext[0] * ext[1] <= 2.5 * bn / (30 * 24)
+
+
 def test_preprocessing_invariants():
     p = synth.plate_problem(21, 22, 23, n_holes=3, target_tris=3000)
     r = prep.preprocess(p)
