@@ -586,15 +586,38 @@ def run_kv_only(n, mesh_spec=None, kernel="owner"):
     print(json.dumps({"kv_launches": n, "copy_bytes": a.numel() * 4}))
 
 
-def run_kv_sweep(sizes):
-    """Average K.v time (FP32 and FP64, internal layout) per owner-block size."""
+def run_kv_sweep(sizes, mesh_spec=None):
+    """Average K.v time (FP32 and FP64, internal layout) per owner-block size,
+    and the average fused PCG iteration of a capped FP32 solve.  mesh_spec:
+    None (the 200k-triangle plate) or "2d:NX" / "3d:NX" structured meshes."""
+    import numpy as np
     import torch
     from paper_2601_03086_amd import core
-    prob = c2_problem()
+    if mesh_spec:
+        import synth
+        kind, nx = mesh_spec.split(":")
+        nx = int(nx)
+        prob = (synth.structured_plate(nx, nx, seed=7) if kind == "2d"
+                else synth.structured_box(nx, nx, 4 * nx, seed=7))
+    else:
+        prob = c2_problem()
     ctx = core.Context(0)
-    b_alg = alg_bytes_kv(prob.n_elems, prob.n_nodes, 2)
+    b_alg = alg_bytes_kv(prob.n_elems, prob.n_nodes, prob.dim)
     for bn in sizes:
         mesh = new_mesh(ctx, prob, bn)
+        ctx.set_timing([FAM_FUSED])
+        ctx.reset_timing()
+        try:
+            u0 = np.random.default_rng(0).normal(size=prob.n_dof)   # residual != 0
+            mesh.solve(u0=u0, tol=1e-14, prec="fp32", krylov="fused", max_iter=600,
+                       history_cap=1)
+        except core.L.PfemError:
+            pass                       # the iteration cap ends the solve
+        nf, msf = ctx.kernel_time(FAM_FUSED)
+        ctx.set_timing(())
+        print(json.dumps({"block_nodes": mesh.info["block_nodes"], "order": ORDER,
+                          "blocks": mesh.info["n_blocks"], "fused_launches": nf,
+                          "fused_avg_us": round(msf / max(nf, 1) * 1e3, 3)}), flush=True)
         for prec in ("fp32", "fp64"):
             dt = torch.float32 if prec == "fp32" else torch.float64
             x = mesh.permute(torch.randn(prob.n_dof, dtype=dt, device="cuda"), True, prec)
@@ -720,7 +743,7 @@ def main():
         run_kv_only(args.kv_only, args.kv_mesh, args.kv_kernel)
         return
     if args.kv_sweep:
-        run_kv_sweep([int(s) for s in args.kv_sweep.split(",")])
+        run_kv_sweep([int(s) for s in args.kv_sweep.split(",")], args.kv_mesh)
         return
     if args.kv_large:
         run_kv_large(args.kv_large)

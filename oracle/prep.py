@@ -14,8 +14,9 @@ readings below make "bit-exact" meaningful by removing every tie:
   coordinate bisection, so that a block is a compact patch instead of a
   sliver of one RCM level.  With L the number of breadth-first levels of
   the Cuthill-McKee search (summed over components), N nodes and w the
-  largest integer with w**d <= bn, k = max(1, round(w N / (L bn))) (halves
-  rounded up): a band is about as many levels thick as a block is wide.  A
+  largest integer with w**d <= bn, k = max(1, min(round(w N / (L bn)),
+  floor(32768 / bn))) (halves rounded up): a band is about as many levels
+  thick as a block is wide, and at most 32768 positions long.  A
   set S of more than bn nodes is split along the axis of largest extent
   max - min over S (smallest axis on ties), ordered by (coordinate, RCM
   position): the first bn * floor(ceil(|S| / bn) / 2) nodes go first, each
@@ -105,10 +106,12 @@ def rcm(conn, n_nodes):
     return new_id
 
 
-def auto_block_nodes(n_nodes):
+def auto_block_nodes(n_nodes, dim):
     """Nodes per owner block when the caller leaves it to the library:
-    ~1200 blocks on large meshes, at least 256 and at most 2048 nodes."""
-    return int(min(2048, max(256, ((n_nodes // 1200) + 31) // 32 * 32)))
+    N/2000 (2D) or N/750 (3D) rounded up to a multiple of 32, at least 224
+    (2D) or 64 (3D), at most 2048."""
+    per, lo = (2000, 224) if dim == 2 else (750, 64)
+    return int(min(2048, max(lo, ((n_nodes // per) + 31) // 32 * 32)))
 
 
 def int_root(bn, dim):
@@ -120,10 +123,11 @@ def int_root(bn, dim):
 
 
 def band_blocks(n_nodes, n_levels, bn, dim):
-    """Blocks per band, k = max(1, round(w N / (L bn))), halves up."""
+    """Blocks per band, k = max(1, min(round(w N / (L bn)), floor(32768 / bn))),
+    halves up (the cap keeps a band within 32768 positions)."""
     w = int_root(bn, dim)
     num = 2 * w * n_nodes + n_levels * bn
-    return max(1, num // (2 * n_levels * bn))
+    return max(1, min(num // (2 * n_levels * bn), 32768 // bn))
 
 
 def bisect_blocks(nodes, coords, pos, bn):
@@ -221,7 +225,7 @@ def preprocess(prob, block_nodes=0, order="blocks"):
     """All bit-exact preprocessing results for a problem, as a dict.
     order: "blocks" (node blocks cut from RCM bands, the library default) or
     "rcm"; block_nodes 0 = auto_block_nodes."""
-    bn = block_nodes or auto_block_nodes(prob.n_nodes)
+    bn = block_nodes or auto_block_nodes(prob.n_nodes, prob.dim)
     if order == "rcm":
         new_id = rcm(prob.conn, prob.n_nodes)
     else:

@@ -47,9 +47,11 @@ __device__ __forceinline__ void load_conn(const int32_t* __restrict__ conn, int 
 // 12 in 3D) when the mesh fits, else plain int32 rows.  Measured on large
 // meshes: packing pays in 2D and in 3D float64, while 3D float32 is faster
 // with one 16-byte load of the plain row.
-template <int D, typename T>
+// PK = 1: the caller guarantees packed connectivity wherever this format
+// uses it (no run-time test, so no wait at a branch join).
+template <int D, typename T, int PK = 0>
 __device__ __forceinline__ void load_conn(const MeshDev& m, int e, int (&nd)[D + 1]) {
-  if ((D == 2 || sizeof(T) == 8) && m.conn_packed) {
+  if ((D == 2 || sizeof(T) == 8) && (PK == 1 || m.conn_packed)) {
     if constexpr (D == 2) {
       typedef unsigned int pu2 __attribute__((ext_vector_type(2)));
       const pu2 q = ldg(reinterpret_cast<const pu2*>(m.connp + (size_t)e * 2));
@@ -90,10 +92,13 @@ __device__ __forceinline__ T mat_mu(const MeshDev& m, int e) {
 }
 // lambda of element e given its mu: one multiply when the mesh has a
 // uniform lambda / mu ratio (one material value per element to stream)
+// (branch-free: a uniform mesh re-reads mu, which is already in flight)
 template <typename T>
 __device__ __forceinline__ T mat_lam(const MeshDev& m, int e, T mu) {
-  if (m.lam_uniform) return (T)m.lam_ratio * mu;
-  if constexpr (sizeof(T) == 4) return ldg(m.lam32 + e); else return ldg(m.lam64 + e);
+  const T* lam;
+  if constexpr (sizeof(T) == 4) lam = m.lam_uniform ? m.mu32 : m.lam32;
+  else lam = m.lam_uniform ? m.mu64 : m.lam64;
+  return ldg(lam + e) * (m.lam_uniform ? (T)m.lam_ratio : T(1));
 }
 
 // Everything one element needs, gathered before any arithmetic so that all
@@ -186,7 +191,7 @@ __device__ __forceinline__ void element_compute(const MeshDev& m,
       grad_tilde<D, T>(in.u, g, Ht);
       NHState<D, T> st;
       nh_state<D, T>(Ht, T(1) / g.det, st);
-      const T coef = (T)((double)lam + (double)mu - (double)lam * st.lnJ);
+      const T coef = lam + mu - lam * st.lnJ;
 #pragma unroll
       for (int a = 0; a <= D; ++a) {
         T n2 = T(0);
@@ -265,9 +270,77 @@ using AccT = typename std::conditional<PFEM_ACC_F64 != 0, double, T>::type;
 // Workgroup = (task, node block).  Elements visited: the block's own sorted
 // range (smallest node inside the block) followed by its halo list
 // (elements owned by earlier blocks that reach into it).  Each thread keeps
-// two elements in flight: both connectivity rows are loaded, then all
-// gathers of both elements, then the arithmetic.  On return acc[] holds the
-// block's owned DOFs (all threads synchronised).
+// EIF elements in flight: all connectivity rows are loaded, then all
+// gathers, then the arithmetic.
+
+// One round of EIF visits per thread: visit t0 + q NT for q < EIF.  A slot
+// past the end loads visit min(t0, total - 1) instead (every block has at
+// least one visit) and is skipped, so every load stays inside the block's
+// own range or halo list even when t0 itself is past the end.
+template <int D, typename T, int OP, bool NL, bool FUSED, int EIF>
+struct VisitRound {
+  int nd[EIF][D + 1];
+  bool on[EIF];
+  ElemIn<D, T, OP, NL, FUSED> in[EIF];
+};
+
+template <int D, typename T, int OP, bool NL, bool FUSED, int NT, int EIF, int PK = 0>
+__device__ __forceinline__ void load_round(const MeshDev& m, const T* __restrict__ U,
+                                           const T* __restrict__ V, int mask, const pi4 br,
+                                           int t0, VisitRound<D, T, OP, NL, FUSED, EIF>& rd) {
+  const int n_own = br.y - br.x;
+  const int n_halo = br.w - br.z;
+  const int total = n_own + n_halo;
+  int e[EIF];
+#pragma unroll
+  for (int q = 0; q < EIF; ++q) {
+    const int t = t0 + q * NT;
+    rd.on[q] = t < total;
+    const int tt = rd.on[q] ? t : min(t0, total - 1);
+    // the halo entry is read unconditionally (clamped; the device list has
+    // one padding entry) so that no load waits at a branch join
+    const int h = ldg(m.halo + br.z + min(max(tt - n_own, 0), max(n_halo - 1, 0)));
+    e[q] = tt < n_own ? br.x + tt : h;
+  }
+#pragma unroll
+  for (int q = 0; q < EIF; ++q) load_conn<D, T, PK>(m, e[q], rd.nd[q]);
+#pragma unroll
+  for (int q = 0; q < EIF; ++q)
+    load_elem<D, T, OP, NL, FUSED>(m, U, V, mask, e[q], rd.nd[q], rd.in[q]);
+}
+
+template <int D, typename T, int OP, bool NL, typename A, bool FUSED, int EIF>
+__device__ __forceinline__ void compute_round(const MeshDev& m,
+                                              VisitRound<D, T, OP, NL, FUSED, EIF>& rd,
+                                              int n0, int nloc, A* acc, T alpha, T beta) {
+  T y[D + 1][D];
+#pragma unroll
+  for (int q = 0; q < EIF; ++q) {
+    if (!rd.on[q]) continue;
+    if constexpr (FUSED) fcg_direction<D, T, OP, NL>(rd.in[q], alpha, beta);
+    element_compute<D, T, OP, NL, FUSED>(m, rd.in[q], y);
+    lds_accumulate<D, T, A>(acc, rd.nd[q], n0, nloc, y);
+  }
+}
+
+// All visits of the block from t_first on (t_first = threadIdx.x: all of
+// them).  acc[] must be zero and visible to every thread; on return it holds
+// the block's owned DOFs (all threads synchronised).
+template <int D, typename T, int OP, bool NL, typename A, bool FUSED = false, int NT = kThreads,
+          int EIF = 2, int PK = 0>
+__device__ __forceinline__ void owner_rounds(const MeshDev& m, const T* __restrict__ U,
+                                             const T* __restrict__ V, int mask, const pi4 br,
+                                             int t_first, int n0, int nloc, A* acc,
+                                             T alpha = T(0), T beta = T(0)) {
+  const int total = (br.y - br.x) + (br.w - br.z);
+  for (int t0 = t_first; t0 < total; t0 += EIF * NT) {
+    VisitRound<D, T, OP, NL, FUSED, EIF> rd;
+    load_round<D, T, OP, NL, FUSED, NT, EIF, PK>(m, U, V, mask, br, t0, rd);
+    compute_round<D, T, OP, NL, A, FUSED, EIF>(m, rd, n0, nloc, acc, alpha, beta);
+  }
+  __syncthreads();
+}
+
 template <int D, typename T, int OP, bool NL, typename A, bool FUSED = false, int NT = kThreads,
           int EIF = 2>
 __device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __restrict__ U,
@@ -277,36 +350,8 @@ __device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __re
   const int nown = nloc * D;
   for (int i = threadIdx.x; i < nown; i += NT) acc[i] = A(0);
   __syncthreads();
-  const int n_own = br.y - br.x;
-  const int total = n_own + (br.w - br.z);
-  // EIF visits in flight per thread: all connectivity rows, then all
-  // gathers, then the arithmetic (a slot past the end repeats slot 0's
-  // loads and is skipped)
-  for (int t0 = threadIdx.x; t0 < total; t0 += EIF * NT) {
-    int e[EIF], nd[EIF][D + 1];
-    bool on[EIF];
-#pragma unroll
-    for (int q = 0; q < EIF; ++q) {
-      const int t = t0 + q * NT;
-      on[q] = t < total;
-      const int tt = on[q] ? t : t0;
-      e[q] = tt < n_own ? br.x + tt : ldg(m.halo + br.z + (tt - n_own));
-    }
-#pragma unroll
-    for (int q = 0; q < EIF; ++q) load_conn<D, T>(m, e[q], nd[q]);
-    ElemIn<D, T, OP, NL, FUSED> in[EIF];
-#pragma unroll
-    for (int q = 0; q < EIF; ++q) load_elem<D, T, OP, NL, FUSED>(m, U, V, mask, e[q], nd[q], in[q]);
-    T y[D + 1][D];
-#pragma unroll
-    for (int q = 0; q < EIF; ++q) {
-      if (q > 0 && !on[q]) continue;
-      if constexpr (FUSED) fcg_direction<D, T, OP, NL>(in[q], alpha, beta);
-      element_compute<D, T, OP, NL, FUSED>(m, in[q], y);
-      lds_accumulate<D, T, A>(acc, nd[q], n0, nloc, y);
-    }
-  }
-  __syncthreads();
+  owner_rounds<D, T, OP, NL, A, FUSED, NT, EIF>(m, U, V, mask, br, threadIdx.x, n0, nloc, acc,
+                                                alpha, beta);
 }
 
 template <int D, typename T, int OP, bool NL>
@@ -368,7 +413,7 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work, const Bas
 // alternate between two slot sets by parity of j.  Unlike the pipelined
 // (Ghysels-Vanroose) form, no recurrence replaces the matvec, which keeps
 // the float32 iteration as stable as the textbook loop.
-template <int D, typename T, bool NL, int NT>
+template <int D, typename T, bool NL, int NT, int PK>
 __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int blk, int it) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // The latency of this launch is a chain of dependent memory round trips,
@@ -395,13 +440,17 @@ __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int b
   const double pa_prev = ldg(&sc->pa[(j + 1) & 1]);   // alpha_{j-1}
   const int active = tp->active;
   const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
-  // branch-free: out-of-range threads load a valid neighbour and discard it
+  // branch-free for up to 2 NT blocks: out-of-range threads load a valid
+  // neighbour and discard it
   const int pb = min((int)threadIdx.x, nb - 1);
-  double pv_in[3];
+  const int pb2 = min((int)threadIdx.x + NT, nb - 1);
+  double pv_in[3], pv2[3];
   pv_in[0] = ldg(part_in + pb);
   pv_in[1] = ldg(part_in + (size_t)nb + pb);
   pv_in[2] = ldg(part_in + (size_t)2 * nb + pb);
-  if ((int)threadIdx.x >= nb) pv_in[0] = pv_in[1] = pv_in[2] = 0.0;
+  pv2[0] = ldg(part_in + pb2);
+  pv2[1] = ldg(part_in + (size_t)nb + pb2);
+  pv2[2] = ldg(part_in + (size_t)2 * nb + pb2);
   const int ln0 = threadIdx.x;
   const int lnc = min(ln0, nloc - 1);
   T rc0[4 * D], pv0[D], dv0[D];
@@ -409,12 +458,31 @@ __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int b
   load_nodal<D, T>(P, n0 + lnc, pv0);
   load_nodal<D, T>(Dd, n0 + lnc, dv0);
   const int bits0 = ldg(m.dmask + n0 + lnc);
-  for (int b = (int)threadIdx.x + NT; b < nb; b += NT) {   // more blocks than threads
+  // 2D: the first round of element visits needs no scalar, so its
+  // connectivity, coordinates and records are in flight while the partials
+  // are summed (in 3D the registers held across the sum cost more
+  // occupancy than the overlap gains: measured 10-20% slower)
+  constexpr int EIF = (D == 2 && !NL) ? PFEM_FCG_EIF : 2;
+  constexpr bool HOIST = D == 2;
+  using A = AccT<T>;
+  A* acc = reinterpret_cast<A*>(smem_raw);
+  const T* U = static_cast<const T*>(tp->u);
+  for (int i = threadIdx.x; i < nloc * D; i += NT) acc[i] = A(0);
+  VisitRound<D, T, OP_APPLY, NL, true, EIF> rd0;
+  if constexpr (HOIST)
+    load_round<D, T, OP_APPLY, NL, true, NT, EIF, PK>(m, U, Rin, 0, br, threadIdx.x, rd0);
+  if ((int)threadIdx.x >= nb) pv_in[0] = pv_in[1] = pv_in[2] = 0.0;
+  if ((int)threadIdx.x + NT < nb) {
+    pv_in[0] += pv2[0];
+    pv_in[1] += pv2[1];
+    pv_in[2] += pv2[2];
+  }
+  for (int b = (int)threadIdx.x + 2 * NT; b < nb; b += NT) {   // more than 2 NT blocks
     pv_in[0] += ldg(part_in + b);
     pv_in[1] += ldg(part_in + (size_t)nb + b);
     pv_in[2] += ldg(part_in + (size_t)2 * nb + b);
   }
-  block_sum_all<3, NT>(pv_in);
+  block_sum_all<3, NT>(pv_in);   // its barriers also publish the zeroed acc[]
   const double delta = pv_in[0], gamma = pv_in[1], rr = pv_in[2];
   if (state_in != 0 || !active) return;
   int state = 0;
@@ -460,12 +528,11 @@ __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int b
     }
   }
   if (state != 0) return;
-  using A = AccT<T>;
-  A* acc = reinterpret_cast<A*>(smem_raw);
   const T alpha = (T)alpha64, beta = (T)beta64;
-  const T* U = static_cast<const T*>(tp->u);
-  owner_accumulate<D, T, OP_APPLY, NL, A, true, NT, (D == 2 && !NL) ? PFEM_FCG_EIF : 2>(
-      m, U, Rin, 0, br, n0, nloc, acc, alpha, beta);
+  if constexpr (HOIST)
+    compute_round<D, T, OP_APPLY, NL, A, true, EIF>(m, rd0, n0, nloc, acc, alpha, beta);
+  owner_rounds<D, T, OP_APPLY, NL, A, true, NT, EIF, PK>(
+      m, U, Rin, 0, br, threadIdx.x + (HOIST ? EIF * NT : 0), n0, nloc, acc, alpha, beta);
   T* Rout = static_cast<T*>(tp->rec[(j + 1) & 1]);
   const bool first = j == 0;
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
@@ -519,11 +586,11 @@ __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int b
 }
 
 // Batched form: workgroup -> (task, node block) through the work table.
-template <int D, typename T, bool NL, int NT>
+template <int D, typename T, bool NL, int NT, int PK>
 __global__ void __launch_bounds__(NT)
 k_fcg(const Task* __restrict__ tasks, const int2* __restrict__ work, int it) {
   const int2 wk = work[blockIdx.x];
-  fcg_iteration<D, T, NL, NT>(tasks + wk.x, wk.y, it);
+  fcg_iteration<D, T, NL, NT, PK>(tasks + wk.x, wk.y, it);
 }
 
 // -------------------------------------------------- alternative scatters
@@ -829,14 +896,19 @@ void launch_energy(Ctx* ctx, int dim, int prec, bool diff, const Task* tasks_dev
 #endif
 
 void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nl, const Task* tasks,
-                     const int2* work, int n_work, int bn_max, int it) {
+                     const int2* work, int n_work, int bn_max, int it, bool packed) {
   if (n_work <= 0) return;
   hipStream_t s = ctx->stream;
   const size_t s32 = (size_t)bn_max * dim * sizeof(AccT<float>);
   const size_t s64 = (size_t)bn_max * dim * sizeof(AccT<double>);
   dim3 grid(n_work);
-#define PFEM_FCG(DD, TT, NLV, SM, NTV) \
-  hipLaunchKernelGGL((k_fcg<DD, TT, NLV, NTV>), grid, dim3(NTV), SM, s, tasks, work, it)
+#define PFEM_FCG(DD, TT, NLV, SM, NTV)                                                     \
+  do {                                                                                      \
+    if (packed)                                                                             \
+      hipLaunchKernelGGL((k_fcg<DD, TT, NLV, NTV, 1>), grid, dim3(NTV), SM, s, tasks, work, it); \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_fcg<DD, TT, NLV, NTV, 0>), grid, dim3(NTV), SM, s, tasks, work, it); \
+  } while (0)
   if (!nl) {
     if (dim == 2 && prec == PFEM_FP32) PFEM_FCG(2, float, false, s32, PFEM_FCG_NT2);
     else if (dim == 2) PFEM_FCG(2, double, false, s64, 256);

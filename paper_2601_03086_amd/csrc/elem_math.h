@@ -206,39 +206,36 @@ __device__ __forceinline__ void linear_stress_tilde(const T (&M)[D][D], T mu, T 
 }
 
 // ------------------------------------------------------------ Neo-Hookean
-// Kinematic state of one element: H = grad u, F^{-T}, ln J (float64).
+// Kinematic state of one element: H = grad u, F^{-T}, J - 1 and ln J in the
+// kernel precision (float32 kernels feed an inexact Krylov solve whose
+// residual is evaluated by the float64 kernels; J - 1 from the invariants
+// keeps its relative accuracy at small strain in either precision).
 template <int D, typename T>
 struct NHState {
   T H[D][D];
   T FinvT[D][D];
-  double j;      // J - 1
-  double lnJ;
-  bool ok;       // J > 0
+  T j;      // J - 1
+  T lnJ;
+  bool ok;  // J > 0
 };
 
 // J - 1 from the invariants of H (exact identities):
 //   2D: tr H + det H;  3D: tr H + ((tr H)^2 - tr H^2)/2 + det H.
 template <int D, typename T>
-__device__ __forceinline__ double jm1(const T (&H)[D][D]) {
+__device__ __forceinline__ T jm1(const T (&h)[D][D]) {
   if constexpr (D == 2) {
-    const double h00 = H[0][0], h01 = H[0][1], h10 = H[1][0], h11 = H[1][1];
-    return (h00 + h11) + (h00 * h11 - h01 * h10);
+    return (h[0][0] + h[1][1]) + (h[0][0] * h[1][1] - h[0][1] * h[1][0]);
   } else {
-    double h[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) h[i][k] = H[i][k];
-    const double tr = h[0][0] + h[1][1] + h[2][2];
-    double trH2 = 0.0;
+    const T tr = h[0][0] + h[1][1] + h[2][2];
+    T trH2 = T(0);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int k = 0; k < 3; ++k) trH2 += h[i][k] * h[k][i];
-    const double det = h[0][0] * (h[1][1] * h[2][2] - h[1][2] * h[2][1]) -
-                       h[0][1] * (h[1][0] * h[2][2] - h[1][2] * h[2][0]) +
-                       h[0][2] * (h[1][0] * h[2][1] - h[1][1] * h[2][0]);
-    return tr + 0.5 * (tr * tr - trH2) + det;
+    const T det = h[0][0] * (h[1][1] * h[2][2] - h[1][2] * h[2][1]) -
+                  h[0][1] * (h[1][0] * h[2][2] - h[1][2] * h[2][0]) +
+                  h[0][2] * (h[1][0] * h[2][1] - h[1][1] * h[2][0]);
+    return tr + T(0.5) * (tr * tr - trH2) + det;
   }
 }
 
@@ -250,10 +247,9 @@ __device__ __forceinline__ void nh_state(const T (&Ht)[D][D], T inv_det,
 #pragma unroll
     for (int k = 0; k < D; ++k) st.H[i][k] = Ht[i][k] * inv_det;
   st.j = jm1<D, T>(st.H);
-  st.ok = st.j > -1.0;
-  const double J = 1.0 + st.j;
-  st.lnJ = st.ok ? log1p(st.j) : 0.0;
-  const T invJ = (T)(st.ok ? 1.0 / J : 0.0);
+  st.ok = st.j > T(-1);
+  st.lnJ = st.ok ? log1p(st.j) : T(0);
+  const T invJ = st.ok ? T(1) / (T(1) + st.j) : T(0);
   T F[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)
@@ -282,7 +278,7 @@ __device__ __forceinline__ void nh_state(const T (&Ht)[D][D], T inv_det,
 template <int D, typename T>
 __device__ __forceinline__ void nh_piola(const NHState<D, T>& st, T mu, T lam,
                                          T (&P)[D][D]) {
-  const T ll = (T)((double)lam * st.lnJ);
+  const T ll = lam * st.lnJ;
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -304,7 +300,7 @@ __device__ __forceinline__ void nh_dpiola(const NHState<D, T>& st, T mu, T lam,
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int k = 0; k < D; ++k) tr += st.FinvT[i][k] * dF[i][k];
-  const T c2 = (T)((double)mu - (double)lam * st.lnJ);
+  const T c2 = mu - lam * st.lnJ;
   T A[D][D];  // A = dF^T F^{-T}
 #pragma unroll
   for (int i = 0; i < D; ++i)

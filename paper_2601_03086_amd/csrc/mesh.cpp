@@ -8,9 +8,11 @@
 //    unvisited neighbours ordered by (degree, caller id); the visiting order
 //    is reversed at the end;
 //  * node blocks (default numbering): the RCM order is cut into bands of
-//    k * bn consecutive positions, k = max(1, round(w N / (L bn))) with L the
-//    number of breadth-first levels of the search (summed over components)
-//    and w the largest integer with w^d <= bn, halves rounded up; each band
+//    k * bn consecutive positions, k = max(1, min(round(w N / (L bn)),
+//    floor(32768 / bn))) with L the number of breadth-first levels of the
+//    search (summed over components) and w the largest integer with
+//    w^d <= bn, halves rounded up (a band stays within 32768 positions, so
+//    element node offsets fit 16 bits on ordinary meshes); each band
 //    is cut into blocks of bn nodes by recursive coordinate bisection: a set
 //    of more than bn nodes is ordered along its axis of largest extent
 //    (smallest axis on ties) by (coordinate, RCM position) and split after
@@ -221,7 +223,8 @@ static void number_nodes(const pfem_mesh* m, int bn, bool blocks,
     int64_t w = 1;
     auto ipow = [&](int64_t x) { int64_t r = 1; for (int i = 0; i < m->dim; ++i) r *= x; return r; };
     while (ipow(w + 1) <= bn) ++w;
-    const int64_t k = std::max<int64_t>(1, (2 * w * N + n_levels * bn) / (2 * n_levels * bn));
+    const int64_t k = std::max<int64_t>(
+        1, std::min<int64_t>((2 * w * N + n_levels * bn) / (2 * n_levels * bn), 32768 / bn));
     const int64_t band = k * bn;
     for (int64_t b0 = 0; b0 < N; b0 += band)
       bisect_blocks(q.data() + b0, q.data() + std::min(N, b0 + band), m->coords.data(),
@@ -254,11 +257,13 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
   // 0. nodes per owner block
   int bn = block_nodes;
   if (bn <= 0) {
-    // about 1200 blocks on large meshes (fills the chip), at least 256 nodes
-    // per block on small ones: the fused PCG launch sums every block's
-    // partials in every block, which grows with the square of the block count
-    const int64_t target = 1200;
-    bn = (int)std::min<int64_t>(2048, std::max<int64_t>(256, ((N / target) + 31) / 32 * 32));
+    // N/2000 (2D) or N/750 (3D) nodes, a multiple of 32, at least 224 (2D) or
+    // 64 (3D), at most 2048: measured optimum of the owner kernels on compact
+    // blocks (enough workgroups to fill the chip, few halo revisits; the
+    // fused PCG launch sums every block's partials in every block, so it
+    // also wants few blocks)
+    const int64_t per = D == 2 ? 2000 : 750, lo = D == 2 ? 224 : 64;
+    bn = (int)std::min<int64_t>(2048, std::max<int64_t>(lo, ((N / per) + 31) / 32 * 32));
   }
   require(bn <= block_nodes_max(), PFEM_E_INVALID_ARG, "block_nodes too large");
   // 1. node numbering
@@ -521,7 +526,9 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
     d.lam64 = upload(m->lam_int, d.bytes);
     d.dmask = upload(m->dmask, d.bytes);
     d.blocks = upload(m->blocks, d.bytes);
-    d.halo = upload(m->halo, d.bytes);
+    std::vector<int32_t> halo_pad(m->halo);   // one padding entry: clamped reads
+    halo_pad.push_back(0);
+    d.halo = upload(halo_pad, d.bytes);
     d.fext = upload(m->fext_int, d.bytes);
     d.ubar = upload(m->ubar_int, d.bytes);
     d.colored = upload(m->colored, d.bytes);
@@ -625,7 +632,7 @@ int64_t mesh_device_bytes(const pfem_mesh* m) {
   const int64_t N = m->n_nodes, NE = m->n_elems, D = m->dim;
   auto r = [](int64_t b) { return std::max<int64_t>(b, 1); };
   return r(N * D * 8) + r(N * D * 4) + r(NE * (D + 1) * 4) + r(NE * (D == 2 ? 8 : 12)) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
-         r((int64_t)m->n_blocks * 16) + r((int64_t)m->halo.size() * 4) + 2 * r(N * D * 8) +
+         r((int64_t)m->n_blocks * 16) + r(((int64_t)m->halo.size() + 1) * 4) + 2 * r(N * D * 8) +
          r(NE * 4) + r(N * 4) + r((int64_t)m->n_blocks * 8);
 }
 

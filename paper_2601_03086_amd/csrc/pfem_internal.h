@@ -240,8 +240,9 @@ void launch_fcg_init(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
 void launch_fcg_init_w(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
                        const int2* work_dev, int n_work);
 void launch_pcg_init_finish(Ctx* ctx, const Task* tasks_dev, int n_tasks);
+// packed: every task of the launch has packed connectivity (see MeshDev).
 void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nonlinear, const Task* tasks_dev,
-                     const int2* work_dev, int n_work, int bn_max, int it);
+                     const int2* work_dev, int n_work, int bn_max, int it, bool packed);
 // One workgroup per task: red.out[0..n_slots-1] = sums of partial slots
 // 0..n_slots-1 (n_slots 2 or 3).
 void launch_reduce_store(Ctx* ctx, const Task* tasks_dev, int n_tasks, int n_slots = 2);

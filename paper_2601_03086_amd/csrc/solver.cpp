@@ -328,8 +328,11 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
       // the chunk is timed as one run of k launches
       hipEvent_t ev = nullptr;
       ctx->timing_begin_run(FAM_FUSED, &ev);
+      bool packed = true;
+      for (SlotRun* sr : g.slots) packed = packed && sr->m->md.conn_packed != 0;
       for (int it = 0; it < k; ++it) {
-        launch_fcg_iter(ctx, g.dim, g.prec, g.nl, ua.tasks, ua.work, ua.n_work, ua.bn_max, it);
+        launch_fcg_iter(ctx, g.dim, g.prec, g.nl, ua.tasks, ua.work, ua.n_work, ua.bn_max, it,
+                        packed);
         *nl += 1;
       }
       ctx->timing_end_run(FAM_FUSED, ev, k);

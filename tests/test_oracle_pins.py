@@ -414,13 +414,17 @@ def test_band_size_hand_values():
     assert [prep.int_root(b, d) for b, d in [(255, 2), (256, 2), (26, 3), (27, 3), (1, 3)]] == \
         [15, 16, 2, 3, 1]
     # k = round(w N / (L bn)): 4*1000/(10*16) = 25; 4*80/(8*16) = 2.5 -> 3 (halves up);
-    # 4*100/(8*16) = 3.125 -> 3; tiny ratios clamp to one block per band
+    # 4*100/(8*16) = 3.125 -> 3; tiny ratios clamp to one block per band,
+    # long bands to 32768 positions: 45*2e7/(9000*2048) = 48.8 -> 32768/2048 = 16
     assert prep.band_blocks(1000, 10, 16, 2) == 25
     assert prep.band_blocks(80, 8, 16, 2) == 3
     assert prep.band_blocks(100, 8, 16, 2) == 3
     assert prep.band_blocks(10, 100, 256, 2) == 1
-    assert prep.auto_block_nodes(1000) == 256 and prep.auto_block_nodes(10 ** 6) == 864
-    assert prep.auto_block_nodes(10 ** 8) == 2048
+    assert prep.band_blocks(2 * 10 ** 7, 9000, 2048, 2) == 16
+    # N/2000 (2D) or N/750 (3D) up to a multiple of 32, clamped to [224|64, 2048]
+    assert prep.auto_block_nodes(1000, 2) == 224 and prep.auto_block_nodes(1000, 3) == 64
+    assert prep.auto_block_nodes(500000, 2) == 256 and prep.auto_block_nodes(183000, 3) == 256
+    assert prep.auto_block_nodes(10 ** 8, 2) == 2048 and prep.auto_block_nodes(10 ** 8, 3) == 2048
 
 
 def test_bisect_blocks_hand_example():
