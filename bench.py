@@ -62,7 +62,8 @@ def new_mesh(ctx, prob, bn=0):
 
 def kernel_hash():
     h = hashlib.sha256()
-    for f in ("elem_kernels.hip", "elem_math.h", "reduce.h", "pfem_internal.h"):
+    # the kernels and the mesh layout they read (numbering, blocks, packing)
+    for f in ("elem_kernels.hip", "elem_math.h", "reduce.h", "pfem_internal.h", "mesh.cpp"):
         h.update(open(os.path.join(ROOT, "paper_2601_03086_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
