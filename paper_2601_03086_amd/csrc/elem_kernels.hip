@@ -26,16 +26,18 @@ namespace pfem {
 template <int D, typename T>
 __device__ __forceinline__ void load_nodal(const T* __restrict__ p, int n, T (&o)[D]) {
   if constexpr (D == 2 && sizeof(T) == 4) {
-    const pf2 q = ldg(reinterpret_cast<const pf2*>(p + (size_t)n * 2));
+    const pf2 q = ldx(reinterpret_cast<const pf2*>(p), (uint32_t)n);
     o[0] = q.x;
     o[1] = q.y;
   } else if constexpr (D == 2 && sizeof(T) == 8) {
-    const pd2 q = ldg(reinterpret_cast<const pd2*>(p + (size_t)n * 2));
+    const pd2 q = ldx(reinterpret_cast<const pd2*>(p), (uint32_t)n);
     o[0] = q.x;
     o[1] = q.y;
   } else {
-#pragma unroll
-    for (int i = 0; i < D; ++i) o[i] = ldg(p + (size_t)n * D + i);
+    const Trip<T> q = ldx(reinterpret_cast<const Trip<T>*>(p), (uint32_t)n);
+    o[0] = q.x;
+    o[1] = q.y;
+    o[2] = q.z;
   }
 }
 
@@ -54,13 +56,13 @@ __device__ __forceinline__ void load_conn(const MeshDev& m, int e, int (&nd)[D +
   if ((D == 2 || sizeof(T) == 8) && (PK == 1 || m.conn_packed)) {
     if constexpr (D == 2) {
       typedef unsigned int pu2 __attribute__((ext_vector_type(2)));
-      const pu2 q = ldg(reinterpret_cast<const pu2*>(m.connp + (size_t)e * 2));
+      const pu2 q = ldx(reinterpret_cast<const pu2*>(m.connp), (uint32_t)e);
       nd[0] = (int)q.x;
       nd[1] = (int)(q.x + (q.y & 0xffffu));
       nd[2] = (int)(q.x + (q.y >> 16));
     } else {
-      const uint32_t* p = m.connp + (size_t)e * 3;
-      const uint32_t a = ldg(p), b = ldg(p + 1), c = ldg(p + 2);
+      const Trip<uint32_t> q = ldx(reinterpret_cast<const Trip<uint32_t>*>(m.connp), (uint32_t)e);
+      const uint32_t a = q.x, b = q.y, c = q.z;
       nd[0] = (int)a;
       nd[1] = (int)(a + (b & 0xffffu));
       nd[2] = (int)(a + (b >> 16));
@@ -75,20 +77,20 @@ template <int D>
 __device__ __forceinline__ void load_conn(const int32_t* __restrict__ conn, int e,
                                           int (&nd)[D + 1]) {
   if constexpr (D == 3) {
-    const pi4 q = ldg(reinterpret_cast<const pi4*>(conn + (size_t)e * 4));
+    const pi4 q = ldx(reinterpret_cast<const pi4*>(conn), (uint32_t)e);
     nd[0] = q.x;
     nd[1] = q.y;
     nd[2] = q.z;
     nd[3] = q.w;
   } else {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) nd[a] = ldg(conn + (size_t)e * 3 + a);
+    for (int a = 0; a < 3; ++a) nd[a] = ldx(conn, (uint32_t)(e * 3 + a));
   }
 }
 
 template <typename T>
 __device__ __forceinline__ T mat_mu(const MeshDev& m, int e) {
-  if constexpr (sizeof(T) == 4) return ldg(m.mu32 + e); else return ldg(m.mu64 + e);
+  if constexpr (sizeof(T) == 4) return ldx(m.mu32, (uint32_t)e); else return ldx(m.mu64, (uint32_t)e);
 }
 // lambda of element e given its mu: one multiply when the mesh has a
 // uniform lambda / mu ratio (one material value per element to stream)
@@ -98,7 +100,7 @@ __device__ __forceinline__ T mat_lam(const MeshDev& m, int e, T mu) {
   const T* lam;
   if constexpr (sizeof(T) == 4) lam = m.lam_uniform ? m.mu32 : m.lam32;
   else lam = m.lam_uniform ? m.mu64 : m.lam64;
-  return ldg(lam + e) * (m.lam_uniform ? (T)m.lam_ratio : T(1));
+  return ldx(lam, (uint32_t)e) * (m.lam_uniform ? (T)m.lam_ratio : T(1));
 }
 
 // Everything one element needs, gathered before any arithmetic so that all
@@ -133,7 +135,7 @@ __device__ __forceinline__ void load_elem(const MeshDev& m, const T* __restrict_
     if (mask & PFEM_MASK_IN) {
 #pragma unroll
       for (int a = 0; a <= D; ++a) {
-        const int bits = ldg(m.dmask + nd[a]);
+        const int bits = ldx(m.dmask, (uint32_t)nd[a]);
 #pragma unroll
         for (int i = 0; i < D; ++i)
           if (bits & (1 << i)) in.v[a][i] = T(0);
@@ -299,7 +301,7 @@ __device__ __forceinline__ void load_round(const MeshDev& m, const T* __restrict
     const int tt = rd.on[q] ? t : min(t0, total - 1);
     // the halo entry is read unconditionally (clamped; the device list has
     // one padding entry) so that no load waits at a branch join
-    const int h = ldg(m.halo + br.z + min(max(tt - n_own, 0), max(n_halo - 1, 0)));
+    const int h = ldx(m.halo, (uint32_t)(br.z + min(max(tt - n_own, 0), max(n_halo - 1, 0))));
     e[q] = tt < n_own ? br.x + tt : h;
   }
 #pragma unroll

@@ -42,15 +42,18 @@ __device__ __forceinline__ void load_coords(const double* __restrict__ X,
   if constexpr (D == 2) {
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
-      const pd2 q = ldg(reinterpret_cast<const pd2*>(X + (size_t)nd[a] * 2));
+      const pd2 q = ldx(reinterpret_cast<const pd2*>(X), (uint32_t)nd[a]);
       x[a][0] = q.x;
       x[a][1] = q.y;
     }
   } else {
 #pragma unroll
-    for (int a = 0; a <= D; ++a)
-#pragma unroll
-      for (int i = 0; i < D; ++i) x[a][i] = ldg(X + (size_t)nd[a] * D + i);
+    for (int a = 0; a <= D; ++a) {
+      const Trip<double> q = ldx(reinterpret_cast<const Trip<double>*>(X), (uint32_t)nd[a]);
+      x[a][0] = q.x;
+      x[a][1] = q.y;
+      x[a][2] = q.z;
+    }
   }
 }
 
@@ -61,12 +64,14 @@ __device__ __forceinline__ void load_coords_q(const uint32_t* __restrict__ Xq,
   for (int a = 0; a <= D; ++a) {
     if constexpr (D == 2) {
       typedef unsigned int pu2 __attribute__((ext_vector_type(2)));
-      const pu2 q = ldg(reinterpret_cast<const pu2*>(Xq + (size_t)nd[a] * 2));
+      const pu2 q = ldx(reinterpret_cast<const pu2*>(Xq), (uint32_t)nd[a]);
       x[a][0] = q.x;
       x[a][1] = q.y;
     } else {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) x[a][i] = ldg(Xq + (size_t)nd[a] * 3 + i);
+      const Trip<uint32_t> q = ldx(reinterpret_cast<const Trip<uint32_t>*>(Xq), (uint32_t)nd[a]);
+      x[a][0] = q.x;
+      x[a][1] = q.y;
+      x[a][2] = q.z;
     }
   }
 }

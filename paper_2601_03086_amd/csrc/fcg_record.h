@@ -10,20 +10,20 @@ namespace pfem {
 template <int D, typename T>
 __device__ __forceinline__ void load_record(const T* __restrict__ rec, int n, T (&o)[4 * D]) {
   if constexpr (sizeof(T) == 4) {
-    const pf4* q = reinterpret_cast<const pf4*>(rec + (size_t)n * 4 * D);
+    const pf4* q = reinterpret_cast<const pf4*>(rec);
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const pf4 t = ldg(q + k);
+      const pf4 t = ldx(q, (uint32_t)(n * D + k));
       o[4 * k] = t.x;
       o[4 * k + 1] = t.y;
       o[4 * k + 2] = t.z;
       o[4 * k + 3] = t.w;
     }
   } else {
-    const pd2* q = reinterpret_cast<const pd2*>(rec + (size_t)n * 4 * D);
+    const pd2* q = reinterpret_cast<const pd2*>(rec);
 #pragma unroll
     for (int k = 0; k < 2 * D; ++k) {
-      const pd2 t = ldg(q + k);
+      const pd2 t = ldx(q, (uint32_t)(n * 2 * D + k));
       o[2 * k] = t.x;
       o[2 * k + 1] = t.y;
     }

@@ -266,6 +266,12 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
     bn = (int)std::min<int64_t>(2048, std::max<int64_t>(lo, ((N / per) + 31) / 32 * 32));
   }
   require(bn <= block_nodes_max(), PFEM_E_INVALID_ARG, "block_nodes too large");
+  // the element kernels address mesh and solver arrays with 32-bit byte
+  // offsets; the largest per-node array is the FP64 fused-PCG record (4 d
+  // doubles), the largest per-element one the 16-byte 3D connectivity row
+  require(N * 32 * D < (int64_t(1) << 32) && NE * 16 < (int64_t(1) << 32), PFEM_E_INVALID_MESH,
+          "mesh too large: at most " + std::to_string((int64_t(1) << 32) / (32 * D) - 1) +
+              " nodes and 268435455 elements per mesh");
   // 1. node numbering
   number_nodes(m, bn, m->node_order == PFEM_ORDER_BLOCKS, m->perm);
   m->bw_in = bandwidth(m, nullptr);

@@ -42,6 +42,12 @@ typedef float pf2 __attribute__((ext_vector_type(2)));
 typedef float pf4 __attribute__((ext_vector_type(4)));
 typedef double pd2 __attribute__((ext_vector_type(2)));
 typedef int pi4 __attribute__((ext_vector_type(4)));
+// three consecutive 4-byte values (a 3D node's coordinates or DOFs), loaded
+// as one 12-byte access
+template <typename T>
+struct Trip {
+  T x, y, z;
+};
 
 // ------------------------------------------------------- device descriptors
 // Everything a kernel needs to know about one finalized mesh (POD).
@@ -279,6 +285,14 @@ __device__ __forceinline__ T ldg(const T* p) {
 template <typename T>
 __device__ __forceinline__ void stg(T* p, T v) {
   *(PFEM_GLOBAL T*)p = v;
+}
+// Element i of a device array through a 32-bit byte offset (mesh arrays
+// stay below 4 GiB, checked at upload): with a uniform base pointer the
+// load takes the scalar-base + 32-bit-offset form and needs no 64-bit
+// address arithmetic per lane.
+template <typename T>
+__device__ __forceinline__ T ldx(const T* base, uint32_t i) {
+  return *(const PFEM_GLOBAL T*)((const PFEM_GLOBAL char*)base + i * (uint32_t)sizeof(T));
 }
 
 // Host-side helpers.
