@@ -684,7 +684,7 @@ def run_kv_large(spec, reps=50):
             print(json.dumps({
                 "mesh": f"{kind} {prob.n_elems} elems {prob.n_nodes} nodes",
                 "prec": prec, "block_nodes": mesh.info["block_nodes"], "order": ORDER,
-                "bandwidth": mesh.info["bandwidth_rcm"],
+                "bandwidth": mesh.info["bandwidth_internal"],
                 "visits_per_elem": round(mesh.info["owner_elem_visits"] / prob.n_elems, 3),
                 "alg_bytes": b_alg, "avg_us": round(us, 2),
                 "alg_GBps": round(b_alg / (us * 1e-6) / 1e9, 1),

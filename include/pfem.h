@@ -190,8 +190,8 @@ typedef struct {
   int32_t dim, model;
   int64_t n_nodes, n_elems, n_dof, n_free;
   int32_t n_colors, n_blocks, block_nodes;
-  int64_t bandwidth_in, bandwidth_rcm;     /* max |i-j| over element node pairs:
-                                              caller and internal numbering */
+  int64_t bandwidth_in, bandwidth_internal;   /* max |i-j| over element node pairs:
+                                                caller and internal numbering */
   int64_t owner_elem_visits;                /* sum over blocks of touched range lengths */
   int64_t device_bytes;                     /* mesh arrays resident on the device */
   int64_t solve_bytes_fp32, solve_bytes_fp64;   /* extra device bytes of one solve */

@@ -45,7 +45,7 @@ class pfem_mesh_info(C.Structure):
                 ("n_nodes", C.c_int64), ("n_elems", C.c_int64), ("n_dof", C.c_int64),
                 ("n_free", C.c_int64), ("n_colors", C.c_int32), ("n_blocks", C.c_int32),
                 ("block_nodes", C.c_int32), ("bandwidth_in", C.c_int64),
-                ("bandwidth_rcm", C.c_int64), ("owner_elem_visits", C.c_int64),
+                ("bandwidth_internal", C.c_int64), ("owner_elem_visits", C.c_int64),
                 ("device_bytes", C.c_int64), ("solve_bytes_fp32", C.c_int64),
                 ("solve_bytes_fp64", C.c_int64), ("f_ext_norm", C.c_double)]
 

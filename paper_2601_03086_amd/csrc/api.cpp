@@ -259,7 +259,7 @@ pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* o) {
   o->n_blocks = m->n_blocks;
   o->block_nodes = m->bn;
   o->bandwidth_in = m->bw_in;
-  o->bandwidth_rcm = m->bw_rcm;
+  o->bandwidth_internal = m->bw_int;
   o->owner_elem_visits = m->owner_visits;
   o->device_bytes = m->finalized ? mesh_device_bytes(m) : 0;
   pfem_solve_opts d32;

@@ -275,7 +275,7 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
   // 1. node numbering
   number_nodes(m, bn, m->node_order == PFEM_ORDER_BLOCKS, m->perm);
   m->bw_in = bandwidth(m, nullptr);
-  m->bw_rcm = bandwidth(m, m->perm.data());
+  m->bw_int = bandwidth(m, m->perm.data());
   // 2. element order
   std::vector<int32_t> keys((size_t)NE * nv);
   for (int64_t e = 0; e < NE; ++e) {

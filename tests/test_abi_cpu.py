@@ -78,7 +78,7 @@ def test_preprocessing_bit_exact(name, order, bn):
     assert np.array_equal(m.query(L.PFEM_Q_FREE_INDEX), ref["free_index"])
     info = m.info
     assert info["n_colors"] == int(ref["color"].max()) + 1
-    assert info["bandwidth_rcm"] == prep.bandwidth(p.conn, ref["perm"])
+    assert info["bandwidth_internal"] == prep.bandwidth(p.conn, ref["perm"])
     assert info["n_free"] == int((ref["free_index"] >= 0).sum())
 
 
