@@ -217,6 +217,33 @@ def test_fused_pcg_fp32_plate(ctx, model):
     assert out["fused"]["kv_count"] <= 1.25 * out["classic"]["kv_count"] + 10
 
 
+@pytest.mark.parametrize("dim,bn", [(2, 16), (2, 48), (3, 16)])
+def test_fused_pcg_small_and_many_blocks(ctx, dim, bn):
+    """Block sizes far from the default: with 16-node blocks a block has
+    fewer element visits than the workgroup has threads (idle slots in the
+    first round, issued before the partial sums are reduced in 2D), and a
+    20k-triangle plate has more than 512 blocks (the prologue sums partials
+    beyond the two branch-free chunks).  FP64 fused against the classic loop,
+    and FP32 mode against the oracle's direct solve."""
+    if dim == 2:
+        p = synth.plate_problem(77, 78, 79, n_holes=6, target_tris=20000)
+    else:
+        p = synth.box_problem(41, 42, n_per_unit=6, n_voids=3, n_load_steps=1,
+                              model="lin_3d")
+    m = _mesh(ctx, p, bn)
+    print(f"[fused blocks] dim={dim} bn={bn} blocks={m.info['n_blocks']}", flush=True)
+    if dim == 2 and bn == 16:
+        assert m.info["n_blocks"] > 512
+    uc, rc, hc = m.solve(tol=1e-10, prec="fp64", krylov="classic")
+    uf, rf, hf = m.solve(tol=1e-10, prec="fp64", krylov="fused")
+    assert rc["status"] == 0 and rf["status"] == 0
+    assert abs(rf["pcg_iters"] - rc["pcg_iters"]) <= 3
+    assert rel(uf, uc) <= 1e-8
+    u32, r32, _ = m.solve(tol=1e-8, prec="fp32", krylov="fused")
+    assert r32["status"] == 0 and r32["rel_residual_final"] <= 1e-8
+    assert rel(u32, uc) <= 1e-5
+
+
 def test_fused_failures_reported(ctx):
     from paper_2601_03086_amd import _lib as L
     p = synth.unit_square_c1(n=9)
