@@ -58,3 +58,21 @@ def dirichlet_from_field(nodes, field_fn, coords, d):
     dn = np.repeat(nodes, d)
     dc = np.tile(np.arange(d), nodes.size)
     return dn, dc, vals.reshape(-1)
+
+
+def fan_problem(m=70000, model="lin_plane_strain"):
+    """m triangles around one centre node (node 0) with the rim on the unit
+    circle: under plain RCM the centre is numbered next to one end, so the
+    element node offsets exceed 16 bits (unpacked connectivity).  Rim nodes
+    1..200 clamped, u_x = 0.01 prescribed on rim nodes m/2 .. m/2 + 200."""
+    th = 2.0 * np.pi * np.arange(m) / m
+    coords = np.vstack([[0.0, 0.0], np.stack([np.cos(th), np.sin(th)], axis=1)])
+    i = np.arange(m)
+    conn = np.stack([np.zeros(m, np.int64), 1 + i, 1 + (i + 1) % m], axis=1)
+    clamp = np.arange(1, 201)
+    pull = np.arange(m // 2, m // 2 + 201)
+    dn = np.concatenate([np.repeat(clamp, 2), pull])
+    dc = np.concatenate([np.tile([0, 1], clamp.size), np.zeros(pull.size, np.int64)])
+    dv = np.concatenate([np.zeros(2 * clamp.size), np.full(pull.size, 0.01)])
+    return make_problem(model, coords, conn, dir_nodes=dn, dir_comps=dc, dir_values=dv,
+                        name="fan")

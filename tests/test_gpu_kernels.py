@@ -105,6 +105,28 @@ def test_rcm_numbering_parity(ctx, name, prec, bn):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_unpacked_connectivity_apply_K(ctx, prec):
+    """A 70k-triangle fan under plain RCM has element node offsets beyond
+    16 bits, so the kernels read plain int32 rows (the run-time format test)
+    instead of packed ones."""
+    from paper_2601_03086_amd import core
+    torch = torch_cuda()
+    p = mk.fan_problem()
+    m = core.Mesh.from_problem(ctx, p, 0, "rcm")
+    assert m.info["bandwidth_internal"] > 65535
+    K = fe.Model(p).assemble()
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    tv = torch.tensor(np.random.default_rng(5).normal(size=p.n_dof), dtype=dt)
+    vv = tv.double().numpy()
+    y = m.apply_K(tv, prec=prec).double().cpu().numpy()
+    # the fan's sliver elements (aspect ratio ~1e4) amplify FP32 geometry
+    # rounding about 10x beyond the usual bound (measured 8.5e-5); an indexing
+    # error in the unpacked path would show at O(1)
+    tol = TOL[prec] if prec == "fp64" else 5e-4
+    assert bound_rel(y, K @ vv, abs(K) @ abs(vv)) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_apply_K_masks_and_internal_layout(ctx, prec):
     torch = torch_cuda()
     from paper_2601_03086_amd import _lib as L

@@ -244,6 +244,27 @@ def test_fused_pcg_small_and_many_blocks(ctx, dim, bn):
     assert rel(u32, uc) <= 1e-5
 
 
+def test_fused_pcg_unpacked_connectivity(ctx):
+    """The fused iteration on a mesh whose connectivity cannot be packed
+    (70k-triangle fan under plain RCM): its FP64 residual history matches
+    the classic loop's (both stop at the iteration cap: the fan's sliver
+    elements make the system far too ill-conditioned to converge here, and
+    past ~25 iterations the two formulations' rounding, amplified by that
+    conditioning, separates the histories at the 1e-3 level; an indexing
+    error would show from the first iteration)."""
+    from paper_2601_03086_amd import core
+    p = mk.fan_problem()
+    m = core.Mesh.from_problem(ctx, p, 0, "rcm")
+    assert m.info["bandwidth_internal"] > 65535
+    _, rc, hc = m.solve(tol=1e-14, prec="fp64", krylov="classic", max_iter=40)
+    _, rf, hf = m.solve(tol=1e-14, prec="fp64", krylov="fused", max_iter=41)
+    print("fan classic", rc["pcg_iters"], "fused", rf["pcg_iters"], flush=True)
+    assert rc["status_name"] == "NOT_CONVERGED" and rf["status_name"] == "NOT_CONVERGED"
+    assert min(len(hc), len(hf)) >= 30
+    assert np.allclose(hf[:20], hc[:20], rtol=1e-5, atol=0)
+    assert np.allclose(hf[:30], hc[:30], rtol=1e-2, atol=0)
+
+
 def test_fused_failures_reported(ctx):
     from paper_2601_03086_amd import _lib as L
     p = synth.unit_square_c1(n=9)
