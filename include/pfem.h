@@ -261,7 +261,7 @@ pfem_status pfem_batch_hvp(pfem_batch* b, int prec, int mask, const void* u,
  *          update evaluated by every workgroup at the nodes it gathers, so
  *          the element pass and all vector updates share a kernel (one
  *          extra matvec per inner solve, w = A u at the start);
- * AUTO     FUSED in FP32 mode on meshes up to 600k triangles / 200k
+ * AUTO     FUSED in FP32 mode on meshes up to 600k triangles / 800k
  *          tetrahedra (latency-bound iterations), CLASSIC otherwise and in
  *          FP64 mode. */
 enum { PFEM_KRYLOV_AUTO = 0, PFEM_KRYLOV_CLASSIC = 1, PFEM_KRYLOV_FUSED = 2 };

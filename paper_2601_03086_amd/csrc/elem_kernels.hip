@@ -1,16 +1,20 @@
 // Element kernels: K.v / Hessian-vector product, internal force, Jacobi
 // diagonal and energy on P1 triangles (D = 2) and tetrahedra (D = 3).
 //
-// Owner-computes scatter (default).  Nodes are numbered by reverse
-// Cuthill-McKee and cut into contiguous blocks of `bn` nodes; elements are
-// sorted by their smallest node id.  One workgroup owns one node block: it
-// walks the (contiguous) range of sorted elements that touch the block,
-// evaluates each element once, accumulates the contributions that land on
-// its own nodes in LDS, and finally writes every owned DOF exactly once with
-// coalesced stores.  No device-wide atomics, no zero-fill of the output, and
-// dot products with the output are fused into the write loop.  Elements that
-// straddle two blocks are evaluated by both; their gathers hit L2 because
-// consecutive blocks are scheduled on the same XCD (work-table remap).
+// Owner-computes scatter (default).  The internal node numbering is cut
+// into contiguous blocks of `bn` nodes (compact patches cut from reverse
+// Cuthill-McKee bands, or plain RCM runs); elements are sorted by their
+// smallest node id.  One workgroup owns one node block: it walks the
+// (contiguous) range of sorted elements whose smallest node it owns plus the
+// list of earlier blocks' elements that reach into it, evaluates each,
+// accumulates the contributions that land on its own nodes in LDS, and
+// finally writes every owned DOF exactly once with coalesced stores.  No
+// device-wide atomics, no zero-fill of the output, and dot products with the
+// output are fused into the write loop.  Elements that straddle two blocks
+// are evaluated by both; their gathers hit L2 because consecutive blocks are
+// scheduled on the same XCD (work-table remap).  The LDS sums follow the
+// order in which the waves reach them, so the last bits may vary from run
+// to run; block partial sums are reduced in a fixed order.
 //
 // Alternatives for comparison: a device-wide atomic scatter over all
 // elements, and a colour-by-colour deterministic scatter.
@@ -256,9 +260,15 @@ __device__ __forceinline__ void lds_accumulate(A* acc, const int (&nd)[D + 1], i
   }
 }
 
-// Element visits in flight per thread in the fused 2D linear iteration.
+// Element visits in flight per thread in the fused 2D linear iteration and
+// in the other fused iterations (3D, Neo-Hookean), whose records and state
+// take more registers: one visit at a time keeps their occupancy (measured:
+// 500k-tet Neo-Hookean warm solve 54.9 ms against 77.4 with two).
 #ifndef PFEM_FCG_EIF
 #define PFEM_FCG_EIF 2
+#endif
+#ifndef PFEM_FCG_EIF_OTHER
+#define PFEM_FCG_EIF_OTHER 1
 #endif
 
 // LDS accumulator type of the owner kernel.
@@ -464,7 +474,7 @@ __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int b
   // connectivity, coordinates and records are in flight while the partials
   // are summed (in 3D the registers held across the sum cost more
   // occupancy than the overlap gains: measured 10-20% slower)
-  constexpr int EIF = (D == 2 && !NL) ? PFEM_FCG_EIF : 2;
+  constexpr int EIF = (D == 2 && !NL) ? PFEM_FCG_EIF : PFEM_FCG_EIF_OTHER;
   constexpr bool HOIST = D == 2;
   using A = AccT<T>;
   A* acc = reinterpret_cast<A*>(smem_raw);

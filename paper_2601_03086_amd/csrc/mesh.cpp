@@ -1,7 +1,7 @@
 // Mesh validation, bit-exact preprocessing and device upload.
 //
 // Preprocessing rules (the paper fixes no ordering; these tie-broken rules
-// make every result reproducible bit for bit):
+// make every preprocessing result reproducible bit for bit):
 //  * reverse Cuthill-McKee on the node graph (nodes adjacent when they share
 //    an element): each connected component starts at the unvisited node of
 //    smallest degree (ties: smallest caller id); a dequeued node appends its
@@ -652,11 +652,11 @@ int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg) {
 bool krylov_fused(const pfem_solve_opts& o, const pfem_mesh* m) {
   if (o.krylov != PFEM_KRYLOV_AUTO) return o.krylov == PFEM_KRYLOV_FUSED;
   // The fused launch wins where an iteration is launch- and latency-bound
-  // (measured: 200k-triangle plate 74 vs 109 ms per solve); on larger
-  // meshes its extra vector traffic and the weaker float32 convergence of
-  // the single-reduction form lose (2M triangles: 1.05 vs 0.69 s; 1M
-  // Neo-Hookean tets: 0.25 vs 0.21 s).
-  const int64_t limit = m->dim == 2 ? 600000 : 200000;
+  // (measured warm FP32 solves: 200k-triangle plate 55 vs 82 ms per solve,
+  // 500k-tet Neo-Hookean box 55 vs 64 ms); on larger meshes its extra vector
+  // traffic and the weaker float32 convergence of the single-reduction form
+  // catch up (600k triangles: 226 vs 221 ms; 1M tets: 123 vs 120 ms).
+  const int64_t limit = m->dim == 2 ? 600000 : 800000;
   return o.prec == PFEM_FP32 && m->n_elems <= limit;
 }
 
