@@ -49,32 +49,25 @@ template <int D>
 __device__ __forceinline__ void load_conn(const int32_t* __restrict__ conn, int e,
                                           int (&nd)[D + 1]);
 
-// Element e's nodes: packed (smallest node + 16-bit offsets, 8 bytes in 2D,
-// 12 in 3D) when the mesh fits, else plain int32 rows.  Measured on large
-// meshes: packing pays in 2D and in 3D float64, while 3D float32 is faster
-// with one 16-byte load of the plain row.
-// PK = 1: the caller guarantees packed connectivity wherever this format
-// uses it (no run-time test, so no wait at a branch join).
+// Element e's nodes: in 2D packed (smallest node + two 16-bit offsets, 8
+// bytes) when the mesh fits, else plain int32 rows; in 3D always the plain
+// 16-byte row (measured: a packed 12-byte row made the 4M-tet K.v 1.4x
+// slower in FP32 and the plain row 15% faster in FP64).
+// PK = 1: the caller guarantees packed 2D connectivity (no run-time test, so
+// no wait at a branch join).
 template <int D, typename T, int PK = 0>
 __device__ __forceinline__ void load_conn(const MeshDev& m, int e, int (&nd)[D + 1]) {
-  if ((D == 2 || sizeof(T) == 8) && (PK == 1 || m.conn_packed)) {
-    if constexpr (D == 2) {
+  if constexpr (D == 2) {
+    if (PK == 1 || m.conn_packed) {
       typedef unsigned int pu2 __attribute__((ext_vector_type(2)));
       const pu2 q = ldx(reinterpret_cast<const pu2*>(m.connp), (uint32_t)e);
       nd[0] = (int)q.x;
       nd[1] = (int)(q.x + (q.y & 0xffffu));
       nd[2] = (int)(q.x + (q.y >> 16));
-    } else {
-      const Trip<uint32_t> q = ldx(reinterpret_cast<const Trip<uint32_t>*>(m.connp), (uint32_t)e);
-      const uint32_t a = q.x, b = q.y, c = q.z;
-      nd[0] = (int)a;
-      nd[1] = (int)(a + (b & 0xffffu));
-      nd[2] = (int)(a + (b >> 16));
-      nd[3] = (int)(a + c);
+      return;
     }
-  } else {
-    load_conn<D>(m.conn, e, nd);
   }
+  load_conn<D>(m.conn, e, nd);
 }
 
 template <int D>
@@ -270,6 +263,11 @@ __device__ __forceinline__ void lds_accumulate(A* acc, const int (&nd)[D + 1], i
 #ifndef PFEM_FCG_EIF_OTHER
 #define PFEM_FCG_EIF_OTHER 1
 #endif
+// Element visits in flight per thread in the (non-fused) owner kernels
+// (measured: 4 is 10-35% slower, 1 within noise in 2D and slower in 3D).
+#ifndef PFEM_OWNER_EIF
+#define PFEM_OWNER_EIF 2
+#endif
 
 // LDS accumulator type of the owner kernel.
 #ifndef PFEM_ACC_F64
@@ -385,7 +383,8 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work, const Bas
   const T* U = operand<const T>(const_cast<void*>(tp->u), const_cast<void*>(ba.u), ba.rel);
   const T* V = operand<const T>(const_cast<void*>(tp->v), const_cast<void*>(ba.v), ba.rel);
   const int mask = ba.rel ? ba.mask : tp->mask;
-  owner_accumulate<D, T, OP, NL, A>(m, U, V, mask, br, n0, nloc, acc);
+  owner_accumulate<D, T, OP, NL, A, false, kThreads, PFEM_OWNER_EIF>(m, U, V, mask, br, n0,
+                                                                     nloc, acc);
   T* Y = operand<T>(tp->y, ba.y, ba.rel);
   const T* W = static_cast<const T*>(tp->w);
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};

@@ -499,26 +499,25 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
       xq[n * D + i] = (uint32_t)std::min(std::max(t, 0.0), 4294967295.0);
     }
   }
-  // packed connectivity: smallest node first, 16-bit offsets of the others
+  // packed 2D connectivity: smallest node first, 16-bit offsets of the
+  // other two (3D kernels read the plain 16-byte rows)
   const int nv = D + 1;
-  const int pw = D == 2 ? 2 : 3;
-  bool packable = true;
-  std::vector<uint32_t> cp((size_t)m->n_elems * pw);
+  bool packable = D == 2;
+  std::vector<uint32_t> cp(packable ? (size_t)m->n_elems * 2 : 0);
   for (int64_t s = 0; packable && s < m->n_elems; ++s) {
     const int32_t* c = &m->conn_int[s * nv];
     int amin = 0;
     for (int a = 1; a < nv; ++a)
       if (c[a] < c[amin]) amin = a;
-    uint32_t off[3];
+    uint32_t off[2];
     for (int k = 1; k < nv; ++k) {
       const int64_t dlt = (int64_t)c[(amin + k) % nv] - c[amin];
       if (dlt > 65535) packable = false;
       off[k - 1] = (uint32_t)dlt;
     }
-    uint32_t* o = &cp[s * pw];
+    uint32_t* o = &cp[s * 2];
     o[0] = (uint32_t)c[amin];
     o[1] = (off[0] & 0xffffu) | ((off[1] & 0xffffu) << 16);
-    if (D == 3) o[2] = off[2];
   }
   if (!packable) cp.clear();
   try {
@@ -637,7 +636,7 @@ void mesh_release_device(pfem_mesh* m) {
 int64_t mesh_device_bytes(const pfem_mesh* m) {
   const int64_t N = m->n_nodes, NE = m->n_elems, D = m->dim;
   auto r = [](int64_t b) { return std::max<int64_t>(b, 1); };
-  return r(N * D * 8) + r(N * D * 4) + r(NE * (D + 1) * 4) + r(NE * (D == 2 ? 8 : 12)) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
+  return r(N * D * 8) + r(N * D * 4) + r(NE * (D + 1) * 4) + r(D == 2 ? NE * 8 : 0) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
          r((int64_t)m->n_blocks * 16) + r(((int64_t)m->halo.size() + 1) * 4) + 2 * r(N * D * 8) +
          r(NE * 4) + r(N * 4) + r((int64_t)m->n_blocks * 8);
 }

@@ -56,9 +56,9 @@ struct MeshDev {
   const uint32_t* Xq;     // n_nodes * dim fixed-point coordinates (float32 kernels):
                           // X = lo + q * qscale, per dimension
   const int32_t* conn;    // n_elems * (dim+1), sorted element order, internal ids
-  const uint32_t* connp;  // packed connectivity (conn_packed): per element the
-                          // smallest node, then 16-bit offsets of the others
-                          // (2 words in 2D, 3 in 3D); node order inside the
+  const uint32_t* connp;  // packed 2D connectivity (conn_packed): per element
+                          // the smallest node, then the 16-bit offsets of the
+                          // other two in one word; node order inside the
                           // element rotated so the smallest comes first
   const float* mu32;      // n_elems
   const float* lam32;     // n_elems
