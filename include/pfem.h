@@ -269,7 +269,8 @@ enum { PFEM_KRYLOV_AUTO = 0, PFEM_KRYLOV_CLASSIC = 1, PFEM_KRYLOV_FUSED = 2 };
 typedef struct {
   double tol;           /* relative residual target |r_f| / |r_f(lifted)| (App. B) */
   double tol_fine;      /* skip iterating if the guess is already below (Sec. 'Warm-start'); 0 = off */
-  int32_t max_iter;     /* cap on K.v products in all Krylov loops; 0 = 10 * n_free */
+  int32_t max_iter;     /* cap on K.v products in all Krylov loops of the solve;
+                           0 = 10 * n_free + 1000 * load steps (1 if linear) */
   int32_t n_load_steps; /* Neo-Hookean: load steps N_f (warm start jumps to N_f) */
   int32_t max_newton;   /* per load step; 0 = 50 */
   int32_t prec;         /* PFEM_FP64 or PFEM_FP32 (FP32 Krylov, FP64 outer residual) */

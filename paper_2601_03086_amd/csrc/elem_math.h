@@ -105,7 +105,7 @@ __device__ __forceinline__ void geometry_x(const MeshDev& m, const ElemX<D, T>& 
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int i = 0; i < D; ++i)
-        e[a][i] = (float)(int)(x.q[a + 1][i] - x.q[0][i]) * m.qscale[i];
+        e[a][i] = (float)((int)x.q[a + 1][i] - (int)x.q[0][i]) * m.qscale[i];   // q < 2^31
   } else {
 #pragma unroll
     for (int a = 0; a < D; ++a)

@@ -481,7 +481,9 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   d.bytes = 0;
   std::vector<float> mu32(m->mu_int.begin(), m->mu_int.end());
   std::vector<float> lam32(m->lam_int.begin(), m->lam_int.end());
-  // 32-bit fixed-point coordinates over the bounding box (float32 kernels)
+  // 31-bit fixed-point coordinates over the bounding box (float32 kernels):
+  // 0 <= q < 2^31, so the difference of any two fits a signed 32-bit integer
+  // (an element spanning more than half the box must not wrap around)
   const int D = m->dim;
   std::vector<uint32_t> xq(m->X_int.size());
   float qscale[3] = {1.f, 1.f, 1.f};
@@ -492,11 +494,11 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
       if (n == 0 || v < lo) lo = v;
       if (n == 0 || v > hi) hi = v;
     }
-    const double step = hi > lo ? (hi - lo) / 4294967295.0 : 1.0;
+    const double step = hi > lo ? (hi - lo) / 2147483647.0 : 1.0;
     qscale[i] = (float)step;
     for (int64_t n = 0; n < m->n_nodes; ++n) {
       const double t = std::round((m->X_int[n * D + i] - lo) / step);
-      xq[n * D + i] = (uint32_t)std::min(std::max(t, 0.0), 4294967295.0);
+      xq[n * D + i] = (uint32_t)std::min(std::max(t, 0.0), 2147483647.0);
     }
   }
   // packed 2D connectivity: smallest node first, 16-bit offsets of the

@@ -53,7 +53,7 @@ struct Trip {
 // Everything a kernel needs to know about one finalized mesh (POD).
 struct MeshDev {
   const double* X;        // n_nodes * dim, internal node order
-  const uint32_t* Xq;     // n_nodes * dim fixed-point coordinates (float32 kernels):
+  const uint32_t* Xq;     // n_nodes * dim 31-bit fixed-point coordinates (float32 kernels):
                           // X = lo + q * qscale, per dimension
   const int32_t* conn;    // n_elems * (dim+1), sorted element order, internal ids
   const uint32_t* connp;  // packed 2D connectivity (conn_packed): per element

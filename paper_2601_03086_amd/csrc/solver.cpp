@@ -192,7 +192,15 @@ void slot_begin(Ctx* ctx, SlotRun* s, const double* u0_dev) {
   s->warm = u0_dev != nullptr;
   s->n_steps = s->nl ? std::max(1, s->o.n_load_steps) : 1;
   s->step = (s->warm || !s->nl) ? s->n_steps : 1;
-  s->max_iter = s->o.max_iter > 0 ? s->o.max_iter : (int)std::min<int64_t>(10 * std::max<int64_t>(m->n_free, 1), INT32_MAX / 2);
+  // automatic cap on K.v products over the whole solve: 10 per free DOF plus
+  // 1000 per load step (a Newton solve runs one Krylov loop per iteration of
+  // every load step; on a mesh with a handful of free DOFs 10 per DOF alone
+  // stopped it after the first steps)
+  s->max_iter = s->o.max_iter > 0
+                    ? s->o.max_iter
+                    : (int)std::min<int64_t>(10 * std::max<int64_t>(m->n_free, 1) +
+                                                 1000 * (int64_t)s->n_steps,
+                                             INT32_MAX / 2);
   s->rep = pfem_solve_report{};
   s->first_resid = true;
   s->minv_valid = false;
