@@ -179,3 +179,27 @@ def test_block_numbering_cuts_straddling_elements():
         v = {o: core.Mesh.from_problem(None, p, bn, o).info["owner_elem_visits"]
              for o in ("blocks", "rcm")}
         assert v["blocks"] <= gain * v["rcm"], (v, p.name)
+
+
+def test_mesh_beyond_32bit_offsets_rejected():
+    """The element kernels address per-node arrays with 32-bit byte offsets;
+    the largest is the FP64 fused-PCG record, 96 bytes per 3D node, so a 3D
+    mesh of 2^32 / 96 nodes or more is refused at finalize, before any
+    preprocessing (disjoint unit tets, every node used)."""
+    L = _lib()
+    from paper_2601_03086_amd import core
+    n_tet = ((1 << 32) // 96 + 4) // 4          # just past the limit
+    n = 4 * n_tet
+    coords = np.zeros((n, 3))
+    base = np.arange(n_tet, dtype=np.float64) * 2.0
+    coords[0::4, 0] = base
+    coords[1::4, 0] = base + 1.0
+    coords[2::4, 0] = base
+    coords[2::4, 1] = 1.0
+    coords[3::4, 0] = base
+    coords[3::4, 2] = 1.0
+    conn = np.arange(n, dtype=np.int32).reshape(-1, 4)
+    with pytest.raises(L.PfemError) as ei:
+        core.Mesh(None, 3, coords, conn, "lin_3d", "E_nu", 1.0, 0.3)
+    assert ei.value.status == L.PFEM_E_INVALID_MESH
+    assert "too large" in str(ei.value)
