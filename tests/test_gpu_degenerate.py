@@ -120,3 +120,45 @@ def test_zero_load(ctx, krylov):
     Kff, _, _ = osolve.reduced_system(om)
     # zero right-hand side: the tolerance is absolute on |K_ff u_f|
     assert np.linalg.norm(Kff @ u[om.free_dofs]) <= 1.1e-10
+
+
+def _two_plates():
+    import synth
+    q = synth.plate_problem(31, 32, 33, n_holes=2, target_tris=1500)
+    n = q.coords.shape[0]
+    coords = np.vstack([q.coords, q.coords + np.array([1.5, 0.2])])
+    conn = np.vstack([q.conn, q.conn + n])
+    dn = np.concatenate([q.dir_nodes, q.dir_nodes + n])
+    dc = np.concatenate([q.dir_comps, q.dir_comps])
+    dv = np.concatenate([q.dir_values, q.dir_values])
+    facets = np.vstack([q.neu_facets, q.neu_facets + n])
+    trac = np.vstack([q.neu_traction, 2.0 * q.neu_traction])
+    return mk.make_problem("lin_plane_strain", coords, conn, E=np.tile(q.p0, 2),
+                           nu=np.tile(q.p1, 2), dir_nodes=dn, dir_comps=dc, dir_values=dv,
+                           facets=facets, traction=trac)
+
+
+@pytest.mark.parametrize("order,bn", [("blocks", 0), ("blocks", 1), ("rcm", 1), ("blocks", 7)])
+def test_two_components_and_tiny_blocks(ctx, order, bn):
+    """Two disconnected plates in one mesh (numbering, bands and halo lists
+    across components) and owner blocks of one or seven nodes: K.v in both
+    precisions and fused / classic solves against the oracle."""
+    from paper_2601_03086_amd import core
+    torch = torch_cuda()
+    p = _two_plates()
+    m = core.Mesh.from_problem(ctx, p, bn, order)
+    om = fe.Model(p)
+    K = om.assemble()
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        tv = torch.tensor(np.random.default_rng(7).normal(size=p.n_dof), dtype=dt)
+        vv = tv.double().numpy()
+        y = m.apply_K(tv, prec=prec).double().cpu().numpy()
+        assert bound_rel(y, K @ vv, abs(K) @ abs(vv)) <= tol
+    uo, _ = osolve.solve_linear(p, method="direct")
+    for krylov in ("classic", "fused"):
+        u, rep, _ = m.solve(tol=1e-10, prec="fp64", krylov=krylov)
+        print(f"[two plates] {order} bn={bn} {krylov}: {rep['status_name']} "
+              f"kv={rep['kv_count']} blocks={m.info['n_blocks']}", flush=True)
+        assert rep["status"] == 0
+        assert rel(u, uo) <= 1e-8
