@@ -28,7 +28,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <numeric>
+#include <thread>
 
 namespace pfem {
 
@@ -104,6 +106,23 @@ static void validate(const pfem_mesh* m) {
   for (size_t i = 0; i < m->mu.size(); ++i)
     require(std::isfinite(m->mu[i]) && std::isfinite(m->lam[i]), PFEM_E_INVALID_ARG,
             "non-finite material parameter");
+}
+
+// f(begin, end) over [0, n) in contiguous chunks on up to 16 host threads
+// (serially below 65536 items); f must only write its own items.
+static void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f) {
+  const int64_t nt = std::min<int64_t>(16, std::max(1u, std::thread::hardware_concurrency()));
+  if (n < 65536 || nt == 1) {
+    f(0, n);
+    return;
+  }
+  const int64_t chunk = (n + nt - 1) / nt;
+  std::vector<std::thread> th;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t b = t * chunk, e = std::min(n, b + chunk);
+    if (b < e) th.emplace_back(f, b, e);
+  }
+  for (auto& x : th) x.join();
 }
 
 // ----------------------------------------------------------------- RCM
@@ -308,32 +327,67 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
     for (int64_t s = 0; s < NE; ++s)
       for (int a = 0; a < nv; ++a) n2e[fill[m->conn_int[s * nv + a]]++] = (int32_t)s;
   }
+  // Greedy first fit in decreasing priority, computed as Jones-Plassmann
+  // rounds (same colours): in each round every uncoloured element none of
+  // whose uncoloured neighbours has a higher priority takes the smallest
+  // colour its (already coloured, all higher-priority) neighbours leave free.
+  // Such elements are pairwise non-adjacent, so a round runs in parallel
+  // and sweeps the elements in their sorted (cache-friendly) order.
   std::vector<uint32_t> h(NE);
   for (int64_t k = 0; k < NE; ++k) h[k] = fmix32((uint32_t)k ^ 0x9E3779B9u);
-  std::vector<int32_t> order(NE);
-  std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    return h[a] != h[b] ? h[a] > h[b] : a > b;
-  });
+  auto higher = [&](int32_t f, int32_t e) { return h[f] != h[e] ? h[f] > h[e] : f > e; };
   m->color.assign(NE, -1);
-  std::vector<int64_t> stamp(64, -1);
-  int ncol = 0;
-  for (int32_t e : order) {
-    for (int a = 0; a < nv; ++a) {
-      const int32_t n = m->conn_int[(size_t)e * nv + a];
-      for (int64_t k = n2e_ptr[n]; k < n2e_ptr[n + 1]; ++k) {
-        const int32_t c = m->color[n2e[k]];
-        if (c >= 0) {
-          if ((size_t)c >= stamp.size()) stamp.resize(2 * c + 2, -1);
-          stamp[c] = e;
+  std::vector<int32_t> active(NE), next;
+  std::iota(active.begin(), active.end(), 0);
+  std::vector<char> ready;
+  int32_t* col = m->color.data();
+  while (!active.empty()) {
+    const int64_t na = (int64_t)active.size();
+    ready.assign(na, 0);
+    parallel_for(na, [&](int64_t b, int64_t e) {
+      for (int64_t i = b; i < e; ++i) {
+        const int32_t el = active[i];
+        bool ok = true;
+        for (int a = 0; a < nv && ok; ++a) {
+          const int32_t n = m->conn_int[(size_t)el * nv + a];
+          for (int64_t k = n2e_ptr[n]; k < n2e_ptr[n + 1]; ++k) {
+            const int32_t f = n2e[k];
+            if (f != el && col[f] < 0 && higher(f, el)) {
+              ok = false;
+              break;
+            }
+          }
         }
+        ready[i] = ok;
       }
-    }
-    int c = 0;
-    while ((size_t)c < stamp.size() && stamp[c] == e) ++c;
-    m->color[e] = c;
-    ncol = std::max(ncol, c + 1);
+    });
+    parallel_for(na, [&](int64_t b, int64_t e) {
+      std::vector<int32_t> stamp(64, -1);
+      for (int64_t i = b; i < e; ++i) {
+        if (!ready[i]) continue;
+        const int32_t el = active[i];
+        for (int a = 0; a < nv; ++a) {
+          const int32_t n = m->conn_int[(size_t)el * nv + a];
+          for (int64_t k = n2e_ptr[n]; k < n2e_ptr[n + 1]; ++k) {
+            const int32_t c = col[n2e[k]];   // never an element of this round
+            if (c >= 0) {
+              if ((size_t)c >= stamp.size()) stamp.resize(2 * (size_t)c + 2, -1);
+              stamp[c] = el;
+            }
+          }
+        }
+        int32_t c = 0;
+        while ((size_t)c < stamp.size() && stamp[c] == el) ++c;
+        col[el] = c;
+      }
+    });
+    next.clear();
+    for (int64_t i = 0; i < na; ++i)
+      if (!ready[i]) next.push_back(active[i]);
+    active.swap(next);
   }
+  int ncol = 0;
+  for (int64_t k = 0; k < NE; ++k) ncol = std::max(ncol, col[k] + 1);
   m->n_colors = ncol;
   m->color_ptr.assign(ncol + 1, 0);
   for (int64_t s = 0; s < NE; ++s) m->color_ptr[m->color[s] + 1]++;

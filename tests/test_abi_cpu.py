@@ -203,3 +203,23 @@ def test_mesh_beyond_32bit_offsets_rejected():
         core.Mesh(None, 3, coords, conn, "lin_3d", "E_nu", 1.0, 0.3)
     assert ei.value.status == L.PFEM_E_INVALID_MESH
     assert "too large" in str(ei.value)
+
+
+@pytest.mark.parametrize("kind", ["plate", "box"])
+def test_parallel_colouring_bit_exact(kind):
+    """Meshes above the size where the library colours in parallel rounds
+    (Jones-Plassmann, several host threads): the colours still equal the
+    oracle's sequential greedy in priority order."""
+    L = _lib()
+    from paper_2601_03086_amd import core
+    if kind == "plate":
+        p = synth.plate_problem(5, 6, 7, n_holes=3, target_tris=80000)
+    else:
+        p = synth.box_problem(8, 9, n_per_unit=16, n_voids=3)
+    assert p.n_elems >= 65536
+    m = core.Mesh.from_problem(None, p)
+    col = m.query(L.PFEM_Q_COLOR)
+    eo = m.query(L.PFEM_Q_ELEM_ORDER)
+    perm = m.query(L.PFEM_Q_PERM)
+    sconn = perm[p.conn[eo]]
+    assert np.array_equal(col, prep.colour_elements(sconn, p.n_nodes))
