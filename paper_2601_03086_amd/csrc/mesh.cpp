@@ -69,13 +69,15 @@ static void validate(const pfem_mesh* m) {
   std::vector<char> used(m->n_nodes, 0);
   for (int64_t e = 0; e < m->n_elems; ++e) {
     const int32_t* c = &m->conn[e * nv];
+    // (messages are built only when a check fails: this loop runs per element)
     for (int a = 0; a < nv; ++a) {
-      require(c[a] >= 0 && c[a] < m->n_nodes, PFEM_E_INVALID_MESH,
-              "element " + std::to_string(e) + " references node out of range");
+      if (!(c[a] >= 0 && c[a] < m->n_nodes))
+        throw Error{PFEM_E_INVALID_MESH,
+                    "element " + std::to_string(e) + " references node out of range"};
       used[c[a]] = 1;
       for (int b = 0; b < a; ++b)
-        require(c[a] != c[b], PFEM_E_INVALID_MESH,
-                "element " + std::to_string(e) + " repeats a node");
+        if (c[a] == c[b])
+          throw Error{PFEM_E_INVALID_MESH, "element " + std::to_string(e) + " repeats a node"};
     }
     // degeneracy: |det J| against the longest edge^D
     double ev[3][3] = {};
@@ -95,12 +97,12 @@ static void validate(const pfem_mesh* m) {
       det = ev[0][0] * (ev[1][1] * ev[2][2] - ev[1][2] * ev[2][1]) -
             ev[0][1] * (ev[1][0] * ev[2][2] - ev[1][2] * ev[2][0]) +
             ev[0][2] * (ev[1][0] * ev[2][1] - ev[1][1] * ev[2][0]);
-    require(std::isfinite(det) && std::fabs(det) > 1e-12 * std::pow(lmax, D),
-            PFEM_E_INVALID_MESH, "element " + std::to_string(e) + " is degenerate");
+    if (!(std::isfinite(det) && std::fabs(det) > 1e-12 * std::pow(lmax, D)))
+      throw Error{PFEM_E_INVALID_MESH, "element " + std::to_string(e) + " is degenerate"};
   }
   for (int64_t n = 0; n < m->n_nodes; ++n)
-    require(used[n], PFEM_E_INVALID_MESH,
-            "node " + std::to_string(n) + " belongs to no element");
+    if (!used[n])
+      throw Error{PFEM_E_INVALID_MESH, "node " + std::to_string(n) + " belongs to no element"};
   for (double v : m->coords)
     require(std::isfinite(v), PFEM_E_INVALID_MESH, "non-finite coordinate");
   for (size_t i = 0; i < m->mu.size(); ++i)

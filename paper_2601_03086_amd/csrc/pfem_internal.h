@@ -35,6 +35,10 @@ const char* last_error_cstr();
 inline void require(bool ok, pfem_status code, const std::string& msg) {
   if (!ok) throw Error{code, msg};
 }
+// literal messages: no string is built unless the check fails (hot loops)
+inline void require(bool ok, pfem_status code, const char* msg) {
+  if (!ok) throw Error{code, std::string(msg)};
+}
 
 // Native vector types: HIP's float2/double2/int4 wrappers copy through
 // generic references, which would turn a global load back into a flat one.
