@@ -109,9 +109,9 @@ def rcm(conn, n_nodes):
 def auto_block_nodes(n_nodes, dim):
     """Nodes per owner block when the caller leaves it to the library:
     N/4000 (2D) or N/750 (3D) rounded up to a multiple of 32, at least 224
-    (2D) or 64 (3D), at most 2048."""
+    (2D) or 64 (3D), at most 1024."""
     per, lo = (4000, 224) if dim == 2 else (750, 64)
-    return int(min(2048, max(lo, ((n_nodes // per) + 31) // 32 * 32)))
+    return int(min(1024, max(lo, ((n_nodes // per) + 31) // 32 * 32)))
 
 
 def int_root(bn, dim):

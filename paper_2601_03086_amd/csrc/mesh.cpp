@@ -279,12 +279,12 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
   int bn = block_nodes;
   if (bn <= 0) {
     // N/4000 (2D) or N/750 (3D) nodes, a multiple of 32, at least 224 (2D) or
-    // 64 (3D), at most 2048: measured optimum of the owner kernels on compact
-    // blocks (enough workgroups to fill the chip, few halo revisits; the
-    // fused PCG launch sums every block's partials in every block, so it
-    // also wants few blocks)
+    // 64 (3D), at most 1024: measured optimum of the owner kernels on compact
+    // blocks (enough workgroups to fill the chip, few halo revisits, LDS for
+    // enough resident workgroups; the fused PCG launch sums every block's
+    // partials in every block, so it also wants few blocks)
     const int64_t per = D == 2 ? 4000 : 750, lo = D == 2 ? 224 : 64;
-    bn = (int)std::min<int64_t>(2048, std::max<int64_t>(lo, ((N / per) + 31) / 32 * 32));
+    bn = (int)std::min<int64_t>(1024, std::max<int64_t>(lo, ((N / per) + 31) / 32 * 32));
   }
   require(bn <= block_nodes_max(), PFEM_E_INVALID_ARG, "block_nodes too large");
   // the element kernels address mesh and solver arrays with 32-bit byte

@@ -421,10 +421,10 @@ def test_band_size_hand_values():
     assert prep.band_blocks(100, 8, 16, 2) == 3
     assert prep.band_blocks(10, 100, 256, 2) == 1
     assert prep.band_blocks(2 * 10 ** 7, 9000, 2048, 2) == 16
-    # N/4000 (2D) or N/750 (3D) up to a multiple of 32, clamped to [224|64, 2048]
+    # N/4000 (2D) or N/750 (3D) up to a multiple of 32, clamped to [224|64, 1024]
     assert prep.auto_block_nodes(1000, 2) == 224 and prep.auto_block_nodes(1000, 3) == 64
     assert prep.auto_block_nodes(2000000, 2) == 512 and prep.auto_block_nodes(183000, 3) == 256
-    assert prep.auto_block_nodes(10 ** 8, 2) == 2048 and prep.auto_block_nodes(10 ** 8, 3) == 2048
+    assert prep.auto_block_nodes(10 ** 8, 2) == 1024 and prep.auto_block_nodes(10 ** 8, 3) == 1024
 
 
 def test_bisect_blocks_hand_example():
