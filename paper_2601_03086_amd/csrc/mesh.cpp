@@ -386,7 +386,53 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
     next.clear();
     for (int64_t i = 0; i < na; ++i)
       if (!ready[i]) next.push_back(active[i]);
+    const int64_t done = na - (int64_t)next.size();
     active.swap(next);
+    if (!active.empty() && done < 1024) {
+      // few elements per round (a node of very high degree, e.g. a fan):
+      // finish with the plain greedy in decreasing priority, same colours.
+      // Nodes of degree > 256 keep a bit set of the colours already used
+      // around them, so an element next to such a hub costs O(colours / 64)
+      // instead of a scan of the hub's whole element list.
+      std::sort(active.begin(), active.end(), [&](int32_t a, int32_t b) { return higher(a, b); });
+      auto set_bit = [](std::vector<uint64_t>& b, int32_t c) {
+        if ((size_t)(c >> 6) >= b.size()) b.resize((size_t)(c >> 6) + 1, 0);
+        b[c >> 6] |= uint64_t(1) << (c & 63);
+      };
+      const int64_t hub_deg = 256;
+      std::vector<std::vector<uint64_t>> hub_used;
+      std::vector<int32_t> hub_id(N, -1);
+      for (int64_t n = 0; n < N; ++n)
+        if (n2e_ptr[n + 1] - n2e_ptr[n] > hub_deg) {
+          hub_id[n] = (int32_t)hub_used.size();
+          hub_used.emplace_back();
+          for (int64_t k = n2e_ptr[n]; k < n2e_ptr[n + 1]; ++k)
+            if (col[n2e[k]] >= 0) set_bit(hub_used.back(), col[n2e[k]]);
+        }
+      std::vector<uint64_t> used;
+      for (int32_t el : active) {
+        used.assign(used.size(), 0);
+        for (int a = 0; a < nv; ++a) {
+          const int32_t n = m->conn_int[(size_t)el * nv + a];
+          if (hub_id[n] >= 0) {
+            const std::vector<uint64_t>& hb = hub_used[hub_id[n]];
+            if (used.size() < hb.size()) used.resize(hb.size(), 0);
+            for (size_t w = 0; w < hb.size(); ++w) used[w] |= hb[w];
+            continue;
+          }
+          for (int64_t k = n2e_ptr[n]; k < n2e_ptr[n + 1]; ++k)
+            if (col[n2e[k]] >= 0) set_bit(used, col[n2e[k]]);
+        }
+        int32_t c = 0;
+        while ((size_t)(c >> 6) < used.size() && ((used[c >> 6] >> (c & 63)) & 1)) ++c;
+        col[el] = c;
+        for (int a = 0; a < nv; ++a) {
+          const int32_t n = m->conn_int[(size_t)el * nv + a];
+          if (hub_id[n] >= 0) set_bit(hub_used[hub_id[n]], c);
+        }
+      }
+      active.clear();
+    }
   }
   int ncol = 0;
   for (int64_t k = 0; k < NE; ++k) ncol = std::max(ncol, col[k] + 1);

@@ -223,3 +223,20 @@ def test_parallel_colouring_bit_exact(kind):
     perm = m.query(L.PFEM_Q_PERM)
     sconn = perm[p.conn[eo]]
     assert np.array_equal(col, prep.colour_elements(sconn, p.n_nodes))
+
+
+def test_colouring_high_degree_node_bit_exact():
+    """A 5000-triangle fan (every element shares the centre node, so all
+    need distinct colours): the library's colours -- its rounds finish with
+    the sequential greedy, using per-node colour sets at nodes of very high
+    degree -- equal the oracle's greedy in priority order."""
+    L = _lib()
+    from paper_2601_03086_amd import core
+    from tests import meshkit as mk
+    p = mk.fan_problem(m=5000)
+    m = core.Mesh.from_problem(None, p, 0, "rcm")
+    col = m.query(L.PFEM_Q_COLOR)
+    perm = m.query(L.PFEM_Q_PERM)
+    sconn = perm[p.conn[m.query(L.PFEM_Q_ELEM_ORDER)]]
+    assert m.info["n_colors"] == 5000
+    assert np.array_equal(col, prep.colour_elements(sconn, p.n_nodes))
