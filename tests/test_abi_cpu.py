@@ -240,3 +240,21 @@ def test_colouring_high_degree_node_bit_exact():
     sconn = perm[p.conn[m.query(L.PFEM_Q_ELEM_ORDER)]]
     assert m.info["n_colors"] == 5000
     assert np.array_equal(col, prep.colour_elements(sconn, p.n_nodes))
+
+
+def test_every_entry_point_rejects_null_arguments():
+    """Every status-returning call reports PFEM_E_INVALID_ARG when its
+    handles and pointers are NULL (no device is touched, nothing crashes),
+    and the void destructors accept NULL."""
+    L = _lib()
+    lib = L.load()
+    ints = (C.c_int, L._I32, L._I64)
+    for name, (res, args) in L.PROTOTYPES.items():
+        if not args:
+            continue
+        st = getattr(lib, name)(*[0 if a in ints else None for a in args])
+        if res is None:
+            assert st is None, name
+        else:
+            assert st == L.PFEM_E_INVALID_ARG, (name, st)
+            assert L.pfem_last_error(), name
