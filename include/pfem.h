@@ -198,8 +198,10 @@ typedef struct {
   double f_ext_norm;
 } pfem_mesh_info;
 pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* out);
-/* Copy a preprocessing array (see PFEM_Q_*) into out (cap entries);
- * *n receives the full length. */
+/* Copy a preprocessing array (see PFEM_Q_*) into out (host, the first
+ * min(cap, length) entries); *n (host) receives the full length.  out may
+ * be NULL to ask for the length only, n may be NULL.  PFEM_E_STATE before
+ * pfem_mesh_finalize; PFEM_E_INVALID_ARG for an unknown query or cap < 0. */
 pfem_status pfem_mesh_query_int(const pfem_mesh* m, int which, int32_t* out,
                                 int64_t cap, int64_t* n);
 void pfem_mesh_destroy(pfem_mesh* m);

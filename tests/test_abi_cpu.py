@@ -258,3 +258,33 @@ def test_every_entry_point_rejects_null_arguments():
         else:
             assert st == L.PFEM_E_INVALID_ARG, (name, st)
             assert L.pfem_last_error(), name
+
+
+def test_host_only_mesh_calls():
+    """A mesh created without a context preprocesses on the host; every call
+    that needs the device reports PFEM_E_STATE, and the query hook answers
+    a length-only request (out NULL) and truncates to cap."""
+    L = _lib()
+    lib = L.load()
+    prob = synth.unit_square_c1(n=5)
+    nn = len(prob.coords)
+    m = _host_mesh(prob)
+    ints = (C.c_int, L._I32, L._I64)
+    for name in ("pfem_hvp", "pfem_apply_K", "pfem_force", "pfem_energy",
+                 "pfem_diag", "pfem_permute", "pfem_solve"):
+        args = L.PROTOTYPES[name][1]
+        st = getattr(lib, name)(m.h, *[0 if a in ints else None for a in args[1:]])
+        assert st == L.PFEM_E_STATE, (name, st)
+        assert b"device" in L.pfem_last_error(), name
+    n = L._I64()
+    assert lib.pfem_mesh_query_int(m.h, L.PFEM_Q_PERM, None, 0, C.byref(n)) == 0
+    assert n.value == nn
+    buf = np.full(8, -7, np.int32)
+    assert lib.pfem_mesh_query_int(m.h, L.PFEM_Q_PERM, buf.ctypes.data, 5, None) == 0
+    full = np.zeros(nn, np.int32)
+    assert lib.pfem_mesh_query_int(m.h, L.PFEM_Q_PERM, full.ctypes.data, nn, C.byref(n)) == 0
+    assert np.array_equal(buf[:5], full[:5]) and (buf[5:] == -7).all()
+    assert sorted(full.tolist()) == list(range(nn))
+    assert lib.pfem_mesh_query_int(m.h, 99, None, 0, None) == L.PFEM_E_INVALID_ARG
+    assert lib.pfem_mesh_query_int(m.h, L.PFEM_Q_PERM, full.ctypes.data, -1, None) \
+        == L.PFEM_E_INVALID_ARG
