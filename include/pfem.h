@@ -332,7 +332,11 @@ pfem_status pfem_server_poll(pfem_server* s, int64_t* done_ids, int64_t cap,
                              int64_t* n_done);
 /* Collect a completed request: u_out host n_dof float64 (may be NULL); times
  * in seconds since the server started (submit, admission, completion).
- * Releases the request. */
+ * Releases the request.  PFEM_E_STATE while the request is queued or live
+ * (nothing is released; call again later), PFEM_E_INVALID_ARG for an
+ * unknown or already collected id; otherwise the request's own status if
+ * it is an error (a device failure inside the worker ends every live
+ * request with that error), else PFEM_OK. */
 pfem_status pfem_server_result(pfem_server* s, int64_t req_id, double* u_out,
                                pfem_solve_report* rep, double* t_submit,
                                double* t_admit, double* t_done);

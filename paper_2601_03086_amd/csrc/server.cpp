@@ -8,12 +8,15 @@
 // step, so requests that arrive while others are on the device overlap with
 // them.  A finished request leaves at the end of its tick and its memory is
 // returned before the next admission check.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
 #include <mutex>
+#include <new>
+#include <string>
 #include <thread>
 
 #include "mesh.h"
@@ -31,7 +34,8 @@ struct Req {
   double t_submit = 0, t_admit = -1, t_done = -1;
   int64_t bytes = 0;
   SlotRun slot;
-  bool admitted = false, done = false, cancel = false, server_uploaded = false;
+  bool admitted = false, done = false, server_uploaded = false;
+  std::atomic<bool> cancel{false};   // set by the client, read by the worker
   std::vector<double> u_out;
   pfem_solve_report rep{};
 };
@@ -61,6 +65,8 @@ struct pfem_server {
   void run();
   void admit(Req* r);
   void complete(Req* r);
+  void retire(Req* r);
+  void fail(pfem_status code, const std::string& msg);
 };
 
 static int64_t req_bytes(const pfem_mesh* m, const pfem_solve_opts& o) {
@@ -114,7 +120,44 @@ void pfem_server::complete(Req* r) {
   r->u0.clear();
   r->u0.shrink_to_fit();
   r->t_done = now();
+}
+
+// With mu held: the request leaves the live set and becomes visible to
+// poll/result.  Only here (and in fail()) is done set, so a client never
+// sees a request the worker still touches.
+void pfem_server::retire(Req* r) {
+  live.erase(std::find(live.begin(), live.end(), r));
+  bytes_in_use -= r->bytes;
   r->done = true;
+  done_ids.push_back(r->id);
+  ++completed;
+}
+
+// With mu held: a device or host failure ends every live request with the
+// error.  Requests taken from the queue for admission are live already.
+void pfem_server::fail(pfem_status code, const std::string& msg) {
+  worker_error = msg;
+  for (Req* r : live) {
+    r->rep = r->slot.rep;
+    r->rep.status = code;
+    r->t_done = now();
+    r->done = true;
+    done_ids.push_back(r->id);
+    ++completed;
+    try {
+      slot_free(&r->slot);
+      // drop the server's mesh reference, as complete() does: the caller
+      // may destroy the mesh once the result is collected
+      if (r->server_uploaded && --mesh_refs[r->m] == 0) {
+        mesh_refs.erase(r->m);
+        mesh_release_device(r->m);
+      }
+    } catch (...) {
+    }
+    r->server_uploaded = false;
+  }
+  live.clear();
+  bytes_in_use = 0;
 }
 
 void pfem_server::run() {
@@ -160,19 +203,20 @@ void pfem_server::run() {
       for (Req* r : cancelled_live) {
         complete(r);
         std::lock_guard<std::mutex> lk(mu);
-        live.erase(std::find(live.begin(), live.end(), r));
-        bytes_in_use -= r->bytes;
-        done_ids.push_back(r->id);
-        ++completed;
+        retire(r);
       }
-      for (Req* r : to_admit) {
-        admit(r);
+      if (!to_admit.empty()) {
+        // live before admission, so that a failure while admitting ends
+        // these requests too instead of losing them
         std::lock_guard<std::mutex> lk(mu);
-        live.push_back(r);
-        bytes_in_use += r->bytes;
+        for (Req* r : to_admit) {
+          live.push_back(r);
+          bytes_in_use += r->bytes;
+        }
         peak_bytes = std::max(peak_bytes, bytes_in_use);
         peak_live = std::max<int64_t>(peak_live, (int64_t)live.size());
       }
+      for (Req* r : to_admit) admit(r);
       std::vector<SlotRun*> slots;
       std::vector<Req*> snapshot;
       {
@@ -191,29 +235,17 @@ void pfem_server::run() {
         if (!r->slot.finished) continue;
         complete(r);
         std::lock_guard<std::mutex> lk(mu);
-        live.erase(std::find(live.begin(), live.end(), r));
-        bytes_in_use -= r->bytes;
-        done_ids.push_back(r->id);
-        ++completed;
+        retire(r);
       }
     } catch (const pfem::Error& e) {
-      // a device failure ends every live request with the error
       std::lock_guard<std::mutex> lk(mu);
-      worker_error = e.msg;
-      for (Req* r : live) {
-        r->rep = r->slot.rep;
-        r->rep.status = e.code;
-        r->t_done = now();
-        r->done = true;
-        done_ids.push_back(r->id);
-        ++completed;
-        try {
-          slot_free(&r->slot);
-        } catch (...) {
-        }
-      }
-      live.clear();
-      bytes_in_use = 0;
+      fail(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+      std::lock_guard<std::mutex> lk(mu);
+      fail(PFEM_E_OOM, "host memory exhausted in the server worker");
+    } catch (const std::exception& e) {
+      std::lock_guard<std::mutex> lk(mu);
+      fail(PFEM_E_DEVICE, std::string("server worker: ") + e.what());
     }
   }
 }
