@@ -241,16 +241,29 @@ pfem_status pfem_diag(pfem_mesh* m, int prec, int layout, const void* u, void* d
  * runs once over all of them (one launch, one work table).  Vectors are
  * concatenated in batch order in INTERNAL layout: mesh i occupies
  * [offset_i, offset_i + n_dof_i) with offsets from pfem_batch_offsets. */
+/* meshes: host array of n finalized meshes uploaded on ctx's device, all of
+ * one dimension (linear and Neo-Hookean may mix; a mesh may appear in
+ * several batches).  The batch references the meshes: they must outlive it.
+ * PFEM_E_INVALID_ARG for n <= 0, a mesh of another context or mixed
+ * dimensions; PFEM_E_STATE for a mesh that is not finalized or has no
+ * device context. */
 pfem_status pfem_batch_create(pfem_ctx* ctx, int32_t n, pfem_mesh* const* meshes,
                               pfem_batch** out);
 void pfem_batch_destroy(pfem_batch* b);
-/* offsets: host, n+1 int64 entries. */
+/* offsets: host, n+1 int64 entries (offsets[n] = total DOFs). */
 pfem_status pfem_batch_offsets(const pfem_batch* b, int64_t* offsets);
-/* energies_dev: device, n float64 (one energy per mesh). */
+/* Per-mesh total potential Pi_i(u_i) (the pretraining loss of each sample).
+ * u: device, concatenated, float64 or float32 per prec; energies_dev:
+ * device, n float64.  An element with J <= 0 makes its mesh's energy +inf. */
 pfem_status pfem_batch_energy(pfem_batch* b, int prec, const void* u,
                               double* energies_dev);
+/* g = dPi/du = f_int(u) - f_ext per mesh (the loss gradient).  u, g: device,
+ * concatenated, prec's type; mask as for pfem_force. */
 pfem_status pfem_batch_force(pfem_batch* b, int prec, int mask, const void* u,
                              void* g);
+/* y = K_T(u) v per mesh (K v for linear meshes).  u, v, y: device,
+ * concatenated, prec's type, y must not alias u or v; mask as for
+ * pfem_hvp. */
 pfem_status pfem_batch_hvp(pfem_batch* b, int prec, int mask, const void* u,
                            const void* v, void* y);
 

@@ -597,7 +597,7 @@ pfem_status pfem_batch_force(pfem_batch* b, int prec, int mask, const void* u, v
 pfem_status pfem_batch_hvp(pfem_batch* b, int prec, int mask, const void* u, const void* v,
                            void* y) {
   PFEM_TRY_BEGIN
-  require(v != nullptr, PFEM_E_INVALID_ARG, "v is NULL");
+  require(b != nullptr && v != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
   for (pfem_mesh* m : b->meshes)
     if (m->nonlinear) require(u != nullptr, PFEM_E_INVALID_ARG, "u is NULL");
   batch_elem(b, prec, mask, OP_APPLY, u, v, y);

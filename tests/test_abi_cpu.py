@@ -258,6 +258,47 @@ def test_every_entry_point_rejects_null_arguments():
         else:
             assert st == L.PFEM_E_INVALID_ARG, (name, st)
             assert L.pfem_last_error(), name
+    # a NULL handle is caught before any other argument is looked at: the
+    # other pointers point at valid host memory and the counts are 1
+    buf = C.create_string_buffer(1 << 20)
+    first_not_handle = {"pfem_ctx_create", "pfem_mesh_create", "pfem_last_error",
+                        "pfem_version", "pfem_solve_opts_default"}
+    for name, (res, args) in L.PROTOTYPES.items():
+        if name in first_not_handle or res is None:
+            continue
+        vals = [None] + [1 if a in ints else C.cast(buf, a) for a in args[1:]]
+        st = getattr(lib, name)(*vals)
+        assert st == L.PFEM_E_INVALID_ARG, (name, st)
+
+
+def test_mesh_setters_reject_bad_arguments():
+    L = _lib()
+    lib = L.load()
+    coords = np.array([[0, 0], [1, 0], [0, 1], [1, 1]], dtype=np.float64)
+    conn = np.array([[0, 1, 2], [1, 3, 2]], dtype=np.int32)
+    cp, kp = coords.ctypes.data, conn.ctypes.data
+    other = C.c_void_p()
+    E = L.PFEM_E_INVALID_ARG
+    assert lib.pfem_mesh_create(None, 2, 4, None, 2, kp, C.byref(other)) == E
+    assert lib.pfem_mesh_create(None, 2, 4, cp, 2, None, C.byref(other)) == E
+    assert lib.pfem_mesh_create(None, 4, 4, cp, 2, kp, C.byref(other)) == E
+    assert lib.pfem_mesh_create(None, 2, -1, cp, 2, kp, C.byref(other)) == L.PFEM_E_INVALID_MESH
+    h = C.c_void_p()
+    assert lib.pfem_mesh_create(None, 2, 4, cp, 2, kp, C.byref(h)) == 0
+    try:
+        p = np.ones(2)
+        assert lib.pfem_mesh_set_material(h, L.PFEM_LIN_PLANE_STRAIN, 0, None, None) == E
+        assert lib.pfem_mesh_set_material(h, L.PFEM_LIN_PLANE_STRAIN, 0, p.ctypes.data, None) == E
+        assert lib.pfem_mesh_set_material(h, 9, 0, p.ctypes.data, p.ctypes.data) == E
+        assert lib.pfem_mesh_set_material(h, L.PFEM_LIN_PLANE_STRAIN, 5,
+                                          p.ctypes.data, p.ctypes.data) == E
+        assert lib.pfem_mesh_set_dirichlet(h, 3, None, None, None) == E
+        assert lib.pfem_mesh_set_dirichlet(h, -3, None, None, None) == E
+        assert lib.pfem_mesh_set_neumann(h, 3, None, None) == E
+        assert lib.pfem_mesh_finalize(h, 0) == L.PFEM_E_STATE      # no material yet
+        assert lib.pfem_mesh_finalize(h, -5) == E
+    finally:
+        lib.pfem_mesh_destroy(h)
 
 
 def test_host_only_mesh_calls():
