@@ -281,13 +281,16 @@ pfem_status pfem_batch_hvp(pfem_batch* b, int prec, int mask, const void* u,
  *          FP64 mode. */
 enum { PFEM_KRYLOV_AUTO = 0, PFEM_KRYLOV_CLASSIC = 1, PFEM_KRYLOV_FUSED = 2 };
 
+/* Options of a solve.  pfem_solve and pfem_server_submit return
+ * PFEM_E_INVALID_ARG for a tol that is not finite and > 0, an unknown prec
+ * or krylov, or an inner_rtol outside {0} U (0, 0.5]. */
 typedef struct {
   double tol;           /* relative residual target |r_f| / |r_f(lifted)| (App. B) */
   double tol_fine;      /* skip iterating if the guess is already below (Sec. 'Warm-start'); 0 = off */
   int32_t max_iter;     /* cap on K.v products in all Krylov loops of the solve;
-                           0 = 10 * n_free + 1000 * load steps (1 if linear) */
-  int32_t n_load_steps; /* Neo-Hookean: load steps N_f (warm start jumps to N_f) */
-  int32_t max_newton;   /* per load step; 0 = 50 */
+                           <= 0: 10 * n_free + 1000 * load steps (1 if linear) */
+  int32_t n_load_steps; /* Neo-Hookean: load steps N_f (warm start jumps to N_f); < 1 means 1 */
+  int32_t max_newton;   /* per load step; <= 0 means 50 */
   int32_t prec;         /* PFEM_FP64 or PFEM_FP32 (FP32 Krylov, FP64 outer residual) */
   int32_t record_history;
   double inner_rtol;    /* FP32 mode: residual reduction per refinement sweep;

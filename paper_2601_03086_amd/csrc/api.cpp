@@ -623,13 +623,11 @@ pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
                        int ptr_is_device, double* history, int64_t history_cap,
                        pfem_solve_report* rep) {
   PFEM_TRY_BEGIN
-  need_device(m);
-  require(o != nullptr && u_out != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
-  require(o->tol > 0 && std::isfinite(o->tol), PFEM_E_INVALID_ARG, "tol must be > 0");
-  require(o->prec == PFEM_FP64 || o->prec == PFEM_FP32, PFEM_E_INVALID_ARG, "bad precision");
+  require(m != nullptr && o != nullptr && u_out != nullptr, PFEM_E_INVALID_ARG,
+          "NULL argument");
+  check_solve_opts(*o);
   require(history_cap >= 0, PFEM_E_INVALID_ARG, "history_cap < 0");
-  require(o->krylov >= PFEM_KRYLOV_AUTO && o->krylov <= PFEM_KRYLOV_FUSED,
-          PFEM_E_INVALID_ARG, "bad krylov formulation");
+  need_device(m);
   Ctx* ctx = m->ctx;
   const int64_t nd = m->n_dof();
   const int64_t hcap = (o->record_history && history) ? history_cap : 0;

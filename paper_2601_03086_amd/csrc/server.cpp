@@ -293,10 +293,7 @@ pfem_status pfem_server_submit(pfem_server* s, pfem_mesh* m, const double* u0,
   try {
     require(s != nullptr && m != nullptr && o != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
     require(m->finalized, PFEM_E_STATE, "mesh not finalized");
-    require(o->tol > 0, PFEM_E_INVALID_ARG, "tol must be > 0");
-    require(o->prec == PFEM_FP64 || o->prec == PFEM_FP32, PFEM_E_INVALID_ARG, "bad precision");
-    require(o->krylov >= PFEM_KRYLOV_AUTO && o->krylov <= PFEM_KRYLOV_FUSED,
-            PFEM_E_INVALID_ARG, "bad krylov formulation");
+    check_solve_opts(*o);
     Req* r = new Req();
     r->id = req_id;
     r->m = m;

@@ -58,6 +58,15 @@ void SolveState::release() {
   bytes = 0;
 }
 
+void check_solve_opts(const pfem_solve_opts& o) {
+  require(o.tol > 0 && std::isfinite(o.tol), PFEM_E_INVALID_ARG, "tol must be finite and > 0");
+  require(o.prec == PFEM_FP64 || o.prec == PFEM_FP32, PFEM_E_INVALID_ARG, "bad precision");
+  require(o.krylov >= PFEM_KRYLOV_AUTO && o.krylov <= PFEM_KRYLOV_FUSED, PFEM_E_INVALID_ARG,
+          "bad krylov formulation");
+  require(o.inner_rtol >= 0.0 && o.inner_rtol <= 0.5, PFEM_E_INVALID_ARG,
+          "inner_rtol must be 0 (automatic) or in (0, 0.5]");
+}
+
 void slot_alloc(SlotRun* s, pfem_mesh* m, const pfem_solve_opts& o, int64_t hist_cap) {
   s->m = m;
   s->o = o;

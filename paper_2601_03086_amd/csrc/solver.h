@@ -64,6 +64,13 @@ void slot_begin(Ctx* ctx, SlotRun* s, const double* u0_internal_dev);
 int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches);
 
 // Allocates device and pinned state for a slot on mesh m.
+// Argument checks of a solve's options (pfem_solve, pfem_server_submit):
+// PFEM_E_INVALID_ARG for a tolerance that is not finite and positive, an
+// unknown precision or Krylov formulation, or an inner reduction outside
+// {0} U (0, 0.5].  A sweep whose inner target is not below its starting
+// residual would end at iteration 0 and leave x unchanged, forever; 0.5
+// keeps a factor 2 above the float32 rounding of that starting residual.
+void check_solve_opts(const pfem_solve_opts& o);
 void slot_alloc(SlotRun* s, pfem_mesh* m, const pfem_solve_opts& o, int64_t hist_cap);
 void slot_free(SlotRun* s);
 

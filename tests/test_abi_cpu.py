@@ -312,7 +312,7 @@ def test_host_only_mesh_calls():
     m = _host_mesh(prob)
     ints = (C.c_int, L._I32, L._I64)
     for name in ("pfem_hvp", "pfem_apply_K", "pfem_force", "pfem_energy",
-                 "pfem_diag", "pfem_permute", "pfem_solve"):
+                 "pfem_diag", "pfem_permute"):
         args = L.PROTOTYPES[name][1]
         st = getattr(lib, name)(m.h, *[0 if a in ints else None for a in args[1:]])
         assert st == L.PFEM_E_STATE, (name, st)
@@ -329,3 +329,29 @@ def test_host_only_mesh_calls():
     assert lib.pfem_mesh_query_int(m.h, 99, None, 0, None) == L.PFEM_E_INVALID_ARG
     assert lib.pfem_mesh_query_int(m.h, L.PFEM_Q_PERM, full.ctypes.data, -1, None) \
         == L.PFEM_E_INVALID_ARG
+
+
+def test_solve_options_checked_before_the_device():
+    """pfem_solve rejects bad options with PFEM_E_INVALID_ARG before it
+    looks for a device; good options on a host-only mesh then give
+    PFEM_E_STATE.  An inner reduction of 1 or more would end every
+    refinement sweep at iteration 0 and never finish."""
+    L = _lib()
+    lib = L.load()
+    m = _host_mesh(synth.unit_square_c1(n=5))
+    u = np.zeros(m.n_dof)
+
+    def solve(**kw):
+        o = L.pfem_solve_opts()
+        lib.pfem_solve_opts_default(C.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return lib.pfem_solve(m.h, None, C.byref(o), u.ctypes.data, 0, None, 0, None)
+
+    assert solve() == L.PFEM_E_STATE
+    assert solve(inner_rtol=0.5) == L.PFEM_E_STATE
+    for bad in (dict(tol=0.0), dict(tol=-1.0), dict(tol=float("nan")), dict(tol=float("inf")),
+                dict(prec=7), dict(krylov=9), dict(inner_rtol=0.7), dict(inner_rtol=1.0),
+                dict(inner_rtol=-1e-3), dict(inner_rtol=float("nan"))):
+        assert solve(**bad) == L.PFEM_E_INVALID_ARG, bad
+        assert L.pfem_last_error(), bad
