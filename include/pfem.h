@@ -155,7 +155,11 @@ pfem_status pfem_mesh_create(pfem_ctx* ctx, int dim, int64_t n_nodes,
 /* Per-element material.  model: PFEM_LIN_* / PFEM_NH_*.  param_kind:
  * PFEM_PARAM_E_NU (p0 = Young's modulus, p1 = Poisson ratio; Lame
  * parameters per Sec. 'Nonlinear hyperelasticity') or PFEM_PARAM_LAME
- * (p0 = mu, p1 = lambda).  p0, p1: host, n_elems float64 each. */
+ * (p0 = mu, p1 = lambda).  p0, p1: host, n_elems float64 each.
+ * PFEM_E_INVALID_ARG (and no material kept) unless every element has
+ * mu > 0 and dim * lambda + 2 mu > 0 (lambda* in plane stress): the
+ * stiffness is then SPD.  Non-finite parameters (nu = 0.5, nu = -1) are
+ * reported by pfem_mesh_finalize.  PFEM_E_STATE after finalize. */
 pfem_status pfem_mesh_set_material(pfem_mesh* m, int model, int param_kind,
                                    const double* p0, const double* p1);
 /* Dirichlet set: n triples (node, comp, final value); host arrays.  Values

@@ -171,12 +171,23 @@ pfem_status pfem_mesh_set_material(pfem_mesh* m, int model, int param_kind, cons
           "bad param_kind");
   const bool three = model == PFEM_LIN_3D || model == PFEM_NH_3D;
   require(three == (m->dim == 3), PFEM_E_INVALID_ARG, "model does not match mesh dimension");
+  std::vector<double> mu(m->n_elems), lam(m->n_elems);
+  for (int64_t e = 0; e < m->n_elems; ++e) {
+    lame_from_params(model, param_kind, p0[e], p1[e], &mu[e], &lam[e]);
+    // the isotropic law (and the Neo-Hookean one at J = 1) is positive
+    // definite iff mu > 0 and the bulk modulus lambda + 2 mu / dim is
+    // positive (lambda* in plane stress); otherwise K is not SPD and the
+    // solves break down.  Non-finite values are caught at finalize.
+    if (std::isfinite(mu[e]) && std::isfinite(lam[e]) &&
+        !(mu[e] > 0.0 && m->dim * lam[e] + 2.0 * mu[e] > 0.0))
+      throw Error{PFEM_E_INVALID_ARG, "element " + std::to_string(e) +
+                                          ": material not positive definite (needs mu > 0 "
+                                          "and dim * lambda + 2 mu > 0)"};
+  }
   m->model = model;
   m->nonlinear = model == PFEM_NH_PLANE_STRAIN || model == PFEM_NH_3D;
-  m->mu.resize(m->n_elems);
-  m->lam.resize(m->n_elems);
-  for (int64_t e = 0; e < m->n_elems; ++e)
-    lame_from_params(model, param_kind, p0[e], p1[e], &m->mu[e], &m->lam[e]);
+  m->mu.swap(mu);
+  m->lam.swap(lam);
   PFEM_TRY_END
 }
 

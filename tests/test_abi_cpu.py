@@ -355,3 +355,34 @@ def test_solve_options_checked_before_the_device():
                 dict(inner_rtol=-1e-3), dict(inner_rtol=float("nan"))):
         assert solve(**bad) == L.PFEM_E_INVALID_ARG, bad
         assert L.pfem_last_error(), bad
+
+
+@pytest.mark.parametrize("dim,model,kind,p0,p1,ok", [
+    (2, "lin_plane_strain", "E_nu", 1.0, 0.3, True),
+    (2, "lin_plane_strain", "E_nu", 0.0, 0.3, False),        # mu = 0
+    (2, "lin_plane_strain", "E_nu", -2.0, 0.3, False),       # mu < 0
+    (2, "nh_plane_strain", "lame", 1.0, -0.9, True),         # lambda + mu > 0
+    (2, "nh_plane_strain", "lame", 1.0, -1.1, False),        # lambda + mu < 0
+    (2, "lin_plane_stress", "E_nu", 1.0, 0.7, True),         # lambda* + mu > 0
+    (3, "lin_3d", "lame", 1.0, -0.6, True),                  # 3 lambda + 2 mu > 0
+    (3, "nh_3d", "lame", 1.0, -0.7, False),                  # 3 lambda + 2 mu < 0
+    (3, "lin_3d", "lame", 0.0, 1.0, False),
+])
+def test_material_must_be_positive_definite(dim, model, kind, p0, p1, ok):
+    """Element stiffness is SPD iff mu > 0 and dim * lambda + 2 mu > 0; other
+    materials are refused when set, and the mesh keeps no material."""
+    L = _lib()
+    from paper_2601_03086_amd import core
+    if dim == 2:
+        coords = np.array([[0, 0], [1, 0], [0, 1], [1, 1]], dtype=np.float64)
+        conn = np.array([[0, 1, 2], [1, 3, 2]], dtype=np.int32)
+    else:
+        coords = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=np.float64)
+        conn = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    if ok:
+        core.Mesh(None, dim, coords, conn, model, kind, p0, p1)
+        return
+    with pytest.raises(L.PfemError) as ei:
+        core.Mesh(None, dim, coords, conn, model, kind, p0, p1)
+    assert ei.value.status == L.PFEM_E_INVALID_ARG
+    assert "positive definite" in str(ei.value)
