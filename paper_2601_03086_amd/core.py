@@ -195,6 +195,26 @@ class Mesh:
             raise ValueError(f"vector has {t.numel()} entries, mesh has {self.n_dof} DOFs")
         return t.contiguous()
 
+    def _out(self, out, prec):
+        """Output vector: a new one, or the caller's, which must be a
+        contiguous tensor of n_dof entries of prec's dtype on the context's
+        device (the kernels write every entry)."""
+        if out is None:
+            return self.new_vec(prec)
+        if not (isinstance(out, torch.Tensor) and out.device == self.ctx.device
+                and out.dtype == _dtype(prec) and out.numel() == self.n_dof
+                and out.is_contiguous()):
+            raise ValueError(f"out must be a contiguous {_dtype(prec)} tensor of "
+                             f"{self.n_dof} entries on {self.ctx.device}")
+        return out
+
+    def _host(self, x):
+        """Host float64 vector of n_dof entries (the library copies n_dof)."""
+        a = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+        if a.size != self.n_dof:
+            raise ValueError(f"vector has {a.size} entries, mesh has {self.n_dof} DOFs")
+        return a
+
     @_on_stream
     def permute(self, x, to_internal=True, prec="fp64"):
         x = self._vec(x, prec)
@@ -206,7 +226,7 @@ class Mesh:
     def hvp(self, u, v, prec="fp32", layout="user", scatter="owner", mask=0, out=None):
         v = self._vec(v, prec)
         u = self._vec(u, prec) if u is not None else None
-        y = torch.empty_like(v) if out is None else out
+        y = self._out(out, prec)
         check(L.pfem_hvp(self.h, PREC[prec], LAYOUT[layout], SCATTER[scatter], mask,
                          _ptr(u), _ptr(v), _ptr(y)))
         return y
@@ -214,7 +234,7 @@ class Mesh:
     @_on_stream
     def apply_K(self, v, prec="fp32", layout="user", scatter="owner", mask=0, out=None):
         v = self._vec(v, prec)
-        y = torch.empty_like(v) if out is None else out
+        y = self._out(out, prec)
         check(L.pfem_apply_K(self.h, PREC[prec], LAYOUT[layout], SCATTER[scatter], mask,
                              _ptr(v), _ptr(y)))
         return y
@@ -222,7 +242,7 @@ class Mesh:
     @_on_stream
     def force(self, u, prec="fp64", layout="user", mask=0, out=None):
         u = self._vec(u, prec)
-        y = torch.empty_like(u) if out is None else out
+        y = self._out(out, prec)
         check(L.pfem_force(self.h, PREC[prec], LAYOUT[layout], mask, _ptr(u), _ptr(y)))
         return y
 
@@ -265,12 +285,11 @@ class Mesh:
         hist = np.zeros(max(history_cap, 1), dtype=np.float64)
         if device_io:
             u0t = self._vec(u0, "fp64") if u0 is not None else None
-            u = self.new_vec("fp64") if out is None else out
+            u = self._out(out, "fp64")
             st = L.pfem_solve(self.h, _ptr(u0t), C.byref(o), _ptr(u), 1, _ptr(hist),
                               history_cap, C.byref(rep))
         else:
-            u0a = (np.ascontiguousarray(u0, dtype=np.float64)
-                   if u0 is not None else None)
+            u0a = self._host(u0) if u0 is not None else None
             u = np.zeros(self.n_dof, dtype=np.float64)
             st = L.pfem_solve(self.h, _ptr(u0a), C.byref(o), _ptr(u), 0, _ptr(hist),
                               history_cap, C.byref(rep))
@@ -308,26 +327,33 @@ class Batch:
 
     __del__ = close
 
+    def _vec(self, x, prec):
+        t = torch.as_tensor(x, device=self.ctx.device, dtype=_dtype(prec))
+        if t.numel() != self.n_dof:
+            raise ValueError(f"vector has {t.numel()} entries, batch has {self.n_dof} DOFs")
+        return t.contiguous()
+
     @_on_stream
     def energy(self, u, prec="fp32"):
-        u = u.contiguous()
+        u = self._vec(u, prec)
         e = torch.empty(len(self.meshes), dtype=torch.float64, device=self.ctx.device)
         check(L.pfem_batch_energy(self.h, PREC[prec], _ptr(u), _ptr(e)))
         return e
 
     @_on_stream
     def force(self, u, prec="fp32", mask=0):
-        u = u.contiguous()
+        u = self._vec(u, prec)
         g = torch.empty_like(u)
         check(L.pfem_batch_force(self.h, PREC[prec], mask, _ptr(u), _ptr(g)))
         return g
 
     @_on_stream
     def hvp(self, u, v, prec="fp32", mask=0):
-        v = v.contiguous()
+        """u may be None when every mesh of the batch is linear."""
+        v = self._vec(v, prec)
+        u = self._vec(u, prec) if u is not None else None
         y = torch.empty_like(v)
-        check(L.pfem_batch_hvp(self.h, PREC[prec], mask, _ptr(u.contiguous()), _ptr(v),
-                               _ptr(y)))
+        check(L.pfem_batch_hvp(self.h, PREC[prec], mask, _ptr(u), _ptr(v), _ptr(y)))
         return y
 
 
@@ -344,7 +370,7 @@ class Server:
 
     def submit(self, req_id, mesh, u0=None, **kw):
         o = Mesh.opts(**kw)
-        u0a = np.ascontiguousarray(u0, dtype=np.float64) if u0 is not None else None
+        u0a = mesh._host(u0) if u0 is not None else None
         check(L.pfem_server_submit(self.h, mesh.h, _ptr(u0a), C.byref(o), int(req_id)))
         self._meshes[req_id] = mesh
 
@@ -355,12 +381,17 @@ class Server:
         return ids[:n.value].tolist()
 
     def result(self, req_id):
-        mesh = self._meshes.pop(req_id)
+        """Collect a finished request (raises PfemError with PFEM_E_STATE
+        while it is queued or live; the mesh stays referenced until then)."""
+        mesh = self._meshes[req_id]
         u = np.zeros(mesh.n_dof, dtype=np.float64)
         rep = L.pfem_solve_report()
         ts, ta, td = C.c_double(), C.c_double(), C.c_double()
         st = L.pfem_server_result(self.h, int(req_id), _ptr(u), C.byref(rep), C.byref(ts),
                                   C.byref(ta), C.byref(td))
+        if st == L.PFEM_E_STATE:
+            check(st)
+        del self._meshes[req_id]     # released by the library
         r = rep.as_dict()
         r["status_name"] = L.STATUS_NAMES.get(rep.status, rep.status)
         r.update(t_submit=ts.value, t_admit=ta.value, t_done=td.value, call_status=st)

@@ -386,3 +386,33 @@ def test_material_must_be_positive_definite(dim, model, kind, p0, p1, ok):
         core.Mesh(None, dim, coords, conn, model, kind, p0, p1)
     assert ei.value.status == L.PFEM_E_INVALID_ARG
     assert "positive definite" in str(ei.value)
+
+
+def test_binding_checks_vector_sizes():
+    """The binding refuses vectors the library would read or write past:
+    output tensors of the wrong size, dtype, device or layout, and host
+    vectors of the wrong length (the library copies n_dof entries)."""
+    import types
+
+    import torch
+    from paper_2601_03086_amd import core
+    m = _host_mesh(synth.unit_square_c1(n=5))
+    m.ctx = types.SimpleNamespace(device=torch.device("cpu"))   # stand-in device
+    try:
+        n = m.n_dof
+        ok = torch.empty(n, dtype=torch.float32)
+        assert m._out(ok, "fp32") is ok
+        assert m._out(None, "fp64").shape == (n,)
+        for bad in (torch.empty(n - 1, dtype=torch.float32),
+                    torch.empty(n, dtype=torch.float64),
+                    torch.empty(2 * n, dtype=torch.float32)[::2],
+                    np.empty(n, np.float32)):
+            with pytest.raises(ValueError):
+                m._out(bad, "fp32")
+        assert m._host(np.arange(n)).dtype == np.float64
+        with pytest.raises(ValueError):
+            m._host(np.zeros(n - 1))
+        with pytest.raises(ValueError):
+            m._vec(torch.zeros(n + 2), "fp32")
+    finally:
+        m.ctx = None
