@@ -416,3 +416,24 @@ def test_binding_checks_vector_sizes():
             m._vec(torch.zeros(n + 2), "fp32")
     finally:
         m.ctx = None
+
+
+def test_header_is_c_and_host_calls_work_from_c(tmp_path):
+    """include/pfem.h compiles as C99 with warnings as errors, and a C
+    program linked against the library drives a host-only mesh."""
+    import shutil
+    import subprocess
+    L = _lib()
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    libdir = os.path.dirname(L.LIB_PATH)
+    exe = str(tmp_path / "c_abi_host")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror",
+                        "-I" + os.path.join(ROOT, "include"),
+                        os.path.join(ROOT, "tests", "c_abi_host.c"),
+                        "-L" + libdir, "-lpfem", "-Wl,-rpath," + libdir, "-o", exe],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "c abi ok" in r.stdout, r.stdout + r.stderr
