@@ -526,3 +526,31 @@ def _jp_colour(sconn, n_nodes):
 def test_free_dof_map_hand_example():
     fm = prep.free_dof_map(3, 2, [0, 2], [1, 0])
     assert fm.tolist() == [0, -1, 1, 2, -1, 3]
+
+
+# ------------------------------------------ unique equilibrium along a path
+@pytest.mark.parametrize("model,d", [("nh_plane_strain", 2), ("nh_3d", 3)])
+def test_newton_path_tangent_stays_positive_definite(model, d):
+    """Along the load steps of a stretched, clamped Neo-Hookean block the
+    reduced tangent K_T,ff(u_n) at every converged state is SPD: the
+    equilibrium the Newton path follows is an isolated energy minimum
+    (strict convexity along the path), so both solvers reach the same
+    state."""
+    coords, conn = mk.patch_2d(6, 3) if d == 2 else mk.patch_3d(3, 3)
+    top = coords[:, d - 1].max()
+    bot = np.nonzero(coords[:, d - 1] == 0)[0]
+    up = np.nonzero(coords[:, d - 1] == top)[0]
+    dn = np.concatenate([np.repeat(bot, d), up])
+    dc = np.concatenate([np.tile(np.arange(d), bot.size), np.full(up.size, d - 1)])
+    dv = np.concatenate([np.zeros(d * bot.size), np.full(up.size, 0.3 * top)])
+    prob = mk.make_problem(model, coords, conn, E=1.0, nu=0.3, dir_nodes=dn,
+                           dir_comps=dc, dir_values=dv, n_load_steps=4)
+    u, rep = solve.newton(prob, tol=1e-10)
+    assert rep["status"] == 0 and len(rep["steps"]) == 4
+    m = fe.Model(prob)
+    fr = m.free_dofs
+    for st in rep["steps"]:
+        KT = m.assemble(st["u"])[fr][:, fr].toarray()
+        assert np.abs(KT - KT.T).max() <= 1e-12 * np.abs(KT).max()
+        ev = np.linalg.eigvalsh(0.5 * (KT + KT.T))
+        assert ev.min() > 1e-6 * ev.max(), st["load_step"]
