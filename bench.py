@@ -88,9 +88,15 @@ def alg_bytes_fused(n_elems, n_nodes, dim, s=4, s_m=4):
 
 
 # --------------------------------------------------------------- CPU baseline
+# The oracle's whole warm solve is the CPU sample (about 4,100 K.v products
+# to 1e-8); the cap only bounds a run that would not converge.
+MAX_KV = 8000
+
+
 def cpu_baseline_worker():
     """The FP64 oracle timed on host cores: Jacobi-PCG (scipy CSR SpMV) from
-    the same warm start to 1e-8, capped at 3000 K.v products."""
+    the same warm start to 1e-8, the complete solve (at most MAX_KV K.v
+    products)."""
     import numpy as np
     import synth
     from oracle import fe, solve as osolve
@@ -103,7 +109,7 @@ def cpu_baseline_worker():
     ustar[m.free_dofs] = uf
     u0 = synth.warm_start_guess(ustar, prob.coords, prob.dir_nodes, seed=3002)
     t0 = time.perf_counter()
-    x, hist, kv, st = osolve.pcg(Kff, Ff, u0[m.free_dofs], 1e-8, max_iter=3000)
+    x, hist, kv, st = osolve.pcg(Kff, Ff, u0[m.free_dofs], 1e-8, max_iter=MAX_KV)
     t = time.perf_counter() - t0
     print(json.dumps({"seconds": t, "kv": kv, "n_dof": prob.n_dof, "status": st,
                       "final_rel": hist[-1], "threads": 1}))
@@ -122,9 +128,9 @@ def cpu_baseline():
     return {"value": d["kv"] * d["n_dof"] / d["seconds"] / 1e9, "unit": "GDOF/s",
             "cores": d["threads"], "kind": "oracle",
             "sample": (f"oracle FP64 Jacobi-PCG (scipy CSR SpMV) on the same plate, "
-                       f"same warm start, to 1e-8: {d['kv']} K.v products in "
-                       f"{d['seconds']:.1f} s (status {d['status']}, final rel "
-                       f"{d['final_rel']:.1e}); 1 thread")}
+                       f"same warm start, the whole solve to 1e-8: {d['kv']} K.v "
+                       f"products in {d['seconds']:.1f} s (status {d['status']}, "
+                       f"final rel {d['final_rel']:.1e}); 1 thread")}
 
 
 # ------------------------------------------------------------------ traffic
