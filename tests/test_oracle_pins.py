@@ -119,6 +119,30 @@ def test_external_force_totals():
     assert np.allclose(f[corners, 0], 0.5 * 0.01 / 32, rtol=1e-14)
 
 
+def test_external_force_3d_resultant_and_moment():
+    """Triangle facets of a rotated unit cube's face under a uniform
+    traction t: the nodal loads sum to t * area (area 1) and their first
+    moment sum_a f_a x_a^T equals t (area * centroid)^T, the exact integral
+    of t x^T over the face.  An unequal split between a facet's nodes or a
+    wrong facet area changes one of the two."""
+    coords, conn = mk.patch_3d(3, 7)
+    top = np.nonzero(coords[:, 2] == 1.0)[0]
+    faces = mk.boundary_faces(conn)
+    faces = faces[np.all(np.isin(faces, top), axis=1)]
+    assert faces.shape[0] == 2 * 3 * 3
+    th = 0.7
+    R = np.array([[np.cos(th), 0, np.sin(th)], [0, 1, 0], [-np.sin(th), 0, np.cos(th)]])
+    R = R @ np.array([[1, 0, 0], [0, np.cos(0.4), -np.sin(0.4)], [0, np.sin(0.4), np.cos(0.4)]])
+    x = coords @ R.T
+    t = np.array([0.3, -0.2, 0.5])
+    prob = mk.make_problem("lin_3d", x, conn, facets=faces,
+                           traction=np.tile(t, (faces.shape[0], 1)))
+    f = fe.external_force(prob).reshape(-1, 3)
+    assert np.allclose(f.sum(0), t, rtol=0, atol=1e-15)
+    centroid = R @ np.array([0.5, 0.5, 1.0])
+    assert np.allclose(f.T @ x, np.outer(t, centroid), rtol=0, atol=1e-14)
+
+
 # ------------------------------------------------------- rigid body modes
 def _rigid_modes(coords):
     d = coords.shape[1]
