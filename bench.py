@@ -125,8 +125,18 @@ def cpu_baseline():
     if r.returncode != 0 or not line:
         return {"error": (r.stderr or r.stdout)[-400:]}
     d = json.loads(line[-1])
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": d["kv"] * d["n_dof"] / d["seconds"] / 1e9, "unit": "GDOF/s",
             "cores": d["threads"], "kind": "oracle",
+            "host": {"cpu_model": model, "affinity_cpus": len(os.sched_getaffinity(0)),
+                     "threads_env": {k: env[k] for k in ("OMP_NUM_THREADS",
+                                                         "OPENBLAS_NUM_THREADS",
+                                                         "MKL_NUM_THREADS")}},
             "sample": (f"oracle FP64 Jacobi-PCG (scipy CSR SpMV) on the same plate, "
                        f"same warm start, the whole solve to 1e-8: {d['kv']} K.v "
                        f"products in {d['seconds']:.1f} s (status {d['status']}, "
