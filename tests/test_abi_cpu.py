@@ -448,3 +448,40 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=300, cwd=ROOT)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """With libpfem.so absent the package raises on load: there is no CPU
+    or PyTorch fallback for any step of the path."""
+    import subprocess
+    import sys
+    code = ("import paper_2601_03086_amd._lib as L\n"
+            f"L.LIB_PATH = {str(tmp_path / 'absent.so')!r}\n"
+            "L._lib = None\n"
+            "try:\n"
+            "    L.load()\n"
+            "except ImportError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    print('loaded')\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       timeout=300, cwd=ROOT)
+    assert "raised:" in r.stdout and "absent.so" in r.stdout, r.stdout + r.stderr
+
+
+def test_oracle_and_library_share_no_code():
+    """The package (Python and C++/HIP sources) never names the oracle, the
+    oracle never names the package, and the shared input generators import
+    neither."""
+    import glob
+    import re
+    pkg = os.path.join(ROOT, "paper_2601_03086_amd")
+    for f in glob.glob(os.path.join(pkg, "*.py")) + glob.glob(os.path.join(pkg, "csrc", "*")):
+        txt = open(f, errors="replace").read()
+        assert not re.search(r"\boracle\b", txt), f
+    for f in glob.glob(os.path.join(ROOT, "oracle", "*.py")):
+        txt = open(f).read()
+        assert "paper_2601_03086_amd" not in txt and "libpfem" not in txt, f
+    for f in glob.glob(os.path.join(ROOT, "synth", "*.py")):
+        txt = open(f).read()
+        assert not re.search(r"^\s*(from|import)\s+(oracle|paper_2601_03086_amd)", txt, re.M), f
