@@ -326,7 +326,14 @@ void pfem_solve_opts_default(pfem_solve_opts* o);
  * final load step).  u0/u_out are device pointers if ptr_is_device else
  * host; caller numbering.  Dirichlet DOFs of u_out hold the prescribed
  * values.  history: host, history_cap float64 relative residuals (may be
- * NULL).  rep: host (may be NULL). */
+ * NULL; entry 0 is the initial guess's, then one per Krylov iteration of
+ * every inner loop in order, truncated to history_cap).  rep: host (may be
+ * NULL).  Returns when the solve has ended (the context stream is
+ * synchronised).  Status: PFEM_OK, PFEM_SKIPPED_FINE, PFEM_NOT_CONVERGED,
+ * or a solver failure (PFEM_E_BREAKDOWN, PFEM_E_INVERTED,
+ * PFEM_E_LINESEARCH) -- all of these still fill u_out (the last iterate),
+ * history and rep; argument, state and device errors leave the outputs
+ * unspecified. */
 pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
                        double* u_out, int ptr_is_device, double* history,
                        int64_t history_cap, pfem_solve_report* rep);
