@@ -117,6 +117,10 @@ typedef struct pfem_server pfem_server;
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
  * run on, or NULL for a library-owned stream (default priority). */
 pfem_status pfem_ctx_create(int device, void* hip_stream, pfem_ctx** out);
+/* Release the handle (NULL is a no-op).  Meshes, batches and servers made
+ * on it keep the device context alive; its stream is synchronised and its
+ * resources freed when the last of them is destroyed.  A caller-supplied
+ * stream is never destroyed. */
 void pfem_ctx_destroy(pfem_ctx* ctx);
 /* Message of the last error on this thread ("" if none). */
 const char* pfem_last_error(void);
@@ -135,8 +139,12 @@ pfem_status pfem_ctx_set_timing(pfem_ctx* ctx, int family_mask);
 /* Time only every `every`-th launch of each per-launch timed family
  * (default 1), so that the event pairs barely perturb a long sequence. */
 pfem_status pfem_ctx_set_timing_sample(pfem_ctx* ctx, int every);
+/* Launches timed and their summed duration (ms) for one family since the
+ * last reset; launches, total_ms: host, may be NULL.  Synchronises the
+ * stream.  PFEM_E_INVALID_ARG for a family outside 0..6. */
 pfem_status pfem_ctx_kernel_time(pfem_ctx* ctx, int family, int64_t* launches,
                                  double* total_ms);
+/* Zero every family's counters (pending timings are collected first). */
 pfem_status pfem_ctx_reset_timing(pfem_ctx* ctx);
 /* Block until all work queued on the context stream has finished. */
 pfem_status pfem_ctx_synchronize(pfem_ctx* ctx);
@@ -201,6 +209,9 @@ typedef struct {
   int64_t solve_bytes_fp32, solve_bytes_fp64;   /* extra device bytes of one solve */
   double f_ext_norm;
 } pfem_mesh_info;
+/* Sizes and preprocessing statistics of a mesh; out: host.  Fields that
+ * preprocessing sets (free DOFs, colours, blocks, bandwidths, device
+ * bytes) are 0 before pfem_mesh_finalize. */
 pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* out);
 /* Copy a preprocessing array (see PFEM_Q_*) into out (host, the first
  * min(cap, length) entries); *n (host) receives the full length.  out may
@@ -208,6 +219,8 @@ pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* out);
  * pfem_mesh_finalize; PFEM_E_INVALID_ARG for an unknown query or cap < 0. */
 pfem_status pfem_mesh_query_int(const pfem_mesh* m, int which, int32_t* out,
                                 int64_t cap, int64_t* n);
+/* Free the mesh and its device arrays (NULL is a no-op).  It must not be in
+ * a live batch or a server request that has not been collected. */
 void pfem_mesh_destroy(pfem_mesh* m);
 
 /* Convert a vector between the caller's and the internal node order.
@@ -253,6 +266,8 @@ pfem_status pfem_diag(pfem_mesh* m, int prec, int layout, const void* u, void* d
  * device context. */
 pfem_status pfem_batch_create(pfem_ctx* ctx, int32_t n, pfem_mesh* const* meshes,
                               pfem_batch** out);
+/* Free the batch's tables after its queued work (NULL is a no-op); the
+ * meshes are not touched. */
 void pfem_batch_destroy(pfem_batch* b);
 /* offsets: host, n+1 int64 entries (offsets[n] = total DOFs). */
 pfem_status pfem_batch_offsets(const pfem_batch* b, int64_t* offsets);
@@ -374,6 +389,9 @@ typedef struct {
   int64_t bytes_in_use, peak_bytes, budget;
   int64_t steps, launches;
 } pfem_server_stats;
+/* Counters of the server (a consistent snapshot; out: host): requests
+ * submitted / completed / live / queued, the most live at once, device
+ * bytes in use, their peak and the budget, worker steps and launches. */
 pfem_status pfem_server_get_stats(pfem_server* s, pfem_server_stats* out);
 /* Stop the worker (live requests are cancelled) and free everything. */
 void pfem_server_destroy(pfem_server* s);
