@@ -117,10 +117,10 @@ typedef struct pfem_server pfem_server;
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
  * run on, or NULL for a library-owned stream (default priority). */
 pfem_status pfem_ctx_create(int device, void* hip_stream, pfem_ctx** out);
-/* Release the handle (NULL is a no-op).  Meshes, batches and servers made
- * on it keep the device context alive; its stream is synchronised and its
- * resources freed when the last of them is destroyed.  A caller-supplied
- * stream is never destroyed. */
+/* Release the handle (NULL is a no-op).  Meshes and batches made on it
+ * keep the device context alive; its stream is synchronised and its
+ * resources freed when the last of them is destroyed (a server runs on a
+ * stream of its own).  A caller-supplied stream is never destroyed. */
 void pfem_ctx_destroy(pfem_ctx* ctx);
 /* Message of the last error on this thread ("" if none). */
 const char* pfem_last_error(void);
