@@ -208,6 +208,8 @@ typedef struct {
   int64_t device_bytes;                     /* mesh arrays resident on the device */
   int64_t solve_bytes_fp32, solve_bytes_fp64;   /* extra device bytes of one solve */
   double f_ext_norm;
+  int32_t band_blocks;                      /* owner blocks per RCM band of the block
+                                               numbering (0 under PFEM_ORDER_RCM) */
 } pfem_mesh_info;
 /* Sizes and preprocessing statistics of a mesh; out: host.  Fields that
  * preprocessing sets (free DOFs, colours, blocks, bandwidths, device

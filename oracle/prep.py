@@ -8,20 +8,17 @@ readings below make "bit-exact" meaningful by removing every tie:
   unvisited node of minimum degree (ties: smallest original id); a dequeued
   node appends its unvisited neighbours sorted by (degree, original id);
   the final order is reversed.  new_id[old] = position in that order.
-* Node blocks (the default numbering; RCM alone is the other choice): the
-  RCM order is cut into bands of k * bn consecutive positions, bn the nodes
-  per owner block, and each band into blocks of bn nodes by recursive
-  coordinate bisection, so that a block is a compact patch instead of a
-  sliver of one RCM level.  With L the number of breadth-first levels of
-  the Cuthill-McKee search (summed over components), N nodes and w the
-  largest integer with w**d <= bn, k = max(1, min(round(w N / (L bn)),
-  floor(32768 / bn))) (halves rounded up): a band is about as many levels
-  thick as a block is wide, and at most 32768 positions long.  A
-  set S of more than bn nodes is split along the axis of largest extent
-  max - min over S (smallest axis on ties), ordered by (coordinate, RCM
-  position): the first bn * floor(ceil(|S| / bn) / 2) nodes go first, each
-  part recursively; a set of at most bn nodes is one block, in RCM order.
-  new_id[old] = position in the concatenated blocks.
+* Node blocks (the default numbering; RCM alone is the other choice): given
+  bn nodes per owner block and k blocks per band -- both performance
+  parameters that the device library chooses and reports, not part of the
+  method -- the RCM order is cut into bands of k * bn consecutive
+  positions and each band into blocks of bn nodes by recursive coordinate
+  bisection, so that a block is a compact patch instead of a sliver of one
+  RCM level.  A set S of more than bn nodes is split along the axis of
+  largest extent max - min over S (smallest axis on ties), ordered by
+  (coordinate, RCM position): the first bn * floor(ceil(|S| / bn) / 2)
+  nodes go first, each part recursively; a set of at most bn nodes is one
+  block, in RCM order.  new_id[old] = position in the concatenated blocks.
 * Element order: sort by (min new id of the element's nodes, the sorted
   tuple of its new ids, original element index).  Node order inside an
   element is kept.
@@ -106,30 +103,6 @@ def rcm(conn, n_nodes):
     return new_id
 
 
-def auto_block_nodes(n_nodes, dim):
-    """Nodes per owner block when the caller leaves it to the library:
-    N/4000 (2D) or N/750 (3D) rounded up to a multiple of 32, at least 224
-    (2D) or 64 (3D), at most 1024."""
-    per, lo = (4000, 224) if dim == 2 else (750, 64)
-    return int(min(1024, max(lo, ((n_nodes // per) + 31) // 32 * 32)))
-
-
-def int_root(bn, dim):
-    """Largest integer w with w**dim <= bn."""
-    w = 1
-    while (w + 1) ** dim <= bn:
-        w += 1
-    return w
-
-
-def band_blocks(n_nodes, n_levels, bn, dim):
-    """Blocks per band, k = max(1, min(round(w N / (L bn)), floor(32768 / bn))),
-    halves up (the cap keeps a band within 32768 positions)."""
-    w = int_root(bn, dim)
-    num = 2 * w * n_nodes + n_levels * bn
-    return max(1, min(num // (2 * n_levels * bn), 32768 // bn))
-
-
 def bisect_blocks(nodes, coords, pos, bn):
     """Recursive coordinate bisection of ``nodes`` into blocks of bn nodes
     (module docstring); returns the nodes in block order."""
@@ -146,14 +119,17 @@ def bisect_blocks(nodes, coords, pos, bn):
                            bisect_blocks(nodes[o[left:]], coords, pos, bn)])
 
 
-def block_numbering(conn, coords, n_nodes, bn):
-    """Node-block numbering (module docstring); new_id (old -> new), int32."""
-    order, n_levels = cuthill_mckee(conn, n_nodes)
+def block_numbering(conn, coords, n_nodes, bn, band_blocks):
+    """Node-block numbering (module docstring) with bn nodes per block and
+    band_blocks blocks per band; new_id (old -> new), int32."""
+    if bn < 1 or band_blocks < 1:
+        raise ValueError("bn and band_blocks must be positive")
+    order, _ = cuthill_mckee(conn, n_nodes)
     rcm_order = np.array(order[::-1], dtype=np.int64)
     pos = np.empty(n_nodes, dtype=np.int64)
     pos[rcm_order] = np.arange(n_nodes)
     coords = np.asarray(coords, dtype=np.float64)
-    band = band_blocks(n_nodes, n_levels, bn, coords.shape[1]) * bn
+    band = band_blocks * bn
     out = [bisect_blocks(rcm_order[b0:b0 + band], coords, pos, bn)
            for b0 in range(0, n_nodes, band)]
     seq = np.concatenate(out)
@@ -221,21 +197,21 @@ def free_dof_map(n_nodes, dim, dir_nodes, dir_comps):
     return out
 
 
-def preprocess(prob, block_nodes=0, order="blocks"):
+def preprocess(prob, block_nodes=0, band_blocks=0, order="blocks"):
     """All bit-exact preprocessing results for a problem, as a dict.
-    order: "blocks" (node blocks cut from RCM bands, the library default) or
-    "rcm"; block_nodes 0 = auto_block_nodes."""
-    bn = block_nodes or auto_block_nodes(prob.n_nodes, prob.dim)
+    order: "blocks" (node blocks cut from RCM bands: block_nodes nodes per
+    block, band_blocks blocks per band, both required) or "rcm" (the
+    numbering ignores both)."""
     if order == "rcm":
         new_id = rcm(prob.conn, prob.n_nodes)
     else:
-        new_id = block_numbering(prob.conn, prob.coords, prob.n_nodes, bn)
+        new_id = block_numbering(prob.conn, prob.coords, prob.n_nodes, block_nodes,
+                                 band_blocks)
     eo = element_order(prob.conn, new_id)
     sconn = np.asarray(new_id)[np.asarray(prob.conn)[eo]]
     col = colour_elements(sconn, prob.n_nodes)
     fmap = free_dof_map(prob.n_nodes, prob.dim, prob.dir_nodes, prob.dir_comps)
-    return {"perm": new_id, "elem_order": eo, "color": col, "free_index": fmap,
-            "block_nodes": bn}
+    return {"perm": new_id, "elem_order": eo, "color": col, "free_index": fmap}
 
 
 def bandwidth(conn, numbering):

@@ -47,7 +47,8 @@ class pfem_mesh_info(C.Structure):
                 ("block_nodes", C.c_int32), ("bandwidth_in", C.c_int64),
                 ("bandwidth_internal", C.c_int64), ("owner_elem_visits", C.c_int64),
                 ("device_bytes", C.c_int64), ("solve_bytes_fp32", C.c_int64),
-                ("solve_bytes_fp64", C.c_int64), ("f_ext_norm", C.c_double)]
+                ("solve_bytes_fp64", C.c_int64), ("f_ext_norm", C.c_double),
+                ("band_blocks", C.c_int32)]
 
 
 class pfem_solve_opts(C.Structure):

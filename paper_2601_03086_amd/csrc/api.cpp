@@ -278,6 +278,7 @@ pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* o) {
   o->solve_bytes_fp32 = m->finalized ? solve_bytes(m, PFEM_FP32, krylov_fused(d32, m)) : 0;
   o->solve_bytes_fp64 = m->finalized ? solve_bytes(m, PFEM_FP64, false) : 0;
   o->f_ext_norm = m->fext_norm;
+  o->band_blocks = m->band_blocks;
   PFEM_TRY_END
 }
 

@@ -232,12 +232,13 @@ static void bisect_blocks(int32_t* b, int32_t* e, const double* X, int D,
 }
 
 // new_id[caller node] = internal node (RCM, or node blocks cut from RCM bands).
-static void number_nodes(const pfem_mesh* m, int bn, bool blocks,
+static void number_nodes(pfem_mesh* m, int bn, bool blocks,
                          std::vector<int32_t>& new_id) {
   const int64_t N = m->n_nodes;
   std::vector<int32_t> q;
   const int64_t n_levels = cuthill_mckee(m, q);
   std::reverse(q.begin(), q.end());            // q[position] = caller node (RCM)
+  m->band_blocks = 0;
   if (blocks) {
     std::vector<int32_t> pos(N);
     for (int64_t i = 0; i < N; ++i) pos[q[i]] = (int32_t)i;
@@ -247,6 +248,7 @@ static void number_nodes(const pfem_mesh* m, int bn, bool blocks,
     const int64_t k = std::max<int64_t>(
         1, std::min<int64_t>((2 * w * N + n_levels * bn) / (2 * n_levels * bn), 32768 / bn));
     const int64_t band = k * bn;
+    m->band_blocks = (int)k;
     for (int64_t b0 = 0; b0 < N; b0 += band)
       bisect_blocks(q.data() + b0, q.data() + std::min(N, b0 + band), m->coords.data(),
                     m->dim, pos, bn);

@@ -101,6 +101,7 @@ struct pfem_mesh {
   std::vector<int32_t> halo;        // halo element lists of all blocks
   std::vector<int2> work;           // single-mesh work table
   int bn = 0, n_blocks = 0, n_colors = 0;
+  int band_blocks = 0;   // owner blocks per RCM band (block numbering; 0 under plain RCM)
   int64_t n_free = 0, bw_in = 0, bw_int = 0, owner_visits = 0;
   double fext_norm = 0.0;
   // internal-order arrays

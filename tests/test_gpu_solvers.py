@@ -148,29 +148,39 @@ def test_nh_plane_strain_with_traction(ctx):
     assert rel(u, uo) <= 1e-7
 
 
-def test_failures_reported(ctx):
+def _negative_modulus_refused(ctx, p):
+    """A negative modulus would make K indefinite: the library refuses it when
+    the material is set, before any device work."""
     from paper_2601_03086_amd import _lib as L
-    p = synth.unit_square_c1(n=9)
-    # negative modulus: K is not positive definite -> breakdown
     q = mk.make_problem("lin_plane_stress", p.coords, p.conn, E=-1.0,
                         dir_nodes=p.dir_nodes, dir_comps=p.dir_comps,
                         dir_values=p.dir_values, facets=p.neu_facets,
                         traction=p.neu_traction)
-    mq = _mesh(ctx, q)
     with pytest.raises(L.PfemError) as ei:
-        mq.solve(tol=1e-10, prec="fp64")
-    assert ei.value.status == L.PFEM_E_BREAKDOWN
+        _mesh(ctx, q)
+    assert ei.value.status == L.PFEM_E_INVALID_ARG
+
+
+def test_failures_reported(ctx):
+    from paper_2601_03086_amd import _lib as L
+    p = synth.unit_square_c1(n=9)
+    _negative_modulus_refused(ctx, p)
     # an iteration cap below what the tolerance needs -> NOT_CONVERGED with history
     m = _mesh(ctx, p)
     u, rep, hist = m.solve(tol=1e-14, prec="fp64", max_iter=5)
     assert rep["status_name"] == "NOT_CONVERGED"
     assert rep["kv_count"] == 5 and len(hist) == 6
-    # a NaN in the guess is caught by the first residual
+    assert np.all(np.isfinite(u))
+    # a NaN in the guess is caught by the first residual, in both precisions
     u0 = np.zeros(p.n_dof)
     u0[7] = np.nan
-    with pytest.raises(L.PfemError) as ei:
-        m.solve(u0=u0, tol=1e-10, prec="fp64")
-    assert ei.value.status == L.PFEM_E_BREAKDOWN
+    for prec in ("fp64", "fp32"):
+        with pytest.raises(L.PfemError) as ei:
+            m.solve(u0=u0, tol=1e-10, prec=prec, krylov="classic")
+        assert ei.value.status == L.PFEM_E_BREAKDOWN
+    # the mesh is still usable after a failed solve
+    u, rep, _ = m.solve(tol=1e-10, prec="fp64")
+    assert rep["status"] == 0
 
 
 def test_fused_pcg_matches_classic_fp64(ctx):
@@ -268,18 +278,19 @@ def test_fused_pcg_unpacked_connectivity(ctx):
 def test_fused_failures_reported(ctx):
     from paper_2601_03086_amd import _lib as L
     p = synth.unit_square_c1(n=9)
-    q = mk.make_problem("lin_plane_stress", p.coords, p.conn, E=-1.0,
-                        dir_nodes=p.dir_nodes, dir_comps=p.dir_comps,
-                        dir_values=p.dir_values, facets=p.neu_facets,
-                        traction=p.neu_traction)
+    _negative_modulus_refused(ctx, p)
+    m = _mesh(ctx, p)
+    # a NaN in the guess: the fused iteration reports the breakdown too
+    u0 = np.zeros(p.n_dof)
+    u0[7] = np.nan
     with pytest.raises(L.PfemError) as ei:
-        _mesh(ctx, q).solve(tol=1e-10, prec="fp32", krylov="fused")
+        m.solve(u0=u0, tol=1e-10, prec="fp32", krylov="fused")
     assert ei.value.status == L.PFEM_E_BREAKDOWN
     # cap of 5 matvecs: the start-up product and 4 iterations
-    m = _mesh(ctx, p)
     u, rep, hist = m.solve(tol=1e-14, prec="fp64", max_iter=5, krylov="fused")
     assert rep["status_name"] == "NOT_CONVERGED"
     assert rep["kv_count"] == 5 and rep["pcg_iters"] == 4 and len(hist) == 5
+    assert np.all(np.isfinite(u))
 
 
 def test_full_size_c2_warm_solve_matches_direct(ctx):
@@ -305,3 +316,27 @@ def test_full_size_c2_warm_solve_matches_direct(ctx):
         assert osolve.relative_residual(Kff, Ff, u[om.free_dofs]) <= 1.05e-8
         assert err <= 1e-5   # error <~ cond(K) * tol; observed far below
         assert np.all(u.reshape(-1, 2)[p.dir_nodes] == 0.0)
+
+
+def test_full_size_c3_fp32_classic_and_fused(ctx):
+    """The Neo-Hookean box at full size (about 1M tetrahedra, 10 load steps
+    from zero) in FP32 mode with both PCG formulations: the classic
+    three-launch loop is what the automatic choice takes at this size.  Both
+    end at a 1e-8 relative residual as the oracle evaluates it on the whole
+    mesh, and agree with each other."""
+    p = synth.box_problem(3, 1003)
+    print(f"[c3 solve] {p.n_elems} tetrahedra", flush=True)
+    m = _mesh(ctx, p)
+    om = fe.Model(p)
+    den = np.linalg.norm(om.gradient(om.lifted(1.0))[om.free_dofs])
+    out = {}
+    for kr in ("classic", "fused"):
+        u, rep, _ = m.solve(tol=1e-8, prec="fp32", krylov=kr,
+                            n_load_steps=p.n_load_steps, history_cap=1)
+        rho = np.linalg.norm(om.gradient(u)[om.free_dofs]) / den
+        print(kr, rep["kv_count"], rep["newton_iters"], rep["rel_residual_final"], rho,
+              flush=True)
+        assert rep["status"] == 0 and rep["load_steps_done"] == p.n_load_steps
+        assert rho <= 1.05e-8
+        out[kr] = u
+    assert rel(out["fused"], out["classic"]) <= 1e-6

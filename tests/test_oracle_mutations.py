@@ -185,7 +185,8 @@ CASES = {
         [(pins.test_preprocessing_invariants, ())]),
     "bisection blocks in reverse order": (
         prep, "bisect_blocks", _bisect_blocks_reversed,
-        [(pins.test_bisect_blocks_hand_example, ())]),
+        [(pins.test_bisect_blocks_hand_example, ()),
+         (pins.test_block_numbering_hand_example, ())]),
     "CG beta inverted": (
         solve, "pcg", _pcg_beta_inverted,
         [(pins.test_pcg_matches_direct_c1, ()), (pins.test_pcg_warm_start_saves_iterations, ())]),

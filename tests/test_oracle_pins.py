@@ -434,21 +434,44 @@ def test_cuthill_mckee_levels_hand_example():
     assert levels == 5
 
 
-def test_band_size_hand_values():
-    assert [prep.int_root(b, d) for b, d in [(255, 2), (256, 2), (26, 3), (27, 3), (1, 3)]] == \
-        [15, 16, 2, 3, 1]
-    # k = round(w N / (L bn)): 4*1000/(10*16) = 25; 4*80/(8*16) = 2.5 -> 3 (halves up);
-    # 4*100/(8*16) = 3.125 -> 3; tiny ratios clamp to one block per band,
-    # long bands to 32768 positions: 45*2e7/(9000*2048) = 48.8 -> 32768/2048 = 16
-    assert prep.band_blocks(1000, 10, 16, 2) == 25
-    assert prep.band_blocks(80, 8, 16, 2) == 3
-    assert prep.band_blocks(100, 8, 16, 2) == 3
-    assert prep.band_blocks(10, 100, 256, 2) == 1
-    assert prep.band_blocks(2 * 10 ** 7, 9000, 2048, 2) == 16
-    # N/4000 (2D) or N/750 (3D) up to a multiple of 32, clamped to [224|64, 1024]
-    assert prep.auto_block_nodes(1000, 2) == 224 and prep.auto_block_nodes(1000, 3) == 64
-    assert prep.auto_block_nodes(2000000, 2) == 512 and prep.auto_block_nodes(183000, 3) == 256
-    assert prep.auto_block_nodes(10 ** 8, 2) == 1024 and prep.auto_block_nodes(10 ** 8, 3) == 1024
+def _grid_3x3():
+    """3 x 3 nodes (id = 3 y + x on the unit lattice), two triangles per
+    square split along the rising diagonal."""
+    X = np.array([[i, j] for j in range(3) for i in range(3)], float)
+    conn = []
+    for j in range(2):
+        for i in range(2):
+            n = 3 * j + i
+            conn += [[n, n + 1, n + 4], [n, n + 4, n + 3]]
+    return X, np.array(conn, dtype=np.int32)
+
+
+def test_block_numbering_hand_example():
+    """Worked by hand on the 3 x 3 grid.  Degrees 3,4,2,4,6,4,2,4,3; the
+    search starts at node 2 (degree 2, smaller id than 6) and visits
+    2 | 1 5 | 0 4 8 | 3 7 | 6 (five levels), so RCM is 6 7 3 8 4 0 5 1 2.
+    Blocks of 3 nodes:
+      - 1 block per band: every band is one block, the numbering is RCM;
+      - 3 blocks per band (all nodes): x and y extents tie, x splits off
+        {6, 3, 0}; the rest has y extent 2 > 1 and splits into {1, 2, 4}
+        and {5, 7, 8}; each block in RCM order: 6 3 0 | 4 1 2 | 7 8 5;
+      - 2 blocks per band: band 6 7 3 8 4 0 splits on x into {6, 3, 0} and
+        {7, 4, 8}; band 5 1 2 stays: 6 3 0 | 7 8 4 | 5 1 2."""
+    X, conn = _grid_3x3()
+    order, levels = prep.cuthill_mckee(conn, 9)
+    assert order == [2, 1, 5, 0, 4, 8, 3, 7, 6] and levels == 5
+    rcm = prep.rcm(conn, 9)
+    assert prep.block_numbering(conn, X, 9, 3, 1).tolist() == rcm.tolist()
+    for k, seq in [(3, [6, 3, 0, 4, 1, 2, 7, 8, 5]), (2, [6, 3, 0, 7, 8, 4, 5, 1, 2])]:
+        exp = np.empty(9, dtype=np.int32)
+        exp[seq] = np.arange(9)
+        assert prep.block_numbering(conn, X, 9, 3, k).tolist() == exp.tolist()
+    # element order under the 3-blocks-per-band numbering: sorted new-id
+    # tuples (0,1,6) (1,2,3) (1,3,6) (2,3,4) (3,4,8) (3,6,7) (3,7,8) (4,5,8)
+    nid = prep.block_numbering(conn, X, 9, 3, 3)
+    assert prep.element_order(conn, nid).tolist() == [5, 1, 4, 0, 3, 7, 6, 2]
+    with pytest.raises(ValueError):
+        prep.block_numbering(conn, X, 9, 3, 0)
 
 
 def test_bisect_blocks_hand_example():
@@ -480,13 +503,13 @@ def test_block_numbering_invariants():
     in their splitting order, and the numbering is a permutation."""
     p = synth.structured_plate(30, 24, 5)
     bn = 32
-    new_id = prep.block_numbering(p.conn, p.coords, p.n_nodes, bn)
+    k = 5
+    new_id = prep.block_numbering(p.conn, p.coords, p.n_nodes, bn, k)
     assert sorted(new_id.tolist()) == list(range(p.n_nodes))
     order, levels = prep.cuthill_mckee(p.conn, p.n_nodes)
     rcm_pos = np.empty(p.n_nodes, np.int64)
     rcm_pos[np.array(order[::-1])] = np.arange(p.n_nodes)
-    band = prep.band_blocks(p.n_nodes, levels, bn, 2) * bn
-    assert band > bn
+    band = k * bn
     for b0 in range(0, p.n_nodes, band):
         members = np.nonzero((new_id >= b0) & (new_id < b0 + band))[0]
         assert np.array_equal(np.sort(rcm_pos[members]),
@@ -503,7 +526,7 @@ def test_block_numbering_invariants():
 
 def test_preprocessing_invariants():
     p = synth.plate_problem(21, 22, 23, n_holes=3, target_tris=3000)
-    r = prep.preprocess(p)
+    r = prep.preprocess(p, 64, 4)
     assert sorted(r["perm"].tolist()) == list(range(p.n_nodes))
     assert sorted(r["elem_order"].tolist()) == list(range(p.n_elems))
     assert prep.bandwidth(p.conn, r["perm"]) <= prep.bandwidth(p.conn, np.arange(p.n_nodes))
