@@ -211,10 +211,12 @@ __device__ __forceinline__ void linear_stress_tilde(const T (&M)[D][D], T mu, T 
 }
 
 // ------------------------------------------------------------ Neo-Hookean
-// Kinematic state of one element: H = grad u, F^{-T}, J - 1 and ln J in the
-// kernel precision (float32 kernels feed an inexact Krylov solve whose
-// residual is evaluated by the float64 kernels; J - 1 from the invariants
-// keeps its relative accuracy at small strain in either precision).
+// Kinematic state of one element: H = grad u, F^{-T}, J - 1 and ln J.
+// J - 1 from the invariants of H keeps its relative accuracy at small strain
+// in either precision.  Near compression (J < 0.7) ln J and 1/J amplify the
+// rounding of J - 1 by 1/J: float32 kernels evaluate J - 1, ln J and 1/J in
+// float64 there (the float64 det F / log J rule of the mixed-precision path),
+// and in float32 elsewhere, where float32 keeps them to a few ulps.
 template <int D, typename T>
 struct NHState {
   T H[D][D];
@@ -244,6 +246,45 @@ __device__ __forceinline__ T jm1(const T (&h)[D][D]) {
   }
 }
 
+// J - 1, ln J and 1/J of the element (0 and ok = false when J <= 0).
+template <int D, typename T>
+__device__ __forceinline__ void nh_volumetric(const T (&H)[D][D], T& j, T& lnJ, T& invJ,
+                                              bool& ok) {
+  j = jm1<D, T>(H);
+  if constexpr (sizeof(T) == 4) {
+    if (j < -0.3f) {
+      // products of two float32 values are exact in float64
+      double jd;
+      if constexpr (D == 2) {
+        jd = ((double)H[0][0] + (double)H[1][1]) +
+             ((double)H[0][0] * H[1][1] - (double)H[0][1] * H[1][0]);
+      } else {
+        const double tr = (double)H[0][0] + (double)H[1][1] + (double)H[2][2];
+        // (tr^2 - tr H^2)/2 = sum of the principal 2x2 minors of H
+        const double m2 = ((double)H[0][0] * H[1][1] - (double)H[0][1] * H[1][0]) +
+                          ((double)H[0][0] * H[2][2] - (double)H[0][2] * H[2][0]) +
+                          ((double)H[1][1] * H[2][2] - (double)H[1][2] * H[2][1]);
+        const double det =
+            (double)H[0][0] * ((double)H[1][1] * H[2][2] - (double)H[1][2] * H[2][1]) -
+            (double)H[0][1] * ((double)H[1][0] * H[2][2] - (double)H[1][2] * H[2][0]) +
+            (double)H[0][2] * ((double)H[1][0] * H[2][1] - (double)H[1][1] * H[2][0]);
+        jd = tr + m2 + det;
+      }
+      ok = jd > -1.0;
+      j = (float)jd;
+      // J rounded once from its float64 value: away from J = 1 the float32
+      // logarithm and reciprocal of it are accurate to a few ulps
+      const float Jf = (float)(1.0 + jd);
+      lnJ = ok ? logf(Jf) : 0.0f;
+      invJ = ok ? 1.0f / Jf : 0.0f;
+      return;
+    }
+  }
+  ok = j > T(-1);
+  lnJ = ok ? log1p(j) : T(0);
+  invJ = ok ? T(1) / (T(1) + j) : T(0);
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void nh_state(const T (&Ht)[D][D], T inv_det,
                                          NHState<D, T>& st) {
@@ -251,10 +292,8 @@ __device__ __forceinline__ void nh_state(const T (&Ht)[D][D], T inv_det,
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int k = 0; k < D; ++k) st.H[i][k] = Ht[i][k] * inv_det;
-  st.j = jm1<D, T>(st.H);
-  st.ok = st.j > T(-1);
-  st.lnJ = st.ok ? log1p(st.j) : T(0);
-  const T invJ = st.ok ? T(1) / (T(1) + st.j) : T(0);
+  T invJ;
+  nh_volumetric<D, T>(st.H, st.j, st.lnJ, invJ, st.ok);
   T F[D][D];
 #pragma unroll
   for (int i = 0; i < D; ++i)

@@ -11,7 +11,7 @@ import pytest
 import synth
 from oracle import fe
 from tests import meshkit as mk
-from tests.gpu_util import bound_rel, rel, smooth_field, torch_cuda
+from tests.gpu_util import assert_bound, bound_rel, rel, smooth_field, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -111,8 +111,11 @@ def test_fp32_energy_force_hvp(ctx, model):
     KT = om.assemble(u)
     ww = w.double().cpu().numpy()
     scale = np.linalg.norm(abs(KT) @ abs(u)) + np.linalg.norm(om.f_ext)
-    assert np.linalg.norm(g.detach().double().cpu().numpy() - om.gradient(u)) <= 3e-5 * scale
-    assert bound_rel(hv.double().cpu().numpy(), KT @ ww, abs(KT) @ abs(ww)) <= 3e-5
+    eg = np.linalg.norm(g.detach().double().cpu().numpy() - om.gradient(u)) / scale
+    print(f"[err] autograd force {model} fp32: {eg:.2e}", flush=True)
+    assert eg <= 1e-5
+    assert_bound(hv.double().cpu().numpy(), KT @ ww, abs(KT) @ abs(ww), 1e-5,
+                 f"autograd hvp {model} fp32")
 
 
 def _internal(vec_user, perm, d):
@@ -157,10 +160,12 @@ def test_batched_energy_matches_per_mesh_oracle(ctx, n):
         KT = om.assemble(uu)
         gi = _internal(om.gradient(uu), pr, 2)
         scale = np.linalg.norm(abs(KT) @ abs(uu)) + np.linalg.norm(om.f_ext)
-        assert np.linalg.norm(g[off[i]:off[i + 1]] - gi) <= 3e-5 * scale, i
+        eg = np.linalg.norm(g[off[i]:off[i + 1]] - gi) / scale
+        print(f"[err] batch force mesh {i}: {eg:.2e}", flush=True)
+        assert eg <= 1e-5, i
         # HVP: K_T in internal order applied to the internal-order direction
         wi = wn[off[i]:off[i + 1]]
         wu = wi.reshape(-1, 2)[pr].reshape(-1)        # back to user order
         ref = _internal(KT @ wu, pr, 2)
         bound = _internal(abs(KT) @ abs(wu), pr, 2)
-        assert bound_rel(hv[off[i]:off[i + 1]], ref, bound) <= 3e-5, i
+        assert_bound(hv[off[i]:off[i + 1]], ref, bound, 1e-5, f"batch hvp mesh {i}")

@@ -6,7 +6,8 @@ import pytest
 import synth
 from oracle import fe
 from tests import meshkit as mk
-from tests.gpu_util import bound_rel, rel, sample_rows, smooth_field, torch_cuda
+from tests.gpu_util import (assert_bound, bound_rel, compressed_field, rel, sample_rows,
+                            smooth_field, torch_cuda)
 
 pytestmark = pytest.mark.gpu
 
@@ -74,7 +75,7 @@ def test_apply_K_parity(ctx, name, prec, scatter, bn):
     y = m.apply_K(torch.tensor(v), prec=prec, scatter=scatter).double().cpu().numpy()
     yref = K @ v
     vv = v.astype(np.float32).astype(np.float64) if prec == "fp32" else v
-    assert bound_rel(y, K @ vv, abs(K) @ abs(vv)) <= TOL[prec]
+    assert_bound(y, K @ vv, abs(K) @ abs(vv), TOL[prec], f"K.v {name} {prec} {scatter}")
     assert rel(y, yref) <= (1e-12 if prec == "fp64" else 1e-4)
 
 
@@ -96,12 +97,10 @@ def test_rcm_numbering_parity(ctx, name, prec, bn):
         tu = torch.tensor(smooth_field(p, 3, 0.08), dtype=dt)
         K = om.assemble(tu.double().numpy())
         y = m.hvp(tu, tv, prec=prec).double().cpu().numpy()
-        tol = TOL[prec] * 3
     else:
         K = om.assemble()
         y = m.apply_K(tv, prec=prec).double().cpu().numpy()
-        tol = TOL[prec]
-    assert bound_rel(y, K @ vv, abs(K) @ abs(vv)) <= tol
+    assert_bound(y, K @ vv, abs(K) @ abs(vv), TOL[prec], f"rcm {name} {prec}")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -123,7 +122,8 @@ def test_unpacked_connectivity_apply_K(ctx, prec):
     # rounding about 10x beyond the usual bound (measured 8.5e-5); an indexing
     # error in the unpacked path would show at O(1)
     tol = TOL[prec] if prec == "fp64" else 5e-4
-    assert bound_rel(y, K @ vv, abs(K) @ abs(vv)) <= tol
+    # norm-wise only: single sliver rows reach 1.5e-2 of their own bound
+    assert bound_rel(y, K @ vv, abs(K) @ abs(vv), f"fan {prec}") <= tol
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -163,29 +163,61 @@ def test_hvp_force_energy_diag_nh(ctx, name, prec, bn):
     om = fe.Model(p)
     u = smooth_field(p, 3, 0.08)
     v = np.random.default_rng(4).normal(size=p.n_dof)
-    KT = om.assemble(u)
     dt = torch.float64 if prec == "fp64" else torch.float32
     tu = torch.tensor(u, dtype=dt)
     y = m.hvp(tu, torch.tensor(v, dtype=dt), prec=prec).double().cpu().numpy()
-    uu = tu.double().numpy()
     vv = torch.tensor(v, dtype=dt).double().numpy()
+    _check_nh_state(m, om, p, tu, vv, y, prec, f"{name} bn={bn}")
+
+
+def _check_nh_state(m, om, p, tu, vv, y, prec, label):
+    """HVP y = K_T(u) v, force, energy and Jacobi diagonal of the device at
+    the state tu against the oracle at the same (rounded) state."""
+    uu = tu.double().numpy()
     KTu = om.assemble(uu)
-    assert bound_rel(y, KTu @ vv, abs(KTu) @ abs(vv)) <= TOL[prec] * 3
+    assert_bound(y, KTu @ vv, abs(KTu) @ abs(vv), TOL[prec], f"hvp {label} {prec}")
     g = m.force(tu, prec=prec).double().cpu().numpy()
     gref = om.gradient(uu)
-    fi = om.internal_force(uu)
-    # |f_int| built from absolute element contributions bounds the FP32 error
+    # |K_T| |u| (+ |f_ext|) bounds the rounding of the element stresses
     scale = np.linalg.norm(abs(KTu) @ abs(uu)) + np.linalg.norm(om.f_ext)
-    assert np.linalg.norm(g - gref) <= TOL[prec] * 3 * scale
+    eg = np.linalg.norm(g - gref) / scale
+    print(f"[err] force {label} {prec}: {eg:.2e}", flush=True)
+    assert eg <= TOL[prec]
     e = m.energy(tu, prec=prec).item()
     eref = om.energy(uu)
+    print(f"[err] energy {label} {prec}: {abs(e - eref) / abs(eref):.2e}", flush=True)
     assert abs(e - eref) <= TOL[prec] * abs(eref)
     d = m.diag(tu, prec=prec).double().cpu().numpy()
     dref = KTu.diagonal().copy()
     con = np.asarray(p.dir_nodes) * p.dim + np.asarray(p.dir_comps)
     dref[con] = 1.0
+    print(f"[err] diag {label} {prec}: {rel(d, dref):.2e}", flush=True)
     assert rel(d, dref) <= TOL[prec]
-    del fi
+
+
+@pytest.mark.parametrize("name", ["plate_nh", "box_nh"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_nh_compressed_state(ctx, name, prec):
+    """Neo-Hookean kernels near compression: a Gaussian patch squeezed to
+    J = 0.2 at its centre (plus a smooth 1% strain field), where ln J and 1/J
+    amplify the rounding of J - 1 (float32 kernels evaluate det F in float64
+    there).  HVP, force, energy and diagonal against the oracle."""
+    torch = torch_cuda()
+    p = PROBS[name]
+    m = _mesh(ctx, name)
+    om = fe.Model(p)
+    # the coarse box (h = 0.2) resolves the patch centre less sharply: aim
+    # lower so that its most compressed element reaches J of about 0.2 too
+    u = compressed_field(p, 0.2 if p.dim == 2 else 0.12, seed=11)
+    Jm = 1.0 + fe.nh_invariants(om.H(u))[0]
+    print(f"[compressed] {name}: J in [{Jm.min():.3f}, {Jm.max():.3f}], "
+          f"{(Jm < 0.7).sum()} of {Jm.size} elements below 0.7", flush=True)
+    assert Jm.min() < 0.25 and Jm.min() > 0.1
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    tu = torch.tensor(u, dtype=dt)
+    tv = torch.tensor(np.random.default_rng(12).normal(size=p.n_dof), dtype=dt)
+    y = m.hvp(tu, tv, prec=prec).double().cpu().numpy()
+    _check_nh_state(m, om, p, tu, tv.double().numpy(), y, prec, f"{name} compressed")
 
 
 @pytest.mark.parametrize("name", ["c1", "plate_lin", "box_lin"])
@@ -234,7 +266,7 @@ def test_full_size_c2_apply_K(ctx):
     for prec in ("fp64", "fp32"):
         y = m.apply_K(torch.tensor(v), prec=prec).double().cpu().numpy()
         vv = v.astype(np.float32).astype(np.float64) if prec == "fp32" else v
-        assert bound_rel(y, K @ vv, Kav) <= TOL[prec]
+        assert_bound(y, K @ vv, Kav, TOL[prec], f"c2 K.v {prec}")
 
 
 def test_full_size_c3_hvp_sampled_rows(ctx):
@@ -262,8 +294,8 @@ def test_full_size_c3_hvp_sampled_rows(ctx):
         vv = torch.tensor(v, dtype=dt).double().numpy()
         KTu = om.assemble(uu)
         ref = (KTu @ vv)[rows]
-        assert bound_rel(y[rows], ref, (abs(KTu) @ abs(vv))[rows]) <= TOL[prec] * 3
+        assert_bound(y[rows], ref, (abs(KTu) @ abs(vv))[rows], TOL[prec], f"c3 hvp {prec}")
         g = m.force(tu, prec=prec).double().cpu().numpy()
         gref = om.internal_force(uu)[rows]   # no tractions in C3
-        assert bound_rel(g[rows], gref, (abs(KTu) @ abs(uu))[rows]) <= TOL[prec] * 3
+        assert_bound(g[rows], gref, (abs(KTu) @ abs(uu))[rows], TOL[prec], f"c3 force {prec}")
     del KT
