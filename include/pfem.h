@@ -251,6 +251,23 @@ pfem_status pfem_force(pfem_mesh* m, int prec, int layout, int mask,
  * order; energy_dev: device, 1 float64.  Elements with J <= 0 give +inf. */
 pfem_status pfem_energy(pfem_mesh* m, int prec, int layout, const void* u,
                         double* energy_dev);
+/* pfem_energy without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and result as
+ * pfem_energy; its block partial sums, reduced sums and (layout
+ * PFEM_LAYOUT_USER) the permuted state live in one library-owned device
+ * array of 16 MiB per GPU, created when the library is loaded and held
+ * until the process ends (its address on a device is looked up when the
+ * first context on that device is created).  Needs 256 + round256(32 *
+ * n_blocks) bytes, plus round256(n_dof * 8 or 4) in user layout (about
+ * 2M float64 DOFs); a larger mesh gets PFEM_E_INVALID_ARG and nothing runs.
+ * Nothing in the array has to start at zero: every call writes what it
+ * reads.  All calls on one GPU share the array, so calls that overlap in
+ * time on one GPU (several contexts or streams, several host threads) race
+ * and must be ordered by the caller.  No hipMalloc, hipFree or other
+ * allocating routine is called. */
+pfem_status pfem_energy_noalloc(pfem_mesh* m, int prec, int layout, const void* u,
+                                double* energy_dev);
 /* diag(K_T(u)) (Jacobi preconditioner of the warm-start PCG); Dirichlet DOFs
  * get 1. */
 pfem_status pfem_diag(pfem_mesh* m, int prec, int layout, const void* u, void* d);

@@ -107,6 +107,7 @@ PROTOTYPES = {
     "pfem_apply_K": (_I32, [_VP, C.c_int, C.c_int, C.c_int, C.c_int, _VP, _VP]),
     "pfem_force": (_I32, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP]),
     "pfem_energy": (_I32, [_VP, C.c_int, C.c_int, _VP, _VP]),
+    "pfem_energy_noalloc": (_I32, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "pfem_diag": (_I32, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "pfem_batch_create": (_I32, [_VP, _I32, _VP, _PVP]),
     "pfem_batch_destroy": (None, [_VP]),

@@ -254,6 +254,19 @@ class Mesh:
         return e
 
     @_on_stream
+    def energy_noalloc(self, u, prec="fp64", layout="user", out=None):
+        """pfem_energy_noalloc: the energy with no allocation inside the
+        library (out: an existing float64 device scalar, written in place)."""
+        u = self._vec(u, prec)
+        e = out if out is not None else torch.empty((), dtype=torch.float64,
+                                                    device=self.ctx.device)
+        if not (isinstance(e, torch.Tensor) and e.dtype == torch.float64
+                and e.device == self.ctx.device and e.numel() == 1):
+            raise ValueError("out must be one float64 entry on the context's device")
+        check(L.pfem_energy_noalloc(self.h, PREC[prec], LAYOUT[layout], _ptr(u), _ptr(e)))
+        return e
+
+    @_on_stream
     def diag(self, u=None, prec="fp64", layout="user"):
         uu = self._vec(u, prec) if u is not None else None
         y = self.new_vec(prec)

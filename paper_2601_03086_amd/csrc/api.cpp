@@ -27,10 +27,6 @@ struct pfem_batch {
   pfem::Task* tasks_plain = nullptr;
 };
 
-namespace pfem {
-void launch_energy_out(Ctx* ctx, const double* red, double* out, int n, int stride);
-}
-
 #define PFEM_TRY_BEGIN try {
 #define PFEM_TRY_END                                   \
   }                                                    \
@@ -66,6 +62,7 @@ pfem_status pfem_ctx_create(int device, void* hip_stream, pfem_ctx** out) {
   PFEM_HIP(hipGetDeviceCount(&n));
   require(device >= 0 && device < n, PFEM_E_INVALID_ARG, "device index out of range");
   PFEM_HIP(hipSetDevice(device));
+  noalloc_init(device);   // this device's address of the allocation-free scratch
   Ctx* c = new Ctx();
   c->device = device;
   try {

@@ -231,6 +231,9 @@ void launch_elem(Ctx* ctx, int dim, int prec, int op, bool nonlinear, int scatte
                  const Task* tasks_dev, const int2* work_dev, int n_work,
                  int bn_max, const Task* host_task_for_alt,
                  const std::vector<int>* color_ptr, const BaseArgs* rel = nullptr);
+// Records, with `device` current, the device address of the allocation-free
+// entry point's scratch array (once per device; pfem_ctx_create calls it).
+void noalloc_init(int device);
 void launch_energy(Ctx* ctx, int dim, int prec, bool diff,
                    const Task* tasks_dev, const int2* work_dev, int n_work,
                    const BaseArgs* rel = nullptr);
@@ -256,6 +259,9 @@ void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nonlinear, const Task* ta
 // One workgroup per task: red.out[0..n_slots-1] = sums of partial slots
 // 0..n_slots-1 (n_slots 2 or 3).
 void launch_reduce_store(Ctx* ctx, const Task* tasks_dev, int n_tasks, int n_slots = 2);
+// out[i] = energy of reduction i (red[i * stride]), +inf where red[i * stride + 1]
+// (elements with J <= 0) is nonzero.
+void launch_energy_out(Ctx* ctx, const double* red, double* out, int n, int stride);
 void launch_dot(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
                 const int2* work_dev, int n_work);
 void launch_set_scalars(Ctx* ctx, Scalars* sc, double den, double target2, int kmax,

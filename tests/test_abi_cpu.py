@@ -327,6 +327,13 @@ def test_host_only_mesh_calls():
         st = getattr(lib, name)(m.h, *[0 if a in ints else None for a in args[1:]])
         assert st == L.PFEM_E_STATE, (name, st)
         assert b"device" in L.pfem_last_error(), name
+    # the allocation-free energy checks the mesh state before any device call
+    dummy = np.zeros(4)
+    st = lib.pfem_energy_noalloc(m.h, L.PFEM_FP64, L.PFEM_LAYOUT_USER,
+                                 dummy.ctypes.data, dummy.ctypes.data)
+    assert st == L.PFEM_E_STATE and b"device" in L.pfem_last_error()
+    assert lib.pfem_energy_noalloc(m.h, 7, L.PFEM_LAYOUT_USER, dummy.ctypes.data,
+                                   dummy.ctypes.data) == L.PFEM_E_INVALID_ARG
     n = L._I64()
     assert lib.pfem_mesh_query_int(m.h, L.PFEM_Q_PERM, None, 0, C.byref(n)) == 0
     assert n.value == nn
