@@ -47,19 +47,24 @@ def relative_residual(Kff, Ff, uf):
     return r / nf if nf > 0 else r
 
 
-def pcg(A, b, x0=None, tol=1e-10, max_iter=None, diag=None):
+def pcg(A, b, x0=None, tol=1e-10, max_iter=None, diag=None, precond=None):
     """Jacobi-PCG with the true-residual confirmation described in the module.
 
     Stops when |r_k| / |b| <= tol and the recomputed residual b - A x also
     satisfies it; otherwise restarts from the true residual.  Returns
     (x, history, kv_count, status) with status 0 converged, 1 max-iter,
     -5 breakdown (p.Ap <= 0).  kv_count counts the products A p only.
+    precond: a function r -> M^-1 r replacing the Jacobi preconditioner.
     """
     n = b.shape[0]
     if max_iter is None:
         max_iter = 10 * n
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
-    Minv = 1.0 / (A.diagonal() if diag is None else diag)
+    if precond is None:
+        dinv = 1.0 / (A.diagonal() if diag is None else diag)
+
+        def precond(v):
+            return dinv * v
     bn = np.linalg.norm(b)
     if bn == 0.0:
         return np.zeros(n), [0.0], 0, 0
@@ -67,7 +72,7 @@ def pcg(A, b, x0=None, tol=1e-10, max_iter=None, diag=None):
     hist = [np.linalg.norm(r) / bn]
     if hist[0] <= tol:
         return x, hist, 0, 0
-    z = Minv * r
+    z = precond(r)
     p = z.copy()
     rz = r @ z
     k = 0
@@ -87,11 +92,11 @@ def pcg(A, b, x0=None, tol=1e-10, max_iter=None, diag=None):
             if np.linalg.norm(rt) / bn <= tol:
                 return x, hist, k, 0
             r = rt
-            z = Minv * r
+            z = precond(r)
             p = z.copy()
             rz = r @ z
             continue
-        z = Minv * r
+        z = precond(r)
         rz_new = r @ z
         beta = rz_new / rz
         rz = rz_new
