@@ -2,6 +2,7 @@
 #include <algorithm>
 
 #include "pfem_internal.h"
+#include "ring_math.h"
 
 namespace pfem {
 
@@ -38,12 +39,8 @@ void* ArgRing::put(const void* src, size_t n) {
   const size_t need = (n + 255) & ~size_t(255);
   require(need <= seg_bytes, PFEM_E_INVALID_ARG,
           "launch descriptor larger than the staging segment");
-  size_t off = off_;
-  int seg = (int)(off / seg_bytes);
-  if ((off % seg_bytes) + need > seg_bytes) {   // does not fit: next segment
-    seg = (seg + 1) % kSeg;
-    off = (size_t)seg * seg_bytes;
-  }
+  int seg = 0;
+  const size_t off = ring_place(off_, need, seg_bytes, kSeg, &seg);
   if (seg != seg_) {
     // leaving seg_: everything that used it has been enqueued
     PFEM_HIP(hipEventRecord(ev_[seg_], stream_));
