@@ -103,8 +103,10 @@ enum {
   PFEM_Q_ELEM_ORDER = 1,      /* n_elems: caller element index at each sorted position */
   PFEM_Q_COLOR = 2,           /* n_elems: colour of each sorted element */
   PFEM_Q_FREE_INDEX = 3,      /* n_nodes*dim: rank among free DOFs (caller numbering) or -1 */
-  PFEM_Q_BLOCKS = 4           /* 3*n_blocks: per node block (first touching elem,
+  PFEM_Q_BLOCKS = 4,          /* 3*n_blocks: per node block (first touching elem,
                                  first owned elem, end elem) in sorted order */
+  PFEM_Q_AGGREGATE = 5        /* n_nodes: coarse aggregate of each caller node (the
+                                 two-level preconditioner's partition) */
 };
 
 typedef struct pfem_ctx pfem_ctx;
@@ -122,7 +124,9 @@ pfem_status pfem_ctx_create(int device, void* hip_stream, pfem_ctx** out);
  * resources freed when the last of them is destroyed (a server runs on a
  * stream of its own).  A caller-supplied stream is never destroyed. */
 void pfem_ctx_destroy(pfem_ctx* ctx);
-/* Message of the last error on this thread ("" if none). */
+/* Message of the last error on this thread ("" if none).  Kept per thread,
+ * not per context: calls without a context (host-only meshes) and the
+ * server calls, which any thread may make, report through it too. */
 const char* pfem_last_error(void);
 /* Library version string. */
 const char* pfem_version(void);
@@ -144,6 +148,32 @@ pfem_status pfem_ctx_set_timing_sample(pfem_ctx* ctx, int every);
  * stream.  PFEM_E_INVALID_ARG for a family outside 0..6. */
 pfem_status pfem_ctx_kernel_time(pfem_ctx* ctx, int family, int64_t* launches,
                                  double* total_ms);
+/* Launches and algorithmic bytes of one family since the last reset.
+ * launches_timed / total_ms: as pfem_ctx_kernel_time.  launches_run: the
+ * launches of the family that did work and whose time is in total_ms (a
+ * launch of a PCG chunk after every solve in it has converged returns at
+ * once and is not counted; a fused chunk, timed as one run, counts only
+ * when every one of its launches did work).  alg_bytes: what those
+ * launches had to move at least, summed over every solve they advanced and
+ * every iteration each one ran
+ * (K.v / Hessian-vector apply: 4 (d+1) N_e connectivity + s N_e material +
+ * d s N_n coordinates + d s N_n input + d s N_n output, plus d s N_n of
+ * state u for Neo-Hookean meshes; fused PCG iteration: the same
+ * connectivity, material and coordinates + 11 d s N_n of node records and
+ * vectors ({r, w, s, M^-1} read, {r, w, s} written, p and d read and
+ * written), plus d s N_n of state u for Neo-Hookean meshes; s = 4 or 8 by
+ * precision).  Counted for the apply (0)
+ * and fused (6) families of solves while the family is timed; 0 for the
+ * others and for kernel-level calls.  So alg_bytes / launches_run is the
+ * average per launch and alg_bytes / total_ms the achieved algorithmic
+ * bandwidth when every launch is timed (sampling 1). */
+typedef struct {
+  int64_t launches_timed;
+  double total_ms;
+  int64_t launches_run;
+  double alg_bytes;
+} pfem_kernel_stats;
+pfem_status pfem_ctx_kernel_stats(pfem_ctx* ctx, int family, pfem_kernel_stats* out);
 /* Zero every family's counters (pending timings are collected first). */
 pfem_status pfem_ctx_reset_timing(pfem_ctx* ctx);
 /* Block until all work queued on the context stream has finished. */
@@ -160,7 +190,8 @@ pfem_status pfem_ctx_synchronize(pfem_ctx* ctx);
 pfem_status pfem_mesh_create(pfem_ctx* ctx, int dim, int64_t n_nodes,
                              const double* coords, int64_t n_elems,
                              const int32_t* conn, pfem_mesh** out);
-/* Per-element material.  model: PFEM_LIN_* / PFEM_NH_*.  param_kind:
+/* Per-element material (both parameters given per element: a uniform one is
+ * an array of n_elems equal values).  model: PFEM_LIN_* / PFEM_NH_*.  param_kind:
  * PFEM_PARAM_E_NU (p0 = Young's modulus, p1 = Poisson ratio; Lame
  * parameters per Sec. 'Nonlinear hyperelasticity') or PFEM_PARAM_LAME
  * (p0 = mu, p1 = lambda).  p0, p1: host, n_elems float64 each.
@@ -180,6 +211,18 @@ pfem_status pfem_mesh_set_dirichlet(pfem_mesh* m, int64_t n, const int32_t* node
  * f_ext puts t |facet| / n_f on each facet node (App. B, f_ext integral). */
 pfem_status pfem_mesh_set_neumann(pfem_mesh* m, int64_t n_facets,
                                   const int32_t* facet_nodes, const double* traction);
+/* Periodic springs (App. D: the virtual elements PFEM uses to impose the
+ * periodic boundary conditions of a unit cell, a penalty): n_pairs node
+ * pairs (host, 2 int32 each, caller ids), each joined by a spring of
+ * stiffness `stiffness` whose energy 1/2 k |u_a - u_b|^2 joins the
+ * potential.  Every owner-scatter kernel includes them (K.v, force,
+ * energy, diagonal); the fused PCG and the coloured / atomic scatters do
+ * not and refuse such meshes.  Linear models only (checked at finalize).
+ * n_pairs = 0 clears.  Must be called before pfem_mesh_finalize
+ * (PFEM_E_STATE after); PFEM_E_INVALID_ARG for a node out of range, a pair
+ * of one node, or a stiffness that is not finite and > 0. */
+pfem_status pfem_mesh_set_periodic(pfem_mesh* m, int64_t n_pairs, const int32_t* pairs,
+                                   double stiffness);
 /* Internal node numbering (not in the paper, which names no ordering; it
  * decides how many elements straddle two owner blocks and so how often the
  * element kernels evaluate an element):
@@ -221,6 +264,30 @@ pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* out);
  * pfem_mesh_finalize; PFEM_E_INVALID_ARG for an unknown query or cap < 0. */
 pfem_status pfem_mesh_query_int(const pfem_mesh* m, int which, int32_t* out,
                                 int64_t cap, int64_t* n);
+/* Device bytes a solve of this mesh in precision prec (PFEM_FP64 /
+ * PFEM_FP32, automatic Krylov formulation) occupies: the mesh arrays plus
+ * one solve's state -- what a server charges against its memory budget
+ * when it admits the request and has to upload the mesh (Sec.
+ * 'Warm-start': many warm-started solves on one device).  bytes: host.
+ * PFEM_E_STATE before pfem_mesh_finalize. */
+pfem_status pfem_mesh_footprint(const pfem_mesh* m, int prec, int64_t* bytes);
+/* Build the coarse space of the two-level preconditioner on the host (see
+ * PFEM_PRECOND_TWO_LEVEL) now rather than at the first solve that asks for
+ * it: aggregates, orthonormal rigid modes, P^T K P and its inverse.  Needs
+ * no device; thread-safe per mesh; a no-op when built.  n_coarse (host, may
+ * be NULL) receives the coarse dimension.  PFEM_E_STATE before
+ * pfem_mesh_finalize. */
+pfem_status pfem_mesh_prepare_coarse(pfem_mesh* m, int32_t* n_coarse);
+/* Upload a finalized host-only mesh (created with ctx NULL) to ctx's
+ * device, so kernel-level and batched calls can use it; a no-op for a mesh
+ * already resident on ctx, PFEM_E_STATE for one resident on another
+ * context.  A server that is handed a resident mesh uses its arrays in
+ * place and charges nothing for them. */
+pfem_status pfem_mesh_upload(pfem_mesh* m, pfem_ctx* ctx);
+/* Free the mesh's device arrays; the mesh stays finalized and host-only
+ * (a no-op for a mesh that is not resident).  It must not be in a live
+ * batch or a server request that has not been collected. */
+pfem_status pfem_mesh_release_device(pfem_mesh* m);
 /* Free the mesh and its device arrays (NULL is a no-op).  It must not be in
  * a live batch or a server request that has not been collected. */
 void pfem_mesh_destroy(pfem_mesh* m);
@@ -234,7 +301,14 @@ pfem_status pfem_permute(pfem_mesh* m, int prec, int to_internal,
 
 /* ------------------------------------------------------ kernel-level calls
  * All vectors are device pointers of n_dof entries in `prec` (float64 or
- * float32), in the layout given.  Mesh must be finalized with a context. */
+ * float32), in the layout given.  Mesh must be finalized with a context.
+ * Device pointers only, by design: these calls sit inside device-resident
+ * loops (the differentiable energy's forward / backward / double backward,
+ * Krylov iterations of a caller, benchmarks), where a host round trip per
+ * call would cost more than the kernel; a host caller copies in once or
+ * uses pfem_solve, which takes host or device vectors.  The scatter
+ * strategy is chosen per call (finalize prepares owner blocks and colours
+ * for all of them). */
 
 /* y = K v (linear models) or y = K_T(u) v (Neo-Hookean; u ignored for linear
  * models and may be NULL).  App. B: incremental internal force
@@ -319,9 +393,21 @@ pfem_status pfem_batch_hvp(pfem_batch* b, int prec, int mask, const void* u,
  *          FP64 mode. */
 enum { PFEM_KRYLOV_AUTO = 0, PFEM_KRYLOV_CLASSIC = 1, PFEM_KRYLOV_FUSED = 2 };
 
+/* Preconditioner of the PCG solves (the paper's CG names none; §5.6 notes
+ * that a stronger one complements the warm start):
+ * JACOBI     M^-1 = D^-1, the diagonal of K (or of K_T(u));
+ * TWO_LEVEL  M^-1 = D^-1 + P (P^T K P)^-1 P^T, P the rigid-body modes of
+ *            linear elasticity on aggregates of consecutive owner blocks
+ *            (PFEM_Q_AGGREGATE), orthonormalised per aggregate over its free
+ *            DOFs; P^T K P from the linear moduli (the Neo-Hookean tangent
+ *            at rest), built on the host and inverted once per mesh (at
+ *            most 1536 coarse DOFs), applied with the classic PCG loop. */
+enum { PFEM_PRECOND_JACOBI = 0, PFEM_PRECOND_TWO_LEVEL = 1 };
+
 /* Options of a solve.  pfem_solve and pfem_server_submit return
- * PFEM_E_INVALID_ARG for a tol that is not finite and > 0, an unknown prec
- * or krylov, or an inner_rtol outside {0} U (0, 0.5]. */
+ * PFEM_E_INVALID_ARG for a tol that is not finite and > 0, an unknown prec,
+ * krylov or precond, the fused formulation with the two-level
+ * preconditioner, or an inner_rtol outside {0} U (0, 0.5]. */
 typedef struct {
   double tol;           /* relative residual target |r_f| / |r_f(lifted)| (App. B) */
   double tol_fine;      /* skip iterating if the guess is already below (Sec. 'Warm-start'); 0 = off */
@@ -334,6 +420,8 @@ typedef struct {
   double inner_rtol;    /* FP32 mode: residual reduction per refinement sweep;
                            0 = automatic (1e-4 for FUSED, 1e-3 for CLASSIC) */
   int32_t krylov;       /* PFEM_KRYLOV_*: PCG formulation of the inner solves */
+  int32_t precond;      /* PFEM_PRECOND_*; TWO_LEVEL uses the classic loop (AUTO) and
+                           refuses PFEM_KRYLOV_FUSED */
 } pfem_solve_opts;
 
 typedef struct {
@@ -372,20 +460,52 @@ pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
                        double* u_out, int ptr_is_device, double* history,
                        int64_t history_cap, pfem_solve_report* rep);
 
-/* --------------------------------------------------------------- serving */
+/* Homogenised elasticity tensor of a periodic cell (App. D; Sec. 'Three-
+ * dimensional solid mechanics homogenization').  The mesh: 3D, linear
+ * (PFEM_LIN_3D), periodic springs set, and one node held at zero by the
+ * Dirichlet set (its 3 components), which removes the rigid translations.
+ * For each of the six unit macroscopic strains eps0^(IJ), (IJ) = 11, 22,
+ * 33, 12, 13, 23 (ones at (p, q) and (q, p) for the shears), the
+ * fluctuation X^v solves (K + P) X^v = F^(IJ), F^(IJ) the element loads of
+ * the uniform stress E : eps0^(IJ), to o->tol (relative residual; o->prec
+ * as for pfem_solve; the classic PCG); the six solves run together, every
+ * element launch covering all of them.  Then
+ * E^H_(IJ)(KL) = 1/|Omega| sum_e vol_e (eps0 - eps^v)^(IJ) : E_e :
+ * (eps0 - eps^v)^(KL), |Omega| the volume of the mesh's bounding box.
+ * u0: NULL (zero starts) or 6 n_dof float64 warm starts of the six
+ * fluctuations (case k at [k n_dof, (k+1) n_dof)); x_out: 6 n_dof float64,
+ * the fluctuations in the same layout; both device pointers if
+ * ptr_is_device, else host; caller numbering.  eh: host, 36 float64, E^H
+ * row-major in the case order above.  reps: host array of 6 reports or
+ * NULL.  Returns the most severe of the six statuses (outputs filled as
+ * for pfem_solve); argument and state errors as for pfem_solve. */
+pfem_status pfem_homogenize(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
+                            double* x_out, int ptr_is_device, double* eh,
+                            pfem_solve_report* reps);
+
+/* --------------------------------------------------------------- serving
+ * Many warm-started solves on one device (Sec. 'Warm-start': the network is
+ * pretrained once and its predictions start the solves of the deployment;
+ * each solve is the same as pfem_solve's).  Requests of uneven size share
+ * the device under a memory budget and are advanced together. */
 /* Create a server on ctx's device: at most max_slots live solves whose
- * device footprint (mesh arrays + solver state) sums to at most
- * hbm_budget_bytes.  A worker thread admits queued requests in arrival
- * order as slots and memory free up, keeps each live solve's state on the
- * device and advances all live solves together, one batched launch per
- * kernel family per step. */
+ * device footprint sums to at most hbm_budget_bytes.  Each live request is
+ * charged its solve state; a mesh the server uploads is charged once, while
+ * the server holds it for one or more live requests (a mesh resident on a
+ * caller's context is used in place and not charged).  A worker thread
+ * admits queued requests in arrival order as slots and memory free up (the
+ * head of the queue waits), keeps each live solve's state on the device and
+ * advances all live solves together, one batched launch per kernel family
+ * per step, so requests that arrive while others run overlap with them. */
 pfem_status pfem_server_create(pfem_ctx* ctx, int64_t hbm_budget_bytes,
                                int32_t max_slots, pfem_server** out);
 /* Queue a solve.  `m` must be finalized (a host-only mesh is fine); the
- * server keeps a reference, so the caller must not destroy it before the
- * result is collected.  u0: host n_dof float64 or NULL.  req_id must be
- * unique among requests not yet collected.  Returns PFEM_E_OOM if the
- * request alone can never fit the budget. */
+ * server keeps a reference, so the caller must not destroy the mesh, nor
+ * upload or release its device arrays, before the result is collected.
+ * u0: host n_dof float64 or NULL (copied).  req_id must be unique among
+ * requests not yet collected.  Returns PFEM_E_OOM if the solve state alone
+ * exceeds the budget; a request that needs the mesh uploaded and can never
+ * fit with it ends with PFEM_E_OOM when it reaches the head of the queue. */
 pfem_status pfem_server_submit(pfem_server* s, pfem_mesh* m, const double* u0,
                                const pfem_solve_opts* o, int64_t req_id);
 /* Completed request ids not yet reported (non-blocking). */
@@ -412,6 +532,13 @@ typedef struct {
  * submitted / completed / live / queued, the most live at once, device
  * bytes in use, their peak and the budget, worker steps and launches. */
 pfem_status pfem_server_get_stats(pfem_server* s, pfem_server_stats* out);
+/* Kernel timing of the server's own stream: the families of
+ * pfem_ctx_set_timing (bitmask; 0 = off), every launch timed.  Counters are
+ * zeroed and the mask takes effect at the worker's next step. */
+pfem_status pfem_server_set_timing(pfem_server* s, int family_mask);
+/* Counters of one family since the last pfem_server_set_timing, as
+ * pfem_ctx_kernel_stats, up to the worker's last completed step. */
+pfem_status pfem_server_kernel_stats(pfem_server* s, int family, pfem_kernel_stats* out);
 /* Stop the worker (live requests are cancelled) and free everything. */
 void pfem_server_destroy(pfem_server* s);
 

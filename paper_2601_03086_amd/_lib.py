@@ -34,6 +34,8 @@ PFEM_SCATTER_OWNER, PFEM_SCATTER_COLORED, PFEM_SCATTER_ATOMIC = 0, 1, 2
 PFEM_LAYOUT_USER, PFEM_LAYOUT_INTERNAL = 0, 1
 PFEM_MASK_NONE, PFEM_MASK_OUT, PFEM_MASK_IN = 0, 1, 2
 PFEM_Q_PERM, PFEM_Q_ELEM_ORDER, PFEM_Q_COLOR, PFEM_Q_FREE_INDEX, PFEM_Q_BLOCKS = range(5)
+PFEM_Q_AGGREGATE = 5
+PFEM_PRECOND_JACOBI, PFEM_PRECOND_TWO_LEVEL = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", 2: "SKIPPED_FINE", -1: "E_INVALID_ARG",
                 -2: "E_INVALID_MESH", -3: "E_OOM", -4: "E_DEVICE", -5: "E_BREAKDOWN",
@@ -55,7 +57,7 @@ class pfem_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("tol_fine", C.c_double), ("max_iter", C.c_int32),
                 ("n_load_steps", C.c_int32), ("max_newton", C.c_int32), ("prec", C.c_int32),
                 ("record_history", C.c_int32), ("inner_rtol", C.c_double),
-                ("krylov", C.c_int32)]
+                ("krylov", C.c_int32), ("precond", C.c_int32)]
 
 
 class pfem_solve_report(C.Structure):
@@ -68,6 +70,11 @@ class pfem_solve_report(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class pfem_kernel_stats(C.Structure):
+    _fields_ = [("launches_timed", C.c_int64), ("total_ms", C.c_double),
+                ("launches_run", C.c_int64), ("alg_bytes", C.c_double)]
 
 
 class pfem_server_stats(C.Structure):
@@ -91,16 +98,22 @@ PROTOTYPES = {
     "pfem_ctx_set_timing": (_I32, [_VP, C.c_int]),
     "pfem_ctx_set_timing_sample": (_I32, [_VP, C.c_int]),
     "pfem_ctx_kernel_time": (_I32, [_VP, C.c_int, C.POINTER(_I64), C.POINTER(_D)]),
+    "pfem_ctx_kernel_stats": (_I32, [_VP, C.c_int, C.POINTER(pfem_kernel_stats)]),
     "pfem_ctx_reset_timing": (_I32, [_VP]),
     "pfem_ctx_synchronize": (_I32, [_VP]),
     "pfem_mesh_create": (_I32, [_VP, C.c_int, _I64, _VP, _I64, _VP, _PVP]),
     "pfem_mesh_set_material": (_I32, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "pfem_mesh_set_dirichlet": (_I32, [_VP, _I64, _VP, _VP, _VP]),
     "pfem_mesh_set_neumann": (_I32, [_VP, _I64, _VP, _VP]),
+    "pfem_mesh_set_periodic": (_I32, [_VP, _I64, _VP, _D]),
     "pfem_mesh_set_node_order": (_I32, [_VP, C.c_int]),
     "pfem_mesh_finalize": (_I32, [_VP, C.c_int]),
     "pfem_mesh_get_info": (_I32, [_VP, C.POINTER(pfem_mesh_info)]),
     "pfem_mesh_query_int": (_I32, [_VP, C.c_int, _VP, _I64, C.POINTER(_I64)]),
+    "pfem_mesh_footprint": (_I32, [_VP, C.c_int, C.POINTER(_I64)]),
+    "pfem_mesh_prepare_coarse": (_I32, [_VP, C.POINTER(_I32)]),
+    "pfem_mesh_upload": (_I32, [_VP, _VP]),
+    "pfem_mesh_release_device": (_I32, [_VP]),
     "pfem_mesh_destroy": (None, [_VP]),
     "pfem_permute": (_I32, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "pfem_hvp": (_I32, [_VP, C.c_int, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP]),
@@ -118,6 +131,8 @@ PROTOTYPES = {
     "pfem_solve_opts_default": (None, [C.POINTER(pfem_solve_opts)]),
     "pfem_solve": (_I32, [_VP, _VP, C.POINTER(pfem_solve_opts), _VP, C.c_int, _VP, _I64,
                           C.POINTER(pfem_solve_report)]),
+    "pfem_homogenize": (_I32, [_VP, _VP, C.POINTER(pfem_solve_opts), _VP, C.c_int, _VP,
+                               _VP]),
     "pfem_server_create": (_I32, [_VP, _I64, _I32, _PVP]),
     "pfem_server_submit": (_I32, [_VP, _VP, _VP, C.POINTER(pfem_solve_opts), _I64]),
     "pfem_server_poll": (_I32, [_VP, _VP, _I64, C.POINTER(_I64)]),
@@ -125,6 +140,8 @@ PROTOTYPES = {
                                   C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]),
     "pfem_server_cancel": (_I32, [_VP, _I64]),
     "pfem_server_get_stats": (_I32, [_VP, C.POINTER(pfem_server_stats)]),
+    "pfem_server_set_timing": (_I32, [_VP, C.c_int]),
+    "pfem_server_kernel_stats": (_I32, [_VP, C.c_int, C.POINTER(pfem_kernel_stats)]),
     "pfem_server_destroy": (None, [_VP]),
 }
 

@@ -61,6 +61,7 @@ SCATTER = {"owner": L.PFEM_SCATTER_OWNER, "colored": L.PFEM_SCATTER_COLORED,
 LAYOUT = {"user": L.PFEM_LAYOUT_USER, "internal": L.PFEM_LAYOUT_INTERNAL}
 KRYLOV = {"auto": L.PFEM_KRYLOV_AUTO, "classic": L.PFEM_KRYLOV_CLASSIC,
           "fused": L.PFEM_KRYLOV_FUSED}
+PRECOND = {"jacobi": L.PFEM_PRECOND_JACOBI, "two_level": L.PFEM_PRECOND_TWO_LEVEL}
 
 
 def _ptr(a):
@@ -115,6 +116,13 @@ class Context:
         check(L.pfem_ctx_kernel_time(self.h, family, C.byref(n), C.byref(ms)))
         return n.value, ms.value
 
+    def kernel_stats(self, family):
+        """pfem_ctx_kernel_stats: launches timed, ms, launches run and
+        algorithmic bytes of one family since the last reset."""
+        k = L.pfem_kernel_stats()
+        check(L.pfem_ctx_kernel_stats(self.h, family, C.byref(k)))
+        return {f: getattr(k, f) for f, _ in k._fields_}
+
     def synchronize(self):
         check(L.pfem_ctx_synchronize(self.h))
 
@@ -124,7 +132,7 @@ class Mesh:
 
     def __init__(self, ctx, dim, coords, conn, model, param_kind, p0, p1,
                  dir_nodes=(), dir_comps=(), dir_values=(), facets=None,
-                 traction=None, block_nodes=0, order="blocks"):
+                 traction=None, block_nodes=0, order="blocks", pairs=None, pair_k=0.0):
         L.load()
         self.ctx = ctx
         self.dim = int(dim)
@@ -152,10 +160,23 @@ class Mesh:
             fa = np.ascontiguousarray(facets, dtype=np.int32)
             tr = np.ascontiguousarray(traction, dtype=np.float64)
             check(L.pfem_mesh_set_neumann(h, fa.shape[0], _ptr(fa), _ptr(tr)))
+        if pairs is not None and len(pairs):
+            pa = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+            check(L.pfem_mesh_set_periodic(h, pa.shape[0], _ptr(pa), float(pair_k)))
+        self.periodic = pairs is not None and len(pairs) > 0
         check(L.pfem_mesh_set_node_order(h, ORDER_IDS[order]))
         check(L.pfem_mesh_finalize(h, int(block_nodes)))
         self.info = self.get_info()
         _LIVE["mesh"].add(self)
+
+    @classmethod
+    def from_cell(cls, ctx, cell, block_nodes=0, order="blocks"):
+        """A periodic cell (homogenisation): linear 3D elements with their
+        (E, nu), the periodic springs, and the pin held at zero."""
+        pin = np.full(3, cell.pin, dtype=np.int32)
+        return cls(ctx, 3, cell.coords, cell.conn, "lin_3d", "E_nu", cell.p0, cell.p1,
+                   pin, np.arange(3, dtype=np.int8), np.zeros(3), None, None,
+                   block_nodes, order, pairs=cell.pairs, pair_k=cell.penalty)
 
     @classmethod
     def from_problem(cls, ctx, prob, block_nodes=0, order="blocks"):
@@ -172,6 +193,28 @@ class Mesh:
             self.h = None
 
     __del__ = close
+
+    def footprint(self, prec="fp32"):
+        """Device bytes of the mesh arrays plus one solve in prec."""
+        b = C.c_int64()
+        check(L.pfem_mesh_footprint(self.h, PREC[prec], C.byref(b)))
+        return b.value
+
+    def prepare_coarse(self):
+        """Build the two-level preconditioner's coarse space now (host);
+        returns the coarse dimension."""
+        n = C.c_int32()
+        check(L.pfem_mesh_prepare_coarse(self.h, C.byref(n)))
+        return n.value
+
+    def upload(self, ctx):
+        """Make a host-only mesh resident on ctx's device."""
+        check(L.pfem_mesh_upload(self.h, ctx.h))
+        self.ctx = ctx
+
+    def release_device(self):
+        """Free the device arrays; the mesh stays usable on the host."""
+        check(L.pfem_mesh_release_device(self.h))
 
     def get_info(self):
         inf = L.pfem_mesh_info()
@@ -276,7 +319,8 @@ class Mesh:
     # ------------------------------------------------------------ solve
     @staticmethod
     def opts(tol=1e-8, prec="fp32", tol_fine=0.0, max_iter=0, n_load_steps=10,
-             max_newton=50, record_history=1, inner_rtol=0.0, krylov="auto"):
+             max_newton=50, record_history=1, inner_rtol=0.0, krylov="auto",
+             precond="jacobi"):
         o = L.pfem_solve_opts()
         L.pfem_solve_opts_default(C.byref(o))
         o.tol = tol
@@ -288,6 +332,7 @@ class Mesh:
         o.record_history = record_history
         o.inner_rtol = inner_rtol
         o.krylov = KRYLOV[krylov]
+        o.precond = PRECOND[precond]
         return o
 
     @_on_stream
@@ -315,6 +360,46 @@ class Mesh:
                 e.report, e.u, e.history = r, u, hist[:rep.history_len].copy()
                 raise
         return u, r, hist[:rep.history_len].copy()
+
+
+def homogenize(mesh, u0=None, device_io=False, **kw):
+    """pfem_homogenize on a periodic cell mesh: returns (fluctuations
+    (6, n_dof), E^H (6, 6), list of six report dicts)."""
+    o = Mesh.opts(**kw)
+    reps = (L.pfem_solve_report * 6)()
+    eh = np.zeros(36, dtype=np.float64)
+    nd = mesh.n_dof
+    ctx = mesh.ctx
+    if device_io:
+        u0t = None
+        if u0 is not None:
+            u0t = torch.as_tensor(u0, dtype=torch.float64, device=ctx.device).reshape(-1)
+            if u0t.numel() != 6 * nd:
+                raise ValueError("u0 must hold 6 n_dof entries")
+            u0t = u0t.contiguous()
+        x = torch.empty(6 * nd, dtype=torch.float64, device=ctx.device)
+        cur = torch.cuda.current_stream(ctx.device)
+        ctx.stream.wait_stream(cur)
+        st = L.pfem_homogenize(mesh.h, _ptr(u0t), C.byref(o), _ptr(x), 1, _ptr(eh), reps)
+        cur.wait_stream(ctx.stream)
+        x = x.reshape(6, nd)
+    else:
+        u0a = None
+        if u0 is not None:
+            u0a = np.ascontiguousarray(u0, dtype=np.float64).reshape(-1)
+            if u0a.size != 6 * nd:
+                raise ValueError("u0 must hold 6 n_dof entries")
+        x = np.zeros(6 * nd, dtype=np.float64)
+        st = L.pfem_homogenize(mesh.h, _ptr(u0a), C.byref(o), _ptr(x), 0, _ptr(eh), reps)
+        x = x.reshape(6, nd)
+    out = []
+    for r in reps:
+        d = r.as_dict()
+        d["status_name"] = L.STATUS_NAMES.get(r.status, r.status)
+        out.append(d)
+    if st < 0:
+        check(st)
+    return x, eh.reshape(6, 6), out
 
 
 class Batch:
@@ -412,6 +497,17 @@ class Server:
 
     def cancel(self, req_id):
         check(L.pfem_server_cancel(self.h, int(req_id)))
+
+    def set_timing(self, families=()):
+        mask = 0
+        for f in families or ():
+            mask |= 1 << f
+        check(L.pfem_server_set_timing(self.h, mask))
+
+    def kernel_stats(self, family):
+        k = L.pfem_kernel_stats()
+        check(L.pfem_server_kernel_stats(self.h, family, C.byref(k)))
+        return {f: getattr(k, f) for f, _ in k._fields_}
 
     def stats(self):
         s = L.pfem_server_stats()

@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include "mesh.h"
+#include "coarse.h"
 #include "solver.h"
 
 using namespace pfem;
@@ -118,6 +119,18 @@ pfem_status pfem_ctx_kernel_time(pfem_ctx* ctx, int family, int64_t* launches,
   PFEM_TRY_END
 }
 
+pfem_status pfem_ctx_kernel_stats(pfem_ctx* ctx, int family, pfem_kernel_stats* out) {
+  PFEM_TRY_BEGIN
+  require(ctx != nullptr && out != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+  require(family >= 0 && family < FAM_COUNT, PFEM_E_INVALID_ARG, "bad kernel family");
+  ctx->c->drain_timing();
+  out->launches_timed = ctx->c->fam_launches[family];
+  out->total_ms = ctx->c->fam_ms[family];
+  out->launches_run = ctx->c->fam_run[family];
+  out->alg_bytes = ctx->c->fam_alg_bytes[family];
+  PFEM_TRY_END
+}
+
 pfem_status pfem_ctx_reset_timing(pfem_ctx* ctx) {
   PFEM_TRY_BEGIN
   require(ctx != nullptr, PFEM_E_INVALID_ARG, "ctx is NULL");
@@ -125,6 +138,8 @@ pfem_status pfem_ctx_reset_timing(pfem_ctx* ctx) {
   for (int i = 0; i < FAM_COUNT; ++i) {
     ctx->c->fam_launches[i] = 0;
     ctx->c->fam_ms[i] = 0.0;
+    ctx->c->fam_run[i] = 0;
+    ctx->c->fam_alg_bytes[i] = 0.0;
   }
   PFEM_TRY_END
 }
@@ -233,6 +248,26 @@ pfem_status pfem_mesh_set_neumann(pfem_mesh* m, int64_t n_facets, const int32_t*
   PFEM_TRY_END
 }
 
+pfem_status pfem_mesh_set_periodic(pfem_mesh* m, int64_t n_pairs, const int32_t* pairs,
+                                   double stiffness) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
+  require(!m->finalized, PFEM_E_STATE, "mesh already finalized");
+  require(n_pairs >= 0 && (n_pairs == 0 || pairs != nullptr), PFEM_E_INVALID_ARG,
+          "bad pair array");
+  require(n_pairs == 0 || (std::isfinite(stiffness) && stiffness > 0), PFEM_E_INVALID_ARG,
+          "spring stiffness must be finite and > 0");
+  for (int64_t q = 0; q < n_pairs; ++q) {
+    const int32_t a = pairs[2 * q], b = pairs[2 * q + 1];
+    require(a >= 0 && a < m->n_nodes && b >= 0 && b < m->n_nodes, PFEM_E_INVALID_ARG,
+            "periodic pair node out of range");
+    require(a != b, PFEM_E_INVALID_ARG, "periodic pair joins a node to itself");
+  }
+  m->pairs.assign(pairs, pairs + 2 * n_pairs);
+  m->pair_k = n_pairs > 0 ? stiffness : 0.0;
+  PFEM_TRY_END
+}
+
 pfem_status pfem_mesh_set_node_order(pfem_mesh* m, int order) {
   PFEM_TRY_BEGIN
   require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
@@ -248,6 +283,8 @@ pfem_status pfem_mesh_finalize(pfem_mesh* m, int block_nodes) {
   require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
   require(!m->finalized, PFEM_E_STATE, "mesh already finalized");
   require(block_nodes >= 0, PFEM_E_INVALID_ARG, "block_nodes < 0");
+  require(m->pairs.empty() || (m->model >= 0 && !m->nonlinear), PFEM_E_INVALID_ARG,
+          "periodic springs need a linear model");
   mesh_finalize_host(m, block_nodes);
   if (m->ctx != nullptr) mesh_upload(m, m->ctx);
   PFEM_TRY_END
@@ -272,8 +309,8 @@ pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* o) {
   o->device_bytes = m->finalized ? mesh_device_bytes(m) : 0;
   pfem_solve_opts d32;
   pfem_solve_opts_default(&d32);   // FP32 mode, AUTO formulation
-  o->solve_bytes_fp32 = m->finalized ? solve_bytes(m, PFEM_FP32, krylov_fused(d32, m)) : 0;
-  o->solve_bytes_fp64 = m->finalized ? solve_bytes(m, PFEM_FP64, false) : 0;
+  o->solve_bytes_fp32 = m->finalized ? solve_bytes(m, PFEM_FP32, krylov_fused(d32, m), false) : 0;
+  o->solve_bytes_fp64 = m->finalized ? solve_bytes(m, PFEM_FP64, false, false) : 0;
   o->f_ext_norm = m->fext_norm;
   o->band_blocks = m->band_blocks;
   PFEM_TRY_END
@@ -300,12 +337,62 @@ pfem_status pfem_mesh_query_int(const pfem_mesh* m, int which, int32_t* out, int
       }
       src = &tmp;
       break;
+    case PFEM_Q_AGGREGATE: {
+      const int G = coarse_group(m);
+      tmp.resize(m->n_nodes);
+      for (int64_t n = 0; n < m->n_nodes; ++n) tmp[n] = (m->perm[n] / m->bn) / G;
+      src = &tmp;
+      break;
+    }
     default: throw Error{PFEM_E_INVALID_ARG, "bad query"};
   }
   if (n) *n = (int64_t)src->size();
   if (out != nullptr) {
     require(cap >= 0, PFEM_E_INVALID_ARG, "cap < 0");
     std::copy(src->begin(), src->begin() + std::min<int64_t>(cap, src->size()), out);
+  }
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_footprint(const pfem_mesh* m, int prec, int64_t* bytes) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr && bytes != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+  require(prec == PFEM_FP64 || prec == PFEM_FP32, PFEM_E_INVALID_ARG, "bad precision");
+  require(m->finalized, PFEM_E_STATE, "mesh not finalized");
+  pfem_solve_opts o;
+  pfem_solve_opts_default(&o);   // AUTO formulation
+  o.prec = prec;
+  *bytes = mesh_device_bytes(m) + solve_bytes(m, prec, krylov_fused(o, m), false);
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_prepare_coarse(pfem_mesh* m, int32_t* n_coarse) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
+  require(m->finalized, PFEM_E_STATE, "mesh not finalized");
+  coarse_build(m);
+  if (n_coarse) *n_coarse = m->coarse->n_c;
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_upload(pfem_mesh* m, pfem_ctx* ctx) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr && ctx != nullptr, PFEM_E_INVALID_ARG, "NULL argument");
+  require(m->finalized, PFEM_E_STATE, "mesh not finalized");
+  if (m->uploaded) {
+    require(m->ctx == ctx->c, PFEM_E_STATE, "mesh is resident on another context");
+  } else {
+    mesh_upload(m, ctx->c);
+  }
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_release_device(pfem_mesh* m) {
+  PFEM_TRY_BEGIN
+  require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
+  if (m->uploaded) {
+    PFEM_HIP(hipSetDevice(m->ctx->device));
+    mesh_release_device(m);
   }
   PFEM_TRY_END
 }
@@ -351,6 +438,8 @@ static void elem_call(pfem_mesh* m, int prec, int layout, int scatter, int mask,
           "bad layout");
   require(scatter >= PFEM_SCATTER_OWNER && scatter <= PFEM_SCATTER_ATOMIC, PFEM_E_INVALID_ARG,
           "bad scatter mode");
+  require(scatter == PFEM_SCATTER_OWNER || m->pairs.empty(), PFEM_E_INVALID_ARG,
+          "periodic springs are applied by the owner scatter only");
   require(y != nullptr, PFEM_E_INVALID_ARG, "output is NULL");
   Ctx* ctx = m->ctx;
   m->scratch.ensure(m->n_dof(), m->n_blocks);
@@ -626,6 +715,7 @@ void pfem_solve_opts_default(pfem_solve_opts* o) {
   o->record_history = 1;
   o->inner_rtol = 0.0;   // automatic (by PCG formulation)
   o->krylov = PFEM_KRYLOV_AUTO;
+  o->precond = PFEM_PRECOND_JACOBI;
 }
 
 pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o, double* u_out,
@@ -645,10 +735,18 @@ pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
   std::unique_ptr<SolveState>& cached = m->solve_state;
   const int prec = o->prec;
   const bool fused = krylov_fused(*o, m);
-  if (!cached || cached->prec != prec || cached->hist_cap < hcap || cached->fused != fused) {
+  require(!(fused && !m->pairs.empty()), PFEM_E_INVALID_ARG,
+          "the fused PCG does not apply periodic springs: use the classic formulation");
+  const bool two_level = o->precond == PFEM_PRECOND_TWO_LEVEL;
+  if (!cached || cached->prec != prec || cached->hist_cap < hcap || cached->fused != fused ||
+      (two_level && cached->tl_dev == nullptr)) {
     cached.reset();
     cached.reset(new SolveState());
     cached->alloc(prec, nd, m->n_blocks, std::max<int64_t>(hcap, 1024), m->nonlinear, fused);
+    if (two_level) {
+      coarse_upload(m, ctx);
+      cached->alloc_two_level(m);
+    }
   }
   SlotRun s;
   s.m = m;

@@ -364,6 +364,27 @@ __device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __re
                                                 alpha, beta);
 }
 
+// Periodic springs at component c of owned node n: the virtual elements of a
+// periodic cell, each a spring of stiffness k to a partner node.  Their
+// energy 1/2 k |x_n - x_b|^2 adds k sum_b (x_n - x_b) to the apply (input
+// X = v) and to the internal force (X = u), and k per partner to the
+// diagonal.  With PFEM_MASK_IN an apply reads zero at Dirichlet DOFs.
+template <int D, typename T, int OP>
+__device__ __forceinline__ T periodic_springs(const MeshDev& m, const T* __restrict__ X, int mask,
+                                              int n, int c, bool con) {
+  const int q0 = ldg(m.pair_ptr + n), q1 = ldg(m.pair_ptr + n + 1);
+  if (OP == OP_DIAG) return (T)(m.pair_k * (double)(q1 - q0));
+  const bool mask_in = OP == OP_APPLY && (mask & PFEM_MASK_IN);
+  const T xn = (mask_in && con) ? T(0) : ldg(X + (size_t)n * D + c);
+  T s = T(0);
+  for (int q = q0; q < q1; ++q) {
+    const int b = ldg(m.pair_nbr + q);
+    const bool cb = mask_in && ((ldg(m.dmask + b) >> c) & 1);
+    s += xn - (cb ? T(0) : ldg(X + (size_t)b * D + c));
+  }
+  return (T)m.pair_k * s;
+}
+
 template <int D, typename T, int OP, bool NL>
 __global__ void __launch_bounds__(kThreads)
 k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work, const BaseArgs ba) {
@@ -387,13 +408,17 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work, const Bas
                                                                      nloc, acc);
   T* Y = operand<T>(tp->y, ba.y, ba.rel);
   const T* W = static_cast<const T*>(tp->w);
+  const double* FE = tp->fext != nullptr ? tp->fext : m.fext;
+  const bool springs = m.pair_ptr != nullptr && !tp->no_pairs;
   double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
   const size_t g0 = (size_t)n0 * D;
   for (int i = threadIdx.x; i < nown; i += kThreads) {
     const size_t gi = g0 + i;
     T val = (T)acc[i];
     const bool con = (ldg(m.dmask + n0 + i / D) >> (i % D)) & 1;
-    if (OP == OP_FORCE) val -= (T)(tp->fscale * ldg(m.fext + gi));
+    if (OP == OP_FORCE) val -= (T)(tp->fscale * ldg(FE + gi));
+    if (springs) val += periodic_springs<D, T, OP>(m, OP == OP_APPLY ? V : U, mask, n0 + i / D,
+                                                   i % D, con);
     if (OP == OP_DIAG) {
       if (con) val = T(1);
       else if (tp->s != 0.0) val = T(1) / val;   // inverse diagonal for PCG
@@ -406,6 +431,113 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work, const Bas
   }
   // an apply only reports y.w (slot 0): PCG init kernels own slots 1 and 2
   write_partials(tp->red, m.n_blocks, blk, part, 0, OP == OP_APPLY ? 1 : 2);
+}
+
+// ------------------------------------------- several right-hand sides
+// K.v for up to kMultiMax right-hand sides on one linear 3D mesh (the six
+// cell problems of a homogenisation): workgroup = node block, and every
+// element is visited once for all of them -- connectivity, coordinates,
+// material and the element geometry are loaded and computed once, then
+// each right-hand side's strain, stress and scatter follows in turn
+// (tasks[r] holds right-hand side r: v = p, y = q, w = p, its partial
+// sums).  A task whose PCG has stopped is skipped.  The LDS holds one
+// float64 accumulator per owned DOF and right-hand side.
+constexpr int kMultiMax = 6;
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_owner_multi(const Task* __restrict__ tasks, int nr, const int2* __restrict__ work) {
+  constexpr int D = 3;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int blk = work[blockIdx.x].y;
+  const MeshDev m = tasks[0].m;
+  bool on[kMultiMax];
+  int any = 0;
+#pragma unroll
+  for (int r = 0; r < kMultiMax; ++r) {
+    const Task* tp = tasks + min(r, nr - 1);
+    on[r] = r < nr && tp->active && !(tp->pcg && ldg(&tp->sc->state) != 0);
+    any |= on[r] ? 1 : 0;
+  }
+  if (!any) return;
+  const int n0 = blk * m.bn;
+  const int nloc = min(m.bn, m.n_nodes - n0);
+  const int nown = nloc * D;
+  const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
+  double* acc = reinterpret_cast<double*>(smem_raw);   // [r][nown]
+  for (int i = threadIdx.x; i < nr * nown; i += kThreads) acc[i] = 0.0;
+  __syncthreads();
+  const int n_own = br.y - br.x;
+  const int n_halo = br.w - br.z;
+  const int total = n_own + n_halo;
+  for (int t = threadIdx.x; t < total; t += kThreads) {
+    const int h = ldx(m.halo, (uint32_t)(br.z + min(max(t - n_own, 0), max(n_halo - 1, 0))));
+    const int e = t < n_own ? br.x + t : h;
+    int nd[D + 1];
+    load_conn<D, T>(m, e, nd);
+    ElemX<D, T> x;
+    load_elem_x<D, T>(m, nd, x);
+    const T mu = mat_mu<T>(m, e);
+    const T lam = mat_lam<T>(m, e, mu);
+    Geo<D, T> g;
+    geometry_x<D, T>(m, x, g);
+    const T adet = g.det < T(0) ? -g.det : g.det;
+    const T s_sym = T(1) / (T(Fact<D>::v) * adet);
+#pragma unroll 1
+    for (int r = 0; r < nr; ++r) {
+      if (!on[r]) continue;
+      const T* V = static_cast<const T*>(tasks[r].v);
+      T v[D + 1][D];
+#pragma unroll
+      for (int a = 0; a <= D; ++a) load_nodal<D, T>(V, nd[a], v[a]);
+      T M[D][D], S[D][D], y[D + 1][D];
+      grad_tilde<D, T>(v, g, M);
+      linear_stress_tilde<D, T>(M, mu, lam, S);
+      scatter_rows<D, T>(S, g, s_sym, y);
+      lds_accumulate<D, T, double>(acc + r * nown, nd, n0, nloc, y);
+    }
+  }
+  __syncthreads();
+  const size_t g0 = (size_t)n0 * D;
+#pragma unroll 1
+  for (int r = 0; r < nr; ++r) {
+    if (!on[r]) continue;   // uniform over the workgroup
+    const Task* tp = tasks + r;
+    T* Y = static_cast<T*>(tp->y);
+    const T* V = static_cast<const T*>(tp->v);
+    const T* W = static_cast<const T*>(tp->w);
+    const bool springs = m.pair_ptr != nullptr && !tp->no_pairs;
+    double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nown; i += kThreads) {
+      const size_t gi = g0 + i;
+      T val = (T)acc[r * nown + i];
+      const bool con = (ldg(m.dmask + n0 + i / D) >> (i % D)) & 1;
+      if (springs) val += periodic_springs<D, T, OP_APPLY>(m, V, tp->mask, n0 + i / D, i % D, con);
+      if ((tp->mask & PFEM_MASK_OUT) && con) val = T(0);
+      stg(Y + gi, val);
+      if (W != nullptr) part[0] += (double)val * (double)ldg(W + gi);
+    }
+    write_partials(tp->red, m.n_blocks, blk, part, 0, 1);
+  }
+}
+
+bool owner_multi_fits(int bn, int nr) {
+  return nr >= 1 && nr <= kMultiMax && (size_t)nr * bn * 3 * sizeof(double) <= 64 * 1024;
+}
+
+void launch_owner_multi(Ctx* ctx, int prec, const Task* tasks_dev, int nr,
+                        const int2* work_dev, int n_work, int bn) {
+  hipEvent_t ev = nullptr;
+  ctx->timing_begin(FAM_APPLY, &ev);
+  const size_t sm = (size_t)nr * bn * 3 * sizeof(double);
+  if (prec == PFEM_FP32)
+    hipLaunchKernelGGL(k_owner_multi<float>, dim3(n_work), dim3(kThreads), sm, ctx->stream,
+                       tasks_dev, nr, work_dev);
+  else
+    hipLaunchKernelGGL(k_owner_multi<double>, dim3(n_work), dim3(kThreads), sm, ctx->stream,
+                       tasks_dev, nr, work_dev);
+  PFEM_HIP(hipGetLastError());
+  ctx->timing_end(FAM_APPLY, ev);
 }
 
 // ----------------------------------------------------- fused PCG iteration
@@ -761,16 +893,38 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work, const Ba
       else part[0] += vol * psi0;
     }
   }
-  // - f_ext . u   (or - s f_ext . v for the difference)
+  // - f_ext . u   (or - s f_ext . v for the difference), and the energy of
+  // the periodic springs, 1/2 k |u_n - u_b|^2 per pair: a quarter from each
+  // end's owner
   const size_t g0 = (size_t)n0 * D;
+  const double* FE = tp->fext != nullptr ? tp->fext : m.fext;
+  const bool springs = m.pair_ptr != nullptr && !tp->no_pairs;
   for (int i = threadIdx.x; i < nloc * D; i += kThreads) {
-    const double f = tp->fscale * ldg(m.fext + g0 + i);
+    const double f = tp->fscale * ldg(FE + g0 + i);
     if (DIFF) {
       const double w = s * f * (double)ldg(V + g0 + i);
       part[0] -= w;
       part[2] += fabs(w);
     } else {
       part[0] -= f * (double)ldg(U + g0 + i);
+    }
+    if (springs) {
+      const int n = n0 + i / D, c = i % D;
+      const int q0 = ldg(m.pair_ptr + n), q1 = ldg(m.pair_ptr + n + 1);
+      const double un = (double)ldg(U + g0 + i);
+      for (int q = q0; q < q1; ++q) {
+        const size_t gb = (size_t)ldg(m.pair_nbr + q) * D + c;
+        const double du = un - (double)ldg(U + gb);
+        const double e0 = 0.25 * m.pair_k * du * du;
+        if (DIFF) {
+          const double dw = du + s * ((double)ldg(V + g0 + i) - (double)ldg(V + gb));
+          const double e1 = 0.25 * m.pair_k * dw * dw;
+          part[0] += e1 - e0;
+          part[2] += e0 + e1;
+        } else {
+          part[0] += e0;
+        }
+      }
     }
   }
   write_partials(tp->red, m.n_blocks, blk, part, 0, DIFF ? 3 : 2);

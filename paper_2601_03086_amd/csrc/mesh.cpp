@@ -25,6 +25,7 @@
 //    with k the sorted position and fmix32 the MurmurHash3 finaliser;
 //  * free DOFs ranked by increasing caller DOF index.
 #include "mesh.h"
+#include "coarse.h"
 
 #include <algorithm>
 #include <cmath>
@@ -61,6 +62,8 @@ void lame_from_params(int model, int param_kind, double p0, double p1, double* m
     if (model == PFEM_LIN_PLANE_STRESS) *lam = 2.0 * p0 * p1 / (p1 + 2.0 * p0);
   }
 }
+
+static void prepare_device_images(pfem_mesh* m);
 
 static void validate(const pfem_mesh* m) {
   const int D = m->dim;
@@ -563,7 +566,106 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
     for (int k = 1; k < 8; ++k) pre[k] = pre[k - 1] + std::max(cnt[k - 1], 0);
     for (int i = 0; i < nb; ++i) m->work[i] = make_int2(0, pre[i % 8] + i / 8);
   }
+  prepare_device_images(m);
   m->finalized = true;
+}
+
+// Host images of the device arrays that are not plain copies, prepared once
+// at finalize so that an upload (a server admitting a request) only copies.
+static void prepare_device_images(pfem_mesh* m) {
+  const int D = m->dim;
+  m->mu32.assign(m->mu_int.begin(), m->mu_int.end());
+  m->lam32.assign(m->lam_int.begin(), m->lam_int.end());
+  // 31-bit fixed-point coordinates over the bounding box (float32 kernels):
+  // 0 <= q < 2^31, so the difference of any two fits a signed 32-bit integer
+  // (an element spanning more than half the box must not wrap around)
+  m->xq.assign(m->X_int.size(), 0u);
+  for (int i = 0; i < 3; ++i) m->qscale[i] = 1.f;
+  for (int i = 0; i < D; ++i) {
+    double lo = 0.0, hi = 0.0;
+    for (int64_t n = 0; n < m->n_nodes; ++n) {
+      const double v = m->X_int[n * D + i];
+      if (n == 0 || v < lo) lo = v;
+      if (n == 0 || v > hi) hi = v;
+    }
+    const double step = hi > lo ? (hi - lo) / 2147483647.0 : 1.0;
+    m->qscale[i] = (float)step;
+    for (int64_t n = 0; n < m->n_nodes; ++n) {
+      const double t = std::round((m->X_int[n * D + i] - lo) / step);
+      m->xq[n * D + i] = (uint32_t)std::min(std::max(t, 0.0), 2147483647.0);
+    }
+  }
+  // packed 2D connectivity: smallest node first, 16-bit offsets of the
+  // other two (3D kernels read the plain 16-byte rows)
+  const int nv = D + 1;
+  bool packable = D == 2;
+  m->connp.assign(packable ? (size_t)m->n_elems * 2 : 0, 0u);
+  for (int64_t s = 0; packable && s < m->n_elems; ++s) {
+    const int32_t* c = &m->conn_int[s * nv];
+    int amin = 0;
+    for (int a = 1; a < nv; ++a)
+      if (c[a] < c[amin]) amin = a;
+    uint32_t off[2];
+    for (int k = 1; k < nv; ++k) {
+      const int64_t dlt = (int64_t)c[(amin + k) % nv] - c[amin];
+      if (dlt > 65535) packable = false;
+      off[k - 1] = (uint32_t)dlt;
+    }
+    uint32_t* o = &m->connp[s * 2];
+    o[0] = (uint32_t)c[amin];
+    o[1] = (off[0] & 0xffffu) | ((off[1] & 0xffffu) << 16);
+  }
+  if (!packable) {
+    m->connp.clear();
+    m->connp.shrink_to_fit();
+  }
+  m->halo_pad = m->halo;   // one padding entry: clamped reads
+  m->halo_pad.push_back(0);
+  // periodic springs: partners of every internal node, sorted (CSR)
+  m->pair_ptr.clear();
+  m->pair_nbr.clear();
+  if (!m->pairs.empty()) {
+    const int64_t np = (int64_t)m->pairs.size() / 2;
+    m->pair_ptr.assign(m->n_nodes + 1, 0);
+    for (int64_t q = 0; q < np; ++q) {
+      ++m->pair_ptr[m->perm[m->pairs[2 * q]] + 1];
+      ++m->pair_ptr[m->perm[m->pairs[2 * q + 1]] + 1];
+    }
+    for (int64_t n = 0; n < m->n_nodes; ++n) m->pair_ptr[n + 1] += m->pair_ptr[n];
+    m->pair_nbr.assign(m->pair_ptr[m->n_nodes], 0);
+    std::vector<int32_t> fill(m->pair_ptr.begin(), m->pair_ptr.end() - 1);
+    for (int64_t q = 0; q < np; ++q) {
+      const int32_t a = m->perm[m->pairs[2 * q]], b = m->perm[m->pairs[2 * q + 1]];
+      m->pair_nbr[fill[a]++] = b;
+      m->pair_nbr[fill[b]++] = a;
+    }
+    for (int64_t n = 0; n < m->n_nodes; ++n)
+      std::sort(m->pair_nbr.begin() + m->pair_ptr[n], m->pair_nbr.begin() + m->pair_ptr[n + 1]);
+  }
+  // volume of the cell the coordinates span (homogenisation divides by it)
+  m->cell_volume = 1.0;
+  for (int i = 0; i < D; ++i) {
+    double lo = 0.0, hi = 0.0;
+    for (int64_t n = 0; n < m->n_nodes; ++n) {
+      const double v = m->X_int[n * D + i];
+      if (n == 0 || v < lo) lo = v;
+      if (n == 0 || v > hi) hi = v;
+    }
+    m->cell_volume *= hi - lo;
+  }
+  // uniform lambda / mu ratio (uniform Poisson ratio): kernels stream mu only
+  m->lam_uniform = false;
+  m->lam_ratio = 0.0;
+  if (m->n_elems > 0 && m->mu_int[0] != 0.0) {
+    const double r = m->lam_int[0] / m->mu_int[0];
+    bool uni = std::isfinite(r);
+    for (int64_t s = 0; uni && s < m->n_elems; ++s)
+      uni = std::fabs(m->lam_int[s] - r * m->mu_int[s]) <= 2e-15 * std::fabs(m->lam_int[s]);
+    if (uni) {
+      m->lam_uniform = true;
+      m->lam_ratio = r;
+    }
+  }
 }
 
 // --------------------------------------------------------------- device
@@ -583,68 +685,28 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   PFEM_HIP(hipSetDevice(ctx->device));
   MeshDevBuffers& d = m->dev;
   d.bytes = 0;
-  std::vector<float> mu32(m->mu_int.begin(), m->mu_int.end());
-  std::vector<float> lam32(m->lam_int.begin(), m->lam_int.end());
-  // 31-bit fixed-point coordinates over the bounding box (float32 kernels):
-  // 0 <= q < 2^31, so the difference of any two fits a signed 32-bit integer
-  // (an element spanning more than half the box must not wrap around)
-  const int D = m->dim;
-  std::vector<uint32_t> xq(m->X_int.size());
-  float qscale[3] = {1.f, 1.f, 1.f};
-  for (int i = 0; i < D; ++i) {
-    double lo = 0.0, hi = 0.0;
-    for (int64_t n = 0; n < m->n_nodes; ++n) {
-      const double v = m->X_int[n * D + i];
-      if (n == 0 || v < lo) lo = v;
-      if (n == 0 || v > hi) hi = v;
-    }
-    const double step = hi > lo ? (hi - lo) / 2147483647.0 : 1.0;
-    qscale[i] = (float)step;
-    for (int64_t n = 0; n < m->n_nodes; ++n) {
-      const double t = std::round((m->X_int[n * D + i] - lo) / step);
-      xq[n * D + i] = (uint32_t)std::min(std::max(t, 0.0), 2147483647.0);
-    }
-  }
-  // packed 2D connectivity: smallest node first, 16-bit offsets of the
-  // other two (3D kernels read the plain 16-byte rows)
-  const int nv = D + 1;
-  bool packable = D == 2;
-  std::vector<uint32_t> cp(packable ? (size_t)m->n_elems * 2 : 0);
-  for (int64_t s = 0; packable && s < m->n_elems; ++s) {
-    const int32_t* c = &m->conn_int[s * nv];
-    int amin = 0;
-    for (int a = 1; a < nv; ++a)
-      if (c[a] < c[amin]) amin = a;
-    uint32_t off[2];
-    for (int k = 1; k < nv; ++k) {
-      const int64_t dlt = (int64_t)c[(amin + k) % nv] - c[amin];
-      if (dlt > 65535) packable = false;
-      off[k - 1] = (uint32_t)dlt;
-    }
-    uint32_t* o = &cp[s * 2];
-    o[0] = (uint32_t)c[amin];
-    o[1] = (off[0] & 0xffffu) | ((off[1] & 0xffffu) << 16);
-  }
-  if (!packable) cp.clear();
+  const bool packable = !m->connp.empty();
   try {
     d.X = upload(m->X_int, d.bytes);
-    d.Xq = upload(xq, d.bytes);
-    d.connp = upload(cp, d.bytes);
+    d.Xq = upload(m->xq, d.bytes);
+    d.connp = upload(m->connp, d.bytes);
     d.conn = upload(m->conn_int, d.bytes);
-    d.mu32 = upload(mu32, d.bytes);
-    d.lam32 = upload(lam32, d.bytes);
+    d.mu32 = upload(m->mu32, d.bytes);
+    d.lam32 = upload(m->lam32, d.bytes);
     d.mu64 = upload(m->mu_int, d.bytes);
     d.lam64 = upload(m->lam_int, d.bytes);
     d.dmask = upload(m->dmask, d.bytes);
     d.blocks = upload(m->blocks, d.bytes);
-    std::vector<int32_t> halo_pad(m->halo);   // one padding entry: clamped reads
-    halo_pad.push_back(0);
-    d.halo = upload(halo_pad, d.bytes);
+    d.halo = upload(m->halo_pad, d.bytes);
     d.fext = upload(m->fext_int, d.bytes);
     d.ubar = upload(m->ubar_int, d.bytes);
     d.colored = upload(m->colored, d.bytes);
     d.perm = upload(m->perm, d.bytes);
     d.work = upload(m->work, d.bytes);
+    if (!m->pair_ptr.empty()) {
+      d.pair_ptr = upload(m->pair_ptr, d.bytes);
+      d.pair_nbr = upload(m->pair_nbr, d.bytes);
+    }
   } catch (...) {
     mesh_release_device(m);
     throw;
@@ -654,7 +716,7 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   md.Xq = d.Xq;
   md.connp = d.connp;
   md.conn_packed = packable ? 1 : 0;
-  for (int i = 0; i < 3; ++i) md.qscale[i] = qscale[i];
+  for (int i = 0; i < 3; ++i) md.qscale[i] = m->qscale[i];
   md.conn = d.conn;
   md.mu32 = d.mu32;
   md.lam32 = d.lam32;
@@ -666,6 +728,9 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   md.fext = d.fext;
   md.ubar = d.ubar;
   md.colored = d.colored;
+  md.pair_ptr = d.pair_ptr;
+  md.pair_nbr = d.pair_nbr;
+  md.pair_k = m->pair_ptr.empty() ? 0.0 : m->pair_k;
   md.n_nodes = (int32_t)m->n_nodes;
   md.n_elems = (int32_t)m->n_elems;
   md.n_blocks = m->n_blocks;
@@ -674,18 +739,8 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   md.model = m->model;
   md.nonlinear = m->nonlinear ? 1 : 0;
   // uniform lambda / mu ratio (uniform Poisson ratio): kernels stream mu only
-  md.lam_uniform = 0;
-  md.lam_ratio = 0.0;
-  if (m->n_elems > 0 && m->mu_int[0] != 0.0) {
-    const double r = m->lam_int[0] / m->mu_int[0];
-    bool uni = std::isfinite(r);
-    for (int64_t s = 0; uni && s < m->n_elems; ++s)
-      uni = std::fabs(m->lam_int[s] - r * m->mu_int[s]) <= 2e-15 * std::fabs(m->lam_int[s]);
-    if (uni) {
-      md.lam_uniform = 1;
-      md.lam_ratio = r;
-    }
-  }
+  md.lam_uniform = m->lam_uniform ? 1 : 0;
+  md.lam_ratio = m->lam_uniform ? m->lam_ratio : 0.0;
   ctx_ref(ctx);
   m->ctx = ctx;
   m->uploaded = true;
@@ -727,7 +782,9 @@ void mesh_release_device(pfem_mesh* m) {
   m->scratch.release();
   MeshDevBuffers& d = m->dev;
   void* ptrs[] = {d.X, d.Xq, d.conn, d.connp, d.mu32, d.lam32, d.mu64, d.lam64, d.dmask, d.blocks,
-                  d.halo, d.fext, d.ubar, d.colored, d.perm, d.work};
+                  d.halo, d.fext, d.ubar, d.colored, d.perm, d.work, d.pair_ptr,
+                  d.pair_nbr, d.coarse_T, d.coarse_rel64, d.coarse_rel32, d.coarse_Ainv32,
+                  d.coarse_Ainv64};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
   d = MeshDevBuffers{};
@@ -744,25 +801,37 @@ int64_t mesh_device_bytes(const pfem_mesh* m) {
   auto r = [](int64_t b) { return std::max<int64_t>(b, 1); };
   return r(N * D * 8) + r(N * D * 4) + r(NE * (D + 1) * 4) + r(D == 2 ? NE * 8 : 0) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
          r((int64_t)m->n_blocks * 16) + r(((int64_t)m->halo.size() + 1) * 4) + 2 * r(N * D * 8) +
-         r(NE * 4) + r(N * 4) + r((int64_t)m->n_blocks * 8);
+         r(NE * 4) + r(N * 4) + r((int64_t)m->n_blocks * 8) +
+         (m->pair_ptr.empty() ? 0 : r((N + 1) * 4) + r((int64_t)m->pair_nbr.size() * 4));
 }
 
-int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg) {
+int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg, bool two_level) {
   const int64_t nd = m->n_dof();
   const int64_t s = prec == PFEM_FP64 ? 8 : 4;
-  return 3 * nd * 8 + (6 + (fused_pcg ? 9 : 0)) * nd * s +
-         (int64_t)m->n_blocks * 2 * kRedSlots * 8 + 4096 + (int64_t)8 * 65536;
+  int64_t b = 3 * nd * 8 + (6 + (fused_pcg ? 9 : 0)) * nd * s +
+              (int64_t)m->n_blocks * 2 * kRedSlots * 8 + 4096 + (int64_t)8 * 65536;
+  if (two_level) {   // the solve's own arrays and the mesh's coarse arrays
+    const int64_t G = coarse_group(m);
+    const int64_t n_agg = (m->n_blocks + G - 1) / G;
+    b += (int64_t)m->n_blocks * 48 + n_agg * 48 + 8 * (n_agg / kCoarseChunkAgg + 1) + 1024 +
+         coarse_device_bytes(m);
+  }
+  return b;
 }
 
 bool krylov_fused(const pfem_solve_opts& o, const pfem_mesh* m) {
   if (o.krylov != PFEM_KRYLOV_AUTO) return o.krylov == PFEM_KRYLOV_FUSED;
+  if (o.precond == PFEM_PRECOND_TWO_LEVEL) return false;   // classic loop only
   // The fused launch wins where an iteration is launch- and latency-bound
   // (measured warm FP32 solves: 200k-triangle plate 55 vs 82 ms per solve,
   // 500k-tet Neo-Hookean box 55 vs 64 ms); on larger meshes its extra vector
   // traffic and the weaker float32 convergence of the single-reduction form
   // catch up (600k triangles: 226 vs 221 ms; 1M tets: 123 vs 120 ms).
   const int64_t limit = m->dim == 2 ? 600000 : 800000;
-  return o.prec == PFEM_FP32 && m->n_elems <= limit;
+  // periodic springs are applied by the owner kernels only (classic loop)
+  return o.prec == PFEM_FP32 && m->n_elems <= limit && m->pairs.empty();
 }
 
 }  // namespace pfem
+
+pfem_mesh::~pfem_mesh() = default;

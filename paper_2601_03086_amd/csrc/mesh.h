@@ -2,11 +2,22 @@
 #pragma once
 
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "pfem_internal.h"
 
 namespace pfem {
+
+struct CoarseHost {
+  int n_rb = 0;              // rigid modes per aggregate (3 in 2D, 6 in 3D)
+  int G = 1;                 // owner blocks per aggregate
+  int n_agg = 0, n_c = 0;    // aggregates, coarse DOFs (n_agg * n_rb)
+  std::vector<double> cent;  // n_agg * 3 centroids (internal coordinates)
+  std::vector<double> T;     // n_agg * n_rb * n_rb: column k = raw-mode coefficients of
+                             // the aggregate's orthonormal coarse DOF k (0: dropped)
+  std::vector<double> Ainv;  // n_c * n_c inverse of P^T K P, row-major
+};
 
 // Device-resident solver state for one solve (one slot).
 struct SolveState {
@@ -29,9 +40,17 @@ struct SolveState {
   Scalars* sc = nullptr;
   double* hist = nullptr;
   int64_t hist_cap = 0;
+  // two-level preconditioner: restriction partials, coarse correction,
+  // coarse partials of r.M^-1 r, and the descriptor the kernels read
+  double* rc_part = nullptr;
+  double* tl_y = nullptr;
+  double* gc_part = nullptr;
+  TwoLevelDev* tl_dev = nullptr;
   int64_t bytes = 0;
   void alloc(int prec, int64_t n_dof, int n_blocks, int64_t hist_cap, bool nonlinear,
              bool fused_pcg);
+  // Adds the two-level arrays for the mesh's coarse space (uploaded).
+  void alloc_two_level(const pfem_mesh* m);
   void release();
   ~SolveState() { release(); }
 };
@@ -53,6 +72,13 @@ struct MeshDevBuffers {
   int32_t* colored = nullptr;
   int32_t* perm = nullptr;
   int2* work = nullptr;      // single-mesh work table (XCD-remapped)
+  int32_t* pair_ptr = nullptr;
+  int32_t* pair_nbr = nullptr;
+  double* coarse_T = nullptr;      // two-level preconditioner (uploaded on first use)
+  double* coarse_rel64 = nullptr;  // node coordinates relative to their aggregate's centroid
+  float* coarse_rel32 = nullptr;
+  float* coarse_Ainv32 = nullptr;
+  double* coarse_Ainv64 = nullptr;
   int64_t bytes = 0;
 };
 
@@ -87,6 +113,8 @@ struct pfem_mesh {
   std::vector<int32_t> facets;
   std::vector<double> traction;
   int64_t n_facets = 0;
+  std::vector<int32_t> pairs;       // periodic node pairs (caller ids), 2 per pair
+  double pair_k = 0.0;              // spring stiffness of every pair
 
   int node_order = PFEM_ORDER_BLOCKS;
   bool finalized = false;
@@ -110,6 +138,16 @@ struct pfem_mesh {
   std::vector<double> mu_int, lam_int;
   std::vector<uint8_t> dmask;
   std::vector<double> fext_int, ubar_int;
+  // device images prepared on the host at finalize, so an upload only copies
+  std::vector<uint32_t> xq;         // 31-bit fixed-point coordinates (float32 kernels)
+  float qscale[3] = {1.f, 1.f, 1.f};
+  std::vector<uint32_t> connp;      // packed 2D connectivity (empty: not packable)
+  std::vector<float> mu32, lam32;
+  std::vector<int32_t> halo_pad;    // halo lists + one padding entry (clamped reads)
+  bool lam_uniform = false;         // lambda = lam_ratio * mu on every element
+  double lam_ratio = 0.0;
+  std::vector<int32_t> pair_ptr, pair_nbr;   // spring partners per internal node (CSR)
+  double cell_volume = 0.0;         // volume of the coordinates' bounding box
 
   // device
   bool uploaded = false;
@@ -117,6 +155,9 @@ struct pfem_mesh {
   pfem::MeshDev md{};
   pfem::CallScratch scratch;
   std::unique_ptr<pfem::SolveState> solve_state;   // cached for pfem_solve
+  std::unique_ptr<pfem::CoarseHost> coarse;        // two-level preconditioner (built on use)
+  std::mutex coarse_mu;
+  ~pfem_mesh();
 
   int64_t n_dof() const { return n_nodes * dim; }
 };
@@ -130,7 +171,7 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes);
 void mesh_upload(pfem_mesh* m, Ctx* ctx);
 void mesh_release_device(pfem_mesh* m);
 int64_t mesh_device_bytes(const pfem_mesh* m);
-int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg);
+int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg, bool two_level);
 // Whether a solve with these options runs the fused (one launch per
 // iteration) PCG.
 bool krylov_fused(const pfem_solve_opts& o, const pfem_mesh* m);

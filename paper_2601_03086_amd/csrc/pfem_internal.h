@@ -80,6 +80,12 @@ struct MeshDev {
   int32_t conn_packed;    // 1: kernels read connp (every offset fits 16 bits)
   double lam_ratio;
   float qscale[3];        // fixed-point coordinate step per dimension
+  // periodic springs (virtual elements of a periodic cell): node n's
+  // partners are pair_nbr[pair_ptr[n] .. pair_ptr[n+1]), each joined to it
+  // by a spring of stiffness pair_k; pair_ptr == nullptr: no springs
+  const int32_t* pair_ptr;
+  const int32_t* pair_nbr;
+  double pair_k;
 };
 
 // Partial sums of one task: slot k of block b at part[k * n_blocks + b].
@@ -110,6 +116,23 @@ struct Scalars {
   int32_t hist_len, hist_cap, total_k, pad0, pad1;
 };
 
+// Two-level preconditioner state of one solve (device memory): the mesh's
+// coarse arrays and the solve's restriction partials and coarse correction.
+struct TwoLevelDev {
+  const double* T;        // n_agg * nrb * nrb: raw-mode coefficients of each coarse DOF
+  const void* rel;        // n_nodes * dim coordinates relative to the aggregate centroid
+                          // (kernel precision)
+  const void* Ainv;       // n_c * n_c inverse coarse matrix (kernel precision), row-major
+  double* rc_part;        // n_blocks * 6: per owner block, raw-mode sums of the residual
+  double* y;              // n_agg * 6: raw-mode coefficients of the coarse correction
+  double* gc_part;        // n_chunks partials of r_c . z_c
+  int32_t nrb, G, n_agg, n_c, n_chunks, pad;
+};
+constexpr int kCoarseChunkAgg = 16;   // aggregates per workgroup of the coarse solve
+// Largest coarse dimension: the device applies the coarse inverse as one
+// dense matrix-vector product per iteration.
+constexpr int kCoarseMax = 1536;
+
 // One unit of work for a launch: a mesh plus operand pointers.
 struct Task {
   MeshDev m;
@@ -131,7 +154,9 @@ struct Task {
   int32_t k_base;         // Krylov iterations done before this chunk (PCG)
   int32_t hist_base;      // history index of iteration 0 of this inner solve (PCG)
   int32_t pcg;            // 1: PCG apply (returns at once unless state == 0)
-  int32_t pad;
+  int32_t no_pairs;       // 1: elements only, without the mesh's periodic springs
+  const double* fext;     // external force of this task (nullptr: the mesh's)
+  const TwoLevelDev* tl;  // two-level preconditioner (nullptr: Jacobi)
   // Fused PCG: per-node records {r, w, s, M^-1} (4 * dim values, kernel
   // precision) by iteration parity -- launch j gathers rec[j & 1] and its
   // owners write rec[(j + 1) & 1] -- and a scratch vector for the start.
@@ -194,6 +219,12 @@ struct Ctx {
   int64_t fam_seen[FAM_COUNT] = {};
   int64_t fam_launches[FAM_COUNT] = {};
   double fam_ms[FAM_COUNT] = {};
+  // launches that did work (timed or not; launches of a group that returned
+  // at once because every solve in it had converged are not counted) and
+  // their algorithmic bytes: for the K.v / HVP apply and the fused PCG
+  // iteration of solves, while the family is timed
+  int64_t fam_run[FAM_COUNT] = {};
+  double fam_alg_bytes[FAM_COUNT] = {};
   struct Timed {
     int fam;
     hipEvent_t a, b;
@@ -231,6 +262,13 @@ void launch_elem(Ctx* ctx, int dim, int prec, int op, bool nonlinear, int scatte
                  const Task* tasks_dev, const int2* work_dev, int n_work,
                  int bn_max, const Task* host_task_for_alt,
                  const std::vector<int>* color_ptr, const BaseArgs* rel = nullptr);
+// K.v for nr (<= 6) right-hand sides on one linear 3D mesh, every element
+// visited once for all of them: tasks_dev[r] carries right-hand side r (all
+// on the same mesh); work_dev is the mesh's own work table.  Usable when
+// owner_multi_fits(bn, nr) (the accumulators fit 64 KB of LDS).
+bool owner_multi_fits(int bn, int nr);
+void launch_owner_multi(Ctx* ctx, int prec, const Task* tasks_dev, int nr,
+                        const int2* work_dev, int n_work, int bn);
 // Records, with `device` current, the device address of the allocation-free
 // entry point's scratch array (once per device; pfem_ctx_create calls it).
 void noalloc_init(int device);
@@ -253,6 +291,20 @@ void launch_fcg_init(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
 void launch_fcg_init_w(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
                        const int2* work_dev, int n_work);
 void launch_pcg_init_finish(Ctx* ctx, const Task* tasks_dev, int n_tasks);
+// Two-level preconditioned PCG (classic loop): the start r = -g with the
+// restriction partials, the coarse solve over (task, chunk) work items,
+// p = M^-1 r; each iteration's update with restriction partials, coarse
+// solve, and the direction p = M^-1 r + beta p.
+void launch_tl_init(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
+                    int n_work);
+void launch_tl_coarse(Ctx* ctx, int prec, const Task* tasks, const int2* cwork, int n_cwork,
+                      int init);
+void launch_tl_prolong_init(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
+                            int n_work);
+void launch_tl_update(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
+                      int n_work, int it);
+void launch_tl_direction(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
+                         int n_work, int it);
 // packed: every task of the launch has packed connectivity (see MeshDev).
 void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nonlinear, const Task* tasks_dev,
                      const int2* work_dev, int n_work, int bn_max, int it, bool packed);
@@ -270,6 +322,14 @@ void launch_set_scalars(Ctx* ctx, Scalars* sc, double den, double target2, int k
 void launch_permute(Ctx* ctx, int prec, int dim, const int32_t* perm,
                     int64_t n_nodes, bool to_internal, const void* in, void* out);
 void launch_fill(Ctx* ctx, int prec, void* p, int64_t n, double value);
+// Homogenisation: the six affine fields eps0^(IJ) . X of a 3D mesh (FP64
+// coordinates, internal order, six fields one after the other), and the 6 x 6
+// Gram matrix out[6 k + l] = scale A_k . B_l of six n-vectors each, through
+// gram6_parts(n) float64 partials per product.
+void launch_affine6(Ctx* ctx, const double* X, int64_t n_nodes, double* out);
+int gram6_parts(int64_t n);
+void launch_gram6(Ctx* ctx, const double* A, const double* B, int64_t n, double* part,
+                  double* out, double scale);
 void launch_cast(Ctx* ctx, bool to32, const void* in, void* out, int64_t n);
 // x64 = base64 + s * inc (inc precision `prec`), then Dirichlet DOFs of the
 // result set to scale * ubar (when set_dirichlet).

@@ -32,9 +32,12 @@ struct Req {
   bool has_u0 = false;
   pfem_solve_opts o{};
   double t_submit = 0, t_admit = -1, t_done = -1;
-  int64_t bytes = 0;
+  int64_t solve_b = 0;   // device bytes of the solve state (charged while live)
+  int64_t mesh_b = 0;    // device bytes of the mesh arrays (charged while the
+                         // server holds the mesh for one or more requests)
   SlotRun slot;
   bool admitted = false, done = false, server_uploaded = false;
+  bool mesh_released = false;   // complete() released the server's copy of the mesh
   std::atomic<bool> cancel{false};   // set by the client, read by the worker
   std::vector<double> u_out;
   pfem_solve_report rep{};
@@ -57,7 +60,11 @@ struct pfem_server {
   int64_t bytes_in_use = 0, peak_bytes = 0, peak_live = 0;
   int64_t submitted = 0, completed = 0, steps = 0, launches = 0;
   std::string worker_error;
-  std::map<pfem_mesh*, int> mesh_refs;   // meshes this server uploaded
+  std::map<pfem_mesh*, int> mesh_refs;   // meshes this server uploaded: live requests on each
+  // kernel timing: a mask requested by the client (-1: no change), applied
+  // by the worker at its next step; counters copied out after every step
+  int timing_req = -1;
+  pfem_kernel_stats kstats[FAM_COUNT] = {};
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -68,10 +75,6 @@ struct pfem_server {
   void retire(Req* r);
   void fail(pfem_status code, const std::string& msg);
 };
-
-static int64_t req_bytes(const pfem_mesh* m, const pfem_solve_opts& o) {
-  return (m->uploaded ? 0 : mesh_device_bytes(m)) + solve_bytes(m, o.prec, krylov_fused(o, m));
-}
 
 void pfem_server::admit(Req* r) {
   pfem_mesh* m = r->m;
@@ -116,6 +119,7 @@ void pfem_server::complete(Req* r) {
   if (r->server_uploaded && --mesh_refs[r->m] == 0) {
     mesh_refs.erase(r->m);
     mesh_release_device(r->m);
+    r->mesh_released = true;
   }
   r->u0.clear();
   r->u0.shrink_to_fit();
@@ -127,7 +131,7 @@ void pfem_server::complete(Req* r) {
 // sees a request the worker still touches.
 void pfem_server::retire(Req* r) {
   live.erase(std::find(live.begin(), live.end(), r));
-  bytes_in_use -= r->bytes;
+  bytes_in_use -= r->solve_b + (r->mesh_released ? r->mesh_b : 0);
   r->done = true;
   done_ids.push_back(r->id);
   ++completed;
@@ -169,6 +173,17 @@ void pfem_server::run() {
       std::unique_lock<std::mutex> lk(mu);
       cv.wait(lk, [&] { return stop || !queue.empty() || !live.empty(); });
       if (stop) break;
+      if (timing_req >= 0) {
+        c->drain_timing();
+        c->timing = timing_req;
+        c->sample_every = 1;
+        for (int f = 0; f < FAM_COUNT; ++f) {
+          c->fam_seen[f] = c->fam_launches[f] = c->fam_run[f] = 0;
+          c->fam_ms[f] = c->fam_alg_bytes[f] = 0.0;
+          kstats[f] = pfem_kernel_stats{};
+        }
+        timing_req = -1;
+      }
       // cancellations in the queue finish at once
       for (auto it = queue.begin(); it != queue.end();) {
         Req* r = *it;
@@ -186,18 +201,6 @@ void pfem_server::run() {
       }
       for (Req* r : live)
         if (r->cancel) cancelled_live.push_back(r);
-      // admission in arrival order: head of line waits for memory
-      int64_t in_use = bytes_in_use;
-      int64_t n_live = (int64_t)live.size() - (int64_t)cancelled_live.size();
-      for (Req* r : cancelled_live) in_use -= r->bytes;
-      while (!queue.empty() && n_live < max_slots) {
-        Req* r = queue.front();
-        if (in_use + r->bytes > budget) break;
-        queue.pop_front();
-        in_use += r->bytes;
-        ++n_live;
-        to_admit.push_back(r);
-      }
     }
     try {
       for (Req* r : cancelled_live) {
@@ -205,13 +208,39 @@ void pfem_server::run() {
         std::lock_guard<std::mutex> lk(mu);
         retire(r);
       }
-      if (!to_admit.empty()) {
-        // live before admission, so that a failure while admitting ends
-        // these requests too instead of losing them
+      {
+        // admission in arrival order: the head of the queue waits for a
+        // slot and for memory.  Charges: the request's solve state, plus the
+        // mesh arrays when the server has to upload the mesh (neither
+        // resident on a context of the caller nor held for another live
+        // request, nor uploaded for an earlier request of this round).  Only
+        // this thread uploads or releases meshes of queued or live requests,
+        // so reading their residency here is race-free.  The requests become
+        // live before admission, so that a failure while admitting ends them
+        // too instead of losing them.
         std::lock_guard<std::mutex> lk(mu);
-        for (Req* r : to_admit) {
+        std::vector<pfem_mesh*> planned;
+        while (!queue.empty() && (int64_t)live.size() < max_slots) {
+          Req* r = queue.front();
+          const bool upload = !r->m->uploaded && mesh_refs.count(r->m) == 0 &&
+                              std::find(planned.begin(), planned.end(), r->m) == planned.end();
+          const int64_t need = r->solve_b + (upload ? r->mesh_b : 0);
+          if (need > budget) {   // can never fit: end it instead of blocking the queue
+            queue.pop_front();
+            r->rep = pfem_solve_report{};
+            r->rep.status = PFEM_E_OOM;
+            r->t_done = now();
+            r->done = true;
+            done_ids.push_back(r->id);
+            ++completed;
+            continue;
+          }
+          if (bytes_in_use + need > budget) break;
+          queue.pop_front();
+          if (upload) planned.push_back(r->m);
+          bytes_in_use += need;
           live.push_back(r);
-          bytes_in_use += r->bytes;
+          to_admit.push_back(r);
         }
         peak_bytes = std::max(peak_bytes, bytes_in_use);
         peak_live = std::max<int64_t>(peak_live, (int64_t)live.size());
@@ -227,9 +256,13 @@ void pfem_server::run() {
       if (!slots.empty()) {
         int64_t nl = 0;
         engine_tick(c, slots, &nl);
+        if (c->timing != 0) c->drain_timing();   // the step ended with a stream sync
         std::lock_guard<std::mutex> lk(mu);
         ++steps;
         launches += nl;
+        for (int f = 0; f < FAM_COUNT; ++f)
+          kstats[f] = pfem_kernel_stats{c->fam_launches[f], c->fam_ms[f], c->fam_run[f],
+                                        c->fam_alg_bytes[f]};
       }
       for (Req* r : snapshot) {
         if (!r->slot.finished) continue;
@@ -300,14 +333,17 @@ pfem_status pfem_server_submit(pfem_server* s, pfem_mesh* m, const double* u0,
     r->o = *o;
     r->has_u0 = u0 != nullptr;
     if (u0) r->u0.assign(u0, u0 + m->n_dof());
-    r->bytes = req_bytes(m, *o);
+    // sizes fixed at finalize; residency is decided by the worker
+    r->solve_b = solve_bytes(m, o->prec, krylov_fused(*o, m),
+                             o->precond == PFEM_PRECOND_TWO_LEVEL);
+    r->mesh_b = mesh_device_bytes(m);
     {
       std::lock_guard<std::mutex> lk(s->mu);
       if (s->all.count(req_id)) {
         delete r;
         throw Error{PFEM_E_INVALID_ARG, "duplicate request id"};
       }
-      if (r->bytes > s->budget) {
+      if (r->solve_b > s->budget) {
         delete r;
         throw Error{PFEM_E_OOM, "request footprint exceeds the server budget"};
       }
@@ -412,6 +448,32 @@ pfem_status pfem_server_get_stats(pfem_server* s, pfem_server_stats* o) {
   o->budget = s->budget;
   o->steps = s->steps;
   o->launches = s->launches;
+  set_error("");
+  return PFEM_OK;
+}
+
+pfem_status pfem_server_set_timing(pfem_server* s, int family_mask) {
+  if (s == nullptr || family_mask < 0) {
+    set_error("NULL server or negative mask");
+    return PFEM_E_INVALID_ARG;
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->timing_req = family_mask;
+    for (int f = 0; f < FAM_COUNT; ++f) s->kstats[f] = pfem_kernel_stats{};
+  }
+  s->cv.notify_one();
+  set_error("");
+  return PFEM_OK;
+}
+
+pfem_status pfem_server_kernel_stats(pfem_server* s, int family, pfem_kernel_stats* out) {
+  if (s == nullptr || out == nullptr || family < 0 || family >= FAM_COUNT) {
+    set_error("NULL argument or bad kernel family");
+    return PFEM_E_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->kstats[family];
   set_error("");
   return PFEM_OK;
 }

@@ -1,6 +1,8 @@
 // Batched solve engine (see solver.h).
 #include "solver.h"
 
+#include "coarse.h"
+
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -45,8 +47,35 @@ void SolveState::alloc(int pr, int64_t nd, int nb, int64_t hcap, bool nonlinear,
   PFEM_HIP(hipMemcpy(sc, &init, sizeof(Scalars), hipMemcpyHostToDevice));
 }
 
+void SolveState::alloc_two_level(const pfem_mesh* m) {
+  const CoarseHost& c = *m->coarse;
+  auto A = [&](void** p, size_t n) {
+    PFEM_HIP(hipMalloc(p, std::max<size_t>(n, 8)));
+    bytes += (int64_t)std::max<size_t>(n, 8);
+  };
+  const int n_chunks = (c.n_agg + kCoarseChunkAgg - 1) / kCoarseChunkAgg;
+  A((void**)&rc_part, (size_t)std::max(m->n_blocks, 1) * 6 * 8);
+  A((void**)&tl_y, (size_t)c.n_agg * 6 * 8);
+  A((void**)&gc_part, (size_t)n_chunks * 8);
+  A((void**)&tl_dev, sizeof(TwoLevelDev));
+  TwoLevelDev t{};
+  t.T = m->dev.coarse_T;
+  t.rel = prec == PFEM_FP64 ? (const void*)m->dev.coarse_rel64 : (const void*)m->dev.coarse_rel32;
+  t.Ainv = prec == PFEM_FP64 ? (const void*)m->dev.coarse_Ainv64 : (const void*)m->dev.coarse_Ainv32;
+  t.rc_part = rc_part;
+  t.y = tl_y;
+  t.gc_part = gc_part;
+  t.nrb = c.n_rb;
+  t.G = c.G;
+  t.n_agg = c.n_agg;
+  t.n_c = c.n_c;
+  t.n_chunks = n_chunks;
+  PFEM_HIP(hipMemcpy(tl_dev, &t, sizeof(t), hipMemcpyHostToDevice));
+}
+
 void SolveState::release() {
-  void* ptrs[] = {x64, g64, aux64, d, r, p, q, minv, u32, rec[0], rec[1], tmp, part, sc, hist};
+  void* ptrs[] = {x64, g64, aux64, d, r, p, q, minv, u32, rec[0], rec[1], tmp, part, sc, hist,
+                  rc_part, tl_y, gc_part, tl_dev};
   for (void* ptr : ptrs)
     if (ptr != nullptr) (void)hipFree(ptr);
   x64 = g64 = aux64 = nullptr;
@@ -55,6 +84,8 @@ void SolveState::release() {
   part = nullptr;
   sc = nullptr;
   hist = nullptr;
+  rc_part = tl_y = gc_part = nullptr;
+  tl_dev = nullptr;
   bytes = 0;
 }
 
@@ -65,9 +96,15 @@ void check_solve_opts(const pfem_solve_opts& o) {
           "bad krylov formulation");
   require(o.inner_rtol >= 0.0 && o.inner_rtol <= 0.5, PFEM_E_INVALID_ARG,
           "inner_rtol must be 0 (automatic) or in (0, 0.5]");
+  require(o.precond == PFEM_PRECOND_JACOBI || o.precond == PFEM_PRECOND_TWO_LEVEL,
+          PFEM_E_INVALID_ARG, "bad preconditioner");
+  require(!(o.precond == PFEM_PRECOND_TWO_LEVEL && o.krylov == PFEM_KRYLOV_FUSED),
+          PFEM_E_INVALID_ARG, "the two-level preconditioner runs with the classic PCG loop");
 }
 
 void slot_alloc(SlotRun* s, pfem_mesh* m, const pfem_solve_opts& o, int64_t hist_cap) {
+  require(!(krylov_fused(o, m) && !m->pairs.empty()), PFEM_E_INVALID_ARG,
+          "the fused PCG does not apply periodic springs: use the classic formulation");
   s->m = m;
   s->o = o;
   s->prec = o.prec == PFEM_FP64 ? PFEM_FP64 : PFEM_FP32;
@@ -75,6 +112,11 @@ void slot_alloc(SlotRun* s, pfem_mesh* m, const pfem_solve_opts& o, int64_t hist
   s->st = new SolveState();
   try {
     s->st->alloc(s->prec, m->n_dof(), m->n_blocks, hist_cap, m->nonlinear, krylov_fused(o, m));
+    if (o.precond == PFEM_PRECOND_TWO_LEVEL) {
+      require(m->uploaded && m->ctx != nullptr, PFEM_E_STATE, "mesh has no device context");
+      coarse_upload(m, m->ctx);
+      s->st->alloc_two_level(m);
+    }
     PFEM_HIP(hipHostMalloc((void**)&s->sc_host, sizeof(Scalars), hipHostMallocDefault));
   } catch (...) {
     delete s->st;
@@ -91,6 +133,28 @@ void slot_free(SlotRun* s) {
 }
 
 // ---------------------------------------------------------------- helpers
+// Algorithmic bytes of one apply (K.v / HVP) or one fused PCG iteration of a
+// slot: connectivity, one material value per element and the coordinates
+// once, then the apply's input and output, or the fused iteration's node
+// records ({r, w, s, M^-1} read, {r, w, s} written) and p and d (read and
+// written); Neo-Hookean meshes also read the state u.
+static double alg_bytes(const SlotRun* s, bool fused) {
+  const double d = s->m->dim, ne = (double)s->m->n_elems, nn = (double)s->m->n_nodes;
+  const double sz = s->prec == PFEM_FP64 ? 8.0 : 4.0;
+  // a right-hand side after the first of a multi-right-hand-side apply
+  // shares the element data read for the first
+  double b = s->shares_elements ? 0.0 : 4.0 * (d + 1.0) * ne + sz * ne + d * sz * nn;
+  b += (fused ? 11.0 : 2.0) * d * sz * nn;
+  if (s->nl) b += d * sz * nn;
+  return b;
+}
+
+// A cached solver state may carry two-level buffers from an earlier solve;
+// the options of this solve decide whether they are used.
+static bool uses_two_level(const SlotRun* s) {
+  return s->o.precond == PFEM_PRECOND_TWO_LEVEL && s->st->tl_dev != nullptr;
+}
+
 static Task base_task(SlotRun* s) {
   Task t{};
   t.m = s->m->md;
@@ -110,6 +174,8 @@ static Task base_task(SlotRun* s) {
   t.k_base = s->k_before;
   t.hist_base = s->hist_base;
   t.fscale = (double)s->step / s->n_steps;   // load step n applies n / N_f of the load
+  t.fext = s->fext;
+  t.tl = uses_two_level(s) ? s->st->tl_dev : nullptr;
   return t;
 }
 
@@ -117,19 +183,21 @@ struct Group {
   int dim, prec;
   bool nl;
   bool fused;
+  bool tl;   // two-level preconditioner
   std::vector<SlotRun*> slots;
 };
 
 // Groups slots by (dim, precision, model kind, PCG formulation) so one
 // templated launch covers a group.
 static std::vector<Group> group_by(const std::vector<SlotRun*>& v, bool force_fp64) {
-  std::map<std::tuple<int, int, int, int>, Group> g;
+  std::map<std::tuple<int, int, int, int, int>, Group> g;
   for (SlotRun* s : v) {
     const int pr = force_fp64 ? PFEM_FP64 : s->prec;
     const bool fused = !force_fp64 && s->st->fused;
-    auto key = std::make_tuple(s->m->dim, pr, s->nl ? 1 : 0, fused ? 1 : 0);
+    const bool tl = !force_fp64 && uses_two_level(s);
+    auto key = std::make_tuple(s->m->dim, pr, s->nl ? 1 : 0, fused ? 1 : 0, tl ? 1 : 0);
     auto it = g.find(key);
-    if (it == g.end()) it = g.emplace(key, Group{s->m->dim, pr, s->nl, fused, {}}).first;
+    if (it == g.end()) it = g.emplace(key, Group{s->m->dim, pr, s->nl, fused, tl, {}}).first;
     it->second.slots.push_back(s);
   }
   std::vector<Group> out;
@@ -171,6 +239,18 @@ static Uploaded upload_group(Ctx* ctx, const Group& g, const std::vector<Task>& 
   for (int i = 0; i < total; ++i) w[i] = nat[pre[i % 8] + i / 8];
   u.work = static_cast<const int2*>(ctx->ring.put(w.data(), w.size() * sizeof(int2)));
   return u;
+}
+
+// Work items (task, chunk of aggregates) of the coarse solve of a group.
+static const int2* coarse_work(Ctx* ctx, const Group& g, int* n_items) {
+  std::vector<int2> w;
+  for (size_t i = 0; i < g.slots.size(); ++i) {
+    const CoarseHost& c = *g.slots[i]->m->coarse;
+    const int nch = (c.n_agg + kCoarseChunkAgg - 1) / kCoarseChunkAgg;
+    for (int k = 0; k < nch; ++k) w.push_back(make_int2((int)i, k));
+  }
+  *n_items = (int)w.size();
+  return static_cast<const int2*>(ctx->ring.put(w.data(), w.size() * sizeof(int2)));
 }
 
 static double inner_target(const SlotRun* s) {
@@ -294,6 +374,16 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
         ts.push_back(t);
       }
       Uploaded u = upload_group(ctx, g, ts);
+      if (g.tl) {   // r = -g, then p = M^-1 r through the coarse solve
+        int ncw = 0;
+        const int2* cw = coarse_work(ctx, g, &ncw);
+        launch_tl_init(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work);
+        launch_tl_coarse(ctx, g.prec, u.tasks, cw, ncw, 1);
+        launch_tl_prolong_init(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work);
+        launch_pcg_init_finish(ctx, u.tasks, (int)ts.size());
+        *nl += 4;
+        continue;
+      }
       if (!g.fused) {
         launch_pcg_init(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work, (int)ts.size());
         *nl += 2;
@@ -314,6 +404,10 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
       Uploaded ua = upload_group(ctx, g, ta);
       launch_elem(ctx, g.dim, g.prec, OP_APPLY, g.nl, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
                   ua.n_work, ua.bn_max, nullptr, nullptr);
+      if (ctx->timing & (1 << FAM_APPLY)) {
+        ctx->fam_run[FAM_APPLY] += 1;
+        for (SlotRun* s : g.slots) ctx->fam_alg_bytes[FAM_APPLY] += alg_bytes(s, false);
+      }
       launch_fcg_init_w(ctx, g.dim, g.prec, u.tasks, u.work, u.n_work);
       launch_pcg_init_finish(ctx, u.tasks, (int)ts.size());
       *nl += 4;
@@ -324,7 +418,10 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
   for (SlotRun* s : all) k = std::max(k, s->chunk);
   for (const Group& g : group_by(all, false)) {
     const int64_t key = ctx->next_key++;
-    for (SlotRun* s : g.slots) s->timing_key = key;
+    for (SlotRun* s : g.slots) {
+      s->timing_key = key;
+      s->chunk_launched = k;
+    }
     std::vector<Task> apply, upd;
     for (SlotRun* s : g.slots) {
       Task t = base_task(s);
@@ -358,13 +455,32 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
       continue;
     }
     Uploaded uu = upload_group(ctx, g, upd);
+    // several right-hand sides on one linear 3D mesh (a homogenisation's
+    // cell problems): one element visit serves all of them
+    bool one_mesh = g.dim == 3 && !g.nl && g.slots.size() >= 2;
+    for (SlotRun* sr : g.slots) one_mesh = one_mesh && sr->m == g.slots[0]->m;
+    const bool multi = one_mesh && owner_multi_fits(g.slots[0]->m->bn, (int)g.slots.size());
+    for (size_t i = 0; i < g.slots.size(); ++i) g.slots[i]->shares_elements = multi && i > 0;
+    int ncw = 0;
+    const int2* cw = g.tl ? coarse_work(ctx, g, &ncw) : nullptr;
     for (int it = 0; it < k; ++it) {
       ctx->cur_it = it;
-      launch_elem(ctx, g.dim, g.prec, OP_APPLY, g.nl, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
-                  ua.n_work, ua.bn_max, nullptr, nullptr);
-      launch_pcg_update(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
-      launch_pcg_direction(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
-      *nl += 3;
+      if (multi)
+        launch_owner_multi(ctx, g.prec, ua.tasks, (int)g.slots.size(), g.slots[0]->m->dev.work,
+                           g.slots[0]->m->n_blocks, g.slots[0]->m->bn);
+      else
+        launch_elem(ctx, g.dim, g.prec, OP_APPLY, g.nl, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
+                    ua.n_work, ua.bn_max, nullptr, nullptr);
+      if (g.tl) {
+        launch_tl_update(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
+        launch_tl_coarse(ctx, g.prec, uu.tasks, cw, ncw, 0);
+        launch_tl_direction(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
+        *nl += 4;
+      } else {
+        launch_pcg_update(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
+        launch_pcg_direction(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
+        *nl += 3;
+      }
     }
     ctx->cur_key = -1;
     ctx->cur_it = 0;
@@ -567,12 +683,30 @@ int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches) {
   for (SlotRun* s : resid) after_resid(ctx, s);
   if (ctx->timing != 0) {
     // launches after the last real iteration of a group returned at once
+    // and are not timed: a classic chunk keeps its launches before that
+    // point, a fused chunk (timed as one run) is kept only when all of its
+    // launches did work.  The kept launches advanced each solve of the
+    // group by its own iterations: those are the algorithmic bytes.
     std::map<int64_t, int> ran;
+    std::map<int64_t, int> fam_of, launched;
     for (SlotRun* s : kall) {
       int& r = ran[s->timing_key];
       r = std::max(r, s->sc_host->k - s->k_before);
+      fam_of[s->timing_key] = s->st->fused ? FAM_FUSED : FAM_APPLY;
+      launched[s->timing_key] = s->chunk_launched;
     }
-    for (auto& kv : ran) ctx->drop_noop(kv.first, kv.second);
+    for (SlotRun* s : kall) {
+      const int fam = fam_of[s->timing_key];
+      const bool kept = fam == FAM_APPLY || ran[s->timing_key] >= launched[s->timing_key];
+      if ((ctx->timing & (1 << fam)) && kept)
+        ctx->fam_alg_bytes[fam] += (s->sc_host->k - s->k_before) * alg_bytes(s, s->st->fused);
+    }
+    for (auto& kv : ran) {
+      ctx->drop_noop(kv.first, kv.second);
+      const int fam = fam_of[kv.first];
+      const bool kept = fam == FAM_APPLY || kv.second >= launched[kv.first];
+      if ((ctx->timing & (1 << fam)) && kept) ctx->fam_run[fam] += kv.second;
+    }
   }
   for (SlotRun* s : kall) after_krylov(ctx, s);
   for (SlotRun* s : ls) after_ls(ctx, s);

@@ -47,12 +47,15 @@ struct SlotRun {
   int hist_base = 0;        // history index of iteration 0 of the inner solve
   int64_t hist_len_host = 0;
   int64_t timing_key = -1;  // launch group of the current chunk
+  int chunk_launched = 0;   // launches of that chunk
   double ls_s = 1.0, ls_slope = 0.0;
   int ls_tries = 0;
   int max_iter = 0;
   bool finished = false;
   pfem_status status = PFEM_OK;
   int64_t id = -1;
+  const double* fext = nullptr;   // external force of this solve (nullptr: the mesh's)
+  bool shares_elements = false;   // applied with earlier slots of one mesh in one visit
 };
 
 // Prepares slot state on the device: x64 <- initial guess (internal order,

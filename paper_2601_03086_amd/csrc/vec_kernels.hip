@@ -125,6 +125,13 @@ __global__ void __launch_bounds__(kThreads) k_pcg_init_finish(const Task* __rest
   if (!tp->active) return;
   double rz, rr;
   sum_slots2(tp->red.part, tp->m.n_blocks, 1, 2, rz, rr);
+  if (tp->tl != nullptr) {   // two-level: the coarse share of r.M^-1 r
+    const TwoLevelDev* tl = tp->tl;
+    double v[1] = {0.0};
+    for (int c = threadIdx.x; c < tl->n_chunks; c += kThreads) v[0] += ldg(tl->gc_part + c);
+    block_sum_all<1>(v);
+    rz += v[0];
+  }
   if (threadIdx.x != 0) return;
   Scalars* sc = tp->sc;
   sc->rz2[0] = rz;
@@ -470,6 +477,83 @@ void launch_axpy_state(Ctx* ctx, int prec, const MeshDev& m, double* out, const 
 
 void launch_lift(Ctx* ctx, const MeshDev& m, double* out, const double* base, double scale) {
   launch_axpy_state(ctx, PFEM_FP64, m, out, base, nullptr, 0.0, true, scale);
+}
+
+// ------------------------------------------------------- homogenisation
+// X^0(IJ) = eps0^(IJ) . X at every node for the six unit strains of App. D
+// (11, 22, 33: a one on the diagonal; 12, 13, 23: ones at (p, q) and
+// (q, p)); out holds the six fields one after the other, internal order.
+__global__ void k_affine6(const double* __restrict__ X, int64_t n_nodes,
+                          double* __restrict__ out) {
+  const int64_t nd = n_nodes * 3;
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < n_nodes;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    const double x[3] = {X[3 * n], X[3 * n + 1], X[3 * n + 2]};
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < 3; ++i) out[k * nd + 3 * n + i] = i == k ? x[k] : 0.0;
+    const int P[3] = {0, 0, 1}, Q[3] = {1, 2, 2};
+    for (int s = 0; s < 3; ++s) {
+      double* o = out + (3 + s) * nd + 3 * n;
+      for (int i = 0; i < 3; ++i) o[i] = 0.0;
+      o[P[s]] = x[Q[s]];
+      o[Q[s]] = x[P[s]];
+    }
+  }
+}
+
+void launch_affine6(Ctx* ctx, const double* X, int64_t n_nodes, double* out) {
+  hipLaunchKernelGGL(k_affine6, dim3(grid_for(n_nodes)), dim3(kThreads), 0, ctx->stream, X,
+                     n_nodes, out);
+  PFEM_HIP(hipGetLastError());
+}
+
+// G[k][l] = A_k . B_l for six vectors A_k and six B_l of n entries (stored
+// one after the other): every workgroup sums its grid-stride share of the
+// 36 products in float64 and stores one partial per product; a one-
+// workgroup kernel then adds the partials in workgroup order (no atomics,
+// the same result on every run).
+__global__ void __launch_bounds__(kThreads)
+k_gram6_part(const double* __restrict__ A, const double* __restrict__ B, int64_t n,
+             double* __restrict__ part) {
+  double v[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) v[k] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    double a[6], b[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      a[k] = A[k * n + i];
+      b[k] = B[k * n + i];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int l = 0; l < 6; ++l) v[6 * k + l] += a[k] * b[l];
+  }
+  block_sum_all<36>(v);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 36; ++k) part[(size_t)k * gridDim.x + blockIdx.x] = v[k];
+}
+
+__global__ void k_gram6_final(const double* __restrict__ part, int n_part,
+                              double* __restrict__ out, double scale) {
+  const int k = threadIdx.x;
+  if (k < 36) {
+    double s = 0.0;
+    for (int b = 0; b < n_part; ++b) s += part[(size_t)k * n_part + b];
+    out[k] = s * scale;
+  }
+}
+
+int gram6_parts(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, 1024)); }
+
+void launch_gram6(Ctx* ctx, const double* A, const double* B, int64_t n, double* part,
+                  double* out, double scale) {
+  const int g = gram6_parts(n);
+  hipLaunchKernelGGL(k_gram6_part, dim3(g), dim3(kThreads), 0, ctx->stream, A, B, n, part);
+  hipLaunchKernelGGL(k_gram6_final, dim3(1), dim3(64), 0, ctx->stream, part, g, out, scale);
+  PFEM_HIP(hipGetLastError());
 }
 
 }  // namespace pfem

@@ -44,20 +44,28 @@ def lifting_weight(coords, dirichlet_nodes, width=0.1):
     return np.minimum(1.0, dist / width)
 
 
+def warm_start_noise(coords, dirichlet_nodes, seed, length=0.2, n_features=256):
+    """The unscaled noise l(x) g(x) of ``warm_start_guess`` (node-major,
+    zero on the Dirichlet nodes)."""
+    coords = np.asarray(coords, dtype=np.float64)
+    n, d = coords.shape
+    g = rff_field(coords, seed, length, n_features, n_comp=d)
+    w = lifting_weight(coords, dirichlet_nodes)
+    return (g * w[:, None]).reshape(-1)
+
+
 def warm_start_guess(u_star, coords, dirichlet_nodes, seed, rel=0.01,
-                     length=0.2, n_features=256):
+                     length=0.2, n_features=256, noise=None):
     """Synthetic network prediction: u_star + s * l(x) * g(x).
 
     u_star: (N_n*d,) node-major reference displacement (it already carries the
     Dirichlet values).  The smooth noise g is one RFF field per component,
     multiplied by the boundary lifting l(x) so the guess keeps the Dirichlet
-    values exactly, and scaled so its 2-norm is ``rel`` * |u_star|.
+    values exactly, and scaled so its 2-norm is ``rel`` * |u_star|.  A noise
+    precomputed by ``warm_start_noise`` may be passed in.
     """
-    coords = np.asarray(coords, dtype=np.float64)
-    n, d = coords.shape
-    g = rff_field(coords, seed, length, n_features, n_comp=d)
-    w = lifting_weight(coords, dirichlet_nodes)
-    noise = (g * w[:, None]).reshape(-1)
+    if noise is None:
+        noise = warm_start_noise(coords, dirichlet_nodes, seed, length, n_features)
     nn = np.linalg.norm(noise)
     s = 0.0 if nn == 0.0 else rel * np.linalg.norm(u_star) / nn
     return np.asarray(u_star, dtype=np.float64) + s * noise

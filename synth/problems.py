@@ -120,13 +120,14 @@ def log_e_field(centroids, seed, sigma=0.5, length=0.1, n_features=1024):
 
 
 def plate_problem(seed_geom, seed_mat, seed_bc, n_holes=8, target_tris=200000,
-                  model="lin_plane_strain", nu=0.3, name=None):
-    """Unit plate with random circular holes and a lognormal E field."""
+                  model="lin_plane_strain", nu=0.3, name=None, e_features=1024):
+    """Unit plate with random circular holes and a lognormal E field
+    (``e_features`` random Fourier features)."""
     coords, conn, holes = meshes.plate_with_holes(_rng(seed_geom), n_holes,
                                                   target_tris)
     coords, conn = meshes._relabel(coords, conn, _rng(seed_geom + 7919))
     cen = coords[conn].mean(axis=1)
-    E = np.exp(log_e_field(cen, seed_mat))
+    E = np.exp(log_e_field(cen, seed_mat, n_features=e_features))
     dn, dc, dv, facets, trac, bmeta = _plate_bcs(coords, _rng(seed_bc))
     ne = conn.shape[0]
     meta = {"holes": holes, **bmeta}
@@ -226,13 +227,22 @@ def serving_stream(n_requests=512, rate=200.0, frac_2d=0.7, smin=1e4,
     return out
 
 
+# random Fourier features of the serving stream's fields: 128 for log E and
+# 64 for the warm-start noise (against 1024 / 256 elsewhere), so that the
+# 512 meshes of a stream are generated in seconds; still unit-variance
+# smooth fields of the stated correlation length
+SERVING_E_FEATURES = 128
+SERVING_NOISE_FEATURES = 64
+
+
 def serving_problem(desc):
     """Build the mesh/problem for one serving-stream request descriptor."""
     s = desc["seed"]
     if desc["kind"] == "2d":
         return plate_problem(s, s + 100000, s + 200000, n_holes=8,
                              target_tris=desc["target_elems"],
-                             model="lin_plane_strain", name=f"req{desc['id']}")
+                             model="lin_plane_strain", name=f"req{desc['id']}",
+                             e_features=SERVING_E_FEATURES)
     n = max(int(round((desc["target_elems"] / (24.0 * 0.98)) ** (1.0 / 3.0))), 4)
     return box_problem(s, s + 100000, n_per_unit=n, n_voids=20,
                        name=f"req{desc['id']}")

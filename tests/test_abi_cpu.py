@@ -258,7 +258,7 @@ def test_every_entry_point_rejects_null_arguments():
     and the void destructors accept NULL."""
     L = _lib()
     lib = L.load()
-    ints = (C.c_int, L._I32, L._I64)
+    ints = (C.c_int, L._I32, L._I64, L._D)
     for name, (res, args) in L.PROTOTYPES.items():
         if not args:
             continue
@@ -502,3 +502,31 @@ def test_oracle_and_library_share_no_code():
     for f in glob.glob(os.path.join(ROOT, "synth", "*.py")):
         txt = open(f).read()
         assert not re.search(r"^\s*(from|import)\s+(oracle|paper_2601_03086_amd)", txt, re.M), f
+
+
+def test_coarse_aggregates_and_preparation():
+    """PFEM_Q_AGGREGATE: groups of consecutive owner blocks, at most 1536
+    coarse DOFs; pfem_mesh_prepare_coarse builds the coarse space on the
+    host (no device); the two-level option is checked before the device."""
+    import synth
+    L = _lib()
+    from paper_2601_03086_amd import core
+    for p, nrb in ((synth.plate_problem(5, 6, 7, n_holes=2, target_tris=4000), 3),
+                   (synth.box_problem(8, 9, n_per_unit=5, n_voids=1, n_load_steps=1), 6)):
+        m = core.Mesh.from_problem(None, p, 32)
+        agg = m.query(L.PFEM_Q_AGGREGATE)
+        perm = m.query(L.PFEM_Q_PERM)
+        blocks = perm // m.info["block_nodes"]
+        G = -(-nrb * m.info["n_blocks"] // 1536)
+        assert np.array_equal(agg, blocks // max(G, 1))
+        n_c = m.prepare_coarse()
+        assert n_c == nrb * (agg.max() + 1) and n_c <= 1536
+        assert m.prepare_coarse() == n_c          # built once
+    o = core.Mesh.opts(precond="two_level", krylov="fused")
+    u = np.zeros(m.n_dof)
+    st = L.load().pfem_solve(m.h, None, C.byref(o), u.ctypes.data, 0, None, 0, None)
+    assert st == L.PFEM_E_INVALID_ARG
+    o = core.Mesh.opts()
+    o.precond = 7
+    st = L.load().pfem_solve(m.h, None, C.byref(o), u.ctypes.data, 0, None, 0, None)
+    assert st == L.PFEM_E_INVALID_ARG

@@ -64,8 +64,9 @@ def test_alone_equals_in_the_mix(ctx):
         srv.submit(i, m, u0=u0, **opts)
     _wait(srv, list(range(len(reqs))))
     st = srv.stats()
-    assert st["peak_live"] <= 3 and st["peak_bytes"] <= budget
-    assert st["completed"] == len(reqs)
+    assert 2 <= st["peak_live"] <= 3 and st["peak_bytes"] <= budget
+    assert st["completed"] == len(reqs) and st["bytes_in_use"] == 0
+    spans = []
     for i, (p, u0, ud) in enumerate(reqs):
         u, r = srv.result(i)
         ua, ra, _ = alone[i]
@@ -76,6 +77,53 @@ def test_alone_equals_in_the_mix(ctx):
         if ud is not None:
             assert rel(u, ud) <= 1e-6
         assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+        spans.append((r["t_admit"], r["t_done"]))
+    # the requests overlapped on the device: one was admitted while another
+    # was live (admitted earlier, not yet done)
+    assert any(a0 < a1 < d0 for i, (a0, d0) in enumerate(spans)
+               for j, (a1, _) in enumerate(spans) if i != j)
+    srv.close()
+
+
+def test_mesh_charged_once(ctx):
+    """Two requests on one host mesh: the mesh arrays are charged once while
+    the server holds them, each request its solve state; a budget for the
+    mesh and two solves runs both at once, a budget for the mesh and one
+    solve runs them one after the other, and the memory in use returns to 0.
+    A request whose mesh and solve can never fit ends with E_OOM when it
+    reaches the head of the queue, without blocking the one behind it."""
+    from paper_2601_03086_amd import _lib as L
+    from paper_2601_03086_amd import core
+    p = synth.plate_problem(811, 812, 813, n_holes=3, target_tris=20000)
+    m = core.Mesh.from_problem(None, p)
+    mesh_b = m.info["device_bytes"]
+    solve_b = m.info["solve_bytes_fp32"]
+    assert m.footprint("fp32") == mesh_b + solve_b
+    opts = dict(tol=1e-8, prec="fp32")
+    for budget, live in ((mesh_b + 2 * solve_b, 2), (mesh_b + solve_b, 1)):
+        srv = core.Server(ctx, budget, max_slots=4)
+        srv.submit(0, m, **opts)
+        srv.submit(1, m, tol=1e-9, prec="fp32")
+        _wait(srv, [0, 1])
+        st = srv.stats()
+        print(budget, st, flush=True)
+        assert st["peak_live"] == live and st["bytes_in_use"] == 0
+        assert st["peak_bytes"] == mesh_b + live * solve_b
+        for i in (0, 1):
+            _, r = srv.result(i)
+            assert r["status"] == 0
+        srv.close()
+    # mesh + solve beyond the budget, solve alone within it
+    small = synth.plate_problem(821, 822, 823, n_holes=2, target_tris=3000)
+    ms = core.Mesh.from_problem(None, small)
+    srv = core.Server(ctx, mesh_b + solve_b - 1, max_slots=4)
+    srv.submit(0, m, **opts)
+    srv.submit(1, ms, **opts)
+    _wait(srv, [0, 1])
+    _, r0 = srv.result(0)
+    _, r1 = srv.result(1)
+    assert r0["status"] == L.PFEM_E_OOM and r1["status"] == 0
+    assert srv.stats()["bytes_in_use"] == 0
     srv.close()
 
 
