@@ -1,28 +1,38 @@
 #!/usr/bin/env python3
-"""Benchmark: matrix-free K.v throughput inside warm-started solves (one GPU).
+"""Benchmark: warm-started solves served with continuous batching (one GPU).
 
-Workload (default): the plane-strain plate with 8 random holes, about 2e5 P1
-triangles, lognormal E field, clamped bottom edge and a random traction
-segment on the top edge.  One step is one warm-started solve to a 1e-8
-relative residual (FP32 Jacobi-PCG with FP64 residual refinement), starting
-from a synthetic network prediction (reference solution + 1% smooth noise).
-Inputs are resident in device memory before the timed region.
+Workload (default): a serving stream of 512 solve requests, each on its own
+seeded mesh (70% plane-strain plates with 8 random holes, linear; 30%
+1x1x4 boxes with 20 ellipsoidal voids, compressible Neo-Hookean), sizes
+log-uniform in 1e4-5e5 elements, Poisson arrivals at 200/s.  Every request
+carries a warm start (its reference solution + 1% smooth noise, standing
+in for a network prediction) and is solved to a 1e-8 relative residual in
+FP32 mode (FP32 element kernels and Krylov vectors, FP64 dots, residuals
+and state).  Meshes, references (FP64, 1e-11, from zero) and guesses are
+prepared before the timed region; the server uploads each mesh when it
+admits the request.  The timed region is one open-loop replay of the whole
+stream; its K steps are K windows of consecutive arrivals.
 
-value = sum over timed solves of (K.v products * n_dof) / wall time, in
-GDOF/s.  The PCG runs in its fused form: one launch per iteration does the
-element pass (K.v) and every vector update.  The roofline object
-describes that kernel: algorithmic bytes per launch (K.v inputs plus the
-fused vector pass) divided by its average launch time, measured with HIP
-events on the library stream during the timed solves.
+value = served solves/s (512 / (last completion - first submission)), with
+p50 / p99 latency (completion - submission).  Beside it: the same stream
+from zero starts under the same arrivals, the same requests solved one at a
+time (warm and zero), batched K.v over all resident plates (a working set
+beyond the caches), the 200k-triangle plate's solve, an oracle check of 16
+served results, and the oracle timed on host cores.  The roofline object
+describes the stream's dominant kernel, the fused PCG iteration batched
+over the live requests: algorithmic bytes over the launches that did work
+(counted by the library per solve and iteration) divided by their
+duration, measured with HIP events on the server's stream.
 
 Other modes (not the default line):
   --kv-only N        N back-to-back K.v launches, or with --kv-kernel fused
                      about N fused PCG iterations (for rocprofv3 counters)
   --parse-pmc DIR    mean counter values per kernel from rocprofv3 CSVs
-  --config NAME      c1 | c3 | c4 | sweep | rotate | serve: the other
-                     workloads (unit square, 3D Neo-Hookean box, 64-mesh
-                     batch, K.v size sweep, rotating-buffer K.v, serving
-                     stream), one JSON line each
+  --config NAME      c1 | c2 | c3 | c4 | sweep | rotate | homog: the other
+                     workloads (unit square, 200k-triangle plate alone, 3D
+                     Neo-Hookean box, 64-mesh batch, K.v size sweep,
+                     rotating-buffer K.v, 64^3 TPMS cell homogenisation),
+                     one JSON line each
 """
 import argparse
 import glob
@@ -343,6 +353,50 @@ def run_c4():
     print(json.dumps(res), flush=True)
 
 
+def run_homog(n=64, seed=6001):
+    """Homogenisation of a 64^3 TPMS cell (solid voxels of the level set, 6
+    Kuhn tetrahedra each, periodic springs): the six cell problems solved
+    together in FP32 mode to 1e-8 from zero and from warm starts (reference
+    fluctuations, FP64 to 1e-11, plus 1% smooth noise), and the batched
+    apply of the six right-hand sides, one element visit for all six."""
+    import torch
+    from synth import tpms
+    from synth.fields import rff_field
+    from paper_2601_03086_amd import core
+    ctx = core.Context(0)
+    t0 = time.perf_counter()
+    cell = tpms.tpms_cell(seed, n=n)
+    m = core.Mesh.from_cell(ctx, cell)
+    _log(f"# cell {cell.name}: {cell.n_elems} tets, {len(cell.pairs)} pairs, "
+         f"prepared in {time.perf_counter() - t0:.1f}s")
+    Xr, EHr, _ = core.homogenize(m, tol=1e-11, prec="fp64")
+    noise = np.stack([rff_field(cell.coords, seed + 10 + k, 0.2, 64, n_comp=3).reshape(-1)
+                      for k in range(6)])
+    noise[:, 3 * cell.pin:3 * cell.pin + 3] = 0.0
+    u0 = Xr + (0.01 * np.linalg.norm(Xr, axis=1) / np.linalg.norm(noise, axis=1))[:, None] * noise
+    out = {"cell": {**cell.meta, "tets": cell.n_elems, "nodes": cell.n_nodes,
+                    "pairs": int(len(cell.pairs)), "block_nodes": m.info["block_nodes"]}}
+    for name, start in (("zero", None), ("warm", u0)):
+        core.homogenize(m, u0=start, tol=1e-8, prec="fp32")          # warm-up
+        ctx.set_timing([FAM_APPLY])
+        ctx.reset_timing()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        X, EH, reps = core.homogenize(m, u0=start, tol=1e-8, prec="fp32")
+        t = time.perf_counter() - t1
+        k = ctx.kernel_stats(FAM_APPLY)
+        ctx.set_timing(())
+        out[name] = {"ms": round(t * 1e3, 1), "kv": [r["kv_count"] for r in reps],
+                     "status": [r["status_name"] for r in reps],
+                     "EH_rel_err_vs_fp64": float(np.abs(EH - EHr).max() / np.abs(EHr).max()),
+                     "apply": {"launches": k["launches_run"],
+                               "avg_us": round(k["total_ms"] / max(k["launches_run"], 1) * 1e3, 2),
+                               "alg_GBps": round(k["alg_bytes"] / (k["total_ms"] * 1e-3) / 1e9, 1)
+                               if k["total_ms"] else 0.0}}
+    out["EH"] = np.round(EHr, 6).tolist()
+    print(json.dumps({"config": "homogenisation of a TPMS cell", **out}), flush=True)
+
+
 def run_sweep(spec):
     """K.v roofline sweep over generator meshes of the given sizes
     ("2d:2e5,3d:1e6,..." = element counts)."""
@@ -439,90 +493,409 @@ def run_rotate(copies, kind="c2"):
                       "GDOF_s": round(prob.n_dof / us * 1e-3, 2)}), flush=True)
 
 
-def run_serve(n_requests=512, rate=200.0, pool=24, budget_gb=96, max_slots=64):
-    """Serving stream: Poisson arrivals replayed open-loop into the server;
-    requests drawn from a pool of distinct meshes (70% plates, 30% 3D
-    Neo-Hookean boxes, 1e4-5e5 elements), each with a warm start
-    (reference + 1% smooth noise); tol 1e-8, FP32 mode.  Baselines: the
-    pool's requests solved one at a time from zero and from the warm start."""
+# ------------------------------------------------------------ serving (C5)
+SERVE_BUDGET_GB = 96      # device memory the server may hold for live solves
+SERVE_SLOTS = 64          # live solves at once
+VERIFY_N = 16             # served results checked by the oracle
+VERIFY_MAX_ELEMS = 30000  # ... drawn among requests of at most this size
+CPU_SAMPLE_N = 24         # the oracle's timed sample: the first plates of the
+CPU_SAMPLE_MAX_ELEMS = 100000   # stream with at most this many triangles
+
+
+def _gen_request(desc):
+    """Worker process: one request's problem and its unscaled warm-start
+    noise (the scale needs the reference solution)."""
+    import synth
+    p = synth.serving_problem(desc)
+    noise = synth.warm_start_noise(p.coords, p.dir_nodes, seed=desc["seed"] + 7,
+                                   n_features=synth.SERVING_NOISE_FEATURES)
+    return desc["id"], p, noise
+
+
+def _host_workers():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def gen_stream(n_requests, rate):
+    """The stream's request descriptors, problems and warm-start noises,
+    generated in worker processes (largest first) before any GPU use."""
+    import multiprocessing as mp
+    import synth
+    descs = synth.serving_stream(n_requests=n_requests, rate=rate)
+    order = sorted(range(len(descs)), key=lambda i: -descs[i]["target_elems"])
+    probs, noises = [None] * len(descs), [None] * len(descs)
+    with mp.get_context("fork").Pool(_host_workers()) as pool:
+        for i, p, nz in pool.imap_unordered(_gen_request, [descs[i] for i in order]):
+            probs[i], noises[i] = p, nz
+    return descs, probs, noises
+
+
+def host_meshes(probs):
+    """Finalized host-only meshes (the server uploads them on admission)."""
+    import concurrent.futures as cf
+    from paper_2601_03086_amd import core
+    with cf.ThreadPoolExecutor(4) as ex:
+        return list(ex.map(lambda p: core.Mesh.from_problem(None, p, 0, ORDER), probs))
+
+
+def _solve_kw(p, tol, prec):
+    kw = dict(tol=tol, prec=prec)
+    if p.nonlinear:
+        kw["n_load_steps"] = p.n_load_steps
+    return kw
+
+
+def serve(ctx, meshes, probs, u0s, t_arrive, ids, tol=1e-8, prec="fp32", timing=False,
+          keep=(), budget_gb=SERVE_BUDGET_GB, slots=SERVE_SLOTS):
+    """Open-loop replay: request ids[k] is submitted at t_arrive[k] seconds
+    after the server starts (u0s None: zero start).  Returns per-request
+    reports (library timestamps: submission, admission, completion), the
+    solutions of the ids in `keep`, server statistics and, with timing, the
+    kernel statistics of the apply and fused-iteration families."""
+    from paper_2601_03086_amd import core
+    srv = core.Server(ctx, int(budget_gb * (1 << 30)), max_slots=slots)
+    if timing:
+        srv.set_timing([FAM_APPLY, FAM_FUSED])
+    n = len(ids)
+    res, sols = {}, {}
+    nxt = 0
+    t0 = time.perf_counter()
+    last_log = t0
+    while len(res) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and t_arrive[nxt] <= now:
+            i = ids[nxt]
+            srv.submit(i, meshes[i], u0=None if u0s is None else u0s[i],
+                       **_solve_kw(probs[i], tol, prec))
+            nxt += 1
+        for rid in srv.poll():
+            u, r = srv.result(rid)
+            res[rid] = r
+            if rid in keep:
+                sols[rid] = u
+        if time.perf_counter() - last_log > 20:
+            last_log = time.perf_counter()
+            _log(f"#   {len(res)}/{n} done at {now:.1f}s")
+        time.sleep(0.0003)
+    st = srv.stats()
+    ks = {}
+    if timing:
+        ks = {nm: srv.kernel_stats(f) for f, nm in ((FAM_APPLY, "apply"),
+                                                   (FAM_FUSED, "fused_iter"))}
+    srv.close()
+    return res, sols, st, ks
+
+
+def stream_summary(res, probs, ids):
+    lat = np.sort([res[i]["t_done"] - res[i]["t_submit"] for i in ids])
+    t_first = min(res[i]["t_submit"] for i in ids)
+    t_last = max(res[i]["t_done"] for i in ids)
+    wall = t_last - t_first
+    kv = sum(res[i]["kv_count"] for i in ids)
+    gdof = sum(res[i]["kv_count"] * probs[i].n_dof for i in ids) / wall / 1e9
+    bad = [i for i in ids if res[i]["status"] not in (0, 2)]
+    return {"solves_per_s": round(len(ids) / wall, 2), "wall_s": round(wall, 3),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 1),
+                           "p99": round(float(np.percentile(lat, 99)) * 1e3, 1),
+                           "max": round(float(lat[-1]) * 1e3, 1)},
+            "kv_per_request": round(kv / len(ids), 1), "kv_GDOF_s": round(gdof, 3),
+            "failed": len(bad),
+            "worst_rel_residual": max(res[i]["rel_residual_final"] for i in ids)}
+
+
+def sequential(ctx, meshes, probs, u0s, ids, tol=1e-8, prec="fp32"):
+    """The same requests solved one at a time with pfem_solve (mesh upload
+    untimed, solve timed with its device-synchronising return)."""
+    import torch
+    tt, kv, lat = 0.0, 0, []
+    for i in ids:
+        m = meshes[i]
+        m.upload(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep, _ = m.solve(u0=None if u0s is None else u0s[i], history_cap=1,
+                            **_solve_kw(probs[i], tol, prec))
+        dt = time.perf_counter() - t0
+        m.release_device()
+        assert rep["status"] in (0, 2), rep
+        tt += dt
+        kv += rep["kv_count"]
+        lat.append(dt)
+    return {"solves_per_s": round(len(ids) / tt, 2), "mean_ms": round(tt / len(ids) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
+            "kv_per_request": round(kv / len(ids), 1)}, lat
+
+
+def batch_kv_point(ctx, meshes, probs, ids, prec, reps=20):
+    """One batched K.v (HVP at u = 0 for Neo-Hookean meshes) over many
+    resident meshes: a working set beyond the caches, every mesh a
+    distinct seeded plate or box of the stream."""
+    import torch
+    from paper_2601_03086_amd import core
+    ms = [meshes[i] for i in ids]
+    for m in ms:
+        m.upload(ctx)
+    b = core.Batch(ctx, ms)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    x = torch.randn(b.n_dof, dtype=dt, device="cuda")
+    nl = any(probs[i].nonlinear for i in ids)
+    u = torch.zeros_like(x) if nl else None
+    for _ in range(3):
+        b.hvp(u, x, prec=prec)
+    ctx.set_timing([FAM_APPLY])
+    ctx.reset_timing()
+    for _ in range(reps):
+        b.hvp(u, x, prec=prec)
+    n, t_ms = ctx.kernel_time(FAM_APPLY)
+    ctx.set_timing(())
+    us = t_ms / n * 1e3
+    s = 4 if prec == "fp32" else 8
+    b_alg = sum(alg_bytes_kv(probs[i].n_elems, probs[i].n_nodes, probs[i].dim, s=s, s_m=s)
+                + (probs[i].dim * s * probs[i].n_nodes if probs[i].nonlinear else 0)
+                for i in ids)
+    b.close()
+    for m in ms:
+        m.release_device()
+    n_dof = sum(probs[i].n_dof for i in ids)
+    return {"meshes": len(ids), "elements": int(sum(probs[i].n_elems for i in ids)),
+            "dim": probs[ids[0]].dim, "prec": prec,
+            "op": "HVP at u=0 (Neo-Hookean)" if nl else "K.v (linear)",
+            "alg_bytes": int(b_alg), "avg_us": round(us, 1),
+            "alg_GBps": round(b_alg / (us * 1e-6) / 1e9, 1),
+            "frac_hbm": round(b_alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "GDOF_s": round(n_dof / (us * 1e-6) / 1e9, 2)}
+
+
+def _verify_one(args):
+    """Oracle check of one served result (worker process): the oracle's
+    relative residual of the served field, and its distance to the
+    oracle's own solution (direct solve for linear plates, Newton with the
+    request's load steps for Neo-Hookean boxes)."""
+    i, p, u = args
+    import scipy.sparse.linalg as spla
+    from oracle import fe, solve as osolve
+    om = fe.Model(p)
+    if not p.nonlinear:
+        Kff, Ff, uD = osolve.reduced_system(om)
+        ud = uD.copy()
+        ud[om.free_dofs] = spla.spsolve(Kff.tocsc(), Ff)
+        rho = osolve.relative_residual(Kff, Ff, u[om.free_dofs])
+    else:
+        den = np.linalg.norm(om.gradient(om.lifted(1.0))[om.free_dofs])
+        rho = np.linalg.norm(om.gradient(u)[om.free_dofs]) / den
+        ud, _ = osolve.newton(p, tol=1e-11, n_load_steps=p.n_load_steps)
+    err = float(np.linalg.norm(u - ud) / np.linalg.norm(ud))
+    return i, float(rho), err
+
+
+def verify_subset(probs, sols, ids):
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(len(ids), _host_workers())) as pool:
+        out = pool.map(_verify_one, [(i, probs[i], sols[i]) for i in ids], chunksize=1)
+    rho = max(o[1] for o in out)
+    err = max(o[2] for o in out)
+    return {"requests": len(ids), "ids": [int(o[0]) for o in out],
+            "plates": sum(1 for i in ids if not probs[i].nonlinear),
+            "boxes": sum(1 for i in ids if probs[i].nonlinear),
+            "worst_oracle_rel_residual": rho, "worst_rel_error_vs_oracle_solution": err,
+            "pass": bool(rho <= 1.05e-8 and err <= 1e-5)}
+
+
+def cpu_sample_worker(path):
+    """The FP64 oracle timed on one host core: Jacobi-PCG (scipy CSR SpMV)
+    from each sampled plate's warm start to 1e-8 (problems and guesses read
+    from the .npz written by the parent)."""
+    from oracle import fe, solve as osolve
+    import synth
+    d = np.load(path, allow_pickle=False)
+    n = int(d["n"])
+    t_total, kv_total = 0.0, 0
+    for k in range(n):
+        p = synth.serving_problem({"id": int(d["ids"][k]), "kind": "2d",
+                                   "target_elems": float(d["targets"][k]),
+                                   "seed": int(d["seeds"][k])})
+        u0 = d[f"u0_{k}"]
+        m = fe.Model(p)
+        Kff, Ff, _ = osolve.reduced_system(m)
+        t0 = time.perf_counter()
+        _, hist, kv, st = osolve.pcg(Kff, Ff, u0[m.free_dofs], 1e-8, max_iter=20000)
+        t_total += time.perf_counter() - t0
+        kv_total += kv
+    print(json.dumps({"seconds": t_total, "solves": n, "kv": kv_total, "threads": 1}))
+
+
+def cpu_sample(descs, u0s, ids):
+    import tempfile
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "sample.npz")
+        arrs = {"n": np.array(len(ids)), "ids": np.array(ids),
+                "targets": np.array([descs[i]["target_elems"] for i in ids]),
+                "seeds": np.array([descs[i]["seed"] for i in ids])}
+        for k, i in enumerate(ids):
+            arrs[f"u0_{k}"] = u0s[i]
+        np.savez(path, **arrs)
+        r = subprocess.run([sys.executable, __file__, "--cpu-sample-worker", path], env=env,
+                           capture_output=True, text=True, timeout=900)
+    line = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not line:
+        return {"error": (r.stderr or r.stdout)[-400:]}
+    d = json.loads(line[-1])
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": round(d["solves"] / d["seconds"], 3), "unit": "solves/s",
+            "cores": d["threads"], "kind": "oracle",
+            "host": {"cpu_model": model, "affinity_cpus": len(os.sched_getaffinity(0)),
+                     "threads_env": {k: env[k] for k in ("OMP_NUM_THREADS",
+                                                         "OPENBLAS_NUM_THREADS",
+                                                         "MKL_NUM_THREADS")}},
+            "sample": (f"oracle FP64 Jacobi-PCG (scipy CSR SpMV, 1 thread) on the first "
+                       f"{d['solves']} plates of the stream with <= {CPU_SAMPLE_MAX_ELEMS} "
+                       f"triangles, each from its warm start to 1e-8: {d['kv']} K.v "
+                       f"products in {d['seconds']:.1f} s")}
+
+
+def run_c5(args):
+    """The serving stream as the headline (see the module docstring)."""
     import torch
     import synth
     from paper_2601_03086_amd import core
+    n_req, rate = args.requests, args.rate
+    t_setup = time.perf_counter()
+    descs, probs, noises = gen_stream(n_req, rate)
+    n_el = np.array([p.n_elems for p in probs])
+    _log(f"# generated {n_req} meshes ({int(n_el.sum())} elements, "
+         f"{sum(p.dim == 2 for p in probs)} plates) in {time.perf_counter() - t_setup:.1f}s")
+    t1 = time.perf_counter()
+    meshes = host_meshes(probs)
+    _log(f"# preprocessed on the host in {time.perf_counter() - t1:.1f}s")
     ctx = core.Context(0)
-    descs = synth.serving_stream(n_requests=pool, rate=rate)
-    probs, hmeshes, guesses, refs = [], [], [], []
+    ids = list(range(n_req))
+    t_arr = [d["t_arrive"] for d in descs]
+    # references (untimed): every request from zero, FP64, to 1e-11, batched
+    t1 = time.perf_counter()
+    ref, refsol, _, _ = serve(ctx, meshes, probs, None, [0.0] * n_req, ids, tol=1e-11,
+                              prec="fp64", keep=set(ids))
+    bad = [i for i in ids if ref[i]["status"] != 0]
+    assert not bad, ("reference solves failed", bad[:5], ref[bad[0]])
+    u0s = [synth.warm_start_guess(refsol[i], probs[i].coords, probs[i].dir_nodes, 0,
+                                  noise=noises[i]) for i in ids]
+    del refsol
+    _log(f"# references in {time.perf_counter() - t1:.1f}s")
+    # warm-up: the first W windows of the stream, untimed
+    w_ids = ids[:min(n_req, -(-args.warmup * n_req // args.steps))]
+    if w_ids:
+        serve(ctx, meshes, probs, u0s, t_arr[:len(w_ids)], w_ids)
+    _log(f"# setup {time.perf_counter() - t_setup:.1f}s")
+    # the timed stream: K windows of arrivals, one continuous replay
+    rng = np.random.default_rng(5997)
+    small = [i for i in ids if n_el[i] <= (VERIFY_MAX_ELEMS if probs[i].dim == 2
+                                             else VERIFY_MAX_ELEMS * 2 // 3)]
+    vset = sorted(rng.choice(small, size=min(VERIFY_N, len(small)), replace=False).tolist())
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for dsc in descs:
-        p = synth.serving_problem(dsc)
-        probs.append(p)
-        dm = new_mesh(ctx, p)
-        kw = dict(tol=1e-10, prec="fp64", history_cap=1)
-        if p.nonlinear:
-            kw["n_load_steps"] = p.n_load_steps
-        uref, rr, _ = dm.solve(**kw)
-        dm.close()
-        refs.append(rr)
-        guesses.append(synth.warm_start_guess(uref, p.coords, p.dir_nodes, seed=dsc["seed"] + 7))
-        hmeshes.append(new_mesh(None, p))
-        _log(f"# pool {len(probs)}/{pool}: {dsc['kind']} {p.n_elems} elems, ref "
-             f"{rr['status_name']} ({time.perf_counter() - t0:.0f}s)")
-    opts = dict(tol=1e-8, prec="fp32")
-
-    def solve_kw(p):
-        return dict(opts, n_load_steps=p.n_load_steps) if p.nonlinear else dict(opts)
-
-    # baselines: one at a time on a device mesh (uploaded beforehand)
-    base = {}
-    for name in ("zero", "warm"):
-        tt, kv = 0.0, 0
-        for i, p in enumerate(probs):
-            dm = new_mesh(ctx, p)
-            _, rep, t = _timed_solve(dm, u0=guesses[i] if name == "warm" else None,
-                                     history_cap=1, **solve_kw(p))
-            dm.close()
-            tt += t
-            kv += rep["kv_count"]
-        base[name] = {"mean_ms": round(tt / len(probs) * 1e3, 2), "solves_per_s":
-                      round(len(probs) / tt, 2), "kv_mean": kv / len(probs)}
-        _log(f"# sequential {name}: {tt / len(probs) * 1e3:.1f} ms per request")
-    # the stream
-    arrivals = synth.serving_stream(n_requests=n_requests, rate=rate)
-    srv = core.Server(ctx, int(budget_gb * (1 << 30)), max_slots=max_slots)
-    t_start = time.perf_counter()
-    done, results = set(), {}
-    nxt = 0
-    while len(done) < n_requests:
-        now = time.perf_counter() - t_start
-        while nxt < n_requests and arrivals[nxt]["t_arrive"] <= now:
-            i = nxt % pool
-            srv.submit(nxt, hmeshes[i], u0=guesses[i], **solve_kw(probs[i]))
-            nxt += 1
-        for rid in srv.poll():
-            done.add(rid)
-            _, r = srv.result(rid)
-            results[rid] = r
-        if len(done) and len(done) % 64 == 0 and len(done) != getattr(run_serve, "_last", -1):
-            run_serve._last = len(done)
-            _log(f"# stream: {len(done)}/{n_requests} done at {now:.1f}s")
-        time.sleep(0.0005)
-    st = srv.stats()
-    srv.close()
-    lat = sorted(r["t_done"] - r["t_submit"] for r in results.values())
-    t_first = min(r["t_submit"] for r in results.values())
-    t_last = max(r["t_done"] for r in results.values())
-    ok = sum(1 for r in results.values() if r["status"] in (0, 2))
-    worst = max(r["rel_residual_final"] for r in results.values())
-    print(json.dumps({
-        "config": f"C5 serving stream: {n_requests} requests from a pool of {pool} meshes "
-                  f"(plates and 3D Neo-Hookean boxes, 1e4-5e5 elements), Poisson arrivals "
-                  f"{rate}/s, warm starts, tol 1e-8, FP32 mode",
-        "offered_per_s": rate, "achieved_solves_per_s": round(n_requests / (t_last - t_first), 2),
-        "latency_ms": {"p50": round(lat[len(lat) // 2] * 1e3, 1),
-                       "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))] * 1e3, 1),
-                       "max": round(lat[-1] * 1e3, 1)},
-        "ok": ok, "worst_rel_residual": worst, "peak_live": st["peak_live"],
-        "peak_bytes": st["peak_bytes"], "launches": st["launches"],
-        "sequential_zero": base["zero"], "sequential_warm": base["warm"]}), flush=True)
+    res_w, sols, st_w, ks = serve(ctx, meshes, probs, u0s, t_arr, ids, timing=True,
+                                  keep=set(vset))
+    torch.cuda.synchronize()
+    t_timed = time.perf_counter() - t0
+    warm = stream_summary(res_w, probs, ids)
+    _log(f"# warm stream: {warm}")
+    fk = ks["fused_iter"]
+    _log(f"# fused iteration: {fk}")
+    if args.stream_only:       # profiling runs: setup, warm-up and the timed stream
+        print(json.dumps({"served_warm": warm, "fused_iter": fk, "apply": ks["apply"],
+                          "ms_per_step": round(t_timed / args.steps * 1e3, 3)}), flush=True)
+        return
+    res_z, _, st_z, _ = serve(ctx, meshes, probs, None, t_arr, ids)
+    zero = stream_summary(res_z, probs, ids)
+    _log(f"# zero-start stream: {zero}")
+    seq_w, lat_sw = sequential(ctx, meshes, probs, u0s, ids)
+    _log(f"# sequential warm: {seq_w}")
+    seq_z, _ = sequential(ctx, meshes, probs, None, ids)
+    _log(f"# sequential zero: {seq_z}")
+    plates = [i for i in ids if probs[i].dim == 2]
+    boxes = [i for i in ids if probs[i].dim == 3]
+    kv_points = [batch_kv_point(ctx, meshes, probs, plates, "fp32"),
+                 batch_kv_point(ctx, meshes, probs, plates, "fp64"),
+                 batch_kv_point(ctx, meshes, probs, boxes, "fp32")]
+    _log(f"# batched K.v: {kv_points}")
+    c2 = c2_leg(ctx, args)
+    _log(f"# C2: {c2}")
+    ver = verify_subset(probs, sols, vset)
+    _log(f"# oracle check: {ver}")
+    # the dominant kernel of the stream: the fused PCG iteration
+    avg_ms = fk["total_ms"] / max(fk["launches_run"], 1)
+    achieved = fk["alg_bytes"] / (fk["total_ms"] * 1e-3) / 1e9 if fk["total_ms"] else 0.0
+    res = {
+        "metric": METRIC,
+        "value": warm["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_timed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"serving stream: {n_req} solve requests on {n_req} distinct seeded "
+                         f"meshes, Poisson arrivals {rate:g}/s, 70% plane-strain plates with "
+                         f"8 holes (linear) / 30% 1x1x4 boxes with 20 voids (Neo-Hookean), "
+                         f"1e4-5e5 elements log-uniform, warm starts = reference + 1% smooth "
+                         f"noise, tol 1e-8 relative residual, continuous batching under a "
+                         f"{SERVE_BUDGET_GB} GiB / {SERVE_SLOTS}-slot budget; one step = one "
+                         f"of {args.steps} arrival windows of the one timed stream"),
+            "requests": n_req, "elements_total": int(n_el.sum()),
+            "plates": len(plates), "boxes": len(boxes), "rate_per_s": rate, "tol": 1e-8,
+            "precision": "fp32 element math and Krylov vectors; fp64 dots, residuals, "
+                         "state, line-search energy and det F near compression",
+        },
+        "latency_ms": warm["latency_ms"],
+        "served_warm": warm,
+        "served_zero_start": zero,
+        "sequential_warm": seq_w,
+        "sequential_zero_start": seq_z,
+        "server": {"peak_live": st_w["peak_live"], "peak_bytes": st_w["peak_bytes"],
+                   "steps": st_w["steps"], "launches": st_w["launches"]},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_fcg (fused PCG iteration, batched over live requests)",
+            "note": ("HBM is the roof; the batched launches' working sets (alg_bytes_per_"
+                     "launch) fit the 256 MB Infinity Cache and each iteration is a chain "
+                     "of dependent round trips, so latency keeps it below the roof"),
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "alg_bytes_per_launch": round(fk["alg_bytes"] / max(fk["launches_run"], 1)),
+            "avg_launch_us": round(avg_ms * 1e3, 3),
+            "launches_timed": fk["launches_timed"],
+            "apply": ks["apply"],
+        },
+        "kv_large_working_set": kv_points,
+        "c2_plate_solve": c2,
+        "oracle_verified": ver,
+    }
+    if not args.no_cpu_baseline:
+        cs = [i for i in ids if probs[i].dim == 2 and n_el[i] <= CPU_SAMPLE_MAX_ELEMS]
+        cs = cs[:CPU_SAMPLE_N]
+        res["cpu_baseline"] = cpu_sample(descs, u0s, cs)
+        res["cpu_baseline"]["gpu_sequential_same_sample_solves_per_s"] = round(
+            len(cs) / sum(lat_sw[i] for i in cs), 2)
+    print(json.dumps(res), flush=True)
 
 
 # --------------------------------------------------------------------- main
@@ -724,65 +1097,8 @@ def run_kv_large(spec, reps=50):
         del prob
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-baseline-worker", action="store_true")
-    ap.add_argument("--kv-only", type=int, default=0)
-    ap.add_argument("--parse-pmc", default=None)
-    ap.add_argument("--kv-sweep", default=None,
-                    help="comma-separated owner-block sizes to time K.v with")
-    ap.add_argument("--block-nodes", type=int, default=0)
-    ap.add_argument("--order", default="blocks", choices=["blocks", "rcm"],
-                    help="internal node numbering of every mesh")
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"],
-                    help="solve precision (fp32: FP32 Krylov + FP64 refinement)")
-    ap.add_argument("--kv-mesh", default=None, help='mesh for --kv-only, e.g. "3d:40"')
-    ap.add_argument("--kv-kernel", default="owner", choices=["owner", "fused"],
-                    help="--kv-only: K.v launches or fused PCG iterations")
-    ap.add_argument("--kv-large", default=None,
-                    help='e.g. "2d:2000,3d:60": K.v roofline sweep on large meshes')
-    ap.add_argument("--config", default=None,
-                    choices=["c1", "c3", "c4", "sweep", "rotate", "serve"],
-                    help="other workloads (one JSON line each, not the headline)")
-    ap.add_argument("--sizes", default="2d:2e5,2d:1e6,2d:4e6,2d:1.6e7,3d:1e6,3d:4e6,3d:1.6e7",
-                    help="--config sweep sizes (element counts)")
-    ap.add_argument("--copies", type=int, default=192, help="--config rotate copies")
-    ap.add_argument("--requests", type=int, default=512, help="--config serve")
-    ap.add_argument("--rate", type=float, default=200.0, help="--config serve arrivals/s")
-    ap.add_argument("--pool", type=int, default=24, help="--config serve distinct meshes")
-    args = ap.parse_args()
-    global ORDER, BLOCK_NODES
-    ORDER, BLOCK_NODES = args.order, args.block_nodes
-    if args.cpu_baseline_worker:
-        cpu_baseline_worker()
-        return
-    if args.parse_pmc:
-        d = parse_pmc(args.parse_pmc)
-        print(json.dumps(d, indent=1))
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (the library has no multi-GPU path); "
-              f"--gpus {args.gpus} is not supported", file=sys.stderr)
-        sys.exit(2)
-    if args.kv_only:
-        run_kv_only(args.kv_only, args.kv_mesh, args.kv_kernel)
-        return
-    if args.kv_sweep:
-        run_kv_sweep([int(s) for s in args.kv_sweep.split(",")], args.kv_mesh)
-        return
-    if args.kv_large:
-        run_kv_large(args.kv_large)
-        return
-    if args.config:
-        {"c1": run_c1, "c3": run_c3, "c4": run_c4,
-         "sweep": lambda: run_sweep(args.sizes),
-         "rotate": lambda: run_rotate(args.copies),
-         "serve": lambda: run_serve(args.requests, args.rate, args.pool)}[args.config]()
-        return
+def run_c2(args):
+    """The 200k-triangle plate alone: warm FP32 solves (one JSON line)."""
     import torch
     t_setup = time.perf_counter()
     prob, ctx, mesh, u0, uref, ref_hist = setup(args)
@@ -791,8 +1107,11 @@ def main():
     print(f"# setup {time.perf_counter() - t_setup:.1f}s: {prob.n_elems} triangles, "
           f"{prob.n_dof} DOFs, {info['n_blocks']} blocks of {info['block_nodes']} nodes",
           file=sys.stderr, flush=True)
-    opts = dict(tol=1e-8, prec=args.prec, krylov="fused", device_io=True, out=out,
-                history_cap=1)
+    two_level = args.precond == "two_level"
+    if two_level:
+        mesh.prepare_coarse()
+    opts = dict(tol=1e-8, prec=args.prec, krylov="classic" if two_level else "fused",
+                precond=args.precond, device_io=True, out=out, history_cap=1)
     for _ in range(args.warmup):
         mesh.solve(u0=u0, **opts)
     # zero-start reference solve (not timed in the headline)
@@ -800,7 +1119,8 @@ def main():
     # the dominant kernel's duration: HIP events around each chunk of
     # consecutive fused-iteration launches of the timed solves (chunks that
     # ran past convergence are discarded), divided by the launches in it
-    ctx.set_timing([FAM_FUSED])
+    dom = FAM_APPLY if two_level else FAM_FUSED
+    ctx.set_timing([dom])
     ctx.reset_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -815,7 +1135,8 @@ def main():
         reps.append(rep)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    n_apply, ms_apply = ctx.kernel_time(FAM_FUSED)
+    n_apply, ms_apply = ctx.kernel_time(dom)
+    k_dom = ctx.kernel_stats(dom)
     # per-family breakdown from two extra solves with every family timed
     ctx.set_timing(range(7))
     ctx.reset_timing()
@@ -828,12 +1149,13 @@ def main():
             breakdown[nm] = {"launches_per_solve": n_f / 2, "avg_us": round(ms_f / n_f * 1e3, 3)}
     ctx.set_timing(())
     # the same warm solves with the three-launch PCG loop, for comparison
+    opts["krylov"] = "classic"
     torch.cuda.synchronize()
     tc0 = time.perf_counter()
     n_cls = max(2, args.steps // 4)
     kv_cls = 0
     for _ in range(n_cls):
-        _, rc, _ = mesh.solve(u0=u0, **dict(opts, krylov="classic"))
+        _, rc, _ = mesh.solve(u0=u0, **opts)
         kv_cls += rc["kv_count"]
     torch.cuda.synchronize()
     t_cls = time.perf_counter() - tc0
@@ -841,8 +1163,12 @@ def main():
     value = kv_total * prob.n_dof / t / 1e9
     avg_ms = ms_apply / max(n_apply, 1)
     s_val = 4 if args.prec == "fp32" else 8
-    b_alg = alg_bytes_fused(prob.n_elems, prob.n_nodes, 2, s=s_val, s_m=s_val)
-    kernel = f"k_fcg<2, {'float' if args.prec == 'fp32' else 'double'}, false>"
+    if two_level:
+        b_alg = k_dom["alg_bytes"] / max(k_dom["launches_run"], 1)
+        kernel = f"k_owner<2, {'float' if args.prec == 'fp32' else 'double'}, K.v>"
+    else:
+        b_alg = alg_bytes_fused(prob.n_elems, prob.n_nodes, 2, s=s_val, s_m=s_val)
+        kernel = f"k_fcg<2, {'float' if args.prec == 'fp32' else 'double'}, false>"
     achieved = b_alg / (avg_ms * 1e-3) / 1e9
     lat_sorted = sorted(lat)
     res = {
@@ -861,9 +1187,11 @@ def main():
         "config": {
             "workload": ("plane-strain plate, 8 random holes, "
                          f"{prob.n_elems} P1 triangles / {prob.n_dof} DOFs, lognormal E, "
-                         "warm start = reference + 1% smooth noise, Jacobi-PCG to 1e-8 "
+                         "warm start = reference + 1% smooth noise, "
+                         + ("two-level-PCG" if two_level else "Jacobi-PCG") + " to 1e-8 "
                          + ("(FP32 Krylov, FP64 residual refinement)" if args.prec == "fp32"
-                            else "(FP64)") + ", fused one-launch iteration"),
+                            else "(FP64)")
+                         + (", classic loop" if two_level else ", fused one-launch iteration")),
             "n_elems": prob.n_elems, "n_dof": prob.n_dof, "tol": 1e-8,
             "precision": ("fp32 element math and Krylov vectors; fp64 dots, residuals, x"
                           if args.prec == "fp32" else "fp64 throughout"),
@@ -897,6 +1225,147 @@ def main():
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res))
+
+
+def c2_leg(ctx, args, n_solves=5):
+    """The 200k-triangle plate (C2) inside the default run: warm solves to
+    1e-8 in FP32 mode (fused iteration) and in FP64 (fused), K.v rate and
+    time to solution of each, and the fused FP32 iteration's roofline from
+    HIP events on the library stream."""
+    import torch
+    import synth
+    prob = c2_problem()
+    mesh = new_mesh(ctx, prob)
+    uref, _, _ = mesh.solve(tol=1e-11, prec="fp64", device_io=True)
+    u0 = torch.tensor(synth.warm_start_guess(uref.cpu().numpy(), prob.coords, prob.dir_nodes,
+                                             seed=3002), device="cuda", dtype=torch.float64)
+    out = mesh.new_vec("fp64")
+    res = {"mesh": f"{prob.n_elems} triangles, {prob.n_dof} DOFs"}
+    for prec in ("fp32", "fp64"):
+        opts = dict(tol=1e-8, prec=prec, krylov="fused", device_io=True, out=out,
+                    history_cap=1)
+        for _ in range(2):
+            mesh.solve(u0=u0, **opts)
+        ctx.set_timing([FAM_FUSED])
+        ctx.reset_timing()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kv = 0
+        for _ in range(n_solves):
+            _, rep, _ = mesh.solve(u0=u0, **opts)
+            assert rep["status"] == 0 and rep["rel_residual_final"] <= 1e-8, rep
+            kv += rep["kv_count"]
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        k = ctx.kernel_stats(FAM_FUSED)
+        ctx.set_timing(())
+        us = k["total_ms"] / max(k["launches_run"], 1) * 1e3
+        b = k["alg_bytes"] / max(k["launches_run"], 1)
+        res[prec] = {"ms_per_solve": round(t / n_solves * 1e3, 2),
+                     "kv_per_solve": kv / n_solves,
+                     "GDOF_s": round(kv * prob.n_dof / t / 1e9, 2),
+                     "fused_iter": {"alg_bytes_per_launch": round(b), "avg_us": round(us, 3),
+                                    "alg_GBps": round(b / us * 1e-3, 1),
+                                    "frac_hbm": round(b / us * 1e-3 / HBM_PEAK_GBS, 4)}}
+    # the two-level preconditioner (rigid-body coarse space on owner blocks):
+    # warm and zero starts, FP32 mode, classic loop
+    t0 = time.perf_counter()
+    n_c = mesh.prepare_coarse()
+    res["two_level"] = {"coarse_dofs": n_c, "setup_s": round(time.perf_counter() - t0, 3)}
+    for name, start in (("warm", u0), ("zero", None)):
+        opts = dict(tol=1e-8, prec="fp32", precond="two_level", device_io=True, out=out,
+                    history_cap=1)
+        mesh.solve(u0=start, **opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kv = 0
+        for _ in range(n_solves):
+            _, rep, _ = mesh.solve(u0=start, **opts)
+            assert rep["status"] == 0 and rep["rel_residual_final"] <= 1e-8, rep
+            kv += rep["kv_count"]
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res["two_level"][name] = {"ms_per_solve": round(t / n_solves * 1e3, 2),
+                                  "kv_per_solve": kv / n_solves}
+    for name, start in (("jacobi_zero", None),):
+        opts = dict(tol=1e-8, prec="fp32", krylov="fused", device_io=True, out=out, history_cap=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep, _ = mesh.solve(u0=start, **opts)
+        torch.cuda.synchronize()
+        res["fp32"][name] = {"ms": round((time.perf_counter() - t0) * 1e3, 2),
+                             "kv": rep["kv_count"]}
+    mesh.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-worker", action="store_true")
+    ap.add_argument("--kv-only", type=int, default=0)
+    ap.add_argument("--parse-pmc", default=None)
+    ap.add_argument("--kv-sweep", default=None,
+                    help="comma-separated owner-block sizes to time K.v with")
+    ap.add_argument("--block-nodes", type=int, default=0)
+    ap.add_argument("--order", default="blocks", choices=["blocks", "rcm"],
+                    help="internal node numbering of every mesh")
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "two_level"],
+                    help="--config c2 preconditioner")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"],
+                    help="solve precision (fp32: FP32 Krylov + FP64 refinement)")
+    ap.add_argument("--kv-mesh", default=None, help='mesh for --kv-only, e.g. "3d:40"')
+    ap.add_argument("--kv-kernel", default="owner", choices=["owner", "fused"],
+                    help="--kv-only: K.v launches or fused PCG iterations")
+    ap.add_argument("--kv-large", default=None,
+                    help='e.g. "2d:2000,3d:60": K.v roofline sweep on large meshes')
+    ap.add_argument("--config", default=None,
+                    choices=["c1", "c2", "c3", "c4", "sweep", "rotate", "homog"],
+                    help="other workloads (one JSON line each, not the headline)")
+    ap.add_argument("--sizes", default="2d:2e5,2d:1e6,2d:4e6,2d:1.6e7,3d:1e6,3d:4e6,3d:1.6e7",
+                    help="--config sweep sizes (element counts)")
+    ap.add_argument("--copies", type=int, default=192, help="--config rotate copies")
+    ap.add_argument("--requests", type=int, default=512, help="serving stream requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving arrivals per second")
+    ap.add_argument("--cpu-sample-worker", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--stream-only", action="store_true",
+                    help="serving: stop after the timed stream (for profiler runs)")
+    args = ap.parse_args()
+    global ORDER, BLOCK_NODES
+    ORDER, BLOCK_NODES = args.order, args.block_nodes
+    if args.cpu_baseline_worker:
+        cpu_baseline_worker()
+        return
+    if args.cpu_sample_worker:
+        cpu_sample_worker(args.cpu_sample_worker)
+        return
+    if args.parse_pmc:
+        d = parse_pmc(args.parse_pmc)
+        print(json.dumps(d, indent=1))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the library has no multi-GPU path); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    if args.kv_only:
+        run_kv_only(args.kv_only, args.kv_mesh, args.kv_kernel)
+        return
+    if args.kv_sweep:
+        run_kv_sweep([int(s) for s in args.kv_sweep.split(",")], args.kv_mesh)
+        return
+    if args.kv_large:
+        run_kv_large(args.kv_large)
+        return
+    if args.config:
+        {"c1": run_c1, "c2": lambda: run_c2(args), "c3": run_c3, "c4": run_c4,
+         "sweep": lambda: run_sweep(args.sizes),
+         "rotate": lambda: run_rotate(args.copies),
+         "homog": run_homog}[args.config]()
+        return
+    run_c5(args)
 
 
 if __name__ == "__main__":

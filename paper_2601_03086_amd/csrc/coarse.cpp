@@ -338,14 +338,44 @@ void coarse_build(pfem_mesh* m) {
       A[(size_t)i * c->n_c + i] = 1.0;
     }
   spd_inverse(c->n_c, A);
-  c->Ainv.swap(A);
+  // B = T A_c^-1 T^T (T block diagonal, one nrb x nrb block per aggregate):
+  // the coarse correction in raw-mode coordinates, y = B (R^T r), so the
+  // device needs neither T nor the orthonormal coordinates
+  const int n = c->n_c;
+  std::vector<double> C((size_t)n * n);
+  run_threads(c->n_agg, [&](int, int64_t b, int64_t e) {
+    for (int64_t a = b; a < e; ++a) {
+      const double* Ta = &c->T[(size_t)a * nrb * nrb];
+      for (int k = 0; k < nrb; ++k) {        // C = A_c^-1 T^T, rows of aggregate a
+        const double* arow = &A[(size_t)(a * nrb + k) * n];
+        double* crow = &C[(size_t)(a * nrb + k) * n];
+        for (int g = 0; g < c->n_agg; ++g) {
+          const double* Tg = &c->T[(size_t)g * nrb * nrb];
+          for (int l = 0; l < nrb; ++l) {
+            double v = 0.0;
+            for (int q = 0; q < nrb; ++q) v += arow[g * nrb + q] * Tg[l * nrb + q];
+            crow[g * nrb + l] = v;
+          }
+        }
+      }
+      for (int j = 0; j < nrb; ++j) {        // B = T C, rows of aggregate a
+        double* brow = &A[(size_t)(a * nrb + j) * n];
+        for (int col = 0; col < n; ++col) {
+          double v = 0.0;
+          for (int k = 0; k < nrb; ++k) v += Ta[j * nrb + k] * C[(size_t)(a * nrb + k) * n + col];
+          brow[col] = v;
+        }
+      }
+    }
+  }, host_threads());
+  c->B.swap(A);
   m->coarse = std::move(c);
 }
 
 void coarse_upload(pfem_mesh* m, Ctx* ctx) {
   coarse_build(m);
   std::lock_guard<std::mutex> lk(m->coarse_mu);
-  if (m->dev.coarse_Ainv64 != nullptr) return;
+  if (m->dev.coarse_B64 != nullptr) return;
   const CoarseHost& c = *m->coarse;
   const int D = m->dim;
   std::vector<double> rel64(m->X_int.size());
@@ -357,18 +387,17 @@ void coarse_upload(pfem_mesh* m, Ctx* ctx) {
       rel32[n * D + i] = (float)rel64[n * D + i];
     }
   }
-  std::vector<float> a32(c.Ainv.begin(), c.Ainv.end());
+  std::vector<float> b32(c.B.begin(), c.B.end());
   auto up = [&](void** p, const void* src, size_t bytes) {
     PFEM_HIP(hipMalloc(p, std::max<size_t>(bytes, 8)));
     PFEM_HIP(hipMemcpy(*p, src, bytes, hipMemcpyHostToDevice));
     m->dev.bytes += (int64_t)std::max<size_t>(bytes, 8);
   };
   (void)ctx;
-  up((void**)&m->dev.coarse_T, c.T.data(), c.T.size() * 8);
   up((void**)&m->dev.coarse_rel64, rel64.data(), rel64.size() * 8);
   up((void**)&m->dev.coarse_rel32, rel32.data(), rel32.size() * 4);
-  up((void**)&m->dev.coarse_Ainv32, a32.data(), a32.size() * 4);
-  up((void**)&m->dev.coarse_Ainv64, c.Ainv.data(), c.Ainv.size() * 8);
+  up((void**)&m->dev.coarse_B32, b32.data(), b32.size() * 4);
+  up((void**)&m->dev.coarse_B64, c.B.data(), c.B.size() * 8);
 }
 
 int64_t coarse_device_bytes(const pfem_mesh* m) {
@@ -376,7 +405,7 @@ int64_t coarse_device_bytes(const pfem_mesh* m) {
   const int64_t G = coarse_group(m);
   const int64_t n_agg = (m->n_blocks + G - 1) / G;
   const int64_t nc = n_agg * nrb;
-  return n_agg * nrb * nrb * 8 + m->n_dof() * 12 + nc * nc * 12 + 5 * 8;
+  return m->n_dof() * 12 + nc * nc * 12 + 4 * 8;
 }
 
 }  // namespace pfem

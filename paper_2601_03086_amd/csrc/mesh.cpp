@@ -783,8 +783,7 @@ void mesh_release_device(pfem_mesh* m) {
   MeshDevBuffers& d = m->dev;
   void* ptrs[] = {d.X, d.Xq, d.conn, d.connp, d.mu32, d.lam32, d.mu64, d.lam64, d.dmask, d.blocks,
                   d.halo, d.fext, d.ubar, d.colored, d.perm, d.work, d.pair_ptr,
-                  d.pair_nbr, d.coarse_T, d.coarse_rel64, d.coarse_rel32, d.coarse_Ainv32,
-                  d.coarse_Ainv64};
+                  d.pair_nbr, d.coarse_rel64, d.coarse_rel32, d.coarse_B32, d.coarse_B64};
   for (void* p : ptrs)
     if (p != nullptr) (void)hipFree(p);
   d = MeshDevBuffers{};
@@ -813,7 +812,8 @@ int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg, bool two_level
   if (two_level) {   // the solve's own arrays and the mesh's coarse arrays
     const int64_t G = coarse_group(m);
     const int64_t n_agg = (m->n_blocks + G - 1) / G;
-    b += (int64_t)m->n_blocks * 48 + n_agg * 48 + 8 * (n_agg / kCoarseChunkAgg + 1) + 1024 +
+    const int64_t n_c = n_agg * (m->dim == 2 ? 3 : 6);
+    b += (int64_t)m->n_blocks * 48 + n_agg * 48 + 8 * (n_c / kCoarseRows + 1) + 1024 +
          coarse_device_bytes(m);
   }
   return b;

@@ -16,7 +16,8 @@ struct CoarseHost {
   std::vector<double> cent;  // n_agg * 3 centroids (internal coordinates)
   std::vector<double> T;     // n_agg * n_rb * n_rb: column k = raw-mode coefficients of
                              // the aggregate's orthonormal coarse DOF k (0: dropped)
-  std::vector<double> Ainv;  // n_c * n_c inverse of P^T K P, row-major
+  std::vector<double> B;     // n_c * n_c, row-major: T (P^T K P)^-1 T^T, the coarse
+                             // correction in raw-mode coordinates
 };
 
 // Device-resident solver state for one solve (one slot).
@@ -74,11 +75,11 @@ struct MeshDevBuffers {
   int2* work = nullptr;      // single-mesh work table (XCD-remapped)
   int32_t* pair_ptr = nullptr;
   int32_t* pair_nbr = nullptr;
-  double* coarse_T = nullptr;      // two-level preconditioner (uploaded on first use)
+  // two-level preconditioner (uploaded on first use)
   double* coarse_rel64 = nullptr;  // node coordinates relative to their aggregate's centroid
   float* coarse_rel32 = nullptr;
-  float* coarse_Ainv32 = nullptr;
-  double* coarse_Ainv64 = nullptr;
+  float* coarse_B32 = nullptr;     // raw-mode coarse correction matrix
+  double* coarse_B64 = nullptr;
   int64_t bytes = 0;
 };
 

@@ -119,16 +119,16 @@ struct Scalars {
 // Two-level preconditioner state of one solve (device memory): the mesh's
 // coarse arrays and the solve's restriction partials and coarse correction.
 struct TwoLevelDev {
-  const double* T;        // n_agg * nrb * nrb: raw-mode coefficients of each coarse DOF
   const void* rel;        // n_nodes * dim coordinates relative to the aggregate centroid
                           // (kernel precision)
-  const void* Ainv;       // n_c * n_c inverse coarse matrix (kernel precision), row-major
+  const void* B;          // n_c * n_c raw-mode coarse correction T A_c^-1 T^T (kernel
+                          // precision), row-major, symmetric
   double* rc_part;        // n_blocks * 6: per owner block, raw-mode sums of the residual
   double* y;              // n_agg * 6: raw-mode coefficients of the coarse correction
-  double* gc_part;        // n_chunks partials of r_c . z_c
+  double* gc_part;        // n_chunks partials of (R^T r) . y
   int32_t nrb, G, n_agg, n_c, n_chunks, pad;
 };
-constexpr int kCoarseChunkAgg = 16;   // aggregates per workgroup of the coarse solve
+constexpr int kCoarseRows = 8;   // rows of B per workgroup of the coarse solve
 // Largest coarse dimension: the device applies the coarse inverse as one
 // dense matrix-vector product per iteration.
 constexpr int kCoarseMax = 1536;

@@ -53,15 +53,14 @@ void SolveState::alloc_two_level(const pfem_mesh* m) {
     PFEM_HIP(hipMalloc(p, std::max<size_t>(n, 8)));
     bytes += (int64_t)std::max<size_t>(n, 8);
   };
-  const int n_chunks = (c.n_agg + kCoarseChunkAgg - 1) / kCoarseChunkAgg;
+  const int n_chunks = (c.n_c + kCoarseRows - 1) / kCoarseRows;
   A((void**)&rc_part, (size_t)std::max(m->n_blocks, 1) * 6 * 8);
   A((void**)&tl_y, (size_t)c.n_agg * 6 * 8);
   A((void**)&gc_part, (size_t)n_chunks * 8);
   A((void**)&tl_dev, sizeof(TwoLevelDev));
   TwoLevelDev t{};
-  t.T = m->dev.coarse_T;
   t.rel = prec == PFEM_FP64 ? (const void*)m->dev.coarse_rel64 : (const void*)m->dev.coarse_rel32;
-  t.Ainv = prec == PFEM_FP64 ? (const void*)m->dev.coarse_Ainv64 : (const void*)m->dev.coarse_Ainv32;
+  t.B = prec == PFEM_FP64 ? (const void*)m->dev.coarse_B64 : (const void*)m->dev.coarse_B32;
   t.rc_part = rc_part;
   t.y = tl_y;
   t.gc_part = gc_part;
@@ -246,7 +245,7 @@ static const int2* coarse_work(Ctx* ctx, const Group& g, int* n_items) {
   std::vector<int2> w;
   for (size_t i = 0; i < g.slots.size(); ++i) {
     const CoarseHost& c = *g.slots[i]->m->coarse;
-    const int nch = (c.n_agg + kCoarseChunkAgg - 1) / kCoarseChunkAgg;
+    const int nch = (c.n_c + kCoarseRows - 1) / kCoarseRows;
     for (int k = 0; k < nch; ++k) w.push_back(make_int2((int)i, k));
   }
   *n_items = (int)w.size();

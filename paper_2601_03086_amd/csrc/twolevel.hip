@@ -4,11 +4,12 @@
 // part through three passes that ride on the PCG's own launches --
 //   restriction: every owner block sums the raw rigid modes of its nodes
 //     against the new residual, in the same pass as the residual update;
-//   coarse solve: one workgroup per (solve, 16 aggregates) sums the block
-//     partials of every aggregate, maps them to the orthonormal coarse basis
-//     (r_c), multiplies its rows of the dense inverse with r_c (one wave per
-//     row) and maps the result back to raw-mode coefficients y; its partial
-//     of r_c . z_c is the coarse share of r . M^-1 r;
+//   coarse solve: one workgroup per (solve, kCoarseRows rows) sums the
+//     block partials of every aggregate (the raw restriction R^T r) and
+//     multiplies its rows of B = T A_c^-1 T^T with it, giving the raw-mode
+//     coefficients y of the coarse correction (T maps raw modes to the
+//     orthonormal coarse basis; it is folded into B on the host); its
+//     partial of (R^T r) . y is the coarse share of r . M^-1 r;
 //   prolongation: the direction pass evaluates z = D^-1 r + R(x) y at every
 //     DOF it owns, so p = z + beta p needs no extra vector.
 // Every sum runs in a fixed order, as the other reductions of the library.
@@ -96,55 +97,69 @@ k_tl_init(const Task* __restrict__ tasks, const int2* __restrict__ work) {
   write_partials(tp->red, tp->m.n_blocks, wk.y, part, 1, 3);
 }
 
-// The coarse solve of one chunk of aggregates (see the file comment).
+// The coarse solve of one chunk of kCoarseRows rows of B (see the file
+// comment): every workgroup gathers the whole raw restriction R^T r into LDS,
+// then each wave takes two rows of B at once.
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_tl_coarse(const Task* __restrict__ tasks, const int2* __restrict__ cwork, int init) {
+  static_assert(kCoarseRows == 2 * (kThreads / 64), "two rows of B per wave");
   __shared__ double rc[kCoarseMax];
-  __shared__ double zc[kCoarseChunkAgg * 6];
+  __shared__ double ys[kCoarseRows];
   const int2 wk = cwork[blockIdx.x];
   const Task* tp = tasks + wk.x;
   if (!tp->active) return;
   if (!init && ldg(&tp->sc->state) != 0) return;
   const TwoLevelDev tl = *tp->tl;
-  const int nrb = tl.nrb, nb = tp->m.n_blocks;
-  for (int a = threadIdx.x; a < tl.n_agg; a += kThreads) {
-    double raw[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int nrb = tl.nrb, nb = tp->m.n_blocks, n_c = tl.n_c;
+  for (int i = threadIdx.x; i < n_c; i += kThreads) {
+    const int a = i / nrb, j = i - a * nrb;
     const int b1 = min(nb, (a + 1) * tl.G);
-    for (int b = a * tl.G; b < b1; ++b)
-      for (int j = 0; j < nrb; ++j) raw[j] += ldg(tl.rc_part + (size_t)b * 6 + j);
-    const double* Ta = tl.T + (size_t)a * nrb * nrb;
-    for (int k = 0; k < nrb; ++k) {
-      double s = 0.0;
-      for (int j = 0; j < nrb; ++j) s += ldg(Ta + j * nrb + k) * raw[j];
-      rc[a * nrb + k] = s;
-    }
-  }
-  __syncthreads();
-  const int a0 = wk.y * kCoarseChunkAgg, a1 = min(tl.n_agg, a0 + kCoarseChunkAgg);
-  const int r0 = a0 * nrb, r1 = a1 * nrb;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const T* Ainv = static_cast<const T*>(tl.Ainv);
-  for (int i = r0 + wave; i < r1; i += kThreads / 64) {
-    const T* row = Ainv + (size_t)i * tl.n_c;
     double s = 0.0;
-    for (int j = lane; j < tl.n_c; j += 64) s += (double)ldg(row + j) * rc[j];
-    s = wave_sum(s);
-    if (lane == 0) zc[i - r0] = s;
+    for (int b = a * tl.G; b < b1; ++b) s += ldg(tl.rc_part + (size_t)b * 6 + j);
+    rc[i] = s;
   }
   __syncthreads();
-  if ((int)threadIdx.x < a1 - a0) {
-    const int a = a0 + threadIdx.x;
-    const double* Ta = tl.T + (size_t)a * nrb * nrb;
-    for (int j = 0; j < 6; ++j) {
-      double s = 0.0;
-      if (j < nrb)
-        for (int k = 0; k < nrb; ++k) s += ldg(Ta + j * nrb + k) * zc[(a - a0) * nrb + k];
-      tl.y[(size_t)a * 6 + j] = s;
+  const int r0 = wk.y * kCoarseRows, r1 = min(n_c, r0 + kCoarseRows);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const T* B = static_cast<const T*>(tl.B);
+  const int i0 = r0 + 2 * wave;          // uniform over the wave
+  if (i0 < r1) {
+    const bool two = i0 + 1 < r1;
+    const T* ra = B + (size_t)i0 * n_c;
+    const T* rb = B + (size_t)(two ? i0 + 1 : i0) * n_c;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    int j = lane;
+    for (; j + 192 < n_c; j += 256) {
+      const double x0 = rc[j], x1 = rc[j + 64], x2 = rc[j + 128], x3 = rc[j + 192];
+      a0 += (double)ldg(ra + j) * x0;
+      a1 += (double)ldg(ra + j + 64) * x1;
+      a2 += (double)ldg(ra + j + 128) * x2;
+      a3 += (double)ldg(ra + j + 192) * x3;
+      b0 += (double)ldg(rb + j) * x0;
+      b1 += (double)ldg(rb + j + 64) * x1;
+      b2 += (double)ldg(rb + j + 128) * x2;
+      b3 += (double)ldg(rb + j + 192) * x3;
+    }
+    for (; j < n_c; j += 64) {
+      a0 += (double)ldg(ra + j) * rc[j];
+      b0 += (double)ldg(rb + j) * rc[j];
+    }
+    const double sa = wave_sum((a0 + a1) + (a2 + a3));
+    const double sb = wave_sum((b0 + b1) + (b2 + b3));
+    if (lane == 0) {
+      ys[i0 - r0] = sa;
+      if (two) ys[i0 + 1 - r0] = sb;
     }
   }
+  __syncthreads();
   double v[1] = {0.0};
-  for (int i = r0 + threadIdx.x; i < r1; i += kThreads) v[0] += rc[i] * zc[i - r0];
+  if ((int)threadIdx.x < r1 - r0) {
+    const int i = r0 + threadIdx.x, a = i / nrb, j = i - a * nrb;
+    tl.y[(size_t)a * 6 + j] = ys[threadIdx.x];
+    v[0] = rc[i] * ys[threadIdx.x];
+  }
   block_sum_all<1>(v);
   if (threadIdx.x == 0) tl.gc_part[wk.y] = v[0];
 }
