@@ -196,18 +196,34 @@ def linear_moduli(mu, lam, d):
 
 # -------------------------------------------------------------- assembly
 class Model:
-    """Oracle view of one problem: geometry, materials, f_ext, Dirichlet."""
+    """Oracle view of one problem: geometry, materials, f_ext, Dirichlet.
+
+    P1 meshes evaluate one point per element (G = grad N, vol = element
+    measure).  Quadrilateral meshes (prob.elem 'q4' / 'q8', see quad.py)
+    evaluate one point per Gauss point: `conn`, `G`, `vol`, `mu`, `lam` and
+    `dofs` are then per quadrature point (the element's row repeated), and
+    every sum below is a sum over those points.
+    """
 
     def __init__(self, prob):
         self.prob = prob
         self.model = prob.model
         self.d = prob.dim
-        self.conn = np.asarray(prob.conn, dtype=np.int64)
+        self.elem = getattr(prob, "elem", "p1")
+        conn = np.asarray(prob.conn, dtype=np.int64)
         self.coords = np.asarray(prob.coords, dtype=np.float64)
         self.n_dof = self.coords.shape[0] * self.d
-        self.G, self.vol = shape_gradients(self.coords, self.conn)
-        self.mu, self.lam = lame_parameters(prob.model, prob.param_kind,
-                                            prob.p0, prob.p1)
+        mu, lam = lame_parameters(prob.model, prob.param_kind, prob.p0, prob.p1)
+        if self.elem == "p1":
+            self.conn = conn
+            self.G, self.vol = shape_gradients(self.coords, conn)
+            self.elem_of = np.arange(len(conn))
+        else:
+            from . import quad
+            self.G, self.vol, _, self.elem_of = quad.point_geometry(self.coords, conn,
+                                                                    self.elem)
+            self.conn = conn[self.elem_of]
+        self.mu, self.lam = mu[self.elem_of], lam[self.elem_of]
         self.dofs = (self.conn[:, :, None] * self.d
                      + np.arange(self.d)[None, None, :]).reshape(len(self.conn), -1)
         self.f_ext = external_force(prob)
@@ -264,7 +280,8 @@ class Model:
         return self.internal_force(u) - self.f_ext
 
     def element_matrices(self, u=None):
-        """Element stiffness / tangent blocks (E, (d+1)d, (d+1)d).
+        """Element stiffness / tangent blocks (E, (d+1)d, (d+1)d); per
+        quadrature point (E*nq, nv d, nv d) on quadrilateral meshes.
 
         K_e[(a,i),(b,k)] = vol_e sum_{J,L} dN_a/dX_J  A_iJkL  dN_b/dX_L
         with A the linear moduli C (linear models) or the Neo-Hookean
@@ -277,7 +294,7 @@ class Model:
             A = nh_tangent_moduli(self.H(u), self.mu, self.lam)
         Ke = np.einsum("e,eaJ,eiJkL,ebL->eaibk", self.vol, self.G, A, self.G,
                        optimize=True)
-        n = (d + 1) * d
+        n = self.conn.shape[1] * d
         return Ke.reshape(len(self.conn), n, n)
 
     def assemble(self, u=None):
@@ -303,12 +320,21 @@ def external_force(prob):
 
     App. B: f_ext,iI = int_{Gamma_t} N_I t_i dGamma.  For a P1 facet with a
     constant traction this puts t * |facet| / n_f on each of its n_f nodes
-    (n_f = 2 for an edge, 3 for a triangle).  Body force is zero.
+    (n_f = 2 for an edge, 3 for a triangle).  A 3-node edge of a Q8 mesh
+    (ends, then the middle node) integrates its quadratic shape functions
+    (quad.edge_loads).  Body force is zero.
     """
     d = prob.dim
     f = np.zeros(prob.n_dof)
     fac = np.asarray(prob.neu_facets, dtype=np.int64)
     if fac.size == 0:
+        return f
+    if d == 2 and fac.shape[1] == 3:
+        from . import quad
+        fl = quad.edge_loads(prob.coords, fac, prob.neu_traction)
+        for a in range(3):
+            for i in range(2):
+                np.add.at(f, fac[:, a] * 2 + i, fl[:, a, i])
         return f
     P = np.asarray(prob.coords, dtype=np.float64)[fac]
     if d == 2:

@@ -12,12 +12,13 @@ Every generator takes an explicit integer seed and uses
 from .problems import (Problem, MODELS, unit_square_c1, plate_problem,
                        box_problem, c4_member, batch_c4, serving_stream,
                        serving_problem, structured_plate, structured_box,
+                       beam_problem, cook_problem,
                        SERVING_E_FEATURES, SERVING_NOISE_FEATURES)
 from .fields import rff_field, lifting_weight, warm_start_guess, warm_start_noise
 
 __all__ = ["Problem", "MODELS", "unit_square_c1", "plate_problem",
            "box_problem", "c4_member", "batch_c4", "serving_stream",
            "serving_problem", "structured_plate",
-           "structured_box", "rff_field", "lifting_weight",
+           "structured_box", "beam_problem", "cook_problem", "rff_field", "lifting_weight",
            "warm_start_guess", "warm_start_noise", "SERVING_E_FEATURES",
            "SERVING_NOISE_FEATURES"]

@@ -286,3 +286,68 @@ def structured_box(nx, ny, nz, rng, dims=(1.0, 1.0, 4.0), jitter=0.08):
     coords[inner] += rng.uniform(-jitter * h, jitter * h,
                                  size=(int(inner.sum()), 3))
     return _relabel(coords, conn.astype(np.int64), rng)
+
+
+# ---------------------------------------------------- quadrilateral meshes
+def quad_grid(nx, ny, mapping, elem="q4", rng=None):
+    """Structured nx x ny quadrilateral mesh of the image of [0,1]^2 under
+    ``mapping`` ((N, 2) parameters -> (N, 2) points, orientation-preserving).
+
+    Q4: corner nodes; Q8: corners, then the midside nodes of edges (0,1),
+    (1,2), (2,3), (3,0) of each element, placed at the image of the
+    parameter-space midpoint.  Returns coords, conn and the node ids of the
+    left (u = 0) and right (u = 1) edges sorted by v: for Q8 the right-edge
+    list alternates corner, midside, corner, ...  With ``rng`` the nodes are
+    relabelled and the elements shuffled."""
+    ci = lambda i, j: j * (nx + 1) + i                               # corners
+    nc = (nx + 1) * (ny + 1)
+    u, v = np.meshgrid(np.arange(nx + 1) / nx, np.arange(ny + 1) / ny, indexing="xy")
+    par = [np.stack([u.ravel(), v.ravel()], axis=1)]
+    I, J = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    I, J = I.ravel(), J.ravel()
+    corners = np.stack([ci(I, J), ci(I + 1, J), ci(I + 1, J + 1), ci(I, J + 1)], axis=1)
+    left = [ci(0, j) for j in range(ny + 1)]
+    right = [ci(nx, j) for j in range(ny + 1)]
+    if elem == "q8":
+        hi = lambda i, j: nc + j * nx + i                            # edge (i,j)-(i+1,j)
+        nh = nx * (ny + 1)
+        vi = lambda i, j: nc + nh + j * (nx + 1) + i                 # edge (i,j)-(i,j+1)
+        hu, hv = np.meshgrid((np.arange(nx) + 0.5) / nx, np.arange(ny + 1) / ny, indexing="xy")
+        vu, vv = np.meshgrid(np.arange(nx + 1) / nx, (np.arange(ny) + 0.5) / ny, indexing="xy")
+        par += [np.stack([hu.ravel(), hv.ravel()], axis=1),
+                np.stack([vu.ravel(), vv.ravel()], axis=1)]
+        mids = np.stack([hi(I, J), vi(I + 1, J), hi(I, J + 1), vi(I, J)], axis=1)
+        conn = np.concatenate([corners, mids], axis=1)
+        left = [x for j in range(ny) for x in (ci(0, j), vi(0, j))] + [ci(0, ny)]
+        right = [x for j in range(ny) for x in (ci(nx, j), vi(nx, j))] + [ci(nx, ny)]
+    else:
+        conn = corners
+    coords = np.ascontiguousarray(mapping(np.concatenate(par, axis=0)), dtype=np.float64)
+    conn = conn.astype(np.int32)
+    left, right = np.asarray(left, np.int64), np.asarray(right, np.int64)
+    if rng is not None:
+        n = coords.shape[0]
+        perm = rng.permutation(n)
+        inv = np.empty(n, dtype=np.int64)
+        inv[perm] = np.arange(n)
+        coords = np.ascontiguousarray(coords[inv])
+        conn = np.ascontiguousarray(perm[conn][rng.permutation(conn.shape[0])].astype(np.int32))
+        left, right = perm[left], perm[right]
+    return coords, conn, left.astype(np.int32), right.astype(np.int32)
+
+
+def rectangle_map(W, H):
+    """[0,1]^2 -> [0, W] x [0, H]."""
+    return lambda p: np.stack([W * p[:, 0], H * p[:, 1]], axis=1)
+
+
+def cook_map(left_height=44.0, right_low=44.0, right_high=60.0, width=48.0):
+    """Bilinear map of [0,1]^2 onto Cook's tapered membrane: left edge from
+    (0, 0) to (0, left_height), right edge from (width, right_low) to
+    (width, right_high)."""
+    def f(p):
+        s, t = p[:, 0], p[:, 1]
+        y_lo = s * right_low
+        y_hi = left_height + s * (right_high - left_height)
+        return np.stack([width * s, y_lo + t * (y_hi - y_lo)], axis=1)
+    return f

@@ -29,17 +29,18 @@ class Problem:
     name: str
     model: str
     coords: np.ndarray            # (N_n, d) float64
-    conn: np.ndarray              # (N_e, d+1) int32
+    conn: np.ndarray              # (N_e, d+1) int32 (P1); (N_e, 4 | 8) quadrilaterals
     param_kind: str               # "E_nu" | "lame"
     p0: np.ndarray                # (N_e,) float64
     p1: np.ndarray                # (N_e,) float64
     dir_nodes: np.ndarray         # (n_D,) int32
     dir_comps: np.ndarray         # (n_D,) int8
     dir_values: np.ndarray        # (n_D,) float64, final-load values
-    neu_facets: np.ndarray        # (n_F, d) int32
+    neu_facets: np.ndarray        # (n_F, d) int32; Q8 edges: (n_F, 3) ends, then middle
     neu_traction: np.ndarray      # (n_F, d) float64
     n_load_steps: int = 1
     meta: dict = field(default_factory=dict)
+    elem: str = "p1"              # "p1" (triangles / tetrahedra), "q4", "q8"
 
     @property
     def dim(self):
@@ -246,3 +247,68 @@ def serving_problem(desc):
     n = max(int(round((desc["target_elems"] / (24.0 * 0.98)) ** (1.0 / 3.0))), 4)
     return box_problem(s, s + 100000, n_per_unit=n, n_voids=20,
                        name=f"req{desc['id']}")
+
+
+# ------------------------------------------------- quadrilateral benchmarks
+def _edge_segments(nodes, elem):
+    """Boundary edges along a sorted edge-node list (Q8: corner, mid, corner
+    triples, written ends first, then the middle node)."""
+    nodes = np.asarray(nodes, dtype=np.int32)
+    if elem == "q8":
+        return np.stack([nodes[0:-1:2], nodes[2::2], nodes[1::2]], axis=1)
+    return np.stack([nodes[:-1], nodes[1:]], axis=1)
+
+
+def _quad_problem(name, coords, conn, left, right, elem, seed, model, e_mean, trac_mean,
+                  n_load_steps, trac_range=(0.0, 1.0), clamp_range=(0.0, 1.0)):
+    rng = _rng(seed)
+    cen = coords[conn[:, :4]].mean(axis=1)
+    scale = np.ptp(coords, axis=0).max()
+    E = e_mean * np.exp(0.3 * rff_field(cen / scale, seed + 1, 0.25, 256))
+    nu = 0.35 + 0.08 * np.tanh(rff_field(cen / scale, seed + 2, 0.25, 256))
+    lo, hi = clamp_range
+    nl = len(left)
+    clamp = left[int(round(lo * (nl - 1))):int(round(hi * (nl - 1))) + 1]
+    dn, dc, dv = _clamp(clamp, 2)
+    facets = _edge_segments(right, elem)
+    mid = coords[facets[:, :2]].mean(axis=1)
+    ys = coords[right, 1]
+    a, b = trac_range
+    yl = ys.min() + a * (ys.max() - ys.min())
+    yh = ys.min() + b * (ys.max() - ys.min())
+    on = (mid[:, 1] >= yl - 1e-12) & (mid[:, 1] <= yh + 1e-12)
+    facets = facets[on]
+    ty = trac_mean * (1.0 + 0.4 * rff_field(mid[on] / scale, seed + 3, 0.3, 128))
+    trac = np.stack([np.zeros_like(ty), ty], axis=1)
+    return Problem(name, model, coords, conn, "E_nu", E, nu, dn, dc, dv,
+                   facets.astype(np.int32), trac, n_load_steps,
+                   {"seed": seed}, elem)
+
+
+def beam_problem(seed, nx=50, ny=50, elem="q4", model="nh_plane_strain", W=4.0, H=1.0,
+                 e_mean=10.0, traction=-0.08, n_load_steps=5):
+    """Hyperelastic beam (Sec. 'Nonlinear hyperelasticity'): W x H = 4 x 1,
+    left end clamped, a downward traction t_y on the right end varying along
+    it, lognormal E and nu fields; a uniform nx x ny mesh (50 x 50 Q4 in the
+    paper), plane strain."""
+    coords, conn, left, right = meshes.quad_grid(nx, ny, meshes.rectangle_map(W, H), elem,
+                                                 _rng(seed))
+    return _quad_problem(f"beam_{elem}_{nx}x{ny}", coords, conn, left, right, elem, seed,
+                         model, e_mean, traction, n_load_steps)
+
+
+def cook_problem(seed, n=30, elem="q8", model="nh_plane_strain", e_mean=10.0,
+                 traction=0.3, n_load_steps=5):
+    """Cook's membrane (Sec. 'Nonlinear hyperelasticity'): the tapered panel
+    with corners (0,0), (48,44), (48,60), (0,44), on a uniform n x n mesh
+    (30 x 30 Q8 in the paper); the clamped part of the left edge and the
+    loaded part of the right edge are drawn from the seed, the traction t_y
+    varies along it, lognormal E and nu fields, plane strain."""
+    rng = _rng(seed + 7)
+    c0 = rng.uniform(0.0, 0.2)
+    c1 = rng.uniform(0.8, 1.0)
+    t0 = rng.uniform(0.0, 0.3)
+    t1 = rng.uniform(0.7, 1.0)
+    coords, conn, left, right = meshes.quad_grid(n, n, meshes.cook_map(), elem, _rng(seed))
+    return _quad_problem(f"cook_{elem}_{n}x{n}", coords, conn, left, right, elem, seed,
+                         model, e_mean, traction, n_load_steps, (t0, t1), (c0, c1))
