@@ -190,6 +190,26 @@ pfem_status pfem_ctx_synchronize(pfem_ctx* ctx);
 pfem_status pfem_mesh_create(pfem_ctx* ctx, int dim, int64_t n_nodes,
                              const double* coords, int64_t n_elems,
                              const int32_t* conn, pfem_mesh** out);
+/* Element families.  PFEM_ELEM_P1: linear triangles (2D) / tetrahedra (3D),
+ * one point per element (what pfem_mesh_create builds).  PFEM_ELEM_Q4:
+ * bilinear quadrilaterals, 2 x 2 Gauss points; PFEM_ELEM_Q8: 8-node
+ * serendipity quadrilaterals, 3 x 3 Gauss points (Sec. 'Nonlinear
+ * hyperelasticity': the beam on a Q4 mesh and Cook's membrane on a Q8 mesh;
+ * App. B: the isoparametric interpolation X = N_I X_I, u = N_I u_I). */
+enum { PFEM_ELEM_P1 = 0, PFEM_ELEM_Q4 = 1, PFEM_ELEM_Q8 = 2 };
+/* Create a 2D quadrilateral mesh.  elem: PFEM_ELEM_Q4 or PFEM_ELEM_Q8.
+ * coords: host, n_nodes*2 float64.  conn: host, n_elems*4 (Q4) or n_elems*8
+ * (Q8) int32: the corners in order around the element (either
+ * orientation), then for Q8 the midside nodes of edges (0,1), (1,2), (2,3),
+ * (3,0).  Neumann facets of a Q8 mesh are its 3-node edges (pfem_mesh_
+ * set_neumann).  Quadrilateral meshes run every element kernel with the
+ * owner scatter; the fused PCG, the two-level preconditioner and the
+ * coloured / atomic scatters are refused (PFEM_E_INVALID_ARG) -- automatic
+ * Krylov selection picks the classic loop.  Errors as pfem_mesh_create;
+ * PFEM_E_INVALID_ARG for another elem. */
+pfem_status pfem_mesh_create_quad(pfem_ctx* ctx, int elem, int64_t n_nodes,
+                                  const double* coords, int64_t n_elems,
+                                  const int32_t* conn, pfem_mesh** out);
 /* Per-element material (both parameters given per element: a uniform one is
  * an array of n_elems equal values).  model: PFEM_LIN_* / PFEM_NH_*.  param_kind:
  * PFEM_PARAM_E_NU (p0 = Young's modulus, p1 = Poisson ratio; Lame
@@ -207,8 +227,12 @@ pfem_status pfem_mesh_set_material(pfem_mesh* m, int model, int param_kind,
 pfem_status pfem_mesh_set_dirichlet(pfem_mesh* m, int64_t n, const int32_t* node,
                                     const int8_t* comp, const double* value);
 /* Neumann set: n_facets boundary facets (edges in 2D: 2 nodes; triangles in
- * 3D: 3 nodes) each with a constant traction (dim values); host arrays.
- * f_ext puts t |facet| / n_f on each facet node (App. B, f_ext integral). */
+ * 3D: 3 nodes; on a Q8 mesh 3-node edges: the two ends, then the middle
+ * node) each with a constant traction (dim values); host arrays.  f_ext is
+ * the consistent load t int N_a dGamma (App. B, f_ext integral): t |facet|
+ * / n_f on each node of a linear facet; on a Q8 edge the quadratic shape
+ * functions integrated along the edge with 3 Gauss points (t L/6, t L/6,
+ * 2 t L/3 on a straight edge with a centred middle node). */
 pfem_status pfem_mesh_set_neumann(pfem_mesh* m, int64_t n_facets,
                                   const int32_t* facet_nodes, const double* traction);
 /* Periodic springs (App. D: the virtual elements PFEM uses to impose the
@@ -253,6 +277,8 @@ typedef struct {
   double f_ext_norm;
   int32_t band_blocks;                      /* owner blocks per RCM band of the block
                                                numbering (0 under PFEM_ORDER_RCM) */
+  int32_t elem;                             /* PFEM_ELEM_* */
+  int32_t nodes_per_elem;                   /* dim+1 (P1), 4 (Q4), 8 (Q8) */
 } pfem_mesh_info;
 /* Sizes and preprocessing statistics of a mesh; out: host.  Fields that
  * preprocessing sets (free DOFs, colours, blocks, bandwidths, device

@@ -30,6 +30,7 @@ PFEM_PARAM_E_NU, PFEM_PARAM_LAME = 0, 1
 PFEM_FP64, PFEM_FP32 = 0, 1
 PFEM_KRYLOV_AUTO, PFEM_KRYLOV_CLASSIC, PFEM_KRYLOV_FUSED = 0, 1, 2
 PFEM_ORDER_BLOCKS, PFEM_ORDER_RCM = 0, 1
+PFEM_ELEM_P1, PFEM_ELEM_Q4, PFEM_ELEM_Q8 = 0, 1, 2
 PFEM_SCATTER_OWNER, PFEM_SCATTER_COLORED, PFEM_SCATTER_ATOMIC = 0, 1, 2
 PFEM_LAYOUT_USER, PFEM_LAYOUT_INTERNAL = 0, 1
 PFEM_MASK_NONE, PFEM_MASK_OUT, PFEM_MASK_IN = 0, 1, 2
@@ -50,7 +51,8 @@ class pfem_mesh_info(C.Structure):
                 ("bandwidth_internal", C.c_int64), ("owner_elem_visits", C.c_int64),
                 ("device_bytes", C.c_int64), ("solve_bytes_fp32", C.c_int64),
                 ("solve_bytes_fp64", C.c_int64), ("f_ext_norm", C.c_double),
-                ("band_blocks", C.c_int32)]
+                ("band_blocks", C.c_int32), ("elem", C.c_int32),
+                ("nodes_per_elem", C.c_int32)]
 
 
 class pfem_solve_opts(C.Structure):
@@ -102,6 +104,7 @@ PROTOTYPES = {
     "pfem_ctx_reset_timing": (_I32, [_VP]),
     "pfem_ctx_synchronize": (_I32, [_VP]),
     "pfem_mesh_create": (_I32, [_VP, C.c_int, _I64, _VP, _I64, _VP, _PVP]),
+    "pfem_mesh_create_quad": (_I32, [_VP, C.c_int, _I64, _VP, _I64, _VP, _PVP]),
     "pfem_mesh_set_material": (_I32, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "pfem_mesh_set_dirichlet": (_I32, [_VP, _I64, _VP, _VP, _VP]),
     "pfem_mesh_set_neumann": (_I32, [_VP, _I64, _VP, _VP]),

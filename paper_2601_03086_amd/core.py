@@ -54,6 +54,7 @@ MODEL_IDS = {"lin_plane_stress": L.PFEM_LIN_PLANE_STRESS,
              "nh_3d": L.PFEM_NH_3D}
 PARAM_IDS = {"E_nu": L.PFEM_PARAM_E_NU, "lame": L.PFEM_PARAM_LAME}
 ORDER_IDS = {"blocks": L.PFEM_ORDER_BLOCKS, "rcm": L.PFEM_ORDER_RCM}
+ELEM_IDS = {"p1": L.PFEM_ELEM_P1, "q4": L.PFEM_ELEM_Q4, "q8": L.PFEM_ELEM_Q8}
 PREC = {"fp64": L.PFEM_FP64, "fp32": L.PFEM_FP32, L.PFEM_FP64: L.PFEM_FP64,
         L.PFEM_FP32: L.PFEM_FP32}
 SCATTER = {"owner": L.PFEM_SCATTER_OWNER, "colored": L.PFEM_SCATTER_COLORED,
@@ -132,7 +133,8 @@ class Mesh:
 
     def __init__(self, ctx, dim, coords, conn, model, param_kind, p0, p1,
                  dir_nodes=(), dir_comps=(), dir_values=(), facets=None,
-                 traction=None, block_nodes=0, order="blocks", pairs=None, pair_k=0.0):
+                 traction=None, block_nodes=0, order="blocks", pairs=None, pair_k=0.0,
+                 elem="p1"):
         L.load()
         self.ctx = ctx
         self.dim = int(dim)
@@ -143,10 +145,16 @@ class Mesh:
         self.n_dof = self.n_nodes * self.dim
         self.model = model
         self.nonlinear = model.startswith("nh")
+        self.elem = elem
         h = C.c_void_p()
-        check(L.pfem_mesh_create(ctx.h if ctx is not None else None, self.dim,
-                                 self.n_nodes, _ptr(coords), self.n_elems, _ptr(conn),
-                                 C.byref(h)))
+        if elem == "p1":
+            check(L.pfem_mesh_create(ctx.h if ctx is not None else None, self.dim,
+                                     self.n_nodes, _ptr(coords), self.n_elems, _ptr(conn),
+                                     C.byref(h)))
+        else:
+            check(L.pfem_mesh_create_quad(ctx.h if ctx is not None else None, ELEM_IDS[elem],
+                                          self.n_nodes, _ptr(coords), self.n_elems,
+                                          _ptr(conn), C.byref(h)))
         self.h = h
         p0 = np.ascontiguousarray(np.broadcast_to(p0, (self.n_elems,)), dtype=np.float64)
         p1 = np.ascontiguousarray(np.broadcast_to(p1, (self.n_elems,)), dtype=np.float64)
@@ -185,7 +193,7 @@ class Mesh:
         return cls(ctx, prob.coords.shape[1], prob.coords, prob.conn, prob.model,
                    prob.param_kind, prob.p0, prob.p1, prob.dir_nodes, prob.dir_comps,
                    prob.dir_values, prob.neu_facets, prob.neu_traction, block_nodes,
-                   order)
+                   order, elem=getattr(prob, "elem", "p1"))
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

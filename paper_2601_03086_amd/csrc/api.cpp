@@ -14,6 +14,7 @@ struct pfem_batch {
   std::vector<pfem_mesh*> meshes;
   std::vector<int64_t> offsets;       // DOF offsets (n + 1)
   int dim = 0;
+  int kind = 0;                       // element kernel family (pfem::elem_kind)
   int bn_max = 0;
   int n_work = 0;
   int2* work = nullptr;               // persistent device work table (all meshes)
@@ -168,7 +169,32 @@ pfem_status pfem_mesh_create(pfem_ctx* ctx, int dim, int64_t n_nodes, const doub
   m->n_nodes = n_nodes;
   m->n_elems = n_elems;
   m->coords.assign(coords, coords + n_nodes * dim);
-  m->conn.assign(conn, conn + n_elems * (dim + 1));
+  m->nv = dim + 1;
+  m->conn.assign(conn, conn + n_elems * m->nv);
+  *out = m;
+  PFEM_TRY_END
+}
+
+pfem_status pfem_mesh_create_quad(pfem_ctx* ctx, int elem, int64_t n_nodes, const double* coords,
+                                  int64_t n_elems, const int32_t* conn, pfem_mesh** out) {
+  PFEM_TRY_BEGIN
+  require(out != nullptr, PFEM_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  require(elem == PFEM_ELEM_Q4 || elem == PFEM_ELEM_Q8, PFEM_E_INVALID_ARG,
+          "elem must be PFEM_ELEM_Q4 or PFEM_ELEM_Q8");
+  require(n_nodes > 0 && n_elems > 0, PFEM_E_INVALID_MESH, "empty mesh");
+  require(n_nodes < INT32_MAX / 3 && n_elems < INT32_MAX / 8, PFEM_E_INVALID_ARG,
+          "mesh too large for int32 indexing");
+  require(coords != nullptr && conn != nullptr, PFEM_E_INVALID_ARG, "NULL array");
+  pfem_mesh* m = new pfem_mesh();
+  m->ctx = ctx != nullptr ? ctx->c : nullptr;
+  m->dim = 2;
+  m->elem = elem;
+  m->nv = elem == PFEM_ELEM_Q4 ? 4 : 8;
+  m->n_nodes = n_nodes;
+  m->n_elems = n_elems;
+  m->coords.assign(coords, coords + n_nodes * 2);
+  m->conn.assign(conn, conn + n_elems * m->nv);
   *out = m;
   PFEM_TRY_END
 }
@@ -237,13 +263,14 @@ pfem_status pfem_mesh_set_neumann(pfem_mesh* m, int64_t n_facets, const int32_t*
   require(!m->finalized, PFEM_E_STATE, "mesh already finalized");
   require(n_facets >= 0 && (n_facets == 0 || (facet_nodes && traction)), PFEM_E_INVALID_ARG,
           "bad Neumann arrays");
-  for (int64_t i = 0; i < n_facets * m->dim; ++i)
+  const int nfn = m->facet_nodes();
+  for (int64_t i = 0; i < n_facets * nfn; ++i)
     require(facet_nodes[i] >= 0 && facet_nodes[i] < m->n_nodes, PFEM_E_INVALID_ARG,
             "Neumann facet node out of range");
   for (int64_t i = 0; i < n_facets * m->dim; ++i)
     require(std::isfinite(traction[i]), PFEM_E_INVALID_ARG, "non-finite traction");
   m->n_facets = n_facets;
-  m->facets.assign(facet_nodes, facet_nodes + n_facets * m->dim);
+  m->facets.assign(facet_nodes, facet_nodes + n_facets * nfn);
   m->traction.assign(traction, traction + n_facets * m->dim);
   PFEM_TRY_END
 }
@@ -313,6 +340,8 @@ pfem_status pfem_mesh_get_info(const pfem_mesh* m, pfem_mesh_info* o) {
   o->solve_bytes_fp64 = m->finalized ? solve_bytes(m, PFEM_FP64, false, false) : 0;
   o->f_ext_norm = m->fext_norm;
   o->band_blocks = m->band_blocks;
+  o->elem = m->elem;
+  o->nodes_per_elem = m->nv;
   PFEM_TRY_END
 }
 
@@ -370,6 +399,8 @@ pfem_status pfem_mesh_prepare_coarse(pfem_mesh* m, int32_t* n_coarse) {
   PFEM_TRY_BEGIN
   require(m != nullptr, PFEM_E_INVALID_ARG, "mesh is NULL");
   require(m->finalized, PFEM_E_STATE, "mesh not finalized");
+  require(m->elem == PFEM_ELEM_P1, PFEM_E_INVALID_ARG,
+          "the two-level preconditioner is built for P1 meshes");
   coarse_build(m);
   if (n_coarse) *n_coarse = m->coarse->n_c;
   PFEM_TRY_END
@@ -440,6 +471,8 @@ static void elem_call(pfem_mesh* m, int prec, int layout, int scatter, int mask,
           "bad scatter mode");
   require(scatter == PFEM_SCATTER_OWNER || m->pairs.empty(), PFEM_E_INVALID_ARG,
           "periodic springs are applied by the owner scatter only");
+  require(scatter == PFEM_SCATTER_OWNER || m->elem == PFEM_ELEM_P1, PFEM_E_INVALID_ARG,
+          "quadrilateral meshes run the owner scatter only");
   require(y != nullptr, PFEM_E_INVALID_ARG, "output is NULL");
   Ctx* ctx = m->ctx;
   m->scratch.ensure(m->n_dof(), m->n_blocks);
@@ -472,7 +505,7 @@ static void elem_call(pfem_mesh* m, int prec, int layout, int scatter, int mask,
   t.fscale = 1.0;
   if (scatter == PFEM_SCATTER_OWNER) {
     const Task* td = static_cast<const Task*>(ctx->ring.put(&t, sizeof(Task)));
-    launch_elem(ctx, m->dim, prec, op, m->nonlinear, PFEM_SCATTER_OWNER, td, m->dev.work,
+    launch_elem(ctx, m->kind(), prec, op, m->nonlinear, PFEM_SCATTER_OWNER, td, m->dev.work,
                 m->n_blocks, m->bn, nullptr, nullptr);
   } else {
     launch_elem(ctx, m->dim, prec, op, m->nonlinear, scatter, nullptr, nullptr, 0, m->bn, &t,
@@ -534,7 +567,7 @@ pfem_status pfem_energy(pfem_mesh* m, int prec, int layout, const void* u, doubl
   t.red.part = m->scratch.part;
   t.red.out = m->scratch.out;
   const Task* td = static_cast<const Task*>(ctx->ring.put(&t, sizeof(Task)));
-  launch_energy(ctx, m->dim, prec, false, td, m->dev.work, m->n_blocks);
+  launch_energy(ctx, m->kind(), prec, false, td, m->dev.work, m->n_blocks);
   launch_reduce_store(ctx, td, 1);
   launch_energy_out(ctx, m->scratch.out, energy_dev, 1, kRedSlots);
   PFEM_TRY_END
@@ -558,8 +591,13 @@ pfem_status pfem_batch_create(pfem_ctx* ctx, int32_t n, pfem_mesh* const* meshes
       pfem_mesh* m = meshes[i];
       need_device(m);
       require(m->ctx == ctx->c, PFEM_E_INVALID_ARG, "mesh belongs to another context");
-      if (i == 0) b->dim = m->dim;
+      if (i == 0) {
+        b->dim = m->dim;
+        b->kind = m->kind();
+      }
       require(m->dim == b->dim, PFEM_E_INVALID_ARG, "all meshes of a batch share one dimension");
+      require(m->kind() == b->kind, PFEM_E_INVALID_ARG,
+              "all meshes of a batch share one element family");
       b->meshes.push_back(m);
       b->offsets.push_back(b->offsets.back() + m->n_dof());
       b->bn_max = std::max(b->bn_max, m->bn);
@@ -663,7 +701,7 @@ pfem_status pfem_batch_energy(pfem_batch* b, int prec, const void* u, double* en
   Ctx* ctx = b->ctx;
   PFEM_HIP(hipSetDevice(ctx->device));
   const BaseArgs ba{u, nullptr, nullptr, 1, 0};
-  launch_energy(ctx, b->dim, prec, false, b->tasks_red, b->work, b->n_work, &ba);
+  launch_energy(ctx, b->kind, prec, false, b->tasks_red, b->work, b->n_work, &ba);
   launch_reduce_store(ctx, b->tasks_red, (int)b->meshes.size());
   launch_energy_out(ctx, b->outs, energies_dev, (int)b->meshes.size(), kRedSlots);
   PFEM_TRY_END
@@ -680,7 +718,7 @@ static pfem_status batch_elem(pfem_batch* b, int prec, int mask, int op, const v
   const BaseArgs ba{u, v, y, 1, mask};
   for (int kd = 0; kd < 2; ++kd)
     if (b->n_work_kind[kd] > 0)
-      launch_elem(ctx, b->dim, prec, op, kd == 1, PFEM_SCATTER_OWNER, b->tasks_plain,
+      launch_elem(ctx, b->kind, prec, op, kd == 1, PFEM_SCATTER_OWNER, b->tasks_plain,
                   b->work_kind[kd], b->n_work_kind[kd], b->bn_max, nullptr, nullptr, &ba);
   return PFEM_OK;
 }
@@ -734,9 +772,8 @@ pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
   // (re)use the mesh's cached solver state
   std::unique_ptr<SolveState>& cached = m->solve_state;
   const int prec = o->prec;
+  check_solve_mesh(*o, m);
   const bool fused = krylov_fused(*o, m);
-  require(!(fused && !m->pairs.empty()), PFEM_E_INVALID_ARG,
-          "the fused PCG does not apply periodic springs: use the classic formulation");
   const bool two_level = o->precond == PFEM_PRECOND_TWO_LEVEL;
   if (!cached || cached->prec != prec || cached->hist_cap < hcap || cached->fused != fused ||
       (two_level && cached->tl_dev == nullptr)) {

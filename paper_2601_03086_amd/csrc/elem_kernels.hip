@@ -22,6 +22,7 @@
 
 #include "elem_math.h"
 #include "fcg_record.h"
+#include "owner_common.h"
 #include "pfem_internal.h"
 #include "reduce.h"
 
@@ -364,27 +365,6 @@ __device__ __forceinline__ void owner_accumulate(const MeshDev& m, const T* __re
                                                 alpha, beta);
 }
 
-// Periodic springs at component c of owned node n: the virtual elements of a
-// periodic cell, each a spring of stiffness k to a partner node.  Their
-// energy 1/2 k |x_n - x_b|^2 adds k sum_b (x_n - x_b) to the apply (input
-// X = v) and to the internal force (X = u), and k per partner to the
-// diagonal.  With PFEM_MASK_IN an apply reads zero at Dirichlet DOFs.
-template <int D, typename T, int OP>
-__device__ __forceinline__ T periodic_springs(const MeshDev& m, const T* __restrict__ X, int mask,
-                                              int n, int c, bool con) {
-  const int q0 = ldg(m.pair_ptr + n), q1 = ldg(m.pair_ptr + n + 1);
-  if (OP == OP_DIAG) return (T)(m.pair_k * (double)(q1 - q0));
-  const bool mask_in = OP == OP_APPLY && (mask & PFEM_MASK_IN);
-  const T xn = (mask_in && con) ? T(0) : ldg(X + (size_t)n * D + c);
-  T s = T(0);
-  for (int q = q0; q < q1; ++q) {
-    const int b = ldg(m.pair_nbr + q);
-    const bool cb = mask_in && ((ldg(m.dmask + b) >> c) & 1);
-    s += xn - (cb ? T(0) : ldg(X + (size_t)b * D + c));
-  }
-  return (T)m.pair_k * s;
-}
-
 template <int D, typename T, int OP, bool NL>
 __global__ void __launch_bounds__(kThreads)
 k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work, const BaseArgs ba) {
@@ -400,37 +380,12 @@ k_owner(const Task* __restrict__ tasks, const int2* __restrict__ work, const Bas
   const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + blk));
   using A = AccT<T>;
   A* acc = reinterpret_cast<A*>(smem_raw);
-  const int nown = nloc * D;
   const T* U = operand<const T>(const_cast<void*>(tp->u), const_cast<void*>(ba.u), ba.rel);
   const T* V = operand<const T>(const_cast<void*>(tp->v), const_cast<void*>(ba.v), ba.rel);
   const int mask = ba.rel ? ba.mask : tp->mask;
   owner_accumulate<D, T, OP, NL, A, false, kThreads, PFEM_OWNER_EIF>(m, U, V, mask, br, n0,
                                                                      nloc, acc);
-  T* Y = operand<T>(tp->y, ba.y, ba.rel);
-  const T* W = static_cast<const T*>(tp->w);
-  const double* FE = tp->fext != nullptr ? tp->fext : m.fext;
-  const bool springs = m.pair_ptr != nullptr && !tp->no_pairs;
-  double part[kRedSlots] = {0.0, 0.0, 0.0, 0.0};
-  const size_t g0 = (size_t)n0 * D;
-  for (int i = threadIdx.x; i < nown; i += kThreads) {
-    const size_t gi = g0 + i;
-    T val = (T)acc[i];
-    const bool con = (ldg(m.dmask + n0 + i / D) >> (i % D)) & 1;
-    if (OP == OP_FORCE) val -= (T)(tp->fscale * ldg(FE + gi));
-    if (springs) val += periodic_springs<D, T, OP>(m, OP == OP_APPLY ? V : U, mask, n0 + i / D,
-                                                   i % D, con);
-    if (OP == OP_DIAG) {
-      if (con) val = T(1);
-      else if (tp->s != 0.0) val = T(1) / val;   // inverse diagonal for PCG
-    } else if ((mask & PFEM_MASK_OUT) && con) {
-      val = T(0);
-    }
-    stg(Y + gi, val);
-    if (W != nullptr) part[0] += (double)val * (double)ldg(W + gi);
-    part[1] += (double)val * (double)val;
-  }
-  // an apply only reports y.w (slot 0): PCG init kernels own slots 1 and 2
-  write_partials(tp->red, m.n_blocks, blk, part, 0, OP == OP_APPLY ? 1 : 2);
+  owner_epilogue<D, T, OP>(tp, m, acc, U, V, mask, ba, blk, n0, nloc);
 }
 
 // ------------------------------------------- several right-hand sides
@@ -893,41 +848,7 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work, const Ba
       else part[0] += vol * psi0;
     }
   }
-  // - f_ext . u   (or - s f_ext . v for the difference), and the energy of
-  // the periodic springs, 1/2 k |u_n - u_b|^2 per pair: a quarter from each
-  // end's owner
-  const size_t g0 = (size_t)n0 * D;
-  const double* FE = tp->fext != nullptr ? tp->fext : m.fext;
-  const bool springs = m.pair_ptr != nullptr && !tp->no_pairs;
-  for (int i = threadIdx.x; i < nloc * D; i += kThreads) {
-    const double f = tp->fscale * ldg(FE + g0 + i);
-    if (DIFF) {
-      const double w = s * f * (double)ldg(V + g0 + i);
-      part[0] -= w;
-      part[2] += fabs(w);
-    } else {
-      part[0] -= f * (double)ldg(U + g0 + i);
-    }
-    if (springs) {
-      const int n = n0 + i / D, c = i % D;
-      const int q0 = ldg(m.pair_ptr + n), q1 = ldg(m.pair_ptr + n + 1);
-      const double un = (double)ldg(U + g0 + i);
-      for (int q = q0; q < q1; ++q) {
-        const size_t gb = (size_t)ldg(m.pair_nbr + q) * D + c;
-        const double du = un - (double)ldg(U + gb);
-        const double e0 = 0.25 * m.pair_k * du * du;
-        if (DIFF) {
-          const double dw = du + s * ((double)ldg(V + g0 + i) - (double)ldg(V + gb));
-          const double e1 = 0.25 * m.pair_k * dw * dw;
-          part[0] += e1 - e0;
-          part[2] += e0 + e1;
-        } else {
-          part[0] += e0;
-        }
-      }
-    }
-  }
-  write_partials(tp->red, m.n_blocks, blk, part, 0, DIFF ? 3 : 2);
+  energy_epilogue<D, TU, TV, DIFF>(tp, m, U, V, s, blk, n0, nloc, part);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1012,7 +933,9 @@ void launch_elem(Ctx* ctx, int dim, int prec, int op, bool nonlinear, int scatte
   hipEvent_t ev = nullptr;
   ctx->timing_begin(family_of(op), &ev);
   const BaseArgs ba = rel != nullptr ? *rel : BaseArgs{nullptr, nullptr, nullptr, 0, 0};
-  if (scatter_mode == PFEM_SCATTER_OWNER) {
+  if (is_quad_kind(dim)) {   // quadrilaterals: owner scatter only (checked by the callers)
+    launch_quad_elem(ctx, dim, prec, op, nonlinear, tasks_dev, work_dev, n_work, bn_max, ba);
+  } else if (scatter_mode == PFEM_SCATTER_OWNER) {
     if (n_work > 0) {
       if (nonlinear) dispatch_owner<true>(ctx, dim, prec, op, tasks_dev, work_dev, n_work, bn_max, ba);
       else dispatch_owner<false>(ctx, dim, prec, op, tasks_dev, work_dev, n_work, bn_max, ba);
@@ -1034,7 +957,9 @@ void launch_energy(Ctx* ctx, int dim, int prec, bool diff, const Task* tasks_dev
   dim3 grid(n_work), block(kThreads);
   hipStream_t s = ctx->stream;
   // diff: u is float64 state, v is the increment in `prec`
-  if (!diff) {
+  if (is_quad_kind(dim)) {
+    launch_quad_energy(ctx, dim, prec, diff, tasks_dev, work_dev, n_work, ba);
+  } else if (!diff) {
     if (dim == 2 && prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<2, float, float, false>), grid, block, 0, s, tasks_dev, work_dev, ba);
     else if (dim == 2) hipLaunchKernelGGL((k_energy<2, double, double, false>), grid, block, 0, s, tasks_dev, work_dev, ba);
     else if (prec == PFEM_FP32) hipLaunchKernelGGL((k_energy<3, float, float, false>), grid, block, 0, s, tasks_dev, work_dev, ba);

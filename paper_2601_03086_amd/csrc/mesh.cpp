@@ -65,9 +65,74 @@ void lame_from_params(int model, int param_kind, double p0, double p1, double* m
 
 static void prepare_device_images(pfem_mesh* m);
 
+// Reference-coordinate derivatives dN_a/dxi, dN_a/deta of the Q4 (nv = 4)
+// or Q8 serendipity (nv = 8) shape functions: corners (-1,-1), (1,-1),
+// (1,1), (-1,1), then the midsides of edges (0,1), (1,2), (2,3), (3,0).
+static void quad_shape_derivs(int nv, double xi, double eta, double (&dN)[8][2]) {
+  static const double cx[4] = {-1, 1, 1, -1}, cy[4] = {-1, -1, 1, 1};
+  for (int a = 0; a < 4; ++a) {
+    const double p = 1 + xi * cx[a], q = 1 + eta * cy[a];
+    if (nv == 4) {
+      dN[a][0] = 0.25 * cx[a] * q;
+      dN[a][1] = 0.25 * cy[a] * p;
+    } else {   // N = p q (xi cx + eta cy - 1) / 4
+      const double r = xi * cx[a] + eta * cy[a] - 1;
+      dN[a][0] = 0.25 * cx[a] * q * (r + p);
+      dN[a][1] = 0.25 * cy[a] * p * (r + q);
+    }
+  }
+  if (nv == 8) {
+    dN[4][0] = -xi * (1 - eta);            dN[4][1] = -0.5 * (1 - xi * xi);
+    dN[5][0] = 0.5 * (1 - eta * eta);      dN[5][1] = -(1 + xi) * eta;
+    dN[6][0] = -xi * (1 + eta);            dN[6][1] = 0.5 * (1 - xi * xi);
+    dN[7][0] = -0.5 * (1 - eta * eta);     dN[7][1] = -(1 - xi) * eta;
+  }
+}
+
+// Jacobian determinants of a quadrilateral at its corners and 3 x 3 Gauss
+// points; false if they are not all of one sign, or one is tiny against the
+// longest corner distance squared (a degenerate or folded element).
+static bool quad_ok(const pfem_mesh* m, const int32_t* c) {
+  static const double cxi[4] = {-1, 1, 1, -1}, ceta[4] = {-1, -1, 1, 1};
+  const double g = std::sqrt(0.6);
+  double pts[13][2];
+  int np = 0;
+  for (int a = 0; a < 4; ++a) {
+    pts[np][0] = cxi[a];
+    pts[np++][1] = ceta[a];
+  }
+  for (int i = -1; i <= 1; ++i)
+    for (int j = -1; j <= 1; ++j) {
+      pts[np][0] = i * g;
+      pts[np++][1] = j * g;
+    }
+  double lmax = 0.0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < a; ++b) {
+      const double dx = m->coords[c[a] * 2] - m->coords[c[b] * 2];
+      const double dy = m->coords[c[a] * 2 + 1] - m->coords[c[b] * 2 + 1];
+      lmax = std::max(lmax, std::sqrt(dx * dx + dy * dy));
+    }
+  int sign = 0;
+  for (int p = 0; p < np; ++p) {
+    double dN[8][2];
+    quad_shape_derivs(m->nv, pts[p][0], pts[p][1], dN);
+    double J[2][2] = {{0, 0}, {0, 0}};
+    for (int a = 0; a < m->nv; ++a)
+      for (int i = 0; i < 2; ++i)
+        for (int k = 0; k < 2; ++k) J[i][k] += m->coords[(size_t)c[a] * 2 + i] * dN[a][k];
+    const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    if (!(std::isfinite(det) && std::fabs(det) > 1e-12 * lmax * lmax)) return false;
+    const int s = det > 0 ? 1 : -1;
+    if (sign != 0 && s != sign) return false;
+    sign = s;
+  }
+  return true;
+}
+
 static void validate(const pfem_mesh* m) {
   const int D = m->dim;
-  const int nv = D + 1;
+  const int nv = m->nv;
   require(m->model >= 0, PFEM_E_STATE, "material not set");
   std::vector<char> used(m->n_nodes, 0);
   for (int64_t e = 0; e < m->n_elems; ++e) {
@@ -81,6 +146,12 @@ static void validate(const pfem_mesh* m) {
       for (int b = 0; b < a; ++b)
         if (c[a] == c[b])
           throw Error{PFEM_E_INVALID_MESH, "element " + std::to_string(e) + " repeats a node"};
+    }
+    if (m->elem != PFEM_ELEM_P1) {
+      if (!quad_ok(m, c))
+        throw Error{PFEM_E_INVALID_MESH,
+                    "element " + std::to_string(e) + " is degenerate or folded"};
+      continue;
     }
     // degeneracy: |det J| against the longest edge^D
     double ev[3][3] = {};
@@ -133,7 +204,7 @@ static void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>&
 // ----------------------------------------------------------------- RCM
 static void node_graph(const pfem_mesh* m, std::vector<int64_t>& ptr,
                        std::vector<int32_t>& nbr) {
-  const int nv = m->dim + 1;
+  const int nv = m->nv;
   const int64_t N = m->n_nodes;
   std::vector<int64_t> cnt(N + 1, 0);
   for (int64_t e = 0; e < m->n_elems; ++e)
@@ -261,7 +332,7 @@ static void number_nodes(pfem_mesh* m, int bn, bool blocks,
 }
 
 static int64_t bandwidth(const pfem_mesh* m, const int32_t* numbering) {
-  const int nv = m->dim + 1;
+  const int nv = m->nv;
   int64_t bw = 0;
   for (int64_t e = 0; e < m->n_elems; ++e) {
     int32_t lo = INT32_MAX, hi = INT32_MIN;
@@ -278,7 +349,7 @@ static int64_t bandwidth(const pfem_mesh* m, const int32_t* numbering) {
 void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
   validate(m);
   const int D = m->dim;
-  const int nv = D + 1;
+  const int nv = m->nv;
   const int64_t N = m->n_nodes, NE = m->n_elems;
   // 0. nodes per owner block
   int bn = block_nodes;
@@ -472,11 +543,35 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
         m->dmask[m->perm[n]] |= (uint8_t)(1u << c);
         m->ubar_int[(int64_t)m->perm[n] * D + c] = dv[n * D + c];
       }
-  // 5. external force (App. B: t |facet| / n_f on each facet node)
+  // 5. external force (App. B: t |facet| / n_f on each node of a linear
+  // facet; a Q8 edge integrates its quadratic shape functions)
   std::vector<double> fext(ndof, 0.0);
+  const int nfn = m->facet_nodes();
   for (int64_t f = 0; f < m->n_facets; ++f) {
-    const int32_t* fn = &m->facets[f * D];
+    const int32_t* fn = &m->facets[f * nfn];
     const double* t = &m->traction[f * D];
+    if (nfn == 3 && D == 2) {
+      // nodes (end, end, middle): N = s(s-1)/2, s(s+1)/2, 1 - s^2 on
+      // s in [-1, 1]; 3 Gauss points along the edge
+      const double gs[3] = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)};
+      const double gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+      double w[3] = {0, 0, 0};
+      for (int q = 0; q < 3; ++q) {
+        const double sq = gs[q];
+        const double N[3] = {0.5 * sq * (sq - 1), 0.5 * sq * (sq + 1), 1 - sq * sq};
+        const double dN[3] = {sq - 0.5, sq + 0.5, -2 * sq};
+        double tx = 0, ty = 0;
+        for (int a = 0; a < 3; ++a) {
+          tx += dN[a] * m->coords[(size_t)fn[a] * 2];
+          ty += dN[a] * m->coords[(size_t)fn[a] * 2 + 1];
+        }
+        const double ds = std::sqrt(tx * tx + ty * ty);
+        for (int a = 0; a < 3; ++a) w[a] += gw[q] * ds * N[a];
+      }
+      for (int a = 0; a < 3; ++a)
+        for (int i = 0; i < 2; ++i) fext[(int64_t)fn[a] * 2 + i] += t[i] * w[a];
+      continue;
+    }
     double meas;
     if (D == 2) {
       const double dx = m->coords[fn[1] * 2] - m->coords[fn[0] * 2];
@@ -597,8 +692,8 @@ static void prepare_device_images(pfem_mesh* m) {
   }
   // packed 2D connectivity: smallest node first, 16-bit offsets of the
   // other two (3D kernels read the plain 16-byte rows)
-  const int nv = D + 1;
-  bool packable = D == 2;
+  const int nv = m->nv;
+  bool packable = D == 2 && m->elem == PFEM_ELEM_P1;
   m->connp.assign(packable ? (size_t)m->n_elems * 2 : 0, 0u);
   for (int64_t s = 0; packable && s < m->n_elems; ++s) {
     const int32_t* c = &m->conn_int[s * nv];
@@ -736,6 +831,7 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx) {
   md.n_blocks = m->n_blocks;
   md.bn = m->bn;
   md.dim = m->dim;
+  md.nv = m->nv;
   md.model = m->model;
   md.nonlinear = m->nonlinear ? 1 : 0;
   // uniform lambda / mu ratio (uniform Poisson ratio): kernels stream mu only
@@ -798,7 +894,8 @@ void mesh_release_device(pfem_mesh* m) {
 int64_t mesh_device_bytes(const pfem_mesh* m) {
   const int64_t N = m->n_nodes, NE = m->n_elems, D = m->dim;
   auto r = [](int64_t b) { return std::max<int64_t>(b, 1); };
-  return r(N * D * 8) + r(N * D * 4) + r(NE * (D + 1) * 4) + r(D == 2 ? NE * 8 : 0) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
+  return r(N * D * 8) + r(N * D * 4) + r(NE * m->nv * 4) +
+         r(D == 2 && m->elem == PFEM_ELEM_P1 ? NE * 8 : 0) + 2 * r(NE * 4) + 2 * r(NE * 8) + r(N) +
          r((int64_t)m->n_blocks * 16) + r(((int64_t)m->halo.size() + 1) * 4) + 2 * r(N * D * 8) +
          r(NE * 4) + r(N * 4) + r((int64_t)m->n_blocks * 8) +
          (m->pair_ptr.empty() ? 0 : r((N + 1) * 4) + r((int64_t)m->pair_nbr.size() * 4));
@@ -822,6 +919,7 @@ int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg, bool two_level
 bool krylov_fused(const pfem_solve_opts& o, const pfem_mesh* m) {
   if (o.krylov != PFEM_KRYLOV_AUTO) return o.krylov == PFEM_KRYLOV_FUSED;
   if (o.precond == PFEM_PRECOND_TWO_LEVEL) return false;   // classic loop only
+  if (m->elem != PFEM_ELEM_P1) return false;                // quadrilaterals: classic loop
   // The fused launch wins where an iteration is launch- and latency-bound
   // (measured warm FP32 solves: 200k-triangle plate 55 vs 82 ms per solve,
   // 500k-tet Neo-Hookean box 55 vs 64 ms); on larger meshes its extra vector

@@ -102,6 +102,8 @@ struct CallScratch {
 struct pfem_mesh {
   pfem::Ctx* ctx = nullptr;
   int dim = 0;
+  int elem = PFEM_ELEM_P1;          // element family (PFEM_ELEM_*)
+  int nv = 0;                       // nodes per element
   int64_t n_nodes = 0, n_elems = 0;
   std::vector<double> coords;       // caller order
   std::vector<int32_t> conn;        // caller order
@@ -161,6 +163,10 @@ struct pfem_mesh {
   ~pfem_mesh();
 
   int64_t n_dof() const { return n_nodes * dim; }
+  // nodes of a Neumann facet: an edge (2D), a triangle (3D), a 3-node edge (Q8)
+  int facet_nodes() const { return elem == PFEM_ELEM_Q8 ? 3 : dim; }
+  // what the element launches dispatch on (pfem::elem_kind)
+  int kind() const { return pfem::elem_kind(dim, elem); }
 };
 
 struct pfem_ctx {

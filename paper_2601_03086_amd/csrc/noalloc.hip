@@ -97,7 +97,7 @@ extern "C" pfem_status pfem_energy_noalloc(pfem_mesh* m, int prec, int layout, c
     t.red.part = part;
     t.red.out = out;
     const Task* td = static_cast<const Task*>(ctx->ring.put(&t, sizeof(Task)));
-    launch_energy(ctx, m->dim, prec, false, td, m->dev.work, m->n_blocks);
+    launch_energy(ctx, m->kind(), prec, false, td, m->dev.work, m->n_blocks);
     launch_reduce_store(ctx, td, 1);
     launch_energy_out(ctx, out, energy_dev, 1, kRedSlots);
     set_error("");

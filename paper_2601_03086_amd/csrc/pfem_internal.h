@@ -59,7 +59,7 @@ struct MeshDev {
   const double* X;        // n_nodes * dim, internal node order
   const uint32_t* Xq;     // n_nodes * dim 31-bit fixed-point coordinates (float32 kernels):
                           // X = lo + q * qscale, per dimension
-  const int32_t* conn;    // n_elems * (dim+1), sorted element order, internal ids
+  const int32_t* conn;    // n_elems * nv, sorted element order, internal ids
   const uint32_t* connp;  // packed 2D connectivity (conn_packed): per element
                           // the smallest node, then the 16-bit offsets of the
                           // other two in one word; node order inside the
@@ -78,6 +78,7 @@ struct MeshDev {
   int32_t dim, model, nonlinear;
   int32_t lam_uniform;    // 1: lambda = lam_ratio * mu on every element (lam arrays unread)
   int32_t conn_packed;    // 1: kernels read connp (every offset fits 16 bits)
+  int32_t nv;             // nodes per element (conn row length)
   double lam_ratio;
   float qscale[3];        // fixed-point coordinate step per dimension
   // periodic springs (virtual elements of a periodic cell): node n's
@@ -128,6 +129,14 @@ struct TwoLevelDev {
   double* gc_part;        // n_chunks partials of (R^T r) . y
   int32_t nrb, G, n_agg, n_c, n_chunks, pad;
 };
+// Element kernel families: P1 meshes launch by their dimension (2, 3);
+// quadrilateral meshes by these codes (their nodes per element).
+constexpr int kKindQ4 = 4;
+constexpr int kKindQ8 = 8;
+inline int elem_kind(int dim, int elem) {
+  return elem == PFEM_ELEM_Q4 ? kKindQ4 : elem == PFEM_ELEM_Q8 ? kKindQ8 : dim;
+}
+inline bool is_quad_kind(int kind) { return kind == kKindQ4 || kind == kKindQ8; }
 constexpr int kCoarseRows = 8;   // rows of B per workgroup of the coarse solve
 // Largest coarse dimension: the device applies the coarse inverse as one
 // dense matrix-vector product per iteration.
@@ -275,6 +284,12 @@ void noalloc_init(int device);
 void launch_energy(Ctx* ctx, int dim, int prec, bool diff,
                    const Task* tasks_dev, const int2* work_dev, int n_work,
                    const BaseArgs* rel = nullptr);
+// Quadrilateral element kernels (kind kKindQ4 / kKindQ8; owner scatter),
+// called by launch_elem / launch_energy.
+void launch_quad_elem(Ctx* ctx, int kind, int prec, int op, bool nonlinear, const Task* tasks,
+                      const int2* work, int n_work, int bn_max, const BaseArgs& ba);
+void launch_quad_energy(Ctx* ctx, int kind, int prec, bool diff, const Task* tasks,
+                        const int2* work, int n_work, const BaseArgs& ba);
 // PCG vector passes over owned node blocks.
 void launch_pcg_init(Ctx* ctx, int dim, int prec, const Task* tasks_dev,
                      const int2* work_dev, int n_work, int n_tasks);

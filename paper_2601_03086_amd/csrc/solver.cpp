@@ -101,9 +101,19 @@ void check_solve_opts(const pfem_solve_opts& o) {
           PFEM_E_INVALID_ARG, "the two-level preconditioner runs with the classic PCG loop");
 }
 
-void slot_alloc(SlotRun* s, pfem_mesh* m, const pfem_solve_opts& o, int64_t hist_cap) {
+void check_solve_mesh(const pfem_solve_opts& o, const pfem_mesh* m) {
   require(!(krylov_fused(o, m) && !m->pairs.empty()), PFEM_E_INVALID_ARG,
           "the fused PCG does not apply periodic springs: use the classic formulation");
+  if (m->elem != PFEM_ELEM_P1) {
+    require(o.krylov != PFEM_KRYLOV_FUSED, PFEM_E_INVALID_ARG,
+            "quadrilateral meshes run the classic PCG loop");
+    require(o.precond != PFEM_PRECOND_TWO_LEVEL, PFEM_E_INVALID_ARG,
+            "the two-level preconditioner is built for P1 meshes");
+  }
+}
+
+void slot_alloc(SlotRun* s, pfem_mesh* m, const pfem_solve_opts& o, int64_t hist_cap) {
+  check_solve_mesh(o, m);
   s->m = m;
   s->o = o;
   s->prec = o.prec == PFEM_FP64 ? PFEM_FP64 : PFEM_FP32;
@@ -142,7 +152,7 @@ static double alg_bytes(const SlotRun* s, bool fused) {
   const double sz = s->prec == PFEM_FP64 ? 8.0 : 4.0;
   // a right-hand side after the first of a multi-right-hand-side apply
   // shares the element data read for the first
-  double b = s->shares_elements ? 0.0 : 4.0 * (d + 1.0) * ne + sz * ne + d * sz * nn;
+  double b = s->shares_elements ? 0.0 : 4.0 * s->m->nv * ne + sz * ne + d * sz * nn;
   b += (fused ? 11.0 : 2.0) * d * sz * nn;
   if (s->nl) b += d * sz * nn;
   return b;
@@ -179,7 +189,7 @@ static Task base_task(SlotRun* s) {
 }
 
 struct Group {
-  int dim, prec;
+  int dim, kind, prec;   // kind: element kernel family (pfem::elem_kind)
   bool nl;
   bool fused;
   bool tl;   // two-level preconditioner
@@ -194,9 +204,11 @@ static std::vector<Group> group_by(const std::vector<SlotRun*>& v, bool force_fp
     const int pr = force_fp64 ? PFEM_FP64 : s->prec;
     const bool fused = !force_fp64 && s->st->fused;
     const bool tl = !force_fp64 && uses_two_level(s);
-    auto key = std::make_tuple(s->m->dim, pr, s->nl ? 1 : 0, fused ? 1 : 0, tl ? 1 : 0);
+    const int kind = s->m->kind();
+    auto key = std::make_tuple(kind, pr, s->nl ? 1 : 0, fused ? 1 : 0, tl ? 1 : 0);
     auto it = g.find(key);
-    if (it == g.end()) it = g.emplace(key, Group{s->m->dim, pr, s->nl, fused, tl, {}}).first;
+    if (it == g.end())
+      it = g.emplace(key, Group{s->m->dim, kind, pr, s->nl, fused, tl, {}}).first;
     it->second.slots.push_back(s);
   }
   std::vector<Group> out;
@@ -319,7 +331,7 @@ static void do_force(Ctx* ctx, const std::vector<SlotRun*>& v, bool at_lift, int
       ts.push_back(t);
     }
     Uploaded u = upload_group(ctx, g, ts);
-    launch_elem(ctx, g.dim, PFEM_FP64, OP_FORCE, g.nl, PFEM_SCATTER_OWNER, u.tasks, u.work,
+    launch_elem(ctx, g.kind, PFEM_FP64, OP_FORCE, g.nl, PFEM_SCATTER_OWNER, u.tasks, u.work,
                 u.n_work, u.bn_max, nullptr, nullptr);
     launch_reduce_store(ctx, u.tasks, (int)ts.size());
     *nl += 2;
@@ -361,7 +373,7 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
         s->minv_valid = true;
       }
       Uploaded u = upload_group(ctx, g, ts);
-      launch_elem(ctx, g.dim, g.prec, OP_DIAG, g.nl, PFEM_SCATTER_OWNER, u.tasks, u.work, u.n_work,
+      launch_elem(ctx, g.kind, g.prec, OP_DIAG, g.nl, PFEM_SCATTER_OWNER, u.tasks, u.work, u.n_work,
                   u.bn_max, nullptr, nullptr);
       ++*nl;
     }
@@ -401,7 +413,7 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
         ta.push_back(t);
       }
       Uploaded ua = upload_group(ctx, g, ta);
-      launch_elem(ctx, g.dim, g.prec, OP_APPLY, g.nl, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
+      launch_elem(ctx, g.kind, g.prec, OP_APPLY, g.nl, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
                   ua.n_work, ua.bn_max, nullptr, nullptr);
       if (ctx->timing & (1 << FAM_APPLY)) {
         ctx->fam_run[FAM_APPLY] += 1;
@@ -468,7 +480,7 @@ static void do_krylov(Ctx* ctx, const std::vector<SlotRun*>& start,
         launch_owner_multi(ctx, g.prec, ua.tasks, (int)g.slots.size(), g.slots[0]->m->dev.work,
                            g.slots[0]->m->n_blocks, g.slots[0]->m->bn);
       else
-        launch_elem(ctx, g.dim, g.prec, OP_APPLY, g.nl, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
+        launch_elem(ctx, g.kind, g.prec, OP_APPLY, g.nl, PFEM_SCATTER_OWNER, ua.tasks, ua.work,
                     ua.n_work, ua.bn_max, nullptr, nullptr);
       if (g.tl) {
         launch_tl_update(ctx, g.dim, g.prec, uu.tasks, uu.work, uu.n_work, it);
@@ -515,7 +527,7 @@ static void do_linesearch(Ctx* ctx, const std::vector<SlotRun*>& v, int64_t* nl)
       ts.push_back(t);
     }
     Uploaded u = upload_group(ctx, g, ts);
-    launch_energy(ctx, g.dim, g.prec, true, u.tasks, u.work, u.n_work);
+    launch_energy(ctx, g.kind, g.prec, true, u.tasks, u.work, u.n_work);
     launch_reduce_store(ctx, u.tasks, (int)ts.size(), 3);
     *nl += 2;
   }

@@ -74,6 +74,8 @@ int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches);
 // residual would end at iteration 0 and leave x unchanged, forever; 0.5
 // keeps a factor 2 above the float32 rounding of that starting residual.
 void check_solve_opts(const pfem_solve_opts& o);
+// Refuses option / mesh combinations no solve path covers (PFEM_E_INVALID_ARG).
+void check_solve_mesh(const pfem_solve_opts& o, const pfem_mesh* m);
 void slot_alloc(SlotRun* s, pfem_mesh* m, const pfem_solve_opts& o, int64_t hist_cap);
 void slot_free(SlotRun* s);
 

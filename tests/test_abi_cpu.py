@@ -59,6 +59,8 @@ PROBLEMS = {
     "c1": lambda: synth.unit_square_c1(),
     "plate": lambda: synth.plate_problem(31, 32, 33, n_holes=4, target_tris=4000),
     "box": lambda: synth.box_problem(41, 42, n_per_unit=5, n_voids=3, n_load_steps=2),
+    "beam_q4": lambda: synth.beam_problem(43, 24, 12),
+    "cook_q8": lambda: synth.cook_problem(44, 14),
 }
 
 
@@ -271,7 +273,8 @@ def test_every_entry_point_rejects_null_arguments():
     # a NULL handle is caught before any other argument is looked at: the
     # other pointers point at valid host memory and the counts are 1
     buf = C.create_string_buffer(1 << 20)
-    first_not_handle = {"pfem_ctx_create", "pfem_mesh_create", "pfem_last_error",
+    first_not_handle = {"pfem_ctx_create", "pfem_mesh_create", "pfem_mesh_create_quad",
+                        "pfem_last_error",
                         "pfem_version", "pfem_solve_opts_default"}
     for name, (res, args) in L.PROTOTYPES.items():
         if name in first_not_handle or res is None:
@@ -530,3 +533,52 @@ def test_coarse_aggregates_and_preparation():
     o.precond = 7
     st = L.load().pfem_solve(m.h, None, C.byref(o), u.ctypes.data, 0, None, 0, None)
     assert st == L.PFEM_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("elem", ["q4", "q8"])
+def test_quad_mesh_info_loads_and_refusals(elem):
+    """A quadrilateral mesh reports its family, its consistent loads match
+    the oracle's (Q8 edges: quadratic shape functions), and the paths that
+    do not cover quadrilaterals are refused without a device."""
+    from paper_2601_03086_amd import core
+    from oracle import fe
+    L = _lib()
+    p = synth.beam_problem(45, 16, 6, elem=elem) if elem == "q4" else synth.cook_problem(46, 10)
+    m = core.Mesh.from_problem(None, p)
+    assert m.info["elem"] == (L.PFEM_ELEM_Q4 if elem == "q4" else L.PFEM_ELEM_Q8)
+    assert m.info["nodes_per_elem"] == p.conn.shape[1]
+    f = fe.Model(p).f_ext
+    assert abs(m.info["f_ext_norm"] - np.linalg.norm(f)) <= 1e-14 * np.linalg.norm(f)
+    with pytest.raises(L.PfemError) as e:
+        m.prepare_coarse()
+    assert e.value.status == L.PFEM_E_INVALID_ARG
+
+
+def test_quad_mesh_validation():
+    """Folded and degenerate quadrilaterals and a wrong family are refused."""
+    L = _lib()
+    L.load()
+    import ctypes as C
+    coords = np.array([[0, 0], [1, 0], [1, 1], [0, 1], [2, 0], [2, 1]], np.float64)
+    good = np.array([[0, 1, 2, 3], [1, 4, 5, 2]], np.int32)
+    folded = np.array([[0, 1, 2, 3], [1, 4, 2, 5]], np.int32)    # bow-tie
+    flat = np.array([[0, 1, 4, 3]], np.int32)                    # three corners on a line
+
+    def make(conn, elem=L.PFEM_ELEM_Q4):
+        h = C.c_void_p()
+        st = L.pfem_mesh_create_quad(None, elem, coords.shape[0], coords.ctypes.data,
+                                     conn.shape[0], conn.ctypes.data, C.byref(h))
+        if st != 0:
+            return st, None
+        ne = conn.shape[0]
+        E, nu = np.full(ne, 1.0), np.full(ne, 0.3)
+        assert L.pfem_mesh_set_material(h, L.PFEM_LIN_PLANE_STRAIN, L.PFEM_PARAM_E_NU,
+                                        E.ctypes.data, nu.ctypes.data) == 0
+        st = L.pfem_mesh_finalize(h, 0)
+        L.pfem_mesh_destroy(h)
+        return st, h
+
+    assert make(good)[0] == 0
+    assert make(folded)[0] == L.PFEM_E_INVALID_MESH
+    assert make(flat)[0] in (L.PFEM_E_INVALID_MESH,)
+    assert make(good, elem=7)[0] == L.PFEM_E_INVALID_ARG
