@@ -941,6 +941,74 @@ def warm_start_prediction(mesh, uref, u0, hist):
             "error_ratio_A_norm": round(e_zero / e_warm, 2)}
 
 
+def run_quad(n=150, n_seq=10):
+    """The paper's quadrilateral benchmarks (Sec. 'Nonlinear hyperelasticity'):
+    n hyperelastic beams (50 x 50 Q4) and n Cook's membranes (30 x 30 Q8),
+    Neo-Hookean plane strain, distinct seeded material fields and tractions.
+    Per family: FP64 references (served, zero start, 5 load steps, 1e-10)
+    give the warm starts (reference + 1% smooth noise); then all n requests
+    are served at once (FP32 mode, 1e-8) from zero with 5 load steps, from
+    zero with one load step (the paper's comparison) and from the warm
+    starts at the final load; mean Newton iterations and Hessian-vector
+    products per request, solves/s, and the HVP kernel's average duration;
+    the first n_seq requests also one at a time."""
+    import torch
+    import synth
+    from paper_2601_03086_amd import core
+    ctx = core.Context(0)
+    out = {}
+    for fam, gen in (("beam_q4_50x50", lambda s: synth.beam_problem(s)),
+                     ("cook_q8_30x30", lambda s: synth.cook_problem(s))):
+        t0 = time.perf_counter()
+        probs = [gen(7000 + i) for i in range(n)]
+        meshes = host_meshes(probs)
+        ids = list(range(n))
+        ref, refsol, _, _ = serve(ctx, meshes, probs, None, [0.0] * n, ids, tol=1e-10,
+                                  prec="fp64", keep=set(ids))
+        bad = [(i, ref[i]["status"], ref[i]["newton_iters"], ref[i]["rel_residual_final"])
+               for i in ids if ref[i]["status"] != 0]
+        assert not bad, (fam, len(bad), bad[:5])
+        # smooth noise on the scale of the domain (correlation length 0.2 of
+        # its size: the unit-size workloads use 0.2)
+        size = float(np.ptp(probs[0].coords, axis=0).max())
+        u0s = [synth.warm_start_guess(refsol[i], probs[i].coords, probs[i].dir_nodes, 100 + i,
+                                      length=0.2 * size) for i in ids]
+        _log(f"# {fam}: {n} meshes and references in {time.perf_counter() - t0:.1f}s")
+        res = {"elements": probs[0].n_elems, "dofs": probs[0].n_dof}
+        for label, starts, steps in (("zero_5_load_steps", None, 5),
+                                     ("zero_1_load_step", None, 1),
+                                     ("warm", u0s, 5)):
+            for p in probs:
+                p.n_load_steps = steps
+            torch.cuda.synchronize()
+            r, sols, st, ks = serve(ctx, meshes, probs, starts, [0.0] * n, ids, keep={0})
+            summ = stream_summary(r, probs, ids)
+            summ["newton_per_request"] = round(float(np.mean([r[i]["newton_iters"]
+                                                              for i in ids])), 2)
+            summ["failed"] = sum(r[i]["status"] != 0 for i in ids)
+            if label == "warm":
+                # the HVP launches' durations from a second, event-timed run
+                _, _, _, ks = serve(ctx, meshes, probs, starts, [0.0] * n, ids, timing=True)
+                k = ks["apply"]
+                us = k["total_ms"] / max(k["launches_run"], 1) * 1e3
+                b = k["alg_bytes"] / max(k["launches_run"], 1)
+                summ["hvp_launch"] = {"avg_us": round(us, 3), "alg_bytes": round(b),
+                                      "alg_GBps": round(b / us * 1e-3, 1) if us else 0.0}
+                err = float(np.linalg.norm(sols[0] - refsol[0]) / np.linalg.norm(refsol[0]))
+                summ["rel_error_vs_reference"] = err
+            res[label] = summ
+            _log(f"# {fam} {label}: {summ}")
+        for p in probs:
+            p.n_load_steps = 5
+        seq_z, _ = sequential(ctx, meshes, probs, None, ids[:n_seq])
+        seq_w, _ = sequential(ctx, meshes, probs, u0s, ids[:n_seq])
+        res["sequential_zero_5_load_steps"] = seq_z
+        res["sequential_warm"] = seq_w
+        out[fam] = res
+    print(json.dumps({"config": "quad", "requests_per_family": n, **out}), flush=True)
+    ctx.close()
+
+
 def run_kv_only(n, mesh_spec=None, kernel="owner"):
     """n launches of the K.v owner kernel (kernel="owner") or about n fused
     PCG iterations of a capped zero-start FP32 solve (kernel="fused"), then
@@ -1325,7 +1393,7 @@ def main():
     ap.add_argument("--kv-large", default=None,
                     help='e.g. "2d:2000,3d:60": K.v roofline sweep on large meshes')
     ap.add_argument("--config", default=None,
-                    choices=["c1", "c2", "c3", "c4", "sweep", "rotate", "homog"],
+                    choices=["c1", "c2", "c3", "c4", "sweep", "rotate", "homog", "quad"],
                     help="other workloads (one JSON line each, not the headline)")
     ap.add_argument("--sizes", default="2d:2e5,2d:1e6,2d:4e6,2d:1.6e7,3d:1e6,3d:4e6,3d:1.6e7",
                     help="--config sweep sizes (element counts)")
@@ -1365,7 +1433,7 @@ def main():
         {"c1": run_c1, "c2": lambda: run_c2(args), "c3": run_c3, "c4": run_c4,
          "sweep": lambda: run_sweep(args.sizes),
          "rotate": lambda: run_rotate(args.copies),
-         "homog": run_homog}[args.config]()
+         "homog": run_homog, "quad": run_quad}[args.config]()
         return
     run_c5(args)
 

@@ -184,7 +184,8 @@ def test_newton_full_size(ctx, which, prec):
     om = fe.Model(p)
     den = np.linalg.norm(om.gradient(om.lifted(1.0))[om.free_dofs])
     assert np.linalg.norm(om.gradient(u)[om.free_dofs]) / den <= 1.05e-9
-    u0 = synth.warm_start_guess(uo, p.coords, p.dir_nodes, seed=33)
+    u0 = synth.warm_start_guess(uo, p.coords, p.dir_nodes, seed=33,
+                                length=0.2 * np.ptp(p.coords, axis=0).max())
     uw, rw, _ = m.solve(u0=u0, tol=1e-9, prec=prec, n_load_steps=p.n_load_steps)
     print(f"[quad newton] {which} {prec} warm: {rw['newton_iters']} Newton", flush=True)
     assert rw["status"] == 0 and rw["load_steps_done"] == 1
