@@ -542,15 +542,15 @@ def host_meshes(probs):
         return list(ex.map(lambda p: core.Mesh.from_problem(None, p, 0, ORDER), probs))
 
 
-def _solve_kw(p, tol, prec):
-    kw = dict(tol=tol, prec=prec)
+def _solve_kw(p, tol, prec, precond="jacobi"):
+    kw = dict(tol=tol, prec=prec, precond=precond)
     if p.nonlinear:
         kw["n_load_steps"] = p.n_load_steps
     return kw
 
 
 def serve(ctx, meshes, probs, u0s, t_arrive, ids, tol=1e-8, prec="fp32", timing=False,
-          keep=(), budget_gb=SERVE_BUDGET_GB, slots=SERVE_SLOTS):
+          keep=(), budget_gb=SERVE_BUDGET_GB, slots=SERVE_SLOTS, precond="jacobi"):
     """Open-loop replay: request ids[k] is submitted at t_arrive[k] seconds
     after the server starts (u0s None: zero start).  Returns per-request
     reports (library timestamps: submission, admission, completion), the
@@ -570,7 +570,7 @@ def serve(ctx, meshes, probs, u0s, t_arrive, ids, tol=1e-8, prec="fp32", timing=
         while nxt < n and t_arrive[nxt] <= now:
             i = ids[nxt]
             srv.submit(i, meshes[i], u0=None if u0s is None else u0s[i],
-                       **_solve_kw(probs[i], tol, prec))
+                       **_solve_kw(probs[i], tol, prec, precond))
             nxt += 1
         for rid in srv.poll():
             u, r = srv.result(rid)
@@ -819,6 +819,24 @@ def run_c5(args):
     res_z, _, st_z, _ = serve(ctx, meshes, probs, None, t_arr, ids)
     zero = stream_summary(res_z, probs, ids)
     _log(f"# zero-start stream: {zero}")
+    # the same arrivals with the two-level preconditioner (rigid-body coarse
+    # space per mesh, built on the host ahead of the stream like the rest of
+    # each mesh's preprocessing)
+    import concurrent.futures as cf
+    t1 = time.perf_counter()
+    with cf.ThreadPoolExecutor(4) as ex:
+        n_c = list(ex.map(lambda m: m.prepare_coarse(), meshes))
+    t_coarse = time.perf_counter() - t1
+    _log(f"# coarse spaces of {n_req} meshes in {t_coarse:.1f}s (mean {np.mean(n_c):.0f} DOFs)")
+    res_tl, _, _, _ = serve(ctx, meshes, probs, u0s, t_arr, ids, precond="two_level")
+    warm_tl = stream_summary(res_tl, probs, ids)
+    _log(f"# warm stream, two-level: {warm_tl}")
+    res_tlz, _, _, _ = serve(ctx, meshes, probs, None, t_arr, ids, precond="two_level")
+    zero_tl = stream_summary(res_tlz, probs, ids)
+    _log(f"# zero-start stream, two-level: {zero_tl}")
+    two_level = {"served_warm": warm_tl, "served_zero_start": zero_tl,
+                 "coarse_setup_s_total": round(t_coarse, 1),
+                 "coarse_dofs_mean": round(float(np.mean(n_c)), 1)}
     seq_w, lat_sw = sequential(ctx, meshes, probs, u0s, ids)
     _log(f"# sequential warm: {seq_w}")
     seq_z, _ = sequential(ctx, meshes, probs, None, ids)
@@ -886,6 +904,7 @@ def run_c5(args):
             "apply": ks["apply"],
         },
         "kv_large_working_set": kv_points,
+        "two_level_preconditioner": two_level,
         "c2_plate_solve": c2,
         "oracle_verified": ver,
     }
