@@ -1028,33 +1028,45 @@ def run_quad(n=150, n_seq=10):
     ctx.close()
 
 
-def run_kv_only(n, mesh_spec=None, kernel="owner"):
-    """n launches of the K.v owner kernel (kernel="owner") or about n fused
-    PCG iterations of a capped zero-start FP32 solve (kernel="fused"), then
-    five 256 MiB copies that calibrate byte counters."""
+def run_kv_only(n, mesh_spec=None, kernel="owner", op="kv", block_nodes=0):
+    """n launches of the K.v owner kernel (kernel="owner"; op="hvp": the
+    Neo-Hookean Hessian-vector product at a smooth state, strains up to 6%)
+    or about n fused PCG iterations of a capped zero-start FP32 solve
+    (kernel="fused"), then five 256 MiB copies that calibrate byte
+    counters."""
     import torch
     if mesh_spec:
         import synth
         from paper_2601_03086_amd import core
         kind, nx = mesh_spec.split(":")
         nx = int(nx)
-        prob = (synth.structured_plate(nx, nx, seed=7) if kind == "2d"
-                else synth.structured_box(nx, nx, 4 * nx, seed=7))
+        nh = op == "hvp"
+        prob = (synth.structured_plate(nx, nx, seed=7,
+                                       model="nh_plane_strain" if nh else "lin_plane_strain")
+                if kind == "2d" else
+                synth.structured_box(nx, nx, 4 * nx, seed=7, model="nh_3d" if nh else "lin_3d"))
         ctx = core.Context(0)
-        mesh = new_mesh(ctx, prob)
+        mesh = new_mesh(ctx, prob, block_nodes)
     else:
         from paper_2601_03086_amd import core
         prob = c2_problem()
         ctx = core.Context(0)
         mesh = new_mesh(ctx, prob)
     if kernel == "fused":
-        mesh.solve(u0=None, tol=1e-8, prec="fp32", max_iter=n, history_cap=1)
+        mesh.solve(u0=None, tol=1e-8, prec="fp32", max_iter=n, history_cap=1, krylov="fused")
     else:
         x = mesh.permute(torch.randn(prob.n_dof, dtype=torch.float32, device="cuda"),
                          True, "fp32")
         y = torch.empty_like(x)
-        for _ in range(n):
-            mesh.apply_K(x, prec="fp32", layout="internal", out=y)
+        if op == "hvp":
+            X = torch.tensor(prob.coords, device="cuda")
+            u = 0.02 * torch.sin(3.0 * X)                      # smooth, strains up to 6%
+            ui = mesh.permute(u.reshape(-1).float().contiguous(), True, "fp32")
+            for _ in range(n):
+                mesh.hvp(ui, x, prec="fp32", layout="internal", out=y)
+        else:
+            for _ in range(n):
+                mesh.apply_K(x, prec="fp32", layout="internal", out=y)
     a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")   # 256 MiB copy
     b = torch.empty_like(a)
     for _ in range(5):
@@ -1407,6 +1419,8 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"],
                     help="solve precision (fp32: FP32 Krylov + FP64 refinement)")
     ap.add_argument("--kv-mesh", default=None, help='mesh for --kv-only, e.g. "3d:40"')
+    ap.add_argument("--kv-op", default="kv", choices=["kv", "hvp"],
+                    help="--kv-only owner kernel: K.v or the Neo-Hookean HVP")
     ap.add_argument("--kv-kernel", default="owner", choices=["owner", "fused"],
                     help="--kv-only: K.v launches or fused PCG iterations")
     ap.add_argument("--kv-large", default=None,
@@ -1440,7 +1454,7 @@ def main():
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.kv_only:
-        run_kv_only(args.kv_only, args.kv_mesh, args.kv_kernel)
+        run_kv_only(args.kv_only, args.kv_mesh, args.kv_kernel, args.kv_op, args.block_nodes)
         return
     if args.kv_sweep:
         run_kv_sweep([int(s) for s in args.kv_sweep.split(",")], args.kv_mesh)

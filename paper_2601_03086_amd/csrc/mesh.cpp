@@ -130,6 +130,9 @@ static bool quad_ok(const pfem_mesh* m, const int32_t* c) {
   return true;
 }
 
+// Block count above which the automatic block size grows (see finalize).
+constexpr int64_t kBlocksSoftMax = 512;
+
 static void validate(const pfem_mesh* m) {
   const int D = m->dim;
   const int nv = m->nv;
@@ -357,10 +360,14 @@ void mesh_finalize_host(pfem_mesh* m, int block_nodes) {
     // N/4000 (2D) or N/750 (3D) nodes, a multiple of 32, at least 224 (2D) or
     // 64 (3D), at most 1024: measured optimum of the owner kernels on compact
     // blocks (enough workgroups to fill the chip, few halo revisits, LDS for
-    // enough resident workgroups; the fused PCG launch sums every block's
-    // partials in every block, so it also wants few blocks)
+    // enough resident workgroups).  Also at least N/512: every workgroup of a
+    // PCG vector launch and of the fused iteration sums the partials of all
+    // blocks, work that grows as the square of the block count (fused FP32
+    // iteration on a 2M-triangle plate: 62.5 us with 3915 blocks, 41.7 with
+    // 1958, 35.7 with 979)
     const int64_t per = D == 2 ? 4000 : 750, lo = D == 2 ? 224 : 64;
-    bn = (int)std::min<int64_t>(1024, std::max<int64_t>(lo, ((N / per) + 31) / 32 * 32));
+    const int64_t want = std::max(N / per, (N + kBlocksSoftMax - 1) / kBlocksSoftMax);
+    bn = (int)std::min<int64_t>(1024, std::max<int64_t>(lo, (want + 31) / 32 * 32));
   }
   require(bn <= block_nodes_max(), PFEM_E_INVALID_ARG, "block_nodes too large");
   // the element kernels address mesh and solver arrays with 32-bit byte
