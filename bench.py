@@ -534,12 +534,15 @@ def gen_stream(n_requests, rate):
     return descs, probs, noises
 
 
-def host_meshes(probs):
-    """Finalized host-only meshes (the server uploads them on admission)."""
+def host_meshes(probs, block_nodes=None):
+    """Finalized host-only meshes (the server uploads them on admission).
+    block_nodes: {dim: nodes per owner block} (0 or missing: the library's
+    automatic size); None: the --block-nodes value for every mesh."""
     import concurrent.futures as cf
     from paper_2601_03086_amd import core
+    bn = (lambda p: BLOCK_NODES) if block_nodes is None else (lambda p: block_nodes.get(p.dim, 0))
     with cf.ThreadPoolExecutor(4) as ex:
-        return list(ex.map(lambda p: core.Mesh.from_problem(None, p, 0, ORDER), probs))
+        return list(ex.map(lambda p: core.Mesh.from_problem(None, p, bn(p), ORDER), probs))
 
 
 def _solve_kw(p, tol, prec, precond="jacobi"):
@@ -765,6 +768,19 @@ def cpu_sample(descs, u0s, ids):
                        f"products in {d['seconds']:.1f} s")}
 
 
+def serve_block_nodes(args):
+    """Owner-block size of the served meshes, per dimension.  A served
+    launch batches many meshes, so it has workgroups enough for the chip
+    whatever their size, and bigger blocks spread each workgroup's fixed
+    costs (partial sums, scalars, task descriptor) over more elements; a
+    single latency-bound solve wants the library's smaller automatic blocks
+    (the 200k-triangle plate: 58 ms at 224 nodes, 63 at 512, 90 at 1024)."""
+    if args.block_nodes:
+        return {2: args.block_nodes, 3: args.block_nodes}
+    d2, d3 = (int(x) for x in args.serve_block_nodes.split(","))
+    return {2: d2, 3: d3}
+
+
 def run_c5(args):
     """The serving stream as the headline (see the module docstring)."""
     import torch
@@ -777,7 +793,7 @@ def run_c5(args):
     _log(f"# generated {n_req} meshes ({int(n_el.sum())} elements, "
          f"{sum(p.dim == 2 for p in probs)} plates) in {time.perf_counter() - t_setup:.1f}s")
     t1 = time.perf_counter()
-    meshes = host_meshes(probs)
+    meshes = host_meshes(probs, serve_block_nodes(args))
     _log(f"# preprocessed on the host in {time.perf_counter() - t1:.1f}s")
     ctx = core.Context(0)
     ids = list(range(n_req))
@@ -837,9 +853,17 @@ def run_c5(args):
     two_level = {"served_warm": warm_tl, "served_zero_start": zero_tl,
                  "coarse_setup_s_total": round(t_coarse, 1),
                  "coarse_dofs_mean": round(float(np.mean(n_c)), 1)}
-    seq_w, lat_sw = sequential(ctx, meshes, probs, u0s, ids)
+    # one request at a time: meshes with the library's automatic blocks,
+    # the better choice for a lone solve
+    t1 = time.perf_counter()
+    meshes_seq = host_meshes(probs, {2: 0, 3: 0})
+    _log(f"# automatic-block meshes for the sequential legs in {time.perf_counter() - t1:.1f}s")
+    seq_w, lat_sw = sequential(ctx, meshes_seq, probs, u0s, ids)
     _log(f"# sequential warm: {seq_w}")
-    seq_z, _ = sequential(ctx, meshes, probs, None, ids)
+    seq_z, _ = sequential(ctx, meshes_seq, probs, None, ids)
+    for m in meshes_seq:
+        m.close()
+    del meshes_seq
     _log(f"# sequential zero: {seq_z}")
     plates = [i for i in ids if probs[i].dim == 2]
     boxes = [i for i in ids if probs[i].dim == 3]
@@ -876,6 +900,8 @@ def run_c5(args):
                          f"{SERVE_BUDGET_GB} GiB / {SERVE_SLOTS}-slot budget; one step = one "
                          f"of {args.steps} arrival windows of the one timed stream"),
             "requests": n_req, "elements_total": int(n_el.sum()),
+            "owner_block_nodes": {"2d": serve_block_nodes(args)[2] or "auto",
+                                  "3d": serve_block_nodes(args)[3] or "auto"},
             "plates": len(plates), "boxes": len(boxes), "rate_per_s": rate, "tol": 1e-8,
             "precision": "fp32 element math and Krylov vectors; fp64 dots, residuals, "
                          "state, line-search energy and det F near compression",
@@ -1434,6 +1460,8 @@ def main():
     ap.add_argument("--requests", type=int, default=512, help="serving stream requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serving arrivals per second")
     ap.add_argument("--cpu-sample-worker", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--serve-block-nodes", default="768,256",
+                    help="owner-block nodes of the served meshes, 2D,3D (0: automatic)")
     ap.add_argument("--stream-only", action="store_true",
                     help="serving: stop after the timed stream (for profiler runs)")
     args = ap.parse_args()
