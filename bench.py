@@ -826,10 +826,13 @@ def run_c5(args):
     t_timed = time.perf_counter() - t0
     warm = stream_summary(res_w, probs, ids)
     _log(f"# warm stream: {warm}")
+    worker = {k: round(st_w[k], 3) for k in ("admit_s", "tick_s", "complete_s")}
+    _log(f"# worker time: {worker}")
     fk = ks["fused_iter"]
     _log(f"# fused iteration: {fk}")
     if args.stream_only:       # profiling runs: setup, warm-up and the timed stream
         print(json.dumps({"served_warm": warm, "fused_iter": fk, "apply": ks["apply"],
+                          "worker_s": worker,
                           "ms_per_step": round(t_timed / args.steps * 1e3, 3)}), flush=True)
         return
     res_z, _, st_z, _ = serve(ctx, meshes, probs, None, t_arr, ids)
@@ -912,7 +915,7 @@ def run_c5(args):
         "sequential_warm": seq_w,
         "sequential_zero_start": seq_z,
         "server": {"peak_live": st_w["peak_live"], "peak_bytes": st_w["peak_bytes"],
-                   "steps": st_w["steps"], "launches": st_w["launches"]},
+                   "steps": st_w["steps"], "launches": st_w["launches"], "worker_s": worker},
         "roofline": {
             "bound": "hbm",
             "kernel": "k_fcg (fused PCG iteration, batched over live requests)",

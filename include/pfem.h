@@ -553,10 +553,14 @@ typedef struct {
   int64_t submitted, completed, live, queued, peak_live;
   int64_t bytes_in_use, peak_bytes, budget;
   int64_t steps, launches;
+  double admit_s, tick_s, complete_s;   /* worker host seconds: admitting requests
+                                           (uploads, solver state), engine steps,
+                                           completing them (download, frees) */
 } pfem_server_stats;
 /* Counters of the server (a consistent snapshot; out: host): requests
  * submitted / completed / live / queued, the most live at once, device
- * bytes in use, their peak and the budget, worker steps and launches. */
+ * bytes in use, their peak and the budget, worker steps and launches, and
+ * where the worker's time went. */
 pfem_status pfem_server_get_stats(pfem_server* s, pfem_server_stats* out);
 /* Kernel timing of the server's own stream: the families of
  * pfem_ctx_set_timing (bitmask; 0 = off), every launch timed.  Counters are

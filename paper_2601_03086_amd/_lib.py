@@ -80,9 +80,10 @@ class pfem_kernel_stats(C.Structure):
 
 
 class pfem_server_stats(C.Structure):
-    _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "live", "queued",
-                                         "peak_live", "bytes_in_use", "peak_bytes",
-                                         "budget", "steps", "launches")]
+    _fields_ = ([(k, C.c_int64) for k in ("submitted", "completed", "live", "queued",
+                                          "peak_live", "bytes_in_use", "peak_bytes",
+                                          "budget", "steps", "launches")]
+                + [(k, C.c_double) for k in ("admit_s", "tick_s", "complete_s")])
 
 
 _VP = C.c_void_p

@@ -6,13 +6,18 @@
 // tick advances all live requests together: one launch per kernel family
 // and (dimension, precision) group covers every request that needs that
 // step, so requests that arrive while others are on the device overlap with
-// them.  A finished request leaves at the end of its tick and its memory is
-// returned before the next admission check.
+// them.  The host work around the device work overlaps it: while a tick's
+// launches run, the worker admits the next requests (allocation, uploads,
+// initial launches queued behind the tick) and copies out the results of
+// the requests that finished in the previous tick (on a second stream);
+// their memory is freed once the tick has ended, before the next
+// admission check.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -40,12 +45,15 @@ struct Req {
   bool mesh_released = false;   // complete() released the server's copy of the mesh
   std::atomic<bool> cancel{false};   // set by the client, read by the worker
   std::vector<double> u_out;
+  std::vector<double> u_int;   // the solution in internal order, copied from the device
   pfem_solve_report rep{};
 };
 }  // namespace
 
 struct pfem_server {
   Ctx* c = nullptr;   // own stream and descriptor ring on the caller's device
+  hipStream_t side = nullptr;   // result copies that overlap the next tick
+  std::vector<Req*> pending;    // finished in the last tick, results not yet copied
   int64_t budget = 0;
   int max_slots = 0;
   std::thread worker;
@@ -59,6 +67,7 @@ struct pfem_server {
   std::chrono::steady_clock::time_point t0;
   int64_t bytes_in_use = 0, peak_bytes = 0, peak_live = 0;
   int64_t submitted = 0, completed = 0, steps = 0, launches = 0;
+  double admit_s = 0.0, tick_s = 0.0, complete_s = 0.0;   // worker host time
   std::string worker_error;
   std::map<pfem_mesh*, int> mesh_refs;   // meshes this server uploaded: live requests on each
   // kernel timing: a mask requested by the client (-1: no change), applied
@@ -71,6 +80,8 @@ struct pfem_server {
   }
   void run();
   void admit(Req* r);
+  void collect(Req* r);
+  void finish(Req* r);
   void complete(Req* r);
   void retire(Req* r);
   void fail(pfem_status code, const std::string& msg);
@@ -91,11 +102,12 @@ void pfem_server::admit(Req* r) {
   r->slot.id = r->id;
   const double* u0_int = nullptr;
   if (r->has_u0) {
-    PFEM_HIP(hipMemcpyAsync(r->slot.st->g64, r->u0.data(), m->n_dof() * 8,
-                            hipMemcpyHostToDevice, c->stream));
+    // a synchronous copy outside the library stream: it does not wait for
+    // the tick that may be running there (an asynchronous copy from pageable
+    // memory on that stream would)
+    PFEM_HIP(hipMemcpy(r->slot.st->g64, r->u0.data(), m->n_dof() * 8, hipMemcpyHostToDevice));
     launch_permute(c, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, true, r->slot.st->g64,
                    r->slot.st->aux64);
-    PFEM_HIP(hipStreamSynchronize(c->stream));   // u0 host buffer may be released below
     u0_int = r->slot.st->aux64;
   }
   slot_begin(c, &r->slot, u0_int);
@@ -103,15 +115,26 @@ void pfem_server::admit(Req* r) {
   r->t_admit = now();
 }
 
-void pfem_server::complete(Req* r) {
+// Queue the copy of a finished request's solution (internal order) on the
+// side stream; the caller synchronises it.  Its slot is in no tick any
+// more, so the library stream does not write it.
+void pfem_server::collect(Req* r) {
+  if (r->slot.st == nullptr) return;
+  r->u_int.resize(r->m->n_dof());
+  PFEM_HIP(hipMemcpyAsync(r->u_int.data(), r->slot.st->x64, r->m->n_dof() * 8,
+                          hipMemcpyDeviceToHost, side));
+}
+
+// With the copy done and the library stream drained: the caller-order
+// solution, the report, and the request's device memory returned.
+void pfem_server::finish(Req* r) {
   pfem_mesh* m = r->m;
-  if (r->slot.st != nullptr) {
+  if (!r->u_int.empty()) {
+    const int D = m->dim;
     r->u_out.resize(m->n_dof());
-    launch_permute(c, PFEM_FP64, m->dim, m->dev.perm, m->n_nodes, false, r->slot.st->x64,
-                   r->slot.st->g64);
-    PFEM_HIP(hipMemcpyAsync(r->u_out.data(), r->slot.st->g64, m->n_dof() * 8,
-                            hipMemcpyDeviceToHost, c->stream));
-    PFEM_HIP(hipStreamSynchronize(c->stream));
+    for (int64_t n = 0; n < m->n_nodes; ++n)
+      for (int i = 0; i < D; ++i) r->u_out[n * D + i] = r->u_int[(int64_t)m->perm[n] * D + i];
+    std::vector<double>().swap(r->u_int);
   }
   r->rep = r->slot.rep;
   r->rep.status = r->cancel ? PFEM_E_CANCELLED : r->slot.status;
@@ -124,6 +147,13 @@ void pfem_server::complete(Req* r) {
   r->u0.clear();
   r->u0.shrink_to_fit();
   r->t_done = now();
+}
+
+void pfem_server::complete(Req* r) {
+  collect(r);
+  PFEM_HIP(hipStreamSynchronize(side));
+  PFEM_HIP(hipStreamSynchronize(c->stream));
+  finish(r);
 }
 
 // With mu held: the request leaves the live set and becomes visible to
@@ -141,6 +171,7 @@ void pfem_server::retire(Req* r) {
 // error.  Requests taken from the queue for admission are live already.
 void pfem_server::fail(pfem_status code, const std::string& msg) {
   worker_error = msg;
+  pending.clear();   // all of them are live: ended below
   for (Req* r : live) {
     r->rep = r->slot.rep;
     r->rep.status = code;
@@ -199,8 +230,8 @@ void pfem_server::run() {
           ++it;
         }
       }
-      for (Req* r : live)
-        if (r->cancel) cancelled_live.push_back(r);
+      for (Req* r : live)   // (a finished request is collected as usual)
+        if (r->cancel && !r->slot.finished) cancelled_live.push_back(r);
     }
     try {
       for (Req* r : cancelled_live) {
@@ -245,31 +276,66 @@ void pfem_server::run() {
         peak_bytes = std::max(peak_bytes, bytes_in_use);
         peak_live = std::max<int64_t>(peak_live, (int64_t)live.size());
       }
-      for (Req* r : to_admit) admit(r);
+      // this tick: the live requests that were admitted before and have not
+      // finished; during it, admit the new ones and copy out the results of
+      // those that finished in the last tick
       std::vector<SlotRun*> slots;
       std::vector<Req*> snapshot;
       {
         std::lock_guard<std::mutex> lk(mu);
         snapshot = live;
       }
-      for (Req* r : snapshot) slots.push_back(&r->slot);
+      for (Req* r : snapshot)
+        if (std::find(to_admit.begin(), to_admit.end(), r) == to_admit.end() &&
+            !r->slot.finished && r->slot.st != nullptr)
+          slots.push_back(&r->slot);
+      std::vector<Req*> collect_now;
+      collect_now.swap(pending);
+      double t_overlap = 0.0;
+      const std::function<void()> overlap = [&] {
+        const double t0 = now();
+        for (Req* r : to_admit) admit(r);
+        const double t1 = now();
+        for (Req* r : collect_now) collect(r);
+        if (!collect_now.empty()) PFEM_HIP(hipStreamSynchronize(side));
+        const double t2 = now();
+        t_overlap = t2 - t0;
+        std::lock_guard<std::mutex> lk(mu);
+        admit_s += t1 - t0;
+        complete_s += t2 - t1;
+      };
       if (!slots.empty()) {
         int64_t nl = 0;
-        engine_tick(c, slots, &nl);
+        const double t0 = now();
+        engine_tick(c, slots, &nl, &overlap);
         if (c->timing != 0) c->drain_timing();   // the step ended with a stream sync
+        const double dt = now() - t0 - t_overlap;
         std::lock_guard<std::mutex> lk(mu);
+        tick_s += dt;
         ++steps;
         launches += nl;
         for (int f = 0; f < FAM_COUNT; ++f)
           kstats[f] = pfem_kernel_stats{c->fam_launches[f], c->fam_ms[f], c->fam_run[f],
                                         c->fam_alg_bytes[f]};
       }
-      for (Req* r : snapshot) {
-        if (!r->slot.finished) continue;
-        complete(r);
+      if (slots.empty()) {   // nothing to step: the overlap work alone
+        overlap();
+        PFEM_HIP(hipStreamSynchronize(c->stream));
+      }
+      // the stream has drained: return the memory of the collected requests
+      for (Req* r : collect_now) {
+        const double t0 = now();
+        finish(r);
+        const double dt = now() - t0;
         std::lock_guard<std::mutex> lk(mu);
+        complete_s += dt;
         retire(r);
       }
+      // finished in this tick (or at admission): collected during the next
+      for (Req* r : snapshot)
+        if (r->slot.finished &&
+            std::find(collect_now.begin(), collect_now.end(), r) == collect_now.end())
+          pending.push_back(r);
     } catch (const pfem::Error& e) {
       std::lock_guard<std::mutex> lk(mu);
       fail(e.code, e.msg);
@@ -301,6 +367,7 @@ pfem_status pfem_server_create(pfem_ctx* ctx, int64_t hbm_budget_bytes, int32_t 
     try {
       PFEM_HIP(hipStreamCreateWithFlags(&s->c->stream, hipStreamNonBlocking));
       s->c->own_stream = true;
+      PFEM_HIP(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
       s->c->ring.init(16u << 20, s->c->stream);
     } catch (...) {
       ctx_unref(s->c);
@@ -448,6 +515,9 @@ pfem_status pfem_server_get_stats(pfem_server* s, pfem_server_stats* o) {
   o->budget = s->budget;
   o->steps = s->steps;
   o->launches = s->launches;
+  o->admit_s = s->admit_s;
+  o->tick_s = s->tick_s;
+  o->complete_s = s->complete_s;
   set_error("");
   return PFEM_OK;
 }
@@ -488,6 +558,10 @@ void pfem_server_destroy(pfem_server* s) {
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->c->device);
   (void)hipStreamSynchronize(s->c->stream);
+  if (s->side != nullptr) {
+    (void)hipStreamSynchronize(s->side);
+    (void)hipStreamDestroy(s->side);
+  }
   for (Req* r : s->live) {
     try {
       slot_free(&r->slot);

@@ -656,7 +656,8 @@ static void after_ls(Ctx* ctx, SlotRun* s) {
   s->action = A_LS;
 }
 
-int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches) {
+int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches,
+                const std::function<void()>* overlap) {
   std::vector<SlotRun*> den, resid, kstart, kall, ls;
   for (SlotRun* s : live) {
     if (s->finished) continue;
@@ -683,6 +684,7 @@ int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches) {
   for (SlotRun* s : touched)
     PFEM_HIP(hipMemcpyAsync(s->sc_host, s->st->sc, sizeof(Scalars), hipMemcpyDeviceToHost,
                             ctx->stream));
+  if (overlap != nullptr && *overlap) (*overlap)();
   PFEM_HIP(hipStreamSynchronize(ctx->stream));
   if (launches) *launches += nl;
   for (SlotRun* s : touched) s->hist_len_host = s->sc_host->hist_len;

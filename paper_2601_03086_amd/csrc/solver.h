@@ -17,6 +17,8 @@
 // family per tick covers all slots that need it (continuous batching).
 #pragma once
 
+#include <functional>
+
 #include <vector>
 
 #include "mesh.h"
@@ -64,7 +66,11 @@ struct SlotRun {
 void slot_begin(Ctx* ctx, SlotRun* s, const double* u0_internal_dev);
 
 // Runs one tick for every live slot.  Returns the number not finished.
-int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches);
+// overlap (optional): host work to run after the tick's launches are
+// enqueued and before the tick waits for them (work that may enqueue on
+// the library stream only behind them).
+int engine_tick(Ctx* ctx, std::vector<SlotRun*>& live, int64_t* launches,
+                const std::function<void()>* overlap = nullptr);
 
 // Allocates device and pinned state for a slot on mesh m.
 // Argument checks of a solve's options (pfem_solve, pfem_server_submit):
