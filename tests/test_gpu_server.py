@@ -166,3 +166,35 @@ def test_oversize_and_cancel(ctx):
         _, r = srv.result(i)
         assert r["status"] == L.PFEM_E_CANCELLED
     srv.close()
+
+
+def test_finished_at_admission_and_late_cancel(ctx):
+    """A request whose warm start already meets tol_fine finishes when it is
+    admitted (its result is its warm start, reported SKIPPED_FINE) and is
+    collected like the others; a cancel that arrives after a request has
+    finished leaves its result intact; every result equals its lone solve."""
+    from paper_2601_03086_amd import _lib as L
+    from paper_2601_03086_amd import core
+    p = synth.plate_problem(901, 902, 903, n_holes=2, target_tris=3000)
+    q = synth.plate_problem(904, 905, 906, n_holes=2, target_tris=5000)
+    mp = core.Mesh.from_problem(ctx, p)
+    ud, _, _ = mp.solve(tol=1e-11, prec="fp64")
+    u1, r1, _ = core.Mesh.from_problem(ctx, q).solve(tol=1e-9, prec="fp32")
+    hp, hq = core.Mesh.from_problem(None, p), core.Mesh.from_problem(None, q)
+    srv = core.Server(ctx, 1 << 30, max_slots=2)
+    srv.submit(0, hp, u0=ud, tol=1e-9, tol_fine=1e-6, prec="fp32")   # done at admission
+    srv.submit(1, hq, tol=1e-9, prec="fp32")
+    srv.submit(2, hp, u0=ud, tol=1e-9, tol_fine=1e-6, prec="fp32")
+    _wait(srv, [0, 1, 2])
+    srv.cancel(1)                       # too late: it has finished
+    for i in (0, 2):
+        u, r = srv.result(i)
+        assert r["status"] == L.PFEM_SKIPPED_FINE
+        assert np.array_equal(u, ud)
+    u, r = srv.result(1)
+    assert r["status"] == 0
+    assert rel(u, u1) <= 1e-6
+    st = srv.stats()
+    assert st["live"] == 0 and st["bytes_in_use"] == 0
+    assert st["admit_s"] >= 0 and st["tick_s"] > 0 and st["complete_s"] >= 0
+    srv.close()
