@@ -989,6 +989,50 @@ def warm_start_prediction(mesh, uref, u0, hist):
             "error_ratio_A_norm": round(e_zero / e_warm, 2)}
 
 
+def run_crossover():
+    """Warm FP32 solves to 1e-8, fused against classic PCG, on the meshes
+    around the automatic choice between them: plates with 8 holes of 600k,
+    1M and 2M triangles, Neo-Hookean and linear 1x1x4 boxes of 515k and 1M
+    tetrahedra (automatic owner blocks).  The FP64 reference (zero start,
+    1e-10, at most 400k products) gives the warm start, reference + 1%
+    smooth noise; each form is timed as the median of 3 solves (device
+    time on the library stream).  One JSON line per mesh."""
+    import numpy as np
+    import synth
+    from paper_2601_03086_amd import core
+    ctx = core.Context(0)
+    cases = []
+    for tt in (6e5, 1e6, 2e6):
+        cases.append(("plate", lambda tt=tt: synth.plate_problem(2, 1002, 2002, target_tris=tt)))
+    for npu in (28, 35):
+        cases.append(("nh box", lambda npu=npu: synth.box_problem(3, 1003, n_per_unit=npu)))
+        cases.append(("lin box", lambda npu=npu: synth.box_problem(3, 1003, n_per_unit=npu,
+                                                                   model="lin_3d",
+                                                                   n_load_steps=1)))
+    for name, make in cases:
+        t0 = time.perf_counter()
+        prob = make()
+        _log(f"# {name}: {prob.n_elems} elements generated in {time.perf_counter() - t0:.1f}s")
+        mesh = core.Mesh.from_problem(ctx, prob)
+        uref, rref, _ = mesh.solve(tol=1e-10, prec="fp64", max_iter=400000)
+        assert rref["status"] == 0, rref
+        u0 = synth.warm_start_guess(uref, prob.coords, prob.dir_nodes, seed=3002)
+        out = {"config": "fused against classic PCG", "mesh": name, "elems": prob.n_elems,
+               "blocks": mesh.info["n_blocks"], "block_nodes": mesh.info["block_nodes"]}
+        for kr in ("fused", "classic", "auto"):
+            ms = []
+            for _ in range(3):
+                u, rep, _ = mesh.solve(u0=u0, tol=1e-8, prec="fp32", krylov=kr, max_iter=400000)
+                assert rep["status"] == 0 and rep["rel_residual_final"] <= 1e-8, rep
+                ms.append(rep["t_device_ms"])
+            out[kr] = {"ms": round(float(np.median(ms)), 2), "kv": rep["kv_count"],
+                       "newton": rep["newton_iters"],
+                       "rel_err": float(np.linalg.norm(u - uref) / np.linalg.norm(uref))}
+        mesh.close()
+        print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def run_quad(n=150, n_seq=10):
     """The paper's quadrilateral benchmarks (Sec. 'Nonlinear hyperelasticity'):
     n hyperelastic beams (50 x 50 Q4) and n Cook's membranes (30 x 30 Q8),
@@ -1455,7 +1499,8 @@ def main():
     ap.add_argument("--kv-large", default=None,
                     help='e.g. "2d:2000,3d:60": K.v roofline sweep on large meshes')
     ap.add_argument("--config", default=None,
-                    choices=["c1", "c2", "c3", "c4", "sweep", "rotate", "homog", "quad"],
+                    choices=["c1", "c2", "c3", "c4", "sweep", "rotate", "homog", "quad",
+                             "crossover"],
                     help="other workloads (one JSON line each, not the headline)")
     ap.add_argument("--sizes", default="2d:2e5,2d:1e6,2d:4e6,2d:1.6e7,3d:1e6,3d:4e6,3d:1.6e7",
                     help="--config sweep sizes (element counts)")
@@ -1497,7 +1542,8 @@ def main():
         {"c1": run_c1, "c2": lambda: run_c2(args), "c3": run_c3, "c4": run_c4,
          "sweep": lambda: run_sweep(args.sizes),
          "rotate": lambda: run_rotate(args.copies),
-         "homog": run_homog, "quad": run_quad}[args.config]()
+         "homog": run_homog, "quad": run_quad,
+         "crossover": run_crossover}[args.config]()
         return
     run_c5(args)
 

@@ -49,7 +49,8 @@ extern "C" {
 typedef int32_t pfem_status;
 enum {
   PFEM_OK = 0,
-  PFEM_NOT_CONVERGED = 1,     /* max iterations reached; outputs hold the last iterate */
+  PFEM_NOT_CONVERGED = 1,     /* max iterations reached, or (linear) the true residual
+                                 stalled above tol; outputs hold the last iterate */
   PFEM_SKIPPED_FINE = 2,      /* guess already below tol_fine: no iteration run */
   PFEM_E_INVALID_ARG = -1,
   PFEM_E_INVALID_MESH = -2,   /* bad index, degenerate element, orphan node ... */
@@ -414,9 +415,9 @@ pfem_status pfem_batch_hvp(pfem_batch* b, int prec, int mask, const void* u,
  *          update evaluated by every workgroup at the nodes it gathers, so
  *          the element pass and all vector updates share a kernel (one
  *          extra matvec per inner solve, w = A u at the start);
- * AUTO     FUSED in FP32 mode on meshes up to 600k triangles / 800k
- *          tetrahedra (latency-bound iterations), CLASSIC otherwise and in
- *          FP64 mode. */
+ * AUTO     FUSED in FP32 mode on triangle meshes of any size and on
+ *          tetrahedral meshes up to 800k elements, CLASSIC otherwise, in
+ *          FP64 mode, on quadrilaterals and with periodic springs. */
 enum { PFEM_KRYLOV_AUTO = 0, PFEM_KRYLOV_CLASSIC = 1, PFEM_KRYLOV_FUSED = 2 };
 
 /* Preconditioner of the PCG solves (the paper's CG names none; §5.6 notes
@@ -477,7 +478,11 @@ void pfem_solve_opts_default(pfem_solve_opts* o);
  * NULL; entry 0 is the initial guess's, then one per Krylov iteration of
  * every inner loop in order, truncated to history_cap).  rep: host (may be
  * NULL).  Returns when the solve has ended (the context stream is
- * synchronised).  Status: PFEM_OK, PFEM_SKIPPED_FINE, PFEM_NOT_CONVERGED,
+ * synchronised).  A linear solve whose true residual fails to halve over
+ * three refinement sweeps in a row (tol below the accuracy the FP64
+ * residual evaluation attains on the mesh) ends with PFEM_NOT_CONVERGED and
+ * rel_residual_final at that level instead of running to max_iter.
+ * Status: PFEM_OK, PFEM_SKIPPED_FINE, PFEM_NOT_CONVERGED,
  * or a solver failure (PFEM_E_BREAKDOWN, PFEM_E_INVERTED,
  * PFEM_E_LINESEARCH) -- all of these still fill u_out (the last iterate),
  * history and rep; argument, state and device errors leave the outputs

@@ -927,12 +927,14 @@ bool krylov_fused(const pfem_solve_opts& o, const pfem_mesh* m) {
   if (o.krylov != PFEM_KRYLOV_AUTO) return o.krylov == PFEM_KRYLOV_FUSED;
   if (o.precond == PFEM_PRECOND_TWO_LEVEL) return false;   // classic loop only
   if (m->elem != PFEM_ELEM_P1) return false;                // quadrilaterals: classic loop
-  // The fused launch wins where an iteration is launch- and latency-bound
-  // (measured warm FP32 solves: 200k-triangle plate 55 vs 82 ms per solve,
-  // 500k-tet Neo-Hookean box 55 vs 64 ms); on larger meshes its extra vector
-  // traffic and the weaker float32 convergence of the single-reduction form
-  // catch up (600k triangles: 226 vs 221 ms; 1M tets: 123 vs 120 ms).
-  const int64_t limit = m->dim == 2 ? 600000 : 800000;
+  // Measured warm FP32 solves to 1e-8 with the automatic owner blocks
+  // (fused against classic, ms): plates with holes 200k triangles 55 / 82,
+  // 600k 203 / 210, 1M 364 / 436, 2M 741 / 1008 -- the fused form needs up
+  // to 40% more products on the plates but saves two launches and two
+  // vector passes per iteration; Neo-Hookean boxes 515k tets 63 / 76, 1M
+  // tets 134 / 136; linear boxes 515k 49 / 54, 1M 105 / 104.  Fused in 2D
+  // at every size, in 3D up to 800k tetrahedra (beyond, a tie).
+  const int64_t limit = m->dim == 2 ? INT64_MAX : 800000;
   // periodic springs are applied by the owner kernels only (classic loop)
   return o.prec == PFEM_FP32 && m->n_elems <= limit && m->pairs.empty();
 }

@@ -264,6 +264,9 @@ static const int2* coarse_work(Ctx* ctx, const Group& g, int* n_items) {
   return static_cast<const int2*>(ctx->ring.put(w.data(), w.size() * sizeof(int2)));
 }
 
+// Sweeps in a row without halving the true residual that end a linear solve.
+constexpr int kStalledSweeps = 3;
+
 static double inner_target(const SlotRun* s) {
   const double floor_abs = 0.5 * s->o.tol * s->den;
   if (!s->nl) {
@@ -305,6 +308,8 @@ void slot_begin(Ctx* ctx, SlotRun* s, const double* u0_dev) {
   s->first_resid = true;
   s->minv_valid = false;
   s->newton_in_step = 0;
+  s->rho_sweep = 0.0;
+  s->stalled = 0;
   s->finished = false;
   s->status = PFEM_OK;
   const double scale = (double)s->step / s->n_steps;
@@ -573,6 +578,19 @@ static void after_resid(Ctx* ctx, SlotRun* s) {
   if (s->rep.kv_count >= s->max_iter) {
     finish(s, PFEM_NOT_CONVERGED);
     return;
+  }
+  if (!s->nl) {
+    // Every sweep of a linear solve starts from the true residual.  When
+    // tol lies below what the FP64 residual evaluation can resolve on this
+    // mesh (its rounding grows with the mesh size), each sweep meets its
+    // recurred target in a few iterations and the true residual stays at
+    // that floor; three sweeps in a row that fail to halve it end the solve.
+    if (s->rep.outer_sweeps > 0) s->stalled = s->rho > 0.5 * s->rho_sweep ? s->stalled + 1 : 0;
+    if (s->stalled >= kStalledSweeps) {
+      finish(s, PFEM_NOT_CONVERGED);
+      return;
+    }
+    s->rho_sweep = s->rho;
   }
   if (s->nl && s->newton_in_step >= (s->o.max_newton > 0 ? s->o.max_newton : 50)) {
     finish(s, PFEM_NOT_CONVERGED);

@@ -53,6 +53,8 @@ struct SlotRun {
   double ls_s = 1.0, ls_slope = 0.0;
   int ls_tries = 0;
   int max_iter = 0;
+  double rho_sweep = 0.0;   // linear: true residual at the start of the last sweep
+  int stalled = 0;          // linear: sweeps in a row that did not halve it
   bool finished = false;
   pfem_status status = PFEM_OK;
   int64_t id = -1;

@@ -183,6 +183,29 @@ def test_failures_reported(ctx):
     assert rep["status"] == 0
 
 
+
+def test_unattainable_tol_stops_at_the_residual_floor(ctx):
+    """A tol far below what FP64 resolves (1e-18) ends NOT_CONVERGED once
+    the true residual stops falling between refinement sweeps, in both
+    precisions and both PCG forms, long before the iteration cap, with the
+    solution as accurate as the arithmetic allows."""
+    p = synth.plate_problem(341, 342, 343, n_holes=3, target_tris=3000)
+    ud, _ = osolve.solve_linear(p, method="direct")
+    m = _mesh(ctx, p)
+    _, r0, _ = m.solve(tol=1e-10, prec="fp64")
+    assert r0["status"] == 0
+    cap = 10 * len(fe.Model(p).free_dofs)
+    for prec in ("fp64", "fp32"):
+        for kr in ("classic", "fused"):
+            u, rep, _ = m.solve(tol=1e-18, prec=prec, krylov=kr)
+            print(prec, kr, rep["kv_count"], rep["outer_sweeps"], rep["rel_residual_final"],
+                  rel(u, ud), flush=True)
+            assert rep["status_name"] == "NOT_CONVERGED"
+            assert rep["kv_count"] < cap // 4 and rep["kv_count"] < 30 * r0["kv_count"]
+            assert rep["outer_sweeps"] >= 4
+            assert rep["rel_residual_final"] < 1e-12
+            assert rel(u, ud) < 1e-8
+
 def test_fused_pcg_matches_classic_fp64(ctx):
     """The one-launch fused PCG runs the same Krylov iterates as the
     three-launch loop: on C1 in FP64 the residual histories agree and the
