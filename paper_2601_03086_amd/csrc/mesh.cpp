@@ -929,10 +929,10 @@ bool krylov_fused(const pfem_solve_opts& o, const pfem_mesh* m) {
   if (m->elem != PFEM_ELEM_P1) return false;                // quadrilaterals: classic loop
   // Measured warm FP32 solves to 1e-8 with the automatic owner blocks
   // (fused against classic, ms): plates with holes 200k triangles 55 / 82,
-  // 600k 203 / 210, 1M 364 / 436, 2M 741 / 1008 -- the fused form needs up
-  // to 40% more products on the plates but saves two launches and two
-  // vector passes per iteration; Neo-Hookean boxes 515k tets 63 / 76, 1M
-  // tets 134 / 136; linear boxes 515k 49 / 54, 1M 105 / 104.  Fused in 2D
+  // 600k 173 / 209, 1M 308 / 449, 2M 822 / 1003 -- the fused form needs
+  // up to 20% more products on the plates but saves two launches and two
+  // vector passes per iteration; Neo-Hookean boxes 515k tets 65 / 75, 1M
+  // tets 133 / 134; linear boxes 515k 48 / 53, 1M 105 / 104.  Fused in 2D
   // at every size, in 3D up to 800k tetrahedra (beyond, a tie).
   const int64_t limit = m->dim == 2 ? INT64_MAX : 800000;
   // periodic springs are applied by the owner kernels only (classic loop)
