@@ -779,7 +779,8 @@ pfem_status pfem_solve(pfem_mesh* m, const double* u0, const pfem_solve_opts* o,
       (two_level && cached->tl_dev == nullptr)) {
     cached.reset();
     cached.reset(new SolveState());
-    cached->alloc(prec, nd, m->n_blocks, std::max<int64_t>(hcap, 1024), m->nonlinear, fused);
+    cached->alloc(prec, nd, m->n_blocks, std::max<int64_t>(hcap, 1024), m->nonlinear, fused,
+                  nh_cache_values(m));
     if (two_level) {
       coarse_upload(m, ctx);
       cached->alloc_two_level(m);

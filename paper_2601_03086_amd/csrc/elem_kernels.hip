@@ -108,6 +108,7 @@ struct ElemIn {
   ElemX<D, T> x;
   T u[D + 1][D];   // state (Neo-Hookean) or input of the linear force
   T v[D + 1][D];   // direction of the apply
+  T c[OP == OP_HVPC ? D * D + 1 : 1];            // cached {F^-T, ln J}
   T rec[FUSED ? D + 1 : 1][FUSED ? 4 * D : 1];   // fused PCG records
   T mu, lam;
 };
@@ -120,14 +121,17 @@ __device__ __forceinline__ void load_elem(const MeshDev& m, const T* __restrict_
   load_elem_x<D, T>(m, nd, in.x);
   in.mu = mat_mu<T>(m, e);
   in.lam = mat_lam<T>(m, e, in.mu);
-  if constexpr (NL || OP == OP_FORCE) {
+  if constexpr (OP == OP_HVPC) {   // U: the cache, one array of n_elems per value
+#pragma unroll
+    for (int k = 0; k <= D * D; ++k) in.c[k] = ldx(U, (uint32_t)(k * m.n_elems + e));
+  } else if constexpr (NL || OP == OP_FORCE) {
 #pragma unroll
     for (int a = 0; a <= D; ++a) load_nodal<D, T>(U, nd[a], in.u[a]);
   }
   if constexpr (FUSED) {
 #pragma unroll
     for (int a = 0; a <= D; ++a) load_record<D, T>(V, nd[a], in.rec[a]);
-  } else if constexpr (OP == OP_APPLY) {
+  } else if constexpr (is_apply_op(OP)) {
 #pragma unroll
     for (int a = 0; a <= D; ++a) load_nodal<D, T>(V, nd[a], in.v[a]);
     if (mask & PFEM_MASK_IN) {
@@ -214,10 +218,18 @@ __device__ __forceinline__ void element_compute(const MeshDev& m,
     linear_stress_tilde<D, T>(M, mu, lam, S);
     scatter_rows<D, T>(S, g, s_sym, y);
   } else {
-    T Ht[D][D];
-    grad_tilde<D, T>(in.u, g, Ht);
     NHState<D, T> st;
-    nh_state<D, T>(Ht, T(1) / g.det, st);
+    if constexpr (OP == OP_HVPC) {   // the tangent needs F^-T and ln J only
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int k = 0; k < D; ++k) st.FinvT[i][k] = in.c[i * D + k];
+      st.lnJ = in.c[D * D];
+    } else {
+      T Ht[D][D];
+      grad_tilde<D, T>(in.u, g, Ht);
+      nh_state<D, T>(Ht, T(1) / g.det, st);
+    }
     if constexpr (OP == OP_FORCE) {
       T P[D][D];
       nh_piola<D, T>(st, mu, lam, P);
@@ -562,13 +574,16 @@ __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int b
   // occupancy than the overlap gains: measured 10-20% slower)
   constexpr int EIF = (D == 2 && !NL) ? PFEM_FCG_EIF : PFEM_FCG_EIF_OTHER;
   constexpr bool HOIST = D == 2;
+  // Neo-Hookean: the element state {F^-T, ln J} of the Newton step comes
+  // from the solve's per-element cache (tp->u)
+  constexpr int OPA = NL ? OP_HVPC : OP_APPLY;
   using A = AccT<T>;
   A* acc = reinterpret_cast<A*>(smem_raw);
   const T* U = static_cast<const T*>(tp->u);
   for (int i = threadIdx.x; i < nloc * D; i += NT) acc[i] = A(0);
-  VisitRound<D, T, OP_APPLY, NL, true, EIF> rd0;
+  VisitRound<D, T, OPA, NL, true, EIF> rd0;
   if constexpr (HOIST)
-    load_round<D, T, OP_APPLY, NL, true, NT, EIF, PK>(m, U, Rin, 0, br, threadIdx.x, rd0);
+    load_round<D, T, OPA, NL, true, NT, EIF, PK>(m, U, Rin, 0, br, threadIdx.x, rd0);
   if ((int)threadIdx.x >= nb) pv_in[0] = pv_in[1] = pv_in[2] = 0.0;
   if ((int)threadIdx.x + NT < nb) {
     pv_in[0] += pv2[0];
@@ -628,8 +643,8 @@ __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int b
   if (state != 0) return;
   const T alpha = (T)alpha64, beta = (T)beta64;
   if constexpr (HOIST)
-    compute_round<D, T, OP_APPLY, NL, A, true, EIF>(m, rd0, n0, nloc, acc, alpha, beta);
-  owner_rounds<D, T, OP_APPLY, NL, A, true, NT, EIF, PK>(
+    compute_round<D, T, OPA, NL, A, true, EIF>(m, rd0, n0, nloc, acc, alpha, beta);
+  owner_rounds<D, T, OPA, NL, A, true, NT, EIF, PK>(
       m, U, Rin, 0, br, threadIdx.x + (HOIST ? EIF * NT : 0), n0, nloc, acc, alpha, beta);
   T* Rout = static_cast<T*>(tp->rec[(j + 1) & 1]);
   const bool first = j == 0;
@@ -684,8 +699,11 @@ __device__ __forceinline__ void fcg_iteration(const Task* __restrict__ tp, int b
 }
 
 // Batched form: workgroup -> (task, node block) through the work table.
+// The 3D Neo-Hookean float32 iteration is held to 5 waves per SIMD (94
+// registers, no spills; 4 waves without the hint).
 template <int D, typename T, bool NL, int NT, int PK>
 __global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu((D == 3 && NL && sizeof(T) == 4) ? 5 : 1)))
 k_fcg(const Task* __restrict__ tasks, const int2* __restrict__ work, int it) {
   const int2 wk = work[blockIdx.x];
   fcg_iteration<D, T, NL, NT, PK>(tasks + wk.x, wk.y, it);
@@ -851,6 +869,57 @@ k_energy(const Task* __restrict__ tasks, const int2* __restrict__ work, const Ba
   energy_epilogue<D, TU, TV, DIFF>(tp, m, U, V, s, blk, n0, nloc, part);
 }
 
+// ------------------------------------------- Neo-Hookean element cache
+// Per element of the owned ranges (every element exactly once): F^-T and
+// ln J of the state u (task u, nodal, kernel precision) into the task's y,
+// value k of element e at y[k * n_elems + e] (k = D i + j for F^-T_ij,
+// k = D^2 for ln J): what every Hessian-vector product of one Newton step
+// needs of the state, computed once per step instead of once per product.
+template <int D, typename T>
+__global__ void __launch_bounds__(kThreads)
+k_nh_cache(const Task* __restrict__ tasks, const int2* __restrict__ work) {
+  const int2 wk = work[blockIdx.x];
+  const Task* tp = tasks + wk.x;
+  if (!tp->active) return;
+  const MeshDev m = tp->m;
+  const pi4 br = ldg(reinterpret_cast<const pi4*>(m.blocks + wk.y));
+  const T* U = static_cast<const T*>(tp->u);
+  T* C = static_cast<T*>(tp->y);
+  const size_t ne = (size_t)m.n_elems;
+  for (int e = br.x + (int)threadIdx.x; e < br.y; e += kThreads) {
+    int nd[D + 1];
+    load_conn<D, T>(m, e, nd);
+    ElemX<D, T> x;
+    load_elem_x<D, T>(m, nd, x);
+    T u[D + 1][D];
+#pragma unroll
+    for (int a = 0; a <= D; ++a) load_nodal<D, T>(U, nd[a], u[a]);
+    Geo<D, T> g;
+    geometry_x<D, T>(m, x, g);
+    T Ht[D][D];
+    grad_tilde<D, T>(u, g, Ht);
+    NHState<D, T> st;
+    nh_state<D, T>(Ht, T(1) / g.det, st);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int k = 0; k < D; ++k) stg(C + (size_t)(i * D + k) * ne + e, st.FinvT[i][k]);
+    stg(C + (size_t)(D * D) * ne + e, st.lnJ);
+  }
+}
+
+void launch_nh_cache(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
+                     int n_work) {
+  if (n_work <= 0) return;
+  dim3 grid(n_work), block(kThreads);
+  hipStream_t s = ctx->stream;
+  if (dim == 2 && prec == PFEM_FP32) hipLaunchKernelGGL((k_nh_cache<2, float>), grid, block, 0, s, tasks, work);
+  else if (dim == 2) hipLaunchKernelGGL((k_nh_cache<2, double>), grid, block, 0, s, tasks, work);
+  else if (prec == PFEM_FP32) hipLaunchKernelGGL((k_nh_cache<3, float>), grid, block, 0, s, tasks, work);
+  else hipLaunchKernelGGL((k_nh_cache<3, double>), grid, block, 0, s, tasks, work);
+  PFEM_HIP(hipGetLastError());
+}
+
 // ---------------------------------------------------------------- launchers
 template <int D, typename T, bool NL>
 static void launch_owner_typed(Ctx* ctx, int op, const Task* tasks, const int2* work,
@@ -860,6 +929,10 @@ static void launch_owner_typed(Ctx* ctx, int op, const Task* tasks, const int2* 
   switch (op) {
     case OP_APPLY:
       hipLaunchKernelGGL((k_owner<D, T, OP_APPLY, NL>), grid, block, sm, ctx->stream, tasks, work, ba);
+      break;
+    case OP_HVPC:
+      if constexpr (NL)
+        hipLaunchKernelGGL((k_owner<D, T, OP_HVPC, true>), grid, block, sm, ctx->stream, tasks, work, ba);
       break;
     case OP_FORCE:
       hipLaunchKernelGGL((k_owner<D, T, OP_FORCE, NL>), grid, block, sm, ctx->stream, tasks, work, ba);
@@ -905,7 +978,7 @@ static void launch_alt_typed(Ctx* ctx, int op, int mode, const Task& t,
 }
 
 static int family_of(int op) {
-  return op == OP_APPLY ? FAM_APPLY : (op == OP_FORCE ? FAM_FORCE : FAM_DIAG);
+  return is_apply_op(op) ? FAM_APPLY : (op == OP_FORCE ? FAM_FORCE : FAM_DIAG);
 }
 
 template <bool NL>
@@ -930,6 +1003,8 @@ void launch_elem(Ctx* ctx, int dim, int prec, int op, bool nonlinear, int scatte
                  const Task* tasks_dev, const int2* work_dev, int n_work, int bn_max,
                  const Task* host_task_for_alt, const std::vector<int>* color_ptr,
                  const BaseArgs* rel) {
+  require(op != OP_HVPC || (nonlinear && scatter_mode == PFEM_SCATTER_OWNER && !is_quad_kind(dim)),
+          PFEM_E_INVALID_ARG, "the cached Hessian-vector product is an owner-scatter P1 kernel");
   hipEvent_t ev = nullptr;
   ctx->timing_begin(family_of(op), &ev);
   const BaseArgs ba = rel != nullptr ? *rel : BaseArgs{nullptr, nullptr, nullptr, 0, 0};

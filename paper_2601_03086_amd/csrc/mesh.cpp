@@ -912,7 +912,8 @@ int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg, bool two_level
   const int64_t nd = m->n_dof();
   const int64_t s = prec == PFEM_FP64 ? 8 : 4;
   int64_t b = 3 * nd * 8 + (6 + (fused_pcg ? 9 : 0)) * nd * s +
-              (int64_t)m->n_blocks * 2 * kRedSlots * 8 + 4096 + (int64_t)8 * 65536;
+              (int64_t)m->n_blocks * 2 * kRedSlots * 8 + 4096 + (int64_t)8 * 65536 +
+              nh_cache_values(m) * s;
   if (two_level) {   // the solve's own arrays and the mesh's coarse arrays
     const int64_t G = coarse_group(m);
     const int64_t n_agg = (m->n_blocks + G - 1) / G;
@@ -921,6 +922,11 @@ int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg, bool two_level
          coarse_device_bytes(m);
   }
   return b;
+}
+
+int64_t nh_cache_values(const pfem_mesh* m) {
+  if (!m->nonlinear || m->elem != PFEM_ELEM_P1) return 0;
+  return (int64_t)(m->dim * m->dim + 1) * m->n_elems;
 }
 
 bool krylov_fused(const pfem_solve_opts& o, const pfem_mesh* m) {

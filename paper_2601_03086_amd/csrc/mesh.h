@@ -34,6 +34,8 @@ struct SolveState {
   void* q = nullptr;
   void* minv = nullptr;
   void* u32 = nullptr;      // float32 copy of the state (FP32 Neo-Hookean HVP)
+  void* nhc = nullptr;      // Neo-Hookean P1: per-element {F^-T, ln J} of the Newton
+                            // state, (dim^2 + 1) arrays of n_elems (kernel precision)
   bool fused = false;       // fused PCG records present
   void* rec[2] = {nullptr, nullptr};   // fused PCG: {r, w, s, M^-1} per node, by parity
   void* tmp = nullptr;
@@ -49,7 +51,7 @@ struct SolveState {
   TwoLevelDev* tl_dev = nullptr;
   int64_t bytes = 0;
   void alloc(int prec, int64_t n_dof, int n_blocks, int64_t hist_cap, bool nonlinear,
-             bool fused_pcg);
+             bool fused_pcg, int64_t nh_cache_values);
   // Adds the two-level arrays for the mesh's coarse space (uploaded).
   void alloc_two_level(const pfem_mesh* m);
   void release();
@@ -179,6 +181,8 @@ void mesh_upload(pfem_mesh* m, Ctx* ctx);
 void mesh_release_device(pfem_mesh* m);
 int64_t mesh_device_bytes(const pfem_mesh* m);
 int64_t solve_bytes(const pfem_mesh* m, int prec, bool fused_pcg, bool two_level);
+// Values of the per-element Neo-Hookean cache of a solve on m (0: none).
+int64_t nh_cache_values(const pfem_mesh* m);
 // Whether a solve with these options runs the fused (one launch per
 // iteration) PCG.
 bool krylov_fused(const pfem_solve_opts& o, const pfem_mesh* m);

@@ -19,7 +19,7 @@ __device__ __forceinline__ T periodic_springs(const MeshDev& m, const T* __restr
                                               int n, int c, bool con) {
   const int q0 = ldg(m.pair_ptr + n), q1 = ldg(m.pair_ptr + n + 1);
   if (OP == OP_DIAG) return (T)(m.pair_k * (double)(q1 - q0));
-  const bool mask_in = OP == OP_APPLY && (mask & PFEM_MASK_IN);
+  const bool mask_in = is_apply_op(OP) && (mask & PFEM_MASK_IN);
   const T xn = (mask_in && con) ? T(0) : ldg(X + (size_t)n * D + c);
   T s = T(0);
   for (int q = q0; q < q1; ++q) {
@@ -53,7 +53,7 @@ __device__ __forceinline__ void owner_epilogue(const Task* __restrict__ tp, cons
     T val = (T)acc[i];
     const bool con = (ldg(m.dmask + n0 + i / D) >> (i % D)) & 1;
     if (OP == OP_FORCE) val -= (T)(tp->fscale * ldg(FE + gi));
-    if (springs) val += periodic_springs<D, T, OP>(m, OP == OP_APPLY ? V : U, mask, n0 + i / D,
+    if (springs) val += periodic_springs<D, T, OP>(m, is_apply_op(OP) ? V : U, mask, n0 + i / D,
                                                    i % D, con);
     if (OP == OP_DIAG) {
       if (con) val = T(1);
@@ -65,7 +65,7 @@ __device__ __forceinline__ void owner_epilogue(const Task* __restrict__ tp, cons
     if (W != nullptr) part[0] += (double)val * (double)ldg(W + gi);
     part[1] += (double)val * (double)val;
   }
-  write_partials(tp->red, m.n_blocks, blk, part, 0, OP == OP_APPLY ? 1 : 2);
+  write_partials(tp->red, m.n_blocks, blk, part, 0, is_apply_op(OP) ? 1 : 2);
 }
 
 // The owned-DOF terms of the energy kernels, then the block's partials

@@ -191,7 +191,11 @@ __host__ __device__ inline T* operand(void* field, void* base, int rel) {
 }
 
 // Element-kernel operations.
-enum ElemOp { OP_APPLY = 0, OP_FORCE = 1, OP_DIAG = 2 };
+// OP_HVPC: the Neo-Hookean Hessian-vector product with the element state
+// {F^-T, ln J} read from a per-element cache (the task's u) instead of
+// evaluated from the nodal state (P1 meshes, owner scatter).
+enum ElemOp { OP_APPLY = 0, OP_FORCE = 1, OP_DIAG = 2, OP_HVPC = 3 };
+constexpr bool is_apply_op(int op) { return op == OP_APPLY || op == OP_HVPC; }
 
 // Kernel timing families (pfem_ctx_kernel_time).
 enum Family { FAM_APPLY = 0, FAM_FORCE = 1, FAM_ENERGY = 2, FAM_DIAG = 3,
@@ -321,6 +325,10 @@ void launch_tl_update(Ctx* ctx, int dim, int prec, const Task* tasks, const int2
 void launch_tl_direction(Ctx* ctx, int dim, int prec, const Task* tasks, const int2* work,
                          int n_work, int it);
 // packed: every task of the launch has packed connectivity (see MeshDev).
+// Neo-Hookean P1: F^-T and ln J of every element of each task's state u
+// into its y (the cache that OP_HVPC reads); owner work table.
+void launch_nh_cache(Ctx* ctx, int dim, int prec, const Task* tasks_dev, const int2* work_dev,
+                     int n_work);
 void launch_fcg_iter(Ctx* ctx, int dim, int prec, bool nonlinear, const Task* tasks_dev,
                      const int2* work_dev, int n_work, int bn_max, int it, bool packed);
 // One workgroup per task: red.out[0..n_slots-1] = sums of partial slots

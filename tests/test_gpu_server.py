@@ -155,10 +155,18 @@ def test_oversize_and_cancel(ctx):
         srv.submit(0, m, tol=1e-8)
     assert ei.value.status == L.PFEM_E_OOM
     srv.close()
+    # a long request (FP64 from zero to the residual floor of a 100k-triangle
+    # plate: thousands of iterations) is cancelled once it runs, the one
+    # queued behind it before it runs
+    big = core.Mesh.from_problem(None, synth.plate_problem(804, 805, 806, n_holes=4,
+                                                           target_tris=100000))
     srv = core.Server(ctx, 1 << 30, max_slots=1)
-    srv.submit(1, m, tol=1e-13, prec="fp64", max_iter=10 ** 7)   # long
-    srv.submit(2, m, tol=1e-8)                                   # queued behind it
-    time.sleep(0.05)
+    srv.submit(1, big, tol=1e-13, prec="fp64", krylov="classic", max_iter=10 ** 7)
+    srv.submit(2, m, tol=1e-8)
+    t0 = time.time()
+    while srv.stats()["live"] < 1:
+        assert time.time() - t0 < 30, "the long request was never admitted"
+        time.sleep(0.001)
     srv.cancel(1)
     srv.cancel(2)
     _wait(srv, [1, 2], timeout=60)
