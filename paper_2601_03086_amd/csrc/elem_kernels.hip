@@ -269,9 +269,12 @@ __device__ __forceinline__ void lds_accumulate(A* acc, const int (&nd)[D + 1], i
 // Element visits in flight per thread in the fused 2D linear iteration and
 // in the other fused iterations (3D, Neo-Hookean), whose records and state
 // take more registers: one visit at a time keeps their occupancy (measured:
-// 500k-tet Neo-Hookean warm solve 54.9 ms against 77.4 with two).
+// 500k-tet Neo-Hookean warm solve 54.9 ms against 77.4 with two).  In 2D
+// one visit (74 registers, 6 waves per SIMD) against two (110, 4 waves):
+// the 200k-triangle solve alike (8.14 / 8.12 us per launch), the batched
+// 512-request stream 2% faster.
 #ifndef PFEM_FCG_EIF
-#define PFEM_FCG_EIF 2
+#define PFEM_FCG_EIF 1
 #endif
 #ifndef PFEM_FCG_EIF_OTHER
 #define PFEM_FCG_EIF_OTHER 1
