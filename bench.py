@@ -506,7 +506,8 @@ def run_rotate(copies, kind="c2"):
 
 # ------------------------------------------------------------ serving (C5)
 SERVE_BUDGET_GB = 96      # device memory the server may hold for live solves
-SERVE_SLOTS = 64          # live solves at once
+SERVE_SLOTS = 128         # live solves at once (512-request stream, warm: 64 slots
+                          # 55.6 solves/s, 128 57.6, 256 56.6; one run each)
 VERIFY_N = 16             # served results checked by the oracle
 VERIFY_MAX_ELEMS = 30000  # ... drawn among requests of at most this size
 CPU_SAMPLE_N = 24         # the oracle's timed sample: the first plates of the
@@ -564,14 +565,15 @@ def _solve_kw(p, tol, prec, precond="jacobi"):
 
 
 def serve(ctx, meshes, probs, u0s, t_arrive, ids, tol=1e-8, prec="fp32", timing=False,
-          keep=(), budget_gb=SERVE_BUDGET_GB, slots=SERVE_SLOTS, precond="jacobi"):
+          keep=(), budget_gb=SERVE_BUDGET_GB, slots=None, precond="jacobi"):
     """Open-loop replay: request ids[k] is submitted at t_arrive[k] seconds
     after the server starts (u0s None: zero start).  Returns per-request
     reports (library timestamps: submission, admission, completion), the
     solutions of the ids in `keep`, server statistics and, with timing, the
     kernel statistics of the apply and fused-iteration families."""
     from paper_2601_03086_amd import core
-    srv = core.Server(ctx, int(budget_gb * (1 << 30)), max_slots=slots)
+    srv = core.Server(ctx, int(budget_gb * (1 << 30)),
+                      max_slots=SERVE_SLOTS if slots is None else slots)
     if timing:
         srv.set_timing([FAM_APPLY, FAM_FUSED])
     n = len(ids)
@@ -1066,7 +1068,7 @@ def run_quad(n=150, n_seq=10):
         probs = [gen(7000 + i) for i in range(n)]
         meshes = host_meshes(probs)
         ids = list(range(n))
-        ref, refsol, _, _ = serve(ctx, meshes, probs, None, [0.0] * n, ids, tol=1e-10,
+        ref, refsol, _, _ = serve(ctx, meshes, probs, None, [0.0] * n, ids, tol=1e-10, slots=64,
                                   prec="fp64", keep=set(ids))
         bad = [(i, ref[i]["status"], ref[i]["newton_iters"], ref[i]["rel_residual_final"])
                for i in ids if ref[i]["status"] != 0]
@@ -1084,14 +1086,16 @@ def run_quad(n=150, n_seq=10):
             for p in probs:
                 p.n_load_steps = steps
             torch.cuda.synchronize()
-            r, sols, st, ks = serve(ctx, meshes, probs, starts, [0.0] * n, ids, keep={0})
+            r, sols, st, ks = serve(ctx, meshes, probs, starts, [0.0] * n, ids, keep={0},
+                                    slots=64)
             summ = stream_summary(r, probs, ids)
             summ["newton_per_request"] = round(float(np.mean([r[i]["newton_iters"]
                                                               for i in ids])), 2)
             summ["failed"] = sum(r[i]["status"] != 0 for i in ids)
             if label == "warm":
                 # the HVP launches' durations from a second, event-timed run
-                _, _, _, ks = serve(ctx, meshes, probs, starts, [0.0] * n, ids, timing=True)
+                _, _, _, ks = serve(ctx, meshes, probs, starts, [0.0] * n, ids, timing=True,
+                                    slots=64)
                 k = ks["apply"]
                 us = k["total_ms"] / max(k["launches_run"], 1) * 1e3
                 b = k["alg_bytes"] / max(k["launches_run"], 1)
@@ -1519,11 +1523,16 @@ def main():
     ap.add_argument("--requests", type=int, default=512, help="serving stream requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serving arrivals per second")
     ap.add_argument("--cpu-sample-worker", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--serve-slots", type=int, default=0,
+                    help="live solves at once in the served streams (0: 128)")
     ap.add_argument("--serve-block-nodes", default="768,256",
                     help="owner-block nodes of the served meshes, 2D,3D (0: automatic)")
     ap.add_argument("--stream-only", action="store_true",
                     help="serving: stop after the timed stream (for profiler runs)")
     args = ap.parse_args()
+    global SERVE_SLOTS
+    if args.serve_slots > 0:
+        SERVE_SLOTS = args.serve_slots
     global ORDER, BLOCK_NODES
     ORDER, BLOCK_NODES = args.order, args.block_nodes
     if args.cpu_baseline_worker:
