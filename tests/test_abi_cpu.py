@@ -582,3 +582,29 @@ def test_quad_mesh_validation():
     assert make(folded)[0] == L.PFEM_E_INVALID_MESH
     assert make(flat)[0] in (L.PFEM_E_INVALID_MESH,)
     assert make(good, elem=7)[0] == L.PFEM_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("kind", ["plate", "box", "beam_q4"])
+def test_solve_footprint_counts_the_neo_hookean_element_cache(kind):
+    """The footprint a server admits by includes the per-element cache of
+    {F^-T, ln J} that a Neo-Hookean solve on P1 elements keeps for each
+    Newton step: (d^2 + 1) values per element in the kernel precision,
+    and nothing else differs from the linear model on the same mesh
+    (quadrilateral meshes keep no cache)."""
+    if kind == "plate":
+        make = lambda model: synth.plate_problem(51, 52, 53, n_holes=2, target_tris=3000,
+                                                 model=model)
+        models = ("lin_plane_strain", "nh_plane_strain")
+    elif kind == "box":
+        make = lambda model: synth.box_problem(54, 55, n_per_unit=5, n_voids=2, model=model,
+                                               n_load_steps=1)
+        models = ("lin_3d", "nh_3d")
+    else:
+        make = lambda model: synth.beam_problem(56, 12, 6, model=model)
+        models = ("lin_plane_strain", "nh_plane_strain")
+    lin, nh = (_host_mesh(make(mo)) for mo in models)
+    d, ne = lin.info["dim"], lin.info["n_elems"]
+    vals = (d * d + 1) * ne if kind != "beam_q4" else 0
+    assert nh.info["solve_bytes_fp32"] - lin.info["solve_bytes_fp32"] == 4 * vals
+    assert nh.info["solve_bytes_fp64"] - lin.info["solve_bytes_fp64"] == 8 * vals
+    assert nh.footprint("fp32") == nh.info["device_bytes"] + nh.info["solve_bytes_fp32"]
